@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the Wedge-Frontier pull path on one MI355X.
+
+One step = one pass of the whole path over the R-MAT scale-24 workload
+(2^24 vertices, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05), seeded vertex
+relabelling, self-loops and duplicates removed; uint32 weights in [1, 255]):
+  BFS from 4 seeded sources, SSSP from the same 4 sources (threshold gate,
+  theta 1% / 20%, 32 / 16 edges per Wedge bit), CC on the undirected view,
+  and PageRank (20 iterations, d = 0.85, full pull).
+Inputs are resident in HBM before the timed region. The value is whole-step
+GTEPS: (4M + 4M + M + 20M) / step time, M = stored directed edges.
+
+The JSON line also carries the roofline of the dominant kernel (the PageRank
+pull, timed with HIP events on the launch stream over the timed steps) and the
+CPU oracle timed on a bounded sample of the same workload on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTEPS per app (BFS/CC/SSSP/PR) R-MAT s24; learned gate vs threshold rule"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    p = os.path.join(ROOT, "paper_1903_07754_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.txt")
+    if not os.path.exists(p):
+        return None
+    vals = {}
+    for line in open(p):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernels_hip_sha") != kernel_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pr_pull_bytes(info):
+    """Algorithmic bytes of one PageRank pull launch: the in-edge sources (4/edge),
+    the row layout (8 B mask + 4 B segment index per 64 positions, 4 B per
+    destination segment), one compulsory 4 B read of contrib per vertex with
+    out-edges, one 4 B write of S per destination with in-edges."""
+    return (4 * info["m"] + 12 * info["rows"] + 4 * info["nonempty"]
+            + 4 * (info["n"] - info["dangling"]) + 4 * info["nonempty"])
+
+
+def cpu_baseline(ro, col, w, srcs, m):
+    import oracle
+    log("timing the CPU oracle on a sample of the workload")
+    t = {}
+    t0 = time.perf_counter(); oracle.bfs(ro, col, int(srcs[0])); t["bfs"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.cc(ro, col); t["cc"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.sssp(ro, col, w, int(srcs[0])); t["sssp"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.pagerank(ro, col, 2, 0.85); t["pr"] = time.perf_counter() - t0
+    units = m + m + m + 2 * m
+    total = sum(t.values())
+    log("oracle seconds: " + ", ".join(f"{k}={v:.2f}" for k, v in t.items()))
+    return {"value": round(units / total / 1e9, 4), "unit": "GTEPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": ("same R-MAT s24 graph: BFS and SSSP from 1 source (sequential queue BFS, "
+                       "Dial/Dijkstra), CC by union-find (sequential), PageRank 2 of 20 iterations "
+                       "(FP64, OpenMP over destinations); units M+M+M+2M over the summed time"),
+            "seconds": {k: round(v, 3) for k, v in t.items()}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--sources", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1903_07754_amd as W
+
+    torch.cuda.set_device(0)
+    dev_name = torch.cuda.get_device_name(0)
+    log(f"device {dev_name}; generating R-MAT scale {args.scale}")
+    t0 = time.perf_counter()
+    ro, col = gen.rmat(args.scale, 16, seed=1)
+    w = gen.edge_weights(ro, col, seed=4)
+    srcs = [int(s) for s in gen.pick_sources(ro, args.sources, seed=3)]
+    n, m = len(ro) - 1, len(col)
+    log(f"n={n} m={m} generated in {time.perf_counter() - t0:.1f}s; building layouts")
+    t0 = time.perf_counter()
+    g = W.Graph.from_csr(ro, col, w)
+    gs = W.Graph.from_csr(ro, col, symmetrize=True)
+    log(f"layouts built and uploaded in {time.perf_counter() - t0:.1f}s "
+        f"(directed {g.info['device_bytes'] / 2**30:.2f} GiB, undirected m={gs.m})")
+
+    lev = torch.empty(n, dtype=torch.int32, device="cuda")
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    dist = torch.empty(n, dtype=torch.int32, device="cuda")
+    rank = torch.empty(n, dtype=torch.float32, device="cuda")
+    app_s = {"bfs": 0.0, "sssp": 0.0, "cc": 0.0, "pr": 0.0}
+    pull = {"ms": 0.0, "launches": 0}
+
+    def step(timed):
+        for s in srcs:
+            t = time.perf_counter(); W.bfs(g, s, out=lev); dt = time.perf_counter() - t
+            if timed: app_s["bfs"] += dt
+        for s in srcs:
+            t = time.perf_counter(); W.sssp(g, s, out=dist); dt = time.perf_counter() - t
+            if timed: app_s["sssp"] += dt
+        t = time.perf_counter(); W.cc(gs, out=lab); dt = time.perf_counter() - t
+        if timed: app_s["cc"] += dt
+        t = time.perf_counter()
+        _, st = W.pagerank(g, 20, 0.85, out=rank, time_pull=True)
+        dt = time.perf_counter() - t
+        if timed:
+            app_s["pr"] += dt
+            pull["ms"] += st["pull_ms"]
+            pull["launches"] += st["pull_launches"]
+
+    for i in range(args.warmup):
+        step(False)
+        log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    K = args.steps
+    units = (2 * len(srcs) + 1 + 20) * m
+    value = units * K / elapsed / 1e9
+    per_app = {
+        "bfs": round(len(srcs) * m * K / app_s["bfs"] / 1e9, 3),
+        "sssp": round(len(srcs) * m * K / app_s["sssp"] / 1e9, 3),
+        "cc": round(m * K / app_s["cc"] / 1e9, 3),
+        "pr": round(20 * m * K / app_s["pr"] / 1e9, 3),
+    }
+    per_app_ms = {k: round(v * 1e3 / K / (len(srcs) if k in ("bfs", "sssp") else 1), 3)
+                  for k, v in app_s.items()}
+    avg_launch_s = pull["ms"] / 1e3 / max(pull["launches"], 1)
+    alg = pr_pull_bytes(g.info)
+    achieved = alg / avg_launch_s / 1e9
+    workload = f"rmat{args.scale}"
+    traffic = measured_traffic("k_pr_pull", workload)
+    roof = {"kernel": "k_pr_pull", "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": int(alg)}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / K, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32/f32",
+        "data": "synthetic",
+        "config": {"workload": f"R-MAT s{args.scale} ef16 (a,b,c,d)=(.57,.19,.19,.05): "
+                               f"BFS x{len(srcs)} + SSSP x{len(srcs)} + CC + PageRank x20",
+                   "n": n, "m": m, "m_undirected": gs.m, "gate": "threshold",
+                   "theta_ppm": {"bfs": 10000, "cc": 200000, "sssp": 200000},
+                   "chunk_edges": {"bfs": 32, "cc": 16, "sssp": 16}, "device": dev_name},
+        "per_app_gteps": per_app, "per_app_ms": per_app_ms,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ro, col, w, srcs, m)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

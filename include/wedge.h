@@ -1,0 +1,248 @@
+/*
+ * wedge.h -- C ABI of the MI355X (gfx950) Wedge-Frontier pull engine.
+ *
+ * The method is the pull-only frontier optimisation of Grossman & Kozyrakis,
+ * "A New Frontier for Pull-Based Graph Processing" (arXiv 1903.07754):
+ *   1. the pull engine emits the usual source-oriented vertex frontier
+ *      (Wedge Overview; Background, Push vs. Pull);
+ *   2. a fullness decision compares the frontier's out-edge count with a
+ *      threshold (Frontier Transformation, "Frontier Fullness Threshold");
+ *   3. below it, the frontier is translated through an edge index into the
+ *      Wedge Frontier, a bitmap over groups of contiguous in-edge positions
+ *      (Wedge Frontier; Frontier Transformation, "Frontier Precision";
+ *      Implementation, Data Structures);
+ *   4. the pull then visits only the marked groups, or the whole in-edge
+ *      array when the frontier is too full.
+ *
+ * Conventions for every entry point
+ *   - Plain C types only. Vertex ids, levels, labels, distances and weights are
+ *     uint32; edge counts and offsets are uint64 at the ABI and must be < 2^32
+ *     (in-edge positions are stored in 32 bits on the device). n < 2^31.
+ *   - "dev" pointers are device memory owned by the caller (hipMalloc, or
+ *     torch.empty(..., device="cuda")); "host" pointers are ordinary memory.
+ *   - Work is issued on the caller's HIP stream; every run returns after the
+ *     stream has completed it (runs are synchronous for the caller).
+ *   - Errors are status codes; nothing throws across the ABI. All argument
+ *     checks happen before any device work. wedge_last_error() gives a
+ *     thread-local message for the last failure.
+ *   - A graph handle is immutable after creation; one graph must not be used by
+ *     two runs at the same time (its cached workspace is shared). A run on a
+ *     busy graph returns WEDGE_ERR_BUSY.
+ */
+#ifndef WEDGE_H
+#define WEDGE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WEDGE_OK = 0,
+    WEDGE_ERR_INVALID_ARG = -1,   /* null pointer, id out of range, bad option value */
+    WEDGE_ERR_BAD_GRAPH = -2,     /* offsets not monotone, neighbour id >= n, m >= 2^32 ... */
+    WEDGE_ERR_NO_WEIGHTS = -3,    /* SSSP on a graph created without weights */
+    WEDGE_ERR_OOM = -4,           /* device or host allocation failed (or the WEDGE_MAX_DEVICE_BYTES cap) */
+    WEDGE_ERR_HIP = -5,           /* a HIP runtime call or kernel failed; see wedge_last_error() */
+    WEDGE_ERR_UNSUPPORTED = -6,   /* operation not available for this graph (e.g. CC needs WEDGE_SYMMETRIZE) */
+    WEDGE_ERR_MODEL = -7,         /* learned-gate model missing, corrupt or of the wrong version */
+    WEDGE_ERR_NOT_CONVERGED = -8, /* max_iters reached while the frontier was still non-empty */
+    WEDGE_ERR_BUSY = -9           /* the graph is in use by another run */
+} wedge_status;
+
+typedef struct wedge_graph_s* wedge_graph_t;
+
+/* ------------------------------------------------------------------ graphs */
+
+/* wedge_graph_create_* flags */
+#define WEDGE_INPUT_DEVICE 0x1u /* row_off/col/w are device pointers (else host) */
+#define WEDGE_SYMMETRIZE   0x2u /* store the undirected view: each u->v (u != v) also as v->u,
+                                   duplicates merged, self-loops dropped; required by wedge_cc;
+                                   weights are not accepted with this flag */
+#define WEDGE_HOST_ONLY    0x4u /* build and keep the layout in host memory only, touching no
+                                   GPU: the handle then serves wedge_graph_info/_layout and can
+                                   not run applications (WEDGE_ERR_UNSUPPORTED) */
+
+/*
+ * Create a graph from out-edges (CSR, Background, Graph Representation):
+ * row_off[n+1] (uint64, row_off[0] = 0, non-decreasing, row_off[n] = m),
+ * col[m] (uint32 destinations < n), w[m] (uint32 weights, nullable; needed by
+ * wedge_sssp). Self-loops and duplicate edges are accepted as given (PageRank
+ * counts them in the out-degree).
+ *
+ * The library copies what it needs; the caller may free its arrays on return.
+ * It builds, once (the layout of the method's one-off preprocessing):
+ *   - the in-edge array (CSC) with each destination's in-edges ordered by
+ *     ascending source, weights aligned with it;
+ *   - the edge index (Wedge Frontier; Implementation, Data Structures): for
+ *     every CSR edge u->v, the position of that edge in the in-edge array,
+ *     stored in CSR order so a vertex's entries are contiguous;
+ *   - per 64-position row of the in-edge array, a 64-bit mask of the positions
+ *     where a destination's in-edge list begins, the index of the destination
+ *     segment covering the row's first position, and the list of destinations
+ *     with at least one in-edge. These name each position's destination
+ *     without the vertex index (the role the paper gives Vector-Sparse).
+ * The stream orders the uploads; the call returns after they finish.
+ * Returns WEDGE_ERR_BAD_GRAPH for malformed input, WEDGE_ERR_OOM on allocation
+ * failure. *out is set only on success.
+ */
+wedge_status wedge_graph_create_csr(uint32_t n, uint64_t m, const uint64_t* row_off,
+                                    const uint32_t* col, const uint32_t* w, uint32_t flags,
+                                    hipStream_t stream, wedge_graph_t* out);
+
+/* Same, from in-edges: col_off[n+1], src[m] (sources of each destination's
+ * in-edges), w[m] aligned with src. */
+wedge_status wedge_graph_create_csc(uint32_t n, uint64_t m, const uint64_t* col_off,
+                                    const uint32_t* src, const uint32_t* w, uint32_t flags,
+                                    hipStream_t stream, wedge_graph_t* out);
+
+/* Frees device and host memory of the graph. Null is accepted. */
+wedge_status wedge_graph_destroy(wedge_graph_t g);
+
+typedef struct {
+    uint32_t n;            /* vertices */
+    uint64_t m;            /* stored directed edges (after WEDGE_SYMMETRIZE, both directions) */
+    uint32_t nonempty;     /* destinations with at least one in-edge */
+    uint64_t rows;         /* ceil(m / 64) */
+    uint32_t flags;        /* creation flags */
+    uint32_t weighted;     /* 1 when weights are stored */
+    uint32_t dangling;     /* vertices with out-degree 0 */
+    uint32_t pr_tile_edges;/* in-edges per PageRank pull tile */
+    uint64_t pr_spans;     /* destinations whose in-edges cross a PageRank tile boundary */
+    uint64_t device_bytes; /* device memory held by the graph (layout + cached workspace) */
+} wedge_graph_info;
+
+wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info);
+
+/* Layout arrays that wedge_graph_layout can copy out (for inspection and tests). */
+typedef enum {
+    WEDGE_LAYOUT_COL_OFF = 0, /* uint32[n+1] in-edge offsets */
+    WEDGE_LAYOUT_IN_SRC = 1,  /* uint32[m] source of each in-edge position */
+    WEDGE_LAYOUT_IN_W = 2,    /* uint32[m] weight of each in-edge position */
+    WEDGE_LAYOUT_ROW_OFF = 3, /* uint32[n+1] out-edge offsets */
+    WEDGE_LAYOUT_POS = 4,     /* uint32[m] edge index: in-edge position of each CSR edge */
+    WEDGE_LAYOUT_ROWMASK = 5, /* uint64[rows] segment-start bits per 64 positions */
+    WEDGE_LAYOUT_ROWSEG = 6,  /* uint32[rows] segment index covering the row's first position */
+    WEDGE_LAYOUT_NZDST = 7,   /* uint32[nonempty] destination of each segment */
+    WEDGE_LAYOUT_PR_SPANS = 8 /* uint32[3*pr_spans] (vertex, first tile, last tile) */
+} wedge_layout_array;
+
+/* Copy one layout array into host memory `dst` of `bytes` bytes (must be exactly
+ * the array's size). Synchronous. */
+wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void* dst,
+                                uint64_t bytes);
+
+/* ------------------------------------------------------------ applications */
+
+typedef enum {
+    WEDGE_GATE_THRESHOLD = 0,    /* Wedge Frontier iff A_k < floor(theta * m) (the paper's rule) */
+    WEDGE_GATE_ALWAYS_WEDGE = 1, /* build the Wedge Frontier every iteration */
+    WEDGE_GATE_ALWAYS_FULL = 2,  /* never build it: pull over all in-edges every iteration */
+    WEDGE_GATE_LEARNED = 3       /* learned cost model (see wedge_model_*); falls back to the
+                                    threshold rule when no valid model is given */
+} wedge_gate;
+
+/* per-iteration record written to wedge_opts.trace */
+typedef struct {
+    uint32_t iter;          /* k */
+    uint32_t mode;          /* 0 = full pull, 1 = Wedge Frontier */
+    uint32_t chunk_edges;   /* group size used (mode 1) */
+    uint32_t reserved;
+    uint64_t frontier;      /* |F_k| */
+    uint64_t active_edges;  /* A_k = sum of out-degrees over F_k */
+    uint64_t marked_chunks; /* K_k = marked groups (mode 1; 0 in mode 0) */
+    float ms;               /* device time of the iteration (WEDGE_RUN_TIME_ITERS) */
+    float reserved2;
+} wedge_iter_record;
+
+/* wedge_opts.flags */
+#define WEDGE_RUN_TIME_PULL  0x1u /* HIP events around each pull launch; sums into stats */
+#define WEDGE_RUN_TIME_ITERS 0x2u /* HIP events around each iteration; into trace[k].ms */
+
+typedef struct {
+    uint32_t gate;           /* wedge_gate */
+    uint32_t threshold_ppm;  /* theta in parts per million of the traversed edge count; 0 = the
+                                application default (BFS 10000 = 1%, CC/SSSP 200000 = 20%) */
+    uint32_t chunk_edges;    /* edges per Wedge Frontier bit: a power of two in [1, 4096];
+                                0 = application default (BFS 32, CC/SSSP 16) */
+    uint32_t max_iters;      /* 0 = unlimited (n + 1 bounds every application) */
+    uint32_t flags;          /* WEDGE_RUN_* */
+    uint32_t trace_cap;      /* entries available at trace */
+    wedge_iter_record* trace;/* host array, nullable */
+    const void* model;       /* wedge_model_t for WEDGE_GATE_LEARNED, nullable */
+} wedge_opts;
+
+typedef struct {
+    uint32_t iterations;     /* pull iterations executed */
+    uint32_t wedge_iters;    /* of which used the Wedge Frontier */
+    uint32_t full_iters;     /* of which pulled over every in-edge */
+    uint32_t pull_launches;  /* pull kernel launches (timed when WEDGE_RUN_TIME_PULL) */
+    uint64_t edges_scanned;  /* in-edge positions the pull kernels covered */
+    double ms;               /* host wall time of the run, sync to sync */
+    double pull_ms;          /* sum of event-timed pull kernel durations */
+} wedge_stats;
+
+/*
+ * BFS (Evaluation, Applications): level_dev[n] receives the hop level of every
+ * vertex from src, 0xFFFFFFFF when unreachable. opts and stats are nullable.
+ */
+wedge_status wedge_bfs(wedge_graph_t g, uint32_t src, uint32_t* level_dev, const wedge_opts* opts,
+                       hipStream_t stream, wedge_stats* stats);
+
+/*
+ * Connected components by label propagation (HCC; Evaluation, Applications)
+ * on an undirected graph (created with WEDGE_SYMMETRIZE): label_dev[n]
+ * receives the smallest vertex id of each component.
+ */
+wedge_status wedge_cc(wedge_graph_t g, uint32_t* label_dev, const wedge_opts* opts,
+                      hipStream_t stream, wedge_stats* stats);
+
+/*
+ * Single-source shortest paths by Bellman-Ford (Evaluation, Applications):
+ * dist_dev[n] receives path lengths with the stored uint32 weights,
+ * 0xFFFFFFFF when unreachable. Requires weights (WEDGE_ERR_NO_WEIGHTS) and
+ * (n-1) * max weight < 2^32 - 1 (WEDGE_ERR_INVALID_ARG otherwise).
+ */
+wedge_status wedge_sssp(wedge_graph_t g, uint32_t src, uint32_t* dist_dev, const wedge_opts* opts,
+                        hipStream_t stream, wedge_stats* stats);
+
+/*
+ * PageRank (named by the paper, which excludes it from the frontier study as it
+ * has no frontier; Evaluation, Applications): `iters` full pulls of
+ *   r_{k+1}(v) = (1-d)/n + d * (sum_{u->v} r_k(u)/outdeg(u) + D_k/n),
+ * r_0 = 1/n, D_k = rank mass on out-degree-0 vertices. rank_dev[n] (FP32)
+ * receives r_iters. 0 < damping < 1. Results are deterministic (no float
+ * atomics). The gate and chunk options are ignored.
+ */
+wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, float* rank_dev,
+                            const wedge_opts* opts, hipStream_t stream, wedge_stats* stats);
+
+/* ------------------------------------------------------- single steps */
+
+/*
+ * Frontier transformation alone (Wedge Frontier; Implementation, Data
+ * Structures): for the vertex frontier frontier_dev[count] (distinct vertex
+ * ids, any order), set bit g of wbits_dev for every group g of chunk_edges
+ * in-edge positions holding an out-edge of a frontier vertex, then compact the
+ * bitmap into chunk_list_dev (marked group ids, any order) and return their
+ * number in *marked. wbits_dev has ceil(ceil(m/chunk_edges)/64) uint64 words
+ * and is overwritten; chunk_list_dev holds ceil(m/chunk_edges) entries.
+ */
+wedge_status wedge_frontier_translate(wedge_graph_t g, const uint32_t* frontier_dev,
+                                      uint32_t count, uint32_t chunk_edges, uint64_t* wbits_dev,
+                                      uint32_t* chunk_list_dev, uint64_t* marked,
+                                      hipStream_t stream);
+
+/* ------------------------------------------------------------------ misc */
+
+const char* wedge_status_string(wedge_status s);
+const char* wedge_last_error(void);
+/* Library version, e.g. "0.1.0". */
+const char* wedge_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WEDGE_H */

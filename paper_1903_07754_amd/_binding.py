@@ -1,0 +1,269 @@
+"""ctypes binding of libwedge.so (include/wedge.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels. Device buffers are torch tensors on a ROCm device (PyTorch is used
+for device memory and streams only). Importing this module does not touch the
+GPU; loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwedge.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "wedge.h")
+
+OK = 0
+STATUS = {0: "WEDGE_OK", -1: "WEDGE_ERR_INVALID_ARG", -2: "WEDGE_ERR_BAD_GRAPH",
+          -3: "WEDGE_ERR_NO_WEIGHTS", -4: "WEDGE_ERR_OOM", -5: "WEDGE_ERR_HIP",
+          -6: "WEDGE_ERR_UNSUPPORTED", -7: "WEDGE_ERR_MODEL", -8: "WEDGE_ERR_NOT_CONVERGED",
+          -9: "WEDGE_ERR_BUSY"}
+
+INPUT_DEVICE, SYMMETRIZE, HOST_ONLY = 0x1, 0x2, 0x4
+GATE = {"threshold": 0, "wedge": 1, "full": 2, "learned": 3}
+RUN_TIME_PULL, RUN_TIME_ITERS = 0x1, 0x2
+LAYOUT = {"col_off": 0, "in_src": 1, "in_w": 2, "row_off": 3, "pos": 4, "rowmask": 5,
+          "rowseg": 6, "nzdst": 7, "pr_spans": 8}
+
+
+class WedgeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class GraphInfo(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("nonempty", C.c_uint32),
+                ("rows", C.c_uint64), ("flags", C.c_uint32), ("weighted", C.c_uint32),
+                ("dangling", C.c_uint32), ("pr_tile_edges", C.c_uint32),
+                ("pr_spans", C.c_uint64), ("device_bytes", C.c_uint64)]
+
+
+class IterRecord(C.Structure):
+    _fields_ = [("iter", C.c_uint32), ("mode", C.c_uint32), ("chunk_edges", C.c_uint32),
+                ("reserved", C.c_uint32), ("frontier", C.c_uint64), ("active_edges", C.c_uint64),
+                ("marked_chunks", C.c_uint64), ("ms", C.c_float), ("reserved2", C.c_float)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("gate", C.c_uint32), ("threshold_ppm", C.c_uint32), ("chunk_edges", C.c_uint32),
+                ("max_iters", C.c_uint32), ("flags", C.c_uint32), ("trace_cap", C.c_uint32),
+                ("trace", C.POINTER(IterRecord)), ("model", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_uint32), ("wedge_iters", C.c_uint32),
+                ("full_iters", C.c_uint32), ("pull_launches", C.c_uint32),
+                ("edges_scanned", C.c_uint64), ("ms", C.c_double), ("pull_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libwedge.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
+    L.wedge_graph_create_csr.argtypes = [u32, u64, vp, vp, vp, u32, vp, C.POINTER(vp)]
+    L.wedge_graph_create_csc.argtypes = [u32, u64, vp, vp, vp, u32, vp, C.POINTER(vp)]
+    L.wedge_graph_destroy.argtypes = [vp]
+    L.wedge_graph_get_info.argtypes = [vp, C.POINTER(GraphInfo)]
+    L.wedge_graph_layout.argtypes = [vp, C.c_int, vp, u64]
+    L.wedge_bfs.argtypes = [vp, u32, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
+    L.wedge_cc.argtypes = [vp, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
+    L.wedge_sssp.argtypes = [vp, u32, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
+    L.wedge_pagerank.argtypes = [vp, u32, C.c_float, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
+    L.wedge_frontier_translate.argtypes = [vp, vp, u32, u32, vp, vp, C.POINTER(u64), vp]
+    L.wedge_status_string.argtypes = [C.c_int]
+    L.wedge_status_string.restype = C.c_char_p
+    L.wedge_last_error.restype = C.c_char_p
+    L.wedge_version.restype = C.c_char_p
+    for name in ("wedge_graph_create_csr", "wedge_graph_create_csc", "wedge_graph_destroy",
+                 "wedge_graph_get_info", "wedge_graph_layout", "wedge_bfs", "wedge_cc",
+                 "wedge_sssp", "wedge_pagerank", "wedge_frontier_translate"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != OK:
+        raise WedgeError(status, lib().wedge_last_error().decode())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(x):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+class Graph:
+    """A graph held by the library (layout on the device unless host_only)."""
+
+    def __init__(self, handle, keep=None):
+        self._h = C.c_void_p(handle)
+        self._keep = keep
+        info = GraphInfo()
+        check(lib().wedge_graph_get_info(self._h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in GraphInfo._fields_}
+        self.n, self.m = info.n, info.m
+
+    @staticmethod
+    def _make(fn, n, off, ids, w, symmetrize, host_only, stream):
+        flags = (SYMMETRIZE if symmetrize else 0) | (HOST_ONLY if host_only else 0)
+        arrs = [off, ids, w]
+        if not all(a is None or isinstance(a, np.ndarray) for a in arrs):
+            flags |= INPUT_DEVICE
+        else:
+            off = np.ascontiguousarray(off, np.uint64)
+            ids = np.ascontiguousarray(ids, np.uint32)
+            w = None if w is None else np.ascontiguousarray(w, np.uint32)
+        m = int(off[-1]) if isinstance(off, np.ndarray) else int(off[-1].item())
+        h = C.c_void_p()
+        st = fn(n, m, _ptr(off), _ptr(ids) if m else None, _ptr(w), flags,
+                None if host_only else _stream_handle(stream), C.byref(h))
+        check(st)
+        return Graph(h.value)
+
+    @classmethod
+    def from_csr(cls, row_off, col, w=None, symmetrize=False, host_only=False, stream=None):
+        return cls._make(lib().wedge_graph_create_csr, len(row_off) - 1, row_off, col, w,
+                         symmetrize, host_only, stream)
+
+    @classmethod
+    def from_csc(cls, col_off, src, w=None, symmetrize=False, host_only=False, stream=None):
+        return cls._make(lib().wedge_graph_create_csc, len(col_off) - 1, col_off, src, w,
+                         symmetrize, host_only, stream)
+
+    def layout(self, name):
+        dt = np.uint64 if name == "rowmask" else np.uint32
+        sizes = {"col_off": self.n + 1, "in_src": self.m, "in_w": self.m, "row_off": self.n + 1,
+                 "pos": self.m, "rowmask": self.info["rows"], "rowseg": self.info["rows"],
+                 "nzdst": self.info["nonempty"], "pr_spans": 3 * self.info["pr_spans"]}
+        out = np.zeros(max(int(sizes[name]), 1), dt)
+        nbytes = int(sizes[name]) * out.itemsize
+        check(lib().wedge_graph_layout(self._h, LAYOUT[name], out.ctypes.data, nbytes))
+        return out[:int(sizes[name])]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().wedge_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_opts(gate="threshold", theta_ppm=0, chunk=0, max_iters=0, time_pull=False,
+              time_iters=False, trace_cap=0, model=None):
+    o = Opts()
+    o.gate = GATE[gate] if isinstance(gate, str) else int(gate)
+    o.threshold_ppm, o.chunk_edges, o.max_iters = theta_ppm, chunk, max_iters
+    o.flags = (RUN_TIME_PULL if time_pull else 0) | (RUN_TIME_ITERS if time_iters else 0)
+    trace = (IterRecord * trace_cap)() if trace_cap else None
+    o.trace_cap = trace_cap
+    o.trace = C.cast(trace, C.POINTER(IterRecord)) if trace is not None else None
+    o.model = model
+    return o, trace
+
+
+def _trace_list(trace, iters):
+    if trace is None:
+        return None
+    return [{k: getattr(trace[i], k) for k, _ in IterRecord._fields_ if not k.startswith("reserved")}
+            for i in range(min(iters, len(trace)))]
+
+
+def _out_u32(n, out):
+    import torch
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    return out
+
+
+def _run_int(fn, g, args, out, stream, trace_cap, **kw):
+    o, trace = make_opts(trace_cap=trace_cap, **kw)
+    out = _out_u32(g.n, out)
+    st = Stats()
+    check(fn(g.handle, *args, _ptr(out), C.byref(o), _stream_handle(stream), C.byref(st)))
+    return out[:g.n], st.as_dict(), _trace_list(trace, st.iterations)
+
+
+def bfs(g, src, out=None, stream=None, trace_cap=0, **kw):
+    """Levels (int32 tensor viewed as uint32; 0xFFFFFFFF = unreachable), stats, trace."""
+    return _run_int(lib().wedge_bfs, g, (src,), out, stream, trace_cap, **kw)
+
+
+def cc(g, out=None, stream=None, trace_cap=0, **kw):
+    return _run_int(lib().wedge_cc, g, (), out, stream, trace_cap, **kw)
+
+
+def sssp(g, src, out=None, stream=None, trace_cap=0, **kw):
+    return _run_int(lib().wedge_sssp, g, (src,), out, stream, trace_cap, **kw)
+
+
+def pagerank(g, iters=20, damping=0.85, out=None, stream=None, time_pull=False):
+    import torch
+    o, _ = make_opts(time_pull=time_pull)
+    if out is None:
+        out = torch.empty(max(g.n, 1), dtype=torch.float32, device="cuda")
+    st = Stats()
+    check(lib().wedge_pagerank(g.handle, iters, damping, _ptr(out), C.byref(o),
+                               _stream_handle(stream), C.byref(st)))
+    return out[:g.n], st.as_dict()
+
+
+def frontier_translate(g, frontier, chunk, stream=None):
+    """(Wedge bitmap as uint64 tensor, marked chunk ids tensor[:K]) for a device frontier."""
+    import torch
+    nchunks = (g.m + chunk - 1) // chunk
+    words = (nchunks + 63) // 64
+    wbits = torch.zeros(max(words, 1), dtype=torch.int64, device="cuda")
+    lst = torch.zeros(max(nchunks, 1), dtype=torch.int32, device="cuda")
+    marked = C.c_uint64()
+    check(lib().wedge_frontier_translate(g.handle, _ptr(frontier), int(frontier.numel()), chunk,
+                                         _ptr(wbits), _ptr(lst), C.byref(marked),
+                                         _stream_handle(stream)))
+    return wbits[:words], lst[:marked.value]
+
+
+def u32(t):
+    """Host numpy uint32 view of an int32 device tensor."""
+    return t.cpu().numpy().view(np.uint32)
+
+
+def header_functions():
+    """Names of the functions include/wedge.h declares."""
+    import re
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:wedge_status|const char\*)\s+(wedge_\w+)\s*\(", txt, re.M)))

@@ -1,0 +1,566 @@
+// C ABI of the Wedge-Frontier pull engine: argument checks, graph upload, the
+// per-iteration control loop (Wedge Overview, Fig. 5) and PageRank.
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wedge_internal.h"
+
+namespace wedge {
+hipError_t launch_set_f64(double* p, double v, hipStream_t s);
+}
+
+using namespace wedge;
+
+namespace {
+
+thread_local std::string g_err;
+
+wedge_status fail(wedge_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+wedge_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return WEDGE_ERR_HIP;
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+uint64_t device_cap() {
+    const char* e = std::getenv("WEDGE_MAX_DEVICE_BYTES");
+    return e ? std::strtoull(e, nullptr, 10) : 0;
+}
+
+// Device allocation accounted against the graph (and the optional cap).
+wedge_status dev_alloc(wedge_graph_s* g, void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    uint64_t cap = device_cap();
+    if (cap && g->device_bytes + bytes > cap)
+        return fail(WEDGE_ERR_OOM, std::string("device memory cap (WEDGE_MAX_DEVICE_BYTES) exceeded by ") + what);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? WEDGE_ERR_OOM : WEDGE_ERR_HIP,
+                    std::string("hipMalloc failed for ") + what + ": " + hipGetErrorString(e));
+    }
+    g->device_bytes += bytes;
+    return WEDGE_OK;
+}
+
+template <class T>
+wedge_status upload(wedge_graph_s* g, T** dst, const std::vector<T>& src, hipStream_t s,
+                    const char* what) {
+    wedge_status st = dev_alloc(g, (void**)dst, src.size() * sizeof(T), what);
+    if (st != WEDGE_OK) return st;
+    if (!src.empty())
+        HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s), what);
+    return WEDGE_OK;
+}
+
+void free_all(wedge_graph_s* g) {
+    DevGraph& d = g->dev;
+    void* ptrs[] = {d.col_off, d.in_src, d.in_w, d.row_off, d.pos, d.rowmask, d.rowseg, d.nzdst, d.spans};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    Workspace& w = g->ws;
+    void* wp[] = {w.fbits, w.flist[0], w.flist[1], w.degpre[0], w.degpre[1], w.val_prev, w.wbits,
+                  w.chunks, w.ctl, w.pr_sum, w.pr_contrib, w.pr_head, w.pr_tail, w.pr_part, w.pr_d};
+    for (void* p : wp)
+        if (p) (void)hipFree(p);
+    if (w.ctl_host) (void)hipHostFree(w.ctl_host);
+    for (hipEvent_t e : w.ev)
+        if (e) (void)hipEventDestroy(e);
+    d = DevGraph{};
+    w = Workspace{};
+}
+
+bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
+int log2u(uint32_t x) { int l = 0; while ((1u << l) < x) ++l; return l; }
+
+template <class T>
+wedge_status copy_input(const T* p, uint64_t count, bool on_device, std::vector<T>* tmp,
+                        const T** out) {
+    if (!p || !on_device) { *out = p; return WEDGE_OK; }
+    tmp->resize(count ? count : 1);
+    HIP_TRY(hipMemcpy(tmp->data(), p, count * sizeof(T), hipMemcpyDeviceToHost), "copying input graph");
+    *out = tmp->data();
+    return WEDGE_OK;
+}
+
+wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, const uint32_t* ids,
+                    const uint32_t* w, uint32_t flags, hipStream_t stream, wedge_graph_t* out) {
+    if (!out) return fail(WEDGE_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (flags & ~(WEDGE_INPUT_DEVICE | WEDGE_SYMMETRIZE | WEDGE_HOST_ONLY))
+        return fail(WEDGE_ERR_INVALID_ARG, "unknown flag bits");
+    if ((flags & WEDGE_HOST_ONLY) && (flags & WEDGE_INPUT_DEVICE))
+        return fail(WEDGE_ERR_INVALID_ARG, "WEDGE_HOST_ONLY cannot take device input");
+    if (n >= (1u << 31)) return fail(WEDGE_ERR_BAD_GRAPH, "n must be < 2^31");
+    if (m >= (1ull << 32)) return fail(WEDGE_ERR_BAD_GRAPH, "m must be < 2^32");
+    if (!off) return fail(WEDGE_ERR_INVALID_ARG, "offsets pointer is null");
+    if (m && !ids) return fail(WEDGE_ERR_INVALID_ARG, "edge array pointer is null");
+    const bool on_dev = flags & WEDGE_INPUT_DEVICE;
+    std::vector<uint64_t> toff;
+    std::vector<uint32_t> tids, tw;
+    const uint64_t* hoff = nullptr;
+    const uint32_t *hids = nullptr, *hw = nullptr;
+    wedge_status st;
+    if ((st = copy_input(off, (uint64_t)n + 1, on_dev, &toff, &hoff)) != WEDGE_OK) return st;
+    if ((st = copy_input(ids, m, on_dev, &tids, &hids)) != WEDGE_OK) return st;
+    if ((st = copy_input(w, m, on_dev, &tw, &hw)) != WEDGE_OK) return st;
+    auto* g = new wedge_graph_s();
+    g->flags = flags;
+    g->host_only = flags & WEDGE_HOST_ONLY;
+    HostLayout& L = g->host;
+    const bool sym = flags & WEDGE_SYMMETRIZE;
+    st = from_csr ? build_layout_from_csr(n, m, hoff, hids, hw, sym, &L, &g_err)
+                  : build_layout_from_csc(n, m, hoff, hids, hw, sym, &L, &g_err);
+    if (st != WEDGE_OK) { delete g; return st; }
+    g->weighted = !L.in_w.empty() || (w != nullptr);
+    g->dangling = L.dangling;
+    g->max_w = L.max_w;
+    DevGraph& d = g->dev;
+    d.n = L.n;
+    d.m = L.m;
+    d.rows = (L.m + 63) / 64;
+    d.nonempty = (uint32_t)L.nzdst.size();
+    d.nspans = L.spans.size() / 3;
+    if (g->host_only) { *out = g; return WEDGE_OK; }
+    HIP_TRY(hipGetDevice(&g->device), "hipGetDevice");
+    st = WEDGE_OK;
+    if (st == WEDGE_OK) st = upload(g, &d.col_off, L.col_off, stream, "col_off");
+    if (st == WEDGE_OK) st = upload(g, &d.in_src, L.in_src, stream, "in_src");
+    if (st == WEDGE_OK && g->weighted) st = upload(g, &d.in_w, L.in_w, stream, "in_w");
+    if (st == WEDGE_OK) st = upload(g, &d.row_off, L.row_off, stream, "row_off");
+    if (st == WEDGE_OK) st = upload(g, &d.pos, L.pos, stream, "pos");
+    if (st == WEDGE_OK) st = upload(g, &d.rowmask, L.rowmask, stream, "rowmask");
+    if (st == WEDGE_OK) st = upload(g, &d.rowseg, L.rowseg, stream, "rowseg");
+    if (st == WEDGE_OK) st = upload(g, &d.nzdst, L.nzdst, stream, "nzdst");
+    if (st == WEDGE_OK) st = upload(g, &d.spans, L.spans, stream, "spans");
+    if (st == WEDGE_OK) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) st = hip_fail(e, "uploading graph");
+    }
+    if (st != WEDGE_OK) { free_all(g); delete g; return st; }
+    g->host = HostLayout{};  // device graph: drop the host copy
+    *out = g;
+    return WEDGE_OK;
+}
+
+// ----------------------------------------------------------- workspace
+
+wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontier, bool need_chunks) {
+    Workspace& w = g->ws;
+    const DevGraph& d = g->dev;
+    wedge_status st;
+    if (!w.ctl) {
+        if ((st = dev_alloc(g, (void**)&w.ctl, sizeof(Ctl), "counters")) != WEDGE_OK) return st;
+        HIP_TRY(hipHostMalloc((void**)&w.ctl_host, sizeof(Ctl), hipHostMallocDefault), "pinned counters");
+        for (auto& e : w.ev) HIP_TRY(hipEventCreate(&e), "event");
+    }
+    if (need_frontier && !w.fbits) {
+        w.n = d.n;
+        w.m = d.m;
+        const uint64_t fw = ((uint64_t)d.n + 63) / 64;
+        if ((st = dev_alloc(g, (void**)&w.fbits, fw * 8, "frontier bitmap")) != WEDGE_OK) return st;
+        HIP_TRY(hipMemset(w.fbits, 0, fw ? fw * 8 : 8), "clearing frontier bitmap");
+        for (int i = 0; i < 2; ++i) {
+            if ((st = dev_alloc(g, (void**)&w.flist[i], (size_t)d.n * 4, "frontier list")) != WEDGE_OK) return st;
+            if ((st = dev_alloc(g, (void**)&w.degpre[i], (size_t)d.n * 4, "degree prefix")) != WEDGE_OK) return st;
+        }
+        if ((st = dev_alloc(g, (void**)&w.val_prev, (size_t)d.n * 4, "committed values")) != WEDGE_OK) return st;
+    }
+    if (need_chunks) {
+        const uint64_t chunks = (d.m + (1ull << log_chunk) - 1) >> log_chunk;
+        const uint64_t words = (chunks + 63) / 64;
+        if (words > w.wbits_words || !w.wbits) {
+            if (w.wbits) { (void)hipFree(w.wbits); g->device_bytes -= w.wbits_words * 8; w.wbits = nullptr; }
+            if ((st = dev_alloc(g, (void**)&w.wbits, words * 8, "Wedge Frontier bitmap")) != WEDGE_OK) return st;
+            w.wbits_words = words ? words : 1;
+            HIP_TRY(hipMemset(w.wbits, 0, w.wbits_words * 8), "clearing Wedge bitmap");
+        }
+        if (chunks > w.chunks_cap || !w.chunks) {
+            if (w.chunks) { (void)hipFree(w.chunks); g->device_bytes -= w.chunks_cap * 4; w.chunks = nullptr; }
+            if ((st = dev_alloc(g, (void**)&w.chunks, chunks * 4, "chunk list")) != WEDGE_OK) return st;
+            w.chunks_cap = chunks ? chunks : 2;
+        }
+    }
+    return WEDGE_OK;
+}
+
+struct RunGuard {
+    std::mutex& m;
+    bool ok;
+    explicit RunGuard(std::mutex& mu) : m(mu), ok(mu.try_lock()) {}
+    ~RunGuard() { if (ok) m.unlock(); }
+};
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+const wedge_opts kDefaultOpts = {WEDGE_GATE_THRESHOLD, 0, 0, 0, 0, 0, nullptr, nullptr};
+
+wedge_status check_run(wedge_graph_t g, const void* out, const wedge_opts* o) {
+    if (!g) return fail(WEDGE_ERR_INVALID_ARG, "graph is null");
+    if (g->host_only) return fail(WEDGE_ERR_UNSUPPORTED, "graph was created with WEDGE_HOST_ONLY");
+    if (!out && g->dev.n) return fail(WEDGE_ERR_INVALID_ARG, "output pointer is null");
+    if (o->gate > WEDGE_GATE_LEARNED) return fail(WEDGE_ERR_INVALID_ARG, "unknown gate");
+    if (o->chunk_edges && (!is_pow2(o->chunk_edges) || o->chunk_edges > 4096))
+        return fail(WEDGE_ERR_INVALID_ARG, "chunk_edges must be a power of two in [1, 4096]");
+    if (o->trace_cap && !o->trace) return fail(WEDGE_ERR_INVALID_ARG, "trace_cap set but trace is null");
+    if (o->flags & ~(WEDGE_RUN_TIME_PULL | WEDGE_RUN_TIME_ITERS))
+        return fail(WEDGE_ERR_INVALID_ARG, "unknown run flag bits");
+    return WEDGE_OK;
+}
+
+// BFS, CC and SSSP share one control loop; they differ in the pull kernel, the
+// initial frontier and whether values need a committed copy.
+wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* val,
+                              const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
+    const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
+    wedge_status st = check_run(g, val, &o);
+    if (st != WEDGE_OK) return st;
+    const DevGraph& d = g->dev;
+    if (app != kCc && src >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
+    if (app == kSssp) {
+        if (!g->weighted) return fail(WEDGE_ERR_NO_WEIGHTS, "SSSP needs a graph created with weights");
+        if (d.n && (uint64_t)(d.n - 1) * g->max_w >= 0xFFFFFFFFull)
+            return fail(WEDGE_ERR_INVALID_ARG, "(n-1) * max weight must be < 2^32 - 1");
+    }
+    if (app == kCc && !(g->flags & WEDGE_SYMMETRIZE))
+        return fail(WEDGE_ERR_UNSUPPORTED, "CC runs on the undirected view: create the graph with WEDGE_SYMMETRIZE");
+    RunGuard guard(g->busy);
+    if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
+    wedge_stats local{};
+    const double t0 = now_ms();
+    if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
+
+    const uint32_t theta = o.threshold_ppm ? o.threshold_ppm : (app == kBfs ? 10000u : 200000u);
+    const uint32_t chunk = o.chunk_edges ? o.chunk_edges : (app == kBfs ? 32u : 16u);
+    const int lc = log2u(chunk);
+    const uint64_t thr = ((uint64_t)theta * d.m) / 1000000ull;
+    const bool may_wedge = o.gate != WEDGE_GATE_ALWAYS_FULL;
+    if ((st = ensure_workspace(g, lc, true, may_wedge)) != WEDGE_OK) return st;
+    Workspace& w = g->ws;
+    const uint64_t nchunks = (d.m + chunk - 1) >> lc;
+    const uint64_t wwords = (nchunks + 63) / 64;
+    const uint64_t fwords = ((uint64_t)d.n + 63) / 64;
+    HIP_TRY(hipMemsetAsync(w.fbits, 0, fwords * 8, s), "clearing frontier bitmap");
+    if (may_wedge) HIP_TRY(hipMemsetAsync(w.wbits, 0, wwords * 8, s), "clearing Wedge bitmap");
+
+    uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
+    if (app == kCc) {
+        HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, val, w.val_prev, w.flist[0], w.degpre[0], w.ctl, s), "seeding CC");
+    } else {
+        HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
+        if (vprev) HIP_TRY(launch_fill_u32(vprev, d.n, kInf, s), "initialising values");
+        HIP_TRY(launch_seed_source(src, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.ctl, s), "seeding source");
+    }
+    HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
+    HIP_TRY(hipStreamSynchronize(s), "initialising run");
+    uint64_t fcount = w.ctl_host->fnext >> kDegBits;
+    uint64_t active = w.ctl_host->fnext & kDegMask;
+    const uint32_t max_iters = o.max_iters ? o.max_iters : d.n + 1;
+    const bool time_pull = o.flags & WEDGE_RUN_TIME_PULL;
+    const bool time_iter = o.flags & WEDGE_RUN_TIME_ITERS;
+    int cur = 0;
+    uint32_t k = 0;
+    for (; fcount > 0; ++k) {
+        if (k >= max_iters) {
+            local.iterations = k;
+            if (stats) { local.ms = now_ms() - t0; *stats = local; }
+            return fail(WEDGE_ERR_NOT_CONVERGED, "max_iters reached with a non-empty frontier");
+        }
+        bool wedge_mode;
+        switch (o.gate) {
+            case WEDGE_GATE_ALWAYS_WEDGE: wedge_mode = true; break;
+            case WEDGE_GATE_ALWAYS_FULL: wedge_mode = false; break;
+            default: wedge_mode = active < thr; break;  // the fullness threshold (strict <)
+        }
+        HIP_TRY(hipMemsetAsync(w.ctl, 0, 16, s), "clearing counters");
+        if (time_iter) HIP_TRY(hipEventRecord(w.ev[2], s), "event");
+        if (wedge_mode) {
+            HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)fcount, active, d.row_off,
+                                     d.pos, lc, w.wbits, s), "frontier translation");
+            HIP_TRY(launch_compact_chunks(w.wbits, wwords, w.chunks, w.ctl, s), "chunk compaction");
+            if (time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
+            const uint64_t maxk = active < nchunks ? active : nchunks;
+            HIP_TRY(launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev, w.fbits, s), "chunk pull");
+        } else {
+            if (time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
+            HIP_TRY(launch_pull_full(app, d, k, val, vprev, w.fbits, s), "full pull");
+        }
+        if (time_pull) HIP_TRY(hipEventRecord(w.ev[1], s), "event");
+        HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
+                                vprev, val, s), "frontier finalisation");
+        if (time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
+        HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
+        HIP_TRY(hipStreamSynchronize(s), "iteration");
+        float pms = 0.f, ims = 0.f;
+        if (time_pull) HIP_TRY(hipEventElapsedTime(&pms, w.ev[0], w.ev[1]), "event time");
+        if (time_iter) HIP_TRY(hipEventElapsedTime(&ims, w.ev[2], w.ev[3]), "event time");
+        local.pull_ms += pms;
+        local.pull_launches++;
+        const uint64_t marked = wedge_mode ? (w.ctl_host->marked >> kDegBits) : 0;
+        if (o.trace && k < o.trace_cap) {
+            wedge_iter_record& r = o.trace[k];
+            r.iter = k;
+            r.mode = wedge_mode ? 1u : 0u;
+            r.chunk_edges = wedge_mode ? chunk : 0u;
+            r.reserved = 0;
+            r.frontier = fcount;
+            r.active_edges = active;
+            r.marked_chunks = marked;
+            r.ms = ims;
+            r.reserved2 = 0.f;
+        }
+        if (wedge_mode) { local.wedge_iters++; local.edges_scanned += marked << lc; }
+        else { local.full_iters++; local.edges_scanned += d.m; }
+        fcount = w.ctl_host->fnext >> kDegBits;
+        active = w.ctl_host->fnext & kDegMask;
+        cur ^= 1;
+    }
+    local.iterations = k;
+    local.ms = now_ms() - t0;
+    if (stats) *stats = local;
+    return WEDGE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wedge_status wedge_graph_create_csr(uint32_t n, uint64_t m, const uint64_t* row_off,
+                                    const uint32_t* col, const uint32_t* w, uint32_t flags,
+                                    hipStream_t stream, wedge_graph_t* out) {
+    try {
+        return create(true, n, m, row_off, col, w, flags, stream, out);
+    } catch (const std::bad_alloc&) {
+        return fail(WEDGE_ERR_OOM, "host allocation failed while building the layout");
+    }
+}
+
+wedge_status wedge_graph_create_csc(uint32_t n, uint64_t m, const uint64_t* col_off,
+                                    const uint32_t* src, const uint32_t* w, uint32_t flags,
+                                    hipStream_t stream, wedge_graph_t* out) {
+    try {
+        return create(false, n, m, col_off, src, w, flags, stream, out);
+    } catch (const std::bad_alloc&) {
+        return fail(WEDGE_ERR_OOM, "host allocation failed while building the layout");
+    }
+}
+
+wedge_status wedge_graph_destroy(wedge_graph_t g) {
+    if (!g) return WEDGE_OK;
+    if (!g->host_only) free_all(g);
+    delete g;
+    return WEDGE_OK;
+}
+
+wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info) {
+    if (!g || !info) return fail(WEDGE_ERR_INVALID_ARG, "null argument");
+    info->n = g->dev.n;
+    info->m = g->dev.m;
+    info->nonempty = g->dev.nonempty;
+    info->rows = g->dev.rows;
+    info->flags = g->flags;
+    info->weighted = g->weighted ? 1u : 0u;
+    info->dangling = g->dangling;
+    info->pr_tile_edges = 64u * kPrTileRows;
+    info->pr_spans = g->dev.nspans;
+    info->device_bytes = g->device_bytes;
+    return WEDGE_OK;
+}
+
+wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void* dst,
+                                uint64_t bytes) {
+    if (!g || !dst) return fail(WEDGE_ERR_INVALID_ARG, "null argument");
+    const DevGraph& d = g->dev;
+    const HostLayout& L = g->host;
+    const void* hsrc = nullptr;
+    const void* dsrc = nullptr;
+    uint64_t size = 0;
+    switch (which) {
+        case WEDGE_LAYOUT_COL_OFF: size = ((uint64_t)d.n + 1) * 4; hsrc = L.col_off.data(); dsrc = d.col_off; break;
+        case WEDGE_LAYOUT_IN_SRC: size = d.m * 4; hsrc = L.in_src.data(); dsrc = d.in_src; break;
+        case WEDGE_LAYOUT_IN_W:
+            if (!g->weighted) return fail(WEDGE_ERR_NO_WEIGHTS, "graph has no weights");
+            size = d.m * 4; hsrc = L.in_w.data(); dsrc = d.in_w; break;
+        case WEDGE_LAYOUT_ROW_OFF: size = ((uint64_t)d.n + 1) * 4; hsrc = L.row_off.data(); dsrc = d.row_off; break;
+        case WEDGE_LAYOUT_POS: size = d.m * 4; hsrc = L.pos.data(); dsrc = d.pos; break;
+        case WEDGE_LAYOUT_ROWMASK: size = d.rows * 8; hsrc = L.rowmask.data(); dsrc = d.rowmask; break;
+        case WEDGE_LAYOUT_ROWSEG: size = d.rows * 4; hsrc = L.rowseg.data(); dsrc = d.rowseg; break;
+        case WEDGE_LAYOUT_NZDST: size = (uint64_t)d.nonempty * 4; hsrc = L.nzdst.data(); dsrc = d.nzdst; break;
+        case WEDGE_LAYOUT_PR_SPANS: size = d.nspans * 12; hsrc = L.spans.data(); dsrc = d.spans; break;
+        default: return fail(WEDGE_ERR_INVALID_ARG, "unknown layout array");
+    }
+    if (bytes != size) return fail(WEDGE_ERR_INVALID_ARG, "bytes does not match the array size " + std::to_string(size));
+    if (!size) return WEDGE_OK;
+    if (g->host_only) { std::memcpy(dst, hsrc, size); return WEDGE_OK; }
+    HIP_TRY(hipMemcpy(dst, dsrc, size, hipMemcpyDeviceToHost), "copying layout");
+    return WEDGE_OK;
+}
+
+wedge_status wedge_bfs(wedge_graph_t g, uint32_t src, uint32_t* level_dev, const wedge_opts* opts,
+                       hipStream_t stream, wedge_stats* stats) {
+    return run_frontier_app(kBfs, g, src, level_dev, opts, stream, stats);
+}
+
+wedge_status wedge_cc(wedge_graph_t g, uint32_t* label_dev, const wedge_opts* opts,
+                      hipStream_t stream, wedge_stats* stats) {
+    return run_frontier_app(kCc, g, 0, label_dev, opts, stream, stats);
+}
+
+wedge_status wedge_sssp(wedge_graph_t g, uint32_t src, uint32_t* dist_dev, const wedge_opts* opts,
+                        hipStream_t stream, wedge_stats* stats) {
+    return run_frontier_app(kSssp, g, src, dist_dev, opts, stream, stats);
+}
+
+wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, float* rank_dev,
+                            const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
+    const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
+    wedge_status st = check_run(g, rank_dev, &o);
+    if (st != WEDGE_OK) return st;
+    if (!(damping > 0.0f && damping < 1.0f)) return fail(WEDGE_ERR_INVALID_ARG, "damping must be in (0, 1)");
+    RunGuard guard(g->busy);
+    if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
+    wedge_stats local{};
+    const double t0 = now_ms();
+    const DevGraph& d = g->dev;
+    if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
+    Workspace& w = g->ws;
+    if ((st = ensure_workspace(g, 6, false, false)) != WEDGE_OK) return st;
+    if (!w.pr_sum) {
+        w.pr_tiles = (d.rows + kPrTileRows - 1) / kPrTileRows;
+        w.pr_parts = pr_epilogue_blocks(d.n);
+        if ((st = dev_alloc(g, (void**)&w.pr_sum, (size_t)d.n * 4, "PageRank sums")) != WEDGE_OK) return st;
+        if ((st = dev_alloc(g, (void**)&w.pr_contrib, (size_t)d.n * 4, "PageRank contributions")) != WEDGE_OK) return st;
+        if ((st = dev_alloc(g, (void**)&w.pr_head, w.pr_tiles * 4, "PageRank tile heads")) != WEDGE_OK) return st;
+        if ((st = dev_alloc(g, (void**)&w.pr_tail, w.pr_tiles * 4, "PageRank tile tails")) != WEDGE_OK) return st;
+        if ((st = dev_alloc(g, (void**)&w.pr_part, (size_t)w.pr_parts * 8, "PageRank partials")) != WEDGE_OK) return st;
+        if ((st = dev_alloc(g, (void**)&w.pr_d, 16, "dangling mass")) != WEDGE_OK) return st;
+    }
+    const bool time_pull = o.flags & WEDGE_RUN_TIME_PULL;
+    std::vector<hipEvent_t> evs;
+    if (time_pull) {
+        evs.resize(2 * (size_t)iters);
+        for (auto& e : evs) HIP_TRY(hipEventCreate(&e), "event");
+    }
+    auto cleanup = [&] { for (auto e : evs) if (e) (void)hipEventDestroy(e); };
+    hipError_t e = launch_pr_init(d.n, d.row_off, rank_dev, w.pr_contrib, w.pr_sum, s);
+    if (e == hipSuccess) e = launch_set_f64(w.pr_d, (double)g->dangling / (double)d.n, s);
+    for (uint32_t k = 0; k < iters && e == hipSuccess; ++k) {
+        if (time_pull) e = hipEventRecord(evs[2 * k], s);
+        if (e == hipSuccess) e = launch_pr_pull(d, w.pr_contrib, w.pr_sum, w.pr_head, w.pr_tail, s);
+        if (time_pull && e == hipSuccess) e = hipEventRecord(evs[2 * k + 1], s);
+        if (e == hipSuccess) e = launch_pr_fixup(d, w.pr_head, w.pr_tail, w.pr_sum, s);
+        if (e == hipSuccess)
+            e = launch_pr_epilogue(d.n, d.row_off, w.pr_sum, (double)damping, w.pr_d + (k & 1),
+                                   rank_dev, w.pr_contrib, w.pr_part, w.pr_parts,
+                                   w.pr_d + ((k + 1) & 1), s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { cleanup(); return hip_fail(e, "PageRank"); }
+    for (uint32_t k = 0; k < iters && time_pull; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, evs[2 * k], evs[2 * k + 1]) == hipSuccess) local.pull_ms += ms;
+    }
+    cleanup();
+    local.iterations = iters;
+    local.full_iters = iters;
+    local.pull_launches = iters;
+    local.edges_scanned = (uint64_t)iters * d.m;
+    local.ms = now_ms() - t0;
+    if (stats) *stats = local;
+    return WEDGE_OK;
+}
+
+wedge_status wedge_frontier_translate(wedge_graph_t g, const uint32_t* frontier_dev,
+                                      uint32_t count, uint32_t chunk_edges, uint64_t* wbits_dev,
+                                      uint32_t* chunk_list_dev, uint64_t* marked,
+                                      hipStream_t s) {
+    if (!g || !marked || !wbits_dev || !chunk_list_dev || (count && !frontier_dev))
+        return fail(WEDGE_ERR_INVALID_ARG, "null argument");
+    if (g->host_only) return fail(WEDGE_ERR_UNSUPPORTED, "graph was created with WEDGE_HOST_ONLY");
+    if (!is_pow2(chunk_edges) || chunk_edges > 4096)
+        return fail(WEDGE_ERR_INVALID_ARG, "chunk_edges must be a power of two in [1, 4096]");
+    const DevGraph& d = g->dev;
+    if (count > d.n) return fail(WEDGE_ERR_INVALID_ARG, "count exceeds n");
+    RunGuard guard(g->busy);
+    if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
+    const int lc = log2u(chunk_edges);
+    const uint64_t nchunks = (d.m + chunk_edges - 1) >> lc;
+    const uint64_t words = (nchunks + 63) / 64;
+    wedge_status st = ensure_workspace(g, lc, true, false);
+    if (st != WEDGE_OK) return st;
+    Workspace& w = g->ws;
+    // the caller's list gets its out-degree prefix through the frontier bitmap
+    // (ids are checked on the device: out-of-range ids are ignored)
+    HIP_TRY(hipMemsetAsync(w.fbits, 0, ((uint64_t)d.n + 63) / 64 * 8, s), "clearing frontier bitmap");
+    HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
+    HIP_TRY(hipMemsetAsync(wbits_dev, 0, words * 8, s), "clearing caller bitmap");
+    std::vector<uint32_t> ids(count);
+    if (count) {
+        HIP_TRY(hipMemcpyAsync(ids.data(), frontier_dev, (size_t)count * 4, hipMemcpyDeviceToHost, s), "reading frontier");
+        HIP_TRY(hipStreamSynchronize(s), "reading frontier");
+        for (uint32_t i = 0; i < count; ++i)
+            if (ids[i] >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "frontier vertex out of range");
+        // set the bits on the host side copy, upload, and let the compaction
+        // build the list and the out-degree prefix exactly as an iteration does
+        std::vector<uint64_t> fb(((uint64_t)d.n + 63) / 64, 0);
+        for (uint32_t v : ids) fb[v >> 6] |= 1ull << (v & 63);
+        HIP_TRY(hipMemcpyAsync(w.fbits, fb.data(), fb.size() * 8, hipMemcpyHostToDevice, s), "uploading frontier");
+        HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr, s), "frontier list");
+        HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
+        HIP_TRY(hipStreamSynchronize(s), "frontier list");
+        const uint64_t fcount = w.ctl_host->fnext >> kDegBits;
+        const uint64_t active = w.ctl_host->fnext & kDegMask;
+        HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
+        HIP_TRY(launch_translate(w.flist[0], w.degpre[0], (uint32_t)fcount, active, d.row_off, d.pos,
+                                 lc, wbits_dev, s), "frontier translation");
+    }
+    // compact a copy so the caller keeps the bitmap
+    uint64_t* tmp = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&tmp, words ? words * 8 : 8, s), "scratch bitmap");
+    HIP_TRY(hipMemcpyAsync(tmp, wbits_dev, words * 8, hipMemcpyDeviceToDevice, s), "copying bitmap");
+    HIP_TRY(launch_compact_chunks(tmp, words, chunk_list_dev, w.ctl, s), "chunk compaction");
+    HIP_TRY(hipFreeAsync(tmp, s), "scratch bitmap");
+    HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
+    HIP_TRY(hipStreamSynchronize(s), "frontier translation");
+    *marked = w.ctl_host->marked >> kDegBits;
+    return WEDGE_OK;
+}
+
+const char* wedge_status_string(wedge_status s) {
+    switch (s) {
+        case WEDGE_OK: return "ok";
+        case WEDGE_ERR_INVALID_ARG: return "invalid argument";
+        case WEDGE_ERR_BAD_GRAPH: return "malformed graph";
+        case WEDGE_ERR_NO_WEIGHTS: return "graph has no weights";
+        case WEDGE_ERR_OOM: return "out of memory";
+        case WEDGE_ERR_HIP: return "HIP runtime error";
+        case WEDGE_ERR_UNSUPPORTED: return "unsupported for this graph";
+        case WEDGE_ERR_MODEL: return "invalid model";
+        case WEDGE_ERR_NOT_CONVERGED: return "did not converge within max_iters";
+        case WEDGE_ERR_BUSY: return "graph busy";
+    }
+    return "unknown status";
+}
+
+const char* wedge_last_error(void) { return g_err.c_str(); }
+
+const char* wedge_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,733 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the Wedge-Frontier pull engine.
+//
+// Steps of one iteration (Wedge Overview, Fig. 5 control loop):
+//   k_translate      frontier -> Wedge Frontier bitmap (Frontier Transformation)
+//   k_bitmap_compact Wedge bitmap -> marked-chunk list; frontier bitmap ->
+//                    next frontier list + out-degree prefix (+ commit)
+//   k_pull_*         destination-oriented gather/reduce over the marked chunks
+//                    or over every in-edge (Background, Push vs. Pull)
+// and the PageRank full pull with its epilogue.
+//
+// Every kernel is memory-bound: nothing here is a dense contraction.
+#include <hip/hip_runtime.h>
+
+#include "wedge_internal.h"
+
+namespace wedge {
+namespace {
+
+constexpr int kBlock = 256;           // 4 waves
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kPullRows = 4;          // rows (64 positions each) per wave in the integer pulls
+constexpr int kTranslateEpt = 4;      // frontier out-edges per lane in the translation
+constexpr int kCompactWords = 8;      // 64-bit bitmap words per wave in the compaction
+
+struct GraphArgs {
+    uint32_t n;
+    uint32_t m;
+    uint32_t rows;
+    const uint32_t* __restrict__ in_src;
+    const uint32_t* __restrict__ in_w;
+    const uint64_t* __restrict__ rowmask;
+    const uint32_t* __restrict__ rowseg;
+    const uint32_t* __restrict__ nzdst;
+};
+
+GraphArgs args_of(const DevGraph& g) {
+    GraphArgs a;
+    a.n = g.n;
+    a.m = (uint32_t)g.m;
+    a.rows = (uint32_t)g.rows;
+    a.in_src = g.in_src;
+    a.in_w = g.in_w;
+    a.rowmask = g.rowmask;
+    a.rowseg = g.rowseg;
+    a.nzdst = g.nzdst;
+    return a;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+__device__ __forceinline__ uint64_t mask_le(int l) { return l == 63 ? ~0ull : ((2ull << l) - 1ull); }
+__device__ __forceinline__ uint64_t mask_lt(int l) { return (1ull << l) - 1ull; }
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
+
+// Lanes from `l` up to (excluding) the next segment head.
+__device__ __forceinline__ int seg_span(uint64_t heads, int l) {
+    uint64_t rest = l == 63 ? 0ull : (heads >> (l + 1));
+    return rest ? (int)__builtin_ctzll(rest) + 1 : 64 - l;
+}
+
+// Suffix-doubling reduction restricted to the lane's segment: on return the
+// head lane of each segment holds the reduction of its whole segment, combined
+// in a fixed tree order.
+template <typename T, typename Op>
+__device__ __forceinline__ T seg_reduce(T v, int span, Op op) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T w = __shfl_down(v, o, 64);
+        if (o < span) v = op(v, w);
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum_tree(T x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ void set_bit(uint64_t* bits, uint32_t i) {
+    atomicOr(reinterpret_cast<uint32_t*>(bits) + (i >> 5), 1u << (i & 31));
+}
+
+// Destination owning in-edge position p (valid p < m): the row mask marks
+// where destination segments start; rowseg is the segment at the row start.
+__device__ __forceinline__ uint32_t dst_of(const GraphArgs& g, uint32_t p) {
+    uint32_t r = p >> 6, b = p & 63;
+    uint64_t mk = g.rowmask[r];
+    return g.nzdst[g.rowseg[r] + (uint32_t)__popcll(mk & ~1ull & mask_le((int)b))];
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_iota_u32(uint32_t* __restrict__ p, uint32_t count) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        p[i] = i;
+}
+
+// F_0 = {src}: value 0 at the source in one or two value arrays.
+__global__ void k_seed_source(uint32_t src, const uint32_t* __restrict__ row_off,
+                              uint32_t* val_a, uint32_t* val_b, uint32_t* flist, uint32_t* degpre,
+                              Ctl* ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        val_a[src] = 0;
+        if (val_b) val_b[src] = 0;
+        flist[0] = src;
+        degpre[0] = 0;
+        ctl->fnext = (1ull << kDegBits) | (unsigned long long)(row_off[src + 1] - row_off[src]);
+        ctl->marked = 0;
+    }
+}
+
+// F_0 = V with label(v) = v; the out-degree prefix of the identity list is row_off.
+__global__ void k_seed_all(uint32_t n, uint32_t m, const uint32_t* __restrict__ row_off,
+                           uint32_t* __restrict__ label, uint32_t* __restrict__ val_prev,
+                           uint32_t* __restrict__ flist, uint32_t* __restrict__ degpre, Ctl* ctl) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        label[v] = v;
+        val_prev[v] = v;
+        flist[v] = v;
+        degpre[v] = row_off[v];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->fnext = ((unsigned long long)n << kDegBits) | (unsigned long long)m;
+        ctl->marked = 0;
+    }
+}
+
+// ------------------------------------------------- frontier transformation
+//
+// For every out-edge of every frontier vertex (Frontier Transformation: look
+// the vertex up in the edge index and set the bits it lists), set the Wedge
+// Frontier bit of the chunk holding that edge's in-edge position. Work is
+// balanced by edges, not vertices: lane j of wave w takes edge
+// a = w*64*EPT + i*64 + j of the concatenated out-edge lists (degpre is the
+// exclusive out-degree prefix over the list), so a high-degree vertex is split
+// across many waves. Lanes that hit the same bitmap word are merged in the
+// wave, and one atomicOr per distinct word is issued.
+template <int EPT>
+__global__ __launch_bounds__(kBlock) void k_translate(const uint32_t* __restrict__ flist,
+                                                      const uint32_t* __restrict__ degpre,
+                                                      uint32_t fcount, uint32_t active,
+                                                      const uint32_t* __restrict__ row_off,
+                                                      const uint32_t* __restrict__ pos, int lc,
+                                                      uint32_t* __restrict__ wbits32) {
+    const int lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t base = wave * 64ull * EPT;
+    if (base >= active) return;
+    const uint64_t end = min<uint64_t>(base + 64ull * EPT, active);
+    // frontier index range [lo, hi] covering edges [base, end)
+    auto last_le = [&](uint64_t a, uint32_t L, uint32_t H) {
+        while (L < H) {
+            uint32_t M = (L + H + 1) >> 1;
+            if (degpre[M] <= a) L = M; else H = M - 1;
+        }
+        return L;
+    };
+    const uint32_t lo = last_le(base, 0, fcount - 1);
+    const uint32_t hi = last_le(end - 1, lo, fcount - 1);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const uint64_t a = base + (uint64_t)i * 64 + lane;
+        const bool valid = a < end;
+        uint32_t key = kInf, bit = 0;
+        if (valid) {
+            uint32_t j = last_le(a, lo, hi);
+            uint32_t u = flist[j];
+            uint32_t q = row_off[u] + (uint32_t)(a - degpre[j]);
+            uint32_t c = pos[q] >> lc;
+            key = c >> 5;
+            bit = 1u << (c & 31);
+        }
+        uint32_t prev = __shfl_up(key, 1, 64);
+        bool head = lane == 0 || prev != key;
+        uint64_t heads = __ballot(head);
+        bit = seg_reduce(bit, seg_span(heads, lane), [](uint32_t x, uint32_t y) { return x | y; });
+        if (head && valid) atomicOr(wbits32 + key, bit);
+    }
+}
+
+// ------------------------------------------------------- bitmap compaction
+//
+// Turns a bitmap into a list of its set bit indices. Each wave owns G
+// consecutive 64-bit words; lane l stands for bit l of a word, so a ballot-free
+// popcount of the word and of its lanes below gives each set bit its rank.
+// One atomicAdd per block reserves the output range. Words are cleared after
+// reading so the bitmap is all-zero for its next use.
+//   DEG:    also write the exclusive out-degree prefix of the listed vertices
+//           and count their out-degrees (the next frontier's A).
+//   COMMIT: also copy val[v] to val_prev[v] for every listed vertex.
+// Counter layout: (count << 33) | out-degree sum.
+template <bool DEG, bool COMMIT, int G>
+__global__ __launch_bounds__(kBlock) void k_bitmap_compact(
+    uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
+    const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
+    uint32_t* __restrict__ degpre, unsigned long long* counter, uint32_t* __restrict__ val_prev,
+    const uint32_t* __restrict__ val) {
+    __shared__ unsigned long long s_wave[kWavesPerBlock];
+    __shared__ unsigned long long s_base;
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+    const uint64_t w0 = ((uint64_t)blockIdx.x * kWavesPerBlock + wid) * G;
+    uint64_t mk[G];
+    uint32_t deg[G];
+    uint64_t cnt = 0, dsum = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint64_t wi = w0 + g;
+        mk[g] = wi < words ? bits[wi] : 0ull;
+        deg[g] = 0;
+        if (mk[g]) {
+            cnt += __popcll(mk[g]);
+            if (DEG) {
+                if ((mk[g] >> lane) & 1ull) {
+                    uint32_t v = (uint32_t)(wi * 64 + lane);
+                    deg[g] = row_off[v + 1] - row_off[v];
+                }
+                dsum += wave_sum_tree(deg[g]);
+            }
+        }
+    }
+    if (lane == 0) s_wave[wid] = (cnt << kDegBits) | dsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += s_wave[i];
+        s_base = t ? atomicAdd(counter, t) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long base = s_base;
+    for (int i = 0; i < wid; ++i) base += s_wave[i];
+    uint32_t cb = (uint32_t)(base >> kDegBits);
+    uint64_t db = base & kDegMask;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (!mk[g]) continue;
+        const uint64_t wi = w0 + g;
+        const bool act = (mk[g] >> lane) & 1ull;
+        const uint32_t rank = (uint32_t)__popcll(mk[g] & mask_lt(lane));
+        uint32_t dex = 0, dtot = 0;
+        if (DEG) {
+            uint32_t inc = wave_incl_scan(deg[g], lane);
+            dex = inc - deg[g];
+            dtot = __shfl(inc, 63, 64);
+        }
+        if (act) {
+            uint32_t v = (uint32_t)(wi * 64 + lane);
+            if (v < limit) {
+                list[cb + rank] = v;
+                if (DEG) degpre[cb + rank] = (uint32_t)(db + dex);
+                if (COMMIT) val_prev[v] = val[v];
+            }
+        }
+        cb += (uint32_t)__popcll(mk[g]);
+        db += dtot;
+        if (lane == 0) bits[wi] = 0ull;
+    }
+}
+
+// ------------------------------------------------------------- the pulls
+//
+// One lane per in-edge position. A lane reads its destination from the row
+// layout, its source from the streamed in-edge array, and forms the candidate
+// value the edge carries; lanes of one destination are reduced in the wave
+// (min), and the segment head applies the result:
+//   BFS  : destinations already visited are skipped before their in-edges are
+//          read (Evaluation, no-frontier BFS iterations get cheaper); an
+//          unvisited destination with an in-neighbour at level k gets k+1.
+//   CC   : candidate = label_prev[u].
+//   SSSP : candidate = dist_prev[u] + w (u reached).
+// An improvement lowers val[v] with atomicMin (a destination can span several
+// chunks and waves) and sets v's bit in the next-frontier bitmap. Values are
+// read from val_prev, the copy committed at the end of the previous
+// iteration, so every iteration sees one consistent snapshot; BFS only ever
+// writes k+1 and only reads "== k", so it can use a single array.
+// Superfluous edges (chunk members that are not active) never lower a value,
+// which is why any chunk granularity, or none, gives the same result
+// (Frontier Transformation, "Frontier Precision").
+template <int APP, int R>
+__device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&p)[R],
+                                           const bool (&valid)[R], uint32_t iter,
+                                           uint32_t* __restrict__ val,
+                                           const uint32_t* __restrict__ val_prev,
+                                           uint64_t* __restrict__ fbits) {
+    const int lane = lane_id();
+    uint32_t dst[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst_of(g, p[i]) : kInf;
+
+    if (APP == kBfs) {
+        bool need[R];
+        uint32_t u[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) need[i] = valid[i] && val[dst[i]] == kInf;
+#pragma unroll
+        for (int i = 0; i < R; ++i) u[i] = need[i] ? ld_stream(g.in_src + p[i]) : 0u;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const bool found = need[i] && val[u[i]] == iter;
+            const uint32_t prev = __shfl_up(dst[i], 1, 64);
+            const bool head = lane == 0 || prev != dst[i];
+            const uint64_t heads = __ballot(head);
+            const uint64_t fm = __ballot(found);
+            if (head && dst[i] != kInf) {
+                const int span = seg_span(heads, lane);
+                const uint64_t seg = span >= 64 ? ~0ull : ((1ull << span) - 1ull);
+                if ((fm >> lane) & seg) {
+                    val[dst[i]] = iter + 1;
+                    set_bit(fbits, dst[i]);
+                }
+            }
+        }
+    } else {
+        uint32_t u[R], x[R], cand[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) u[i] = valid[i] ? ld_stream(g.in_src + p[i]) : 0u;
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[i] = valid[i] ? val_prev[u[i]] : kInf;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (APP == kCc) cand[i] = x[i];
+            else cand[i] = x[i] != kInf ? x[i] + ld_stream(g.in_w + p[i]) : kInf;
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const uint32_t prev = __shfl_up(dst[i], 1, 64);
+            const bool head = lane == 0 || prev != dst[i];
+            const uint64_t heads = __ballot(head);
+            const uint32_t best = seg_reduce(cand[i], seg_span(heads, lane),
+                                             [](uint32_t a, uint32_t b) { return a < b ? a : b; });
+            if (head && best != kInf) {
+                const uint32_t v = dst[i];
+                if (best < val[v]) {
+                    const uint32_t old = atomicMin(val + v, best);
+                    if (best < old) set_bit(fbits, v);
+                }
+            }
+        }
+    }
+}
+
+// Full pull: wave w covers rows [w*R, w*R + R), i.e. every in-edge once.
+template <int APP, int R>
+__global__ __launch_bounds__(kBlock) void k_pull_full(GraphArgs g, uint32_t iter,
+                                                      uint32_t* __restrict__ val,
+                                                      const uint32_t* __restrict__ val_prev,
+                                                      uint64_t* __restrict__ fbits) {
+    const int lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t r0 = wave * R;
+    if (r0 >= g.rows) return;
+    uint32_t p[R];
+    bool valid[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint64_t pp = (r0 + i) * 64 + lane;
+        valid[i] = pp < g.m;
+        p[i] = (uint32_t)pp;
+    }
+    pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fbits);
+}
+
+// Pull over the marked chunks: the chunk list holds K = *marked chunk ids of
+// 2^lc positions each. A 64-lane slot covers 64 >> lc chunks (lc <= 6) or one
+// 64-position part of a chunk (lc > 6). Waves stride over the slots, R slots at
+// a time; K is read on the device, so the launch needs no host round trip.
+template <int APP, int R>
+__global__ __launch_bounds__(kBlock) void k_pull_chunks(GraphArgs g, uint32_t iter, int lc,
+                                                        const uint32_t* __restrict__ list,
+                                                        const unsigned long long* marked,
+                                                        uint32_t* __restrict__ val,
+                                                        const uint32_t* __restrict__ val_prev,
+                                                        uint64_t* __restrict__ fbits) {
+    const int lane = lane_id();
+    const uint64_t K = *marked >> kDegBits;
+    const uint64_t slots = lc <= 6 ? (K + (64u >> lc) - 1) / (64u >> lc) : K << (lc - 6);
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t s0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * R; s0 < slots;
+         s0 += nwaves * R) {
+        uint32_t p[R];
+        bool valid[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const uint64_t s = s0 + i;
+            uint64_t ci, off;
+            if (lc <= 6) {
+                ci = s * (64u >> lc) + ((uint32_t)lane >> lc);
+                off = (uint32_t)lane & ((1u << lc) - 1u);
+            } else {
+                ci = s >> (lc - 6);
+                off = ((s & ((1ull << (lc - 6)) - 1ull)) << 6) + lane;
+            }
+            uint64_t pp = ~0ull;
+            if (s < slots && ci < K) pp = ((uint64_t)list[ci] << lc) + off;
+            valid[i] = pp < g.m;
+            p[i] = (uint32_t)pp;
+        }
+        pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fbits);
+    }
+}
+
+// ---------------------------------------------------------------- PageRank
+//
+// Full pull of PageRank (no frontier): S(v) = sum over in-edges of
+// contrib(u) = r(u)/outdeg(u). A wave owns a tile of kPrTileRows rows; sums
+// are formed by segmented tree reductions per row, carried across the rows of
+// the tile in order, and written straight to S for destinations that lie
+// inside the tile. A destination crossing a tile boundary leaves its partial
+// from the tile where it starts in tail[tile] and its partials from later tiles
+// in head[tile]; k_pr_fixup adds them in a fixed order. No float atomics: the
+// result is deterministic.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_pr_pull(GraphArgs g, const float* __restrict__ contrib,
+                                                    float* __restrict__ sum,
+                                                    float* __restrict__ head_part,
+                                                    float* __restrict__ tail_part) {
+    const int lane = lane_id();
+    const uint64_t tile = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t r0 = tile * R;
+    if (r0 >= g.rows) return;
+    uint32_t u[R], dst[R];
+    bool valid[R];
+    float x[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint64_t pp = (r0 + i) * 64 + lane;
+        valid[i] = (r0 + i) < g.rows && pp < g.m;
+        u[i] = valid[i] ? ld_stream(g.in_src + pp) : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst_of(g, (uint32_t)((r0 + i) * 64 + lane)) : kInf;
+#pragma unroll
+    for (int i = 0; i < R; ++i) x[i] = valid[i] ? contrib[u[i]] : 0.0f;
+
+    float carry = 0.0f;
+    bool from_before = false;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint64_t r = r0 + i;
+        if (r >= g.rows) break;
+        const uint64_t mk = g.rowmask[r];
+        const uint64_t row_end = min<uint64_t>(r * 64 + 64, g.m);
+        const bool cont_in = !(mk & 1ull);
+        const bool cont_out = row_end < g.m && !(g.rowmask[r + 1] & 1ull);
+        const bool last_row = (i == R - 1) || (r + 1 >= g.rows);
+        const uint64_t pp = r * 64 + lane;
+        const bool head = lane == 0 || ((mk >> lane) & 1ull) || pp == g.m;
+        const uint64_t heads = __ballot(head);
+        const uint64_t vmask = __ballot(valid[i]);
+        float s = seg_reduce(x[i], seg_span(heads, lane), [](float a, float b) { return a + b; });
+        if (i == 0) from_before = cont_in;
+        if (lane == 0 && cont_in) s = carry + s;
+        const uint64_t hv = heads & vmask;
+        const int h_last = 63 - __clzll(hv);
+        if (head && valid[i]) {
+            const bool seg_before = lane == 0 && cont_in && from_before;
+            if (lane == h_last && cont_out) {
+                if (last_row) {
+                    if (seg_before) head_part[tile] = s;
+                    else tail_part[tile] = s;
+                }
+            } else if (seg_before) {
+                head_part[tile] = s;
+            } else {
+                sum[dst[i]] = s;
+            }
+        }
+        const float last_s = __shfl(s, h_last, 64);
+        const bool nfb = h_last == 0 && cont_in && from_before;
+        if (cont_out && !last_row) {
+            carry = last_s;
+            from_before = nfb;
+        }
+    }
+}
+
+// S(v) = tail[first tile] + sum of head[t] over the later tiles v covers.
+__global__ __launch_bounds__(kBlock) void k_pr_fixup(const uint32_t* __restrict__ spans,
+                                                     uint64_t nspans,
+                                                     const float* __restrict__ head_part,
+                                                     const float* __restrict__ tail_part,
+                                                     float* __restrict__ sum) {
+    const int lane = lane_id();
+    const uint64_t e = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (e >= nspans) return;
+    const uint32_t v = spans[3 * e], ta = spans[3 * e + 1], tb = spans[3 * e + 2];
+    float acc = 0.0f;
+    for (uint32_t t = ta + 1 + lane; t <= tb; t += 64) acc += head_part[t];
+    acc = wave_sum_tree(acc);
+    if (lane == 0) sum[v] = tail_part[ta] + acc;
+}
+
+__global__ void k_pr_init(uint32_t n, const uint32_t* __restrict__ row_off, float* __restrict__ rank,
+                          float* __restrict__ contrib, float* __restrict__ sum) {
+    const float r0 = 1.0f / (float)n;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t od = row_off[v + 1] - row_off[v];
+        rank[v] = r0;
+        contrib[v] = od ? r0 / (float)od : 0.0f;
+        sum[v] = 0.0f;
+    }
+}
+
+__global__ void k_set_f64(double* p, double v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// r'(v) = (1-d)/n + d (S(v) + D/n); contrib'(v) = r'/outdeg; per-block sum of
+// the new rank mass on out-degree-0 vertices (the next D), in FP64.
+__global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n,
+                                                        const uint32_t* __restrict__ row_off,
+                                                        const float* __restrict__ sum, double d,
+                                                        const double* __restrict__ dcur,
+                                                        float* __restrict__ rank,
+                                                        float* __restrict__ contrib,
+                                                        double* __restrict__ partials) {
+    __shared__ double s_part[kWavesPerBlock];
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    const double dn = *dcur / (double)n;
+    const double base = (1.0 - d) / (double)n;
+    double acc = 0.0;
+    if (v < n) {
+        const float r = (float)(base + d * ((double)sum[v] + dn));
+        const uint32_t od = row_off[v + 1] - row_off[v];
+        rank[v] = r;
+        contrib[v] = od ? r / (float)od : 0.0f;
+        if (!od) acc = (double)r;
+    }
+    acc = wave_sum_tree(acc);
+    if (lane_id() == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += s_part[i];
+        partials[blockIdx.x] = t;
+    }
+}
+
+// D_next = sum of the per-block partials, in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_pr_dsum(const double* __restrict__ partials,
+                                                    uint32_t parts, double* __restrict__ dnext) {
+    __shared__ double s_part[kWavesPerBlock];
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < parts; i += blockDim.x) acc += partials[i];
+    acc = wave_sum_tree(acc);
+    if (lane_id() == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += s_part[i];
+        *dnext = t;
+    }
+}
+
+uint32_t grid_for(uint64_t threads, uint32_t cap = 1u << 20) {
+    uint64_t b = (threads + kBlock - 1) / kBlock;
+    if (b == 0) b = 1;
+    return (uint32_t)(b < cap ? b : cap);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s) {
+    if (!count) return hipSuccess;
+    k_fill_u32<<<grid_for(count, 8192), kBlock, 0, s>>>(p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s) {
+    if (!count) return hipSuccess;
+    k_iota_u32<<<grid_for(count, 8192), kBlock, 0, s>>>(p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_source(uint32_t src, const uint32_t* row_off, uint32_t* val_a,
+                              uint32_t* val_b, uint32_t* flist, uint32_t* degpre, Ctl* ctl,
+                              hipStream_t s) {
+    k_seed_source<<<1, 64, 0, s>>>(src, row_off, val_a, val_b, flist, degpre, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_all(uint32_t n, uint64_t m, const uint32_t* row_off, uint32_t* label,
+                           uint32_t* val_prev, uint32_t* flist, uint32_t* degpre, Ctl* ctl,
+                           hipStream_t s) {
+    k_seed_all<<<grid_for(n, 8192), kBlock, 0, s>>>(n, (uint32_t)m, row_off, label, val_prev,
+                                                    flist, degpre, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_translate(const uint32_t* flist, const uint32_t* degpre, uint32_t fcount,
+                            uint64_t active, const uint32_t* row_off, const uint32_t* pos,
+                            int log_chunk, uint64_t* wbits, hipStream_t s) {
+    if (!fcount || !active) return hipSuccess;
+    const uint64_t waves = (active + 64ull * kTranslateEpt - 1) / (64ull * kTranslateEpt);
+    const uint64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    k_translate<kTranslateEpt><<<(uint32_t)blocks, kBlock, 0, s>>>(
+        flist, degpre, fcount, (uint32_t)active, row_off, pos, log_chunk,
+        reinterpret_cast<uint32_t*>(wbits));
+    return hipGetLastError();
+}
+
+static hipError_t launch_compact(uint64_t* bits, uint64_t words, uint32_t limit,
+                                 const uint32_t* row_off, uint32_t* list, uint32_t* degpre,
+                                 unsigned long long* counter, uint32_t* val_prev,
+                                 const uint32_t* val, bool deg, bool commit, hipStream_t s) {
+    if (!words) return hipSuccess;
+    const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (!deg)
+        k_bitmap_compact<false, false, kCompactWords><<<blocks, kBlock, 0, s>>>(
+            bits, words, limit, row_off, list, degpre, counter, val_prev, val);
+    else if (!commit)
+        k_bitmap_compact<true, false, kCompactWords><<<blocks, kBlock, 0, s>>>(
+            bits, words, limit, row_off, list, degpre, counter, val_prev, val);
+    else
+        k_bitmap_compact<true, true, kCompactWords><<<blocks, kBlock, 0, s>>>(
+            bits, words, limit, row_off, list, degpre, counter, val_prev, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list, Ctl* ctl,
+                                 hipStream_t s) {
+    return launch_compact(wbits, words, 0xFFFFFFFFu, nullptr, list, nullptr, &ctl->marked,
+                          nullptr, nullptr, false, false, s);
+}
+
+hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
+                           uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
+                           hipStream_t s) {
+    return launch_compact(fbits, ((uint64_t)n + 63) / 64, n, row_off, flist, degpre, &ctl->fnext,
+                          val_prev, val, true, val_prev != nullptr, s);
+}
+
+hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
+                            const uint32_t* val_prev, uint64_t* fbits, hipStream_t s) {
+    if (!g.rows) return hipSuccess;
+    const uint64_t waves = (g.rows + kPullRows - 1) / kPullRows;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    GraphArgs a = args_of(g);
+    switch (app) {
+        case kBfs: k_pull_full<kBfs, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fbits); break;
+        case kCc: k_pull_full<kCc, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fbits); break;
+        default: k_pull_full<kSssp, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fbits); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
+                              const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
+                              uint32_t* val, const uint32_t* val_prev, uint64_t* fbits,
+                              hipStream_t s) {
+    if (!max_chunks) return hipSuccess;
+    const uint64_t slots = log_chunk <= 6
+                               ? (max_chunks + (64u >> log_chunk) - 1) / (64u >> log_chunk)
+                               : max_chunks << (log_chunk - 6);
+    uint64_t waves = (slots + kPullRows - 1) / kPullRows;
+    const uint64_t cap = 256ull * 32;  // resident waves on 256 CUs at 8 waves/SIMD
+    if (waves > cap) waves = cap;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    GraphArgs a = args_of(g);
+    const unsigned long long* mk = &ctl->marked;
+    switch (app) {
+        case kBfs: k_pull_chunks<kBfs, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fbits); break;
+        case kCc: k_pull_chunks<kCc, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fbits); break;
+        default: k_pull_chunks<kSssp, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fbits); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pr_init(uint32_t n, const uint32_t* row_off, float* rank, float* contrib,
+                          float* sum, hipStream_t s) {
+    if (!n) return hipSuccess;
+    k_pr_init<<<grid_for(n, 8192), kBlock, 0, s>>>(n, row_off, rank, contrib, sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, float* head,
+                          float* tail, hipStream_t s) {
+    if (!g.rows) return hipSuccess;
+    const uint64_t tiles = (g.rows + kPrTileRows - 1) / kPrTileRows;
+    const uint32_t blocks = (uint32_t)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    k_pr_pull<kPrTileRows><<<blocks, kBlock, 0, s>>>(args_of(g), contrib, sum, head, tail);
+    return hipGetLastError();
+}
+
+hipError_t launch_pr_fixup(const DevGraph& g, const float* head, const float* tail, float* sum,
+                           hipStream_t s) {
+    if (!g.nspans) return hipSuccess;
+    const uint32_t blocks = (uint32_t)((g.nspans + kWavesPerBlock - 1) / kWavesPerBlock);
+    k_pr_fixup<<<blocks, kBlock, 0, s>>>(g.spans, g.nspans, head, tail, sum);
+    return hipGetLastError();
+}
+
+uint32_t pr_epilogue_blocks(uint32_t n) { return (n + kBlock - 1) / kBlock; }
+
+hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* sum,
+                              double damping, const double* d_cur, float* rank, float* contrib,
+                              double* partials, uint32_t parts, double* d_next, hipStream_t s) {
+    if (!n) return hipSuccess;
+    k_pr_epilogue<<<parts, kBlock, 0, s>>>(n, row_off, sum, damping, d_cur, rank, contrib,
+                                           partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pr_dsum<<<1, kBlock, 0, s>>>(partials, parts, d_next);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_f64(double* p, double v, hipStream_t s) {
+    k_set_f64<<<1, 64, 0, s>>>(p, v);
+    return hipGetLastError();
+}
+
+}  // namespace wedge

@@ -1,0 +1,260 @@
+// Host-side construction of the device graph layout (one-off, at graph create).
+//
+// From the caller's out-edges (CSR) it builds:
+//   * the in-edge array (CSC; Background, Graph Representation) with each
+//     destination's in-edges ordered by ascending source, weights aligned;
+//   * the edge index of the Wedge Frontier (Implementation, Data Structures):
+//     pos[q] = in-edge position of CSR edge q, kept in CSR order so that one
+//     vertex's entries are contiguous and ascend (out-neighbours ascend, and
+//     in-edge positions are grouped by destination);
+//   * the row layout the pull kernels use instead of the vertex index: for
+//     every 64 consecutive in-edge positions a 64-bit mask of where a
+//     destination's in-edge list starts, the segment index covering the row's
+//     first position, and the ids of destinations with in-edges. With one wave
+//     lane per position, a lane finds its destination with one popcount.
+//   * the PageRank tile spans: destinations whose in-edges cross a boundary
+//     between pull tiles of kPrTileRows rows.
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+
+#include "wedge_internal.h"
+
+namespace wedge {
+namespace {
+
+unsigned host_threads() {
+    const char* e = std::getenv("WEDGE_HOST_THREADS");
+    if (!e) e = std::getenv("OMP_NUM_THREADS");
+    long t = e ? std::strtol(e, nullptr, 10) : 0;
+    if (t <= 0) t = (long)std::thread::hardware_concurrency();
+    if (t <= 0) t = 1;
+    return (unsigned)std::min<long>(t, 64);
+}
+
+// Run f(begin, end) over [0, count) split into equal static ranges.
+template <class F>
+void parallel_ranges(uint64_t count, F&& f) {
+    unsigned t = host_threads();
+    if (count < 65536 || t == 1) {
+        f(0, count);
+        return;
+    }
+    std::vector<std::thread> pool;
+    uint64_t step = (count + t - 1) / t;
+    for (unsigned i = 0; i < t; ++i) {
+        uint64_t b = i * step, e = std::min<uint64_t>(count, b + step);
+        if (b >= e) break;
+        pool.emplace_back([=, &f] { f(b, e); });
+    }
+    for (auto& th : pool) th.join();
+}
+
+// Run f(i) for i in [0, count) with dynamic chunks (for skewed work).
+template <class F>
+void parallel_dynamic(uint64_t count, uint64_t grain, F&& f) {
+    unsigned t = host_threads();
+    if (count < 4096 || t == 1) {
+        for (uint64_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<uint64_t> next{0};
+    std::vector<std::thread> pool;
+    for (unsigned i = 0; i < t; ++i)
+        pool.emplace_back([&] {
+            for (;;) {
+                uint64_t b = next.fetch_add(grain);
+                if (b >= count) break;
+                uint64_t e = std::min(count, b + grain);
+                for (uint64_t j = b; j < e; ++j) f(j);
+            }
+        });
+    for (auto& th : pool) th.join();
+}
+
+wedge_status check_offsets(uint32_t n, uint64_t m, const uint64_t* off, const uint32_t* ids,
+                           std::string* err) {
+    if (n >= (1u << 31)) { *err = "n must be < 2^31"; return WEDGE_ERR_BAD_GRAPH; }
+    if (m >= (1ull << 32)) { *err = "m must be < 2^32 (in-edge positions are 32-bit)"; return WEDGE_ERR_BAD_GRAPH; }
+    if (!off) { *err = "offsets pointer is null"; return WEDGE_ERR_INVALID_ARG; }
+    if (m && !ids) { *err = "edge array pointer is null"; return WEDGE_ERR_INVALID_ARG; }
+    if (off[0] != 0) { *err = "offsets[0] must be 0"; return WEDGE_ERR_BAD_GRAPH; }
+    for (uint32_t v = 0; v < n; ++v)
+        if (off[v + 1] < off[v]) { *err = "offsets are not non-decreasing at vertex " + std::to_string(v); return WEDGE_ERR_BAD_GRAPH; }
+    if (off[n] != m) { *err = "offsets[n] != m"; return WEDGE_ERR_BAD_GRAPH; }
+    std::atomic<uint64_t> bad{~0ull};
+    parallel_ranges(m, [&](uint64_t b, uint64_t e) {
+        for (uint64_t j = b; j < e; ++j)
+            if (ids[j] >= n) { bad.store(j); break; }
+    });
+    if (bad.load() != ~0ull) {
+        *err = "vertex id out of range at edge " + std::to_string(bad.load());
+        return WEDGE_ERR_BAD_GRAPH;
+    }
+    return WEDGE_OK;
+}
+
+// Undirected view of a CSR: both directions of every non-loop edge, merged.
+void symmetrize_csr(uint32_t n, const uint64_t* row_off, const uint32_t* col,
+                    std::vector<uint64_t>* sro, std::vector<uint32_t>* scol) {
+    std::vector<uint64_t> deg((size_t)n + 1, 0);
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint64_t j = row_off[u]; j < row_off[u + 1]; ++j)
+            if (col[j] != u) { deg[u + 1]++; deg[col[j] + 1]++; }
+    for (uint32_t v = 0; v < n; ++v) deg[v + 1] += deg[v];
+    std::vector<uint32_t> tmp(deg[n] ? deg[n] : 1);
+    std::vector<uint64_t> cur(deg.begin(), deg.end());
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint64_t j = row_off[u]; j < row_off[u + 1]; ++j)
+            if (col[j] != u) { tmp[cur[u]++] = col[j]; tmp[cur[col[j]]++] = u; }
+    std::vector<uint32_t> kept(n, 0);
+    parallel_dynamic(n, 1024, [&](uint64_t u) {
+        uint32_t* b = tmp.data() + deg[u];
+        uint32_t* e = tmp.data() + deg[u + 1];
+        std::sort(b, e);
+        kept[u] = (uint32_t)(std::unique(b, e) - b);
+    });
+    sro->assign((size_t)n + 1, 0);
+    for (uint32_t u = 0; u < n; ++u) (*sro)[u + 1] = (*sro)[u] + kept[u];
+    scol->resize((*sro)[n]);
+    parallel_dynamic(n, 1024, [&](uint64_t u) {
+        std::memcpy(scol->data() + (*sro)[u], tmp.data() + deg[u], kept[u] * sizeof(uint32_t));
+    });
+}
+
+}  // namespace
+
+wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_off_in,
+                                   const uint32_t* col_in, const uint32_t* w, bool symmetrize,
+                                   HostLayout* L, std::string* err) {
+    wedge_status st = check_offsets(n, m, row_off_in, col_in, err);
+    if (st != WEDGE_OK) return st;
+    std::vector<uint64_t> sro;
+    std::vector<uint32_t> scol;
+    const uint64_t* row_off = row_off_in;
+    const uint32_t* col = col_in;
+    if (symmetrize) {
+        if (w) { *err = "weights are not accepted with WEDGE_SYMMETRIZE"; return WEDGE_ERR_INVALID_ARG; }
+        symmetrize_csr(n, row_off_in, col_in, &sro, &scol);
+        row_off = sro.data();
+        col = scol.data();
+        m = sro[n];
+        if (m >= (1ull << 32)) { *err = "undirected view has >= 2^32 edges"; return WEDGE_ERR_BAD_GRAPH; }
+    }
+    L->n = n;
+    L->m = m;
+
+    // --- in-degrees and in-edge offsets
+    std::vector<uint32_t> indeg(n, 0);
+    parallel_ranges(m, [&](uint64_t b, uint64_t e) {
+        for (uint64_t j = b; j < e; ++j) __atomic_fetch_add(&indeg[col[j]], 1u, __ATOMIC_RELAXED);
+    });
+    L->col_off.assign((size_t)n + 1, 0);
+    for (uint32_t v = 0; v < n; ++v) L->col_off[v + 1] = L->col_off[v] + indeg[v];
+
+    // --- scatter (source << 32 | csr index) into destination buckets, then sort
+    // each bucket: sources ascend, duplicate edges keep CSR order
+    std::vector<uint64_t> keys(m ? m : 1);
+    {
+        std::vector<uint32_t> cur(L->col_off.begin(), L->col_off.end() - 1);
+        // sources of a range of CSR edges: walk rows
+        parallel_ranges(n, [&](uint64_t ub, uint64_t ue) {
+            for (uint64_t u = ub; u < ue; ++u)
+                for (uint64_t j = row_off[u]; j < row_off[u + 1]; ++j) {
+                    uint32_t p = __atomic_fetch_add(&cur[col[j]], 1u, __ATOMIC_RELAXED);
+                    keys[p] = (u << 32) | j;
+                }
+        });
+    }
+    parallel_dynamic(n, 2048, [&](uint64_t v) {
+        uint32_t b = L->col_off[v], e = L->col_off[v + 1];
+        if (e - b > 1) std::sort(keys.begin() + b, keys.begin() + e);
+    });
+    L->in_src.resize(m);
+    L->pos.resize(m);
+    if (w) L->in_w.resize(m);
+    std::atomic<uint32_t> maxw{0};
+    parallel_ranges(m, [&](uint64_t b, uint64_t e) {
+        uint32_t mw = 0;
+        for (uint64_t p = b; p < e; ++p) {
+            uint64_t k = keys[p];
+            uint32_t q = (uint32_t)k;
+            L->in_src[p] = (uint32_t)(k >> 32);
+            L->pos[q] = (uint32_t)p;
+            if (w) { L->in_w[p] = w[q]; mw = std::max(mw, w[q]); }
+        }
+        uint32_t old = maxw.load();
+        while (mw > old && !maxw.compare_exchange_weak(old, mw)) {}
+    });
+    L->max_w = maxw.load();
+    std::vector<uint64_t>().swap(keys);
+
+    // --- out-edge offsets (32-bit) and dangling count
+    L->row_off.resize((size_t)n + 1);
+    uint32_t dang = 0;
+    for (uint32_t u = 0; u <= n; ++u) L->row_off[u] = (uint32_t)row_off[u];
+    for (uint32_t u = 0; u < n; ++u) dang += row_off[u + 1] == row_off[u];
+    L->dangling = dang;
+
+    // --- destinations with in-edges, row masks, row segment bases
+    L->nzdst.clear();
+    L->nzdst.reserve(n);
+    for (uint32_t v = 0; v < n; ++v)
+        if (indeg[v]) L->nzdst.push_back(v);
+    uint64_t rows = (m + 63) / 64;
+    L->rowmask.assign(rows, 0);
+    L->rowseg.assign(rows, 0);
+    uint64_t s = 0;
+    const uint64_t S = L->nzdst.size();
+    for (uint64_t r = 0; r < rows; ++r) {
+        uint64_t lo = r * 64, hi = lo + 64;
+        // advance s to the last segment starting at or before lo
+        while (s + 1 < S && L->col_off[L->nzdst[s + 1]] <= lo) ++s;
+        L->rowseg[r] = (uint32_t)s;
+        for (uint64_t t = s; t < S; ++t) {
+            uint64_t st0 = L->col_off[L->nzdst[t]];
+            if (st0 >= hi) break;
+            if (st0 >= lo) L->rowmask[r] |= 1ull << (st0 - lo);
+        }
+    }
+
+    // --- PageRank tile spans
+    L->spans.clear();
+    const uint64_t T = 64ull * kPrTileRows;
+    for (uint64_t t = 0; t < S; ++t) {
+        uint32_t v = L->nzdst[t];
+        uint64_t a = L->col_off[v], b = (uint64_t)L->col_off[v + 1] - 1;
+        if (a / T != b / T) {
+            L->spans.push_back(v);
+            L->spans.push_back((uint32_t)(a / T));
+            L->spans.push_back((uint32_t)(b / T));
+        }
+    }
+    return WEDGE_OK;
+}
+
+wedge_status build_layout_from_csc(uint32_t n, uint64_t m, const uint64_t* col_off,
+                                   const uint32_t* src, const uint32_t* w, bool symmetrize,
+                                   HostLayout* L, std::string* err) {
+    wedge_status st = check_offsets(n, m, col_off, src, err);
+    if (st != WEDGE_OK) return st;
+    // transpose to CSR (stable: destinations ascend within each source's row)
+    std::vector<uint64_t> row_off((size_t)n + 1, 0);
+    for (uint64_t p = 0; p < m; ++p) row_off[src[p] + 1]++;
+    for (uint32_t u = 0; u < n; ++u) row_off[u + 1] += row_off[u];
+    std::vector<uint64_t> cur(row_off.begin(), row_off.end() - 1);
+    std::vector<uint32_t> col(m ? m : 1);
+    std::vector<uint32_t> cw(w ? (m ? m : 1) : 0);
+    for (uint32_t v = 0; v < n; ++v)
+        for (uint64_t p = col_off[v]; p < col_off[v + 1]; ++p) {
+            uint64_t q = cur[src[p]]++;
+            col[q] = v;
+            if (w) cw[q] = w[p];
+        }
+    return build_layout_from_csr(n, m, row_off.data(), col.data(), w ? cw.data() : nullptr,
+                                 symmetrize, L, err);
+}
+
+}  // namespace wedge

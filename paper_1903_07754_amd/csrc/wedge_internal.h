@@ -1,0 +1,158 @@
+// Internal declarations shared by the host driver (api.cpp, layout.cpp) and the
+// HIP kernels (kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+#include <stddef.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/wedge.h"
+
+namespace wedge {
+
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr int kWave = 64;
+constexpr uint32_t kPrTileRows = 8;  // PageRank pull tile: 8 rows of 64 in-edge positions
+
+enum App : int { kBfs = 1, kCc = 2, kSssp = 3 };
+
+// ------------------------------------------------------------- host layout
+// Everything the device needs, built once on the host from the input graph.
+struct HostLayout {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    std::vector<uint32_t> col_off;   // n+1
+    std::vector<uint32_t> in_src;    // m
+    std::vector<uint32_t> in_w;      // m (empty when unweighted)
+    std::vector<uint32_t> row_off;   // n+1
+    std::vector<uint32_t> pos;       // m, CSR order
+    std::vector<uint64_t> rowmask;   // rows
+    std::vector<uint32_t> rowseg;    // rows
+    std::vector<uint32_t> nzdst;     // nonempty
+    std::vector<uint32_t> spans;     // 3 * pr_spans (v, first tile, last tile)
+    uint32_t dangling = 0;
+    uint32_t max_w = 0;
+};
+
+// Validates and builds the layout from CSR (edges grouped by source) or CSC
+// (grouped by destination). Returns WEDGE_OK or an error with *err set.
+wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_off,
+                                   const uint32_t* col, const uint32_t* w, bool symmetrize,
+                                   HostLayout* out, std::string* err);
+wedge_status build_layout_from_csc(uint32_t n, uint64_t m, const uint64_t* col_off,
+                                   const uint32_t* src, const uint32_t* w, bool symmetrize,
+                                   HostLayout* out, std::string* err);
+
+// ------------------------------------------------------- device structures
+struct DevGraph {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    uint64_t rows = 0;
+    uint32_t nonempty = 0;
+    uint64_t nspans = 0;
+    uint32_t* col_off = nullptr;
+    uint32_t* in_src = nullptr;
+    uint32_t* in_w = nullptr;
+    uint32_t* row_off = nullptr;
+    uint32_t* pos = nullptr;
+    uint64_t* rowmask = nullptr;
+    uint32_t* rowseg = nullptr;
+    uint32_t* nzdst = nullptr;
+    uint32_t* spans = nullptr;
+};
+
+// Iteration counters written by the kernels and read back by the host.
+struct Ctl {
+    unsigned long long fnext;  // (count << 33) | out-degree sum of the next frontier
+    unsigned long long marked; // chunks appended to the chunk list
+    unsigned long long pad[6];
+};
+
+constexpr int kDegBits = 33;
+constexpr unsigned long long kDegMask = (1ull << kDegBits) - 1;
+
+struct Workspace {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    uint64_t* fbits = nullptr;     // ceil(n/64) words: next-frontier bitmap (kept all-zero between uses)
+    uint32_t* flist[2] = {nullptr, nullptr};
+    uint32_t* degpre[2] = {nullptr, nullptr};
+    uint32_t* val_prev = nullptr;  // n
+    uint64_t* wbits = nullptr;     // ceil(ceil(m/chunk)/64) words for the smallest chunk so far
+    uint64_t wbits_words = 0;
+    uint32_t* chunks = nullptr;    // chunk list
+    uint64_t chunks_cap = 0;
+    Ctl* ctl = nullptr;            // device counters
+    Ctl* ctl_host = nullptr;       // pinned mirror
+    // PageRank
+    float* pr_sum = nullptr;       // n
+    float* pr_contrib = nullptr;   // n
+    float* pr_head = nullptr;      // tiles
+    float* pr_tail = nullptr;      // tiles
+    double* pr_part = nullptr;     // per-block dangling partials
+    double* pr_d = nullptr;        // [2] dangling mass
+    uint64_t pr_tiles = 0;
+    uint32_t pr_parts = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+}  // namespace wedge
+
+struct wedge_graph_s {
+    uint32_t flags = 0;
+    bool weighted = false;
+    bool host_only = false;
+    uint32_t dangling = 0;
+    uint32_t max_w = 0;
+    wedge::HostLayout host;        // kept only for WEDGE_HOST_ONLY graphs
+    wedge::DevGraph dev;
+    wedge::Workspace ws;
+    uint64_t device_bytes = 0;
+    int device = 0;
+    std::mutex busy;
+};
+
+namespace wedge {
+
+// ------------------------------------------------------ kernel launchers
+// (kernels.hip). Every launcher enqueues on `s` and returns the launch status.
+hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
+hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
+hipError_t launch_seed_source(uint32_t src, const uint32_t* row_off, uint32_t* val_a,
+                              uint32_t* val_b, uint32_t* flist, uint32_t* degpre, Ctl* ctl,
+                              hipStream_t s);
+hipError_t launch_seed_all(uint32_t n, uint64_t m, const uint32_t* row_off, uint32_t* label,
+                           uint32_t* val_prev, uint32_t* flist, uint32_t* degpre, Ctl* ctl,
+                           hipStream_t s);
+hipError_t launch_translate(const uint32_t* flist, const uint32_t* degpre, uint32_t fcount,
+                            uint64_t active, const uint32_t* row_off, const uint32_t* pos,
+                            int log_chunk, uint64_t* wbits, hipStream_t s);
+hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list, Ctl* ctl,
+                                 hipStream_t s);
+hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
+                            const uint32_t* val_prev, uint64_t* fbits, hipStream_t s);
+hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
+                              const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
+                              uint32_t* val, const uint32_t* val_prev, uint64_t* fbits,
+                              hipStream_t s);
+hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
+                           uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
+                           hipStream_t s);
+// PageRank
+hipError_t launch_pr_init(uint32_t n, const uint32_t* row_off, float* rank, float* contrib,
+                          float* sum, hipStream_t s);
+hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, float* head,
+                          float* tail, hipStream_t s);
+hipError_t launch_pr_fixup(const DevGraph& g, const float* head, const float* tail, float* sum,
+                           hipStream_t s);
+hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* sum,
+                              double damping, const double* d_cur, float* rank, float* contrib,
+                              double* partials, uint32_t parts, double* d_next, hipStream_t s);
+uint32_t pr_epilogue_blocks(uint32_t n);
+
+}  // namespace wedge

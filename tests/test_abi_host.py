@@ -1,0 +1,164 @@
+"""CPU-side checks of the C-ABI library: it loads without a GPU, exports every
+function include/wedge.h declares, builds the layout on the host exactly as the
+method defines it, and rejects malformed input before any device work."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_1903_07754_amd as W
+from paper_1903_07754_amd import _binding as B
+
+
+def test_library_exports_every_header_function():
+    names = W.header_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(W.lib(), n), n
+    assert W.lib().wedge_version() == b"0.1.0"
+    assert W.lib().wedge_status_string(-4) == b"out of memory"
+
+
+def host_graph(ro, col, w=None, symmetrize=False):
+    return W.Graph.from_csr(ro, col, w, symmetrize=symmetrize, host_only=True)
+
+
+@pytest.mark.parametrize("seed,scale", [(1, 8), (2, 10), (3, 12)])
+def test_layout_matches_oracle_csc_and_edge_index(seed, scale):
+    ro, col = gen.rmat(scale, 16, seed=seed)
+    w = gen.edge_weights(ro, col, seed=seed)
+    g = host_graph(ro, col, w)
+    n, m = len(ro) - 1, len(col)
+    co, src, iw = oracle.csc(ro, col, w)
+    np.testing.assert_array_equal(g.layout("col_off"), co.astype(np.uint32))
+    np.testing.assert_array_equal(g.layout("in_src"), src)
+    np.testing.assert_array_equal(g.layout("in_w"), iw)
+    np.testing.assert_array_equal(g.layout("row_off"), ro.astype(np.uint32))
+    # edge index: CSR edge q = (u -> v) sits at in-edge position pos[q]
+    pos = g.layout("pos").astype(np.int64)
+    assert np.array_equal(np.sort(pos), np.arange(m))             # a permutation
+    u = np.repeat(np.arange(n), np.diff(ro.astype(np.int64)))
+    assert np.array_equal(src[pos], u)                             # same source
+    assert np.all(co[col] <= pos) and np.all(pos < co[col.astype(np.int64) + 1])  # same destination
+    # one vertex's entries ascend (out-neighbours ascend)
+    same = u[1:] == u[:-1]
+    assert np.all(np.diff(pos)[same] > 0)
+
+
+@pytest.mark.parametrize("seed,scale", [(4, 9), (5, 11)])
+def test_row_layout_names_every_position_destination(seed, scale):
+    ro, col = gen.rmat(scale, 8, seed=seed)
+    g = host_graph(ro, col)
+    n, m = len(ro) - 1, len(col)
+    co, src, _ = oracle.csc(ro, col)
+    dst_of_pos = np.repeat(np.arange(n), np.diff(co.astype(np.int64)))
+    mask = g.layout("rowmask")
+    seg = g.layout("rowseg").astype(np.int64)
+    nz = g.layout("nzdst")
+    assert np.array_equal(nz, np.flatnonzero(np.diff(co.astype(np.int64)) > 0))
+    p = np.arange(m)
+    r, b = p >> 6, p & 63
+    bits = (mask[r] >> b.astype(np.uint64)) & np.uint64(1)
+    starts = np.zeros(m, bool)
+    starts[co[nz].astype(np.int64)] = True
+    assert np.array_equal(bits.astype(bool), starts)
+    # destination = nz[seg[row] + number of segment starts in (row start, p]]
+    cum = np.cumsum(starts)
+    row_first = r * 64
+    cnt = cum - cum[row_first] + starts[row_first] * 0
+    got = nz[seg[r] + (cum - cum[row_first])]
+    assert np.array_equal(got, dst_of_pos)
+    assert g.info["rows"] == (m + 63) // 64
+    assert g.info["dangling"] == int((np.diff(ro.astype(np.int64)) == 0).sum())
+
+
+def test_pagerank_tile_spans():
+    ro, col = gen.rmat(12, 16, seed=9)
+    g = host_graph(ro, col)
+    co, _, _ = oracle.csc(ro, col)
+    T = g.info["pr_tile_edges"]
+    sp = g.layout("pr_spans").reshape(-1, 3).astype(np.int64)
+    want = []
+    for v in range(len(ro) - 1):
+        a, b = int(co[v]), int(co[v + 1]) - 1
+        if b >= a and a // T != b // T:
+            want.append((v, a // T, b // T))
+    assert [tuple(x) for x in sp] == want
+
+
+def test_symmetrized_layout_is_oracle_undirected_view():
+    ro, col = gen.random_graph(300, 1500, 3)
+    g = host_graph(ro, col, symmetrize=True)
+    sro, scol = oracle.symmetrize(ro, col)
+    assert g.m == len(scol)
+    np.testing.assert_array_equal(g.layout("row_off"), sro.astype(np.uint32))
+    co, src, _ = oracle.csc(sro, scol)
+    np.testing.assert_array_equal(g.layout("in_src"), src)
+
+
+def test_from_csc_equals_from_csr():
+    ro, col = gen.rmat(9, 16, seed=7)
+    w = gen.edge_weights(ro, col, seed=3)
+    co, src, iw = oracle.csc(ro, col, w)
+    a = host_graph(ro, col, w)
+    b = W.Graph.from_csc(co, src, iw, host_only=True)
+    for name in ("col_off", "in_src", "in_w", "row_off", "pos", "rowmask", "rowseg", "nzdst"):
+        np.testing.assert_array_equal(a.layout(name), b.layout(name))
+
+
+def test_degenerate_graphs_build():
+    for ro, col in [(np.zeros(1, np.uint64), np.zeros(0, np.uint32)),          # n = 0
+                    (np.zeros(2, np.uint64), np.zeros(0, np.uint32)),          # one vertex
+                    (np.array([0, 1], np.uint64), np.array([0], np.uint32))]:  # self-loop only
+        g = host_graph(ro, col)
+        assert g.n == len(ro) - 1 and g.m == len(col)
+
+
+def status_of(fn):
+    with pytest.raises(W.WedgeError) as e:
+        fn()
+    return e.value.name
+
+
+def test_malformed_input_is_rejected():
+    ro, col = gen.random_graph(20, 60, 1)
+    bad = ro.copy(); bad[3] = bad[4] + 1
+    assert status_of(lambda: host_graph(bad, col)) == "WEDGE_ERR_BAD_GRAPH"
+    bad = ro.copy(); bad[0] = 1
+    assert status_of(lambda: host_graph(bad, col)) == "WEDGE_ERR_BAD_GRAPH"
+    bad = col.copy(); bad[5] = 20
+    assert status_of(lambda: host_graph(ro, bad)) == "WEDGE_ERR_BAD_GRAPH"
+    w = gen.edge_weights(ro, col)
+    assert status_of(lambda: host_graph(ro, col, w, symmetrize=True)) == "WEDGE_ERR_INVALID_ARG"
+    L = W.lib()
+    h = C.c_void_p()
+    # m >= 2^32, null pointers, unknown flags, host-only with device input
+    assert L.wedge_graph_create_csr(4, 1 << 32, ro.ctypes.data, col.ctypes.data, None,
+                                    B.HOST_ONLY, None, C.byref(h)) == -2
+    assert L.wedge_graph_create_csr(4, 0, None, None, None, B.HOST_ONLY, None, C.byref(h)) == -1
+    assert L.wedge_graph_create_csr(20, len(col), ro.ctypes.data, None, None, B.HOST_ONLY, None,
+                                    C.byref(h)) == -1
+    assert L.wedge_graph_create_csr(20, len(col), ro.ctypes.data, col.ctypes.data, None, 0x80,
+                                    None, C.byref(h)) == -1
+    assert L.wedge_graph_create_csr(20, len(col), ro.ctypes.data, col.ctypes.data, None,
+                                    B.HOST_ONLY | B.INPUT_DEVICE, None, C.byref(h)) == -1
+    assert L.wedge_graph_create_csr(1 << 31, 0, ro.ctypes.data, None, None, B.HOST_ONLY, None,
+                                    C.byref(h)) == -2
+    assert h.value is None
+    assert L.wedge_last_error()
+
+
+def test_runs_on_host_only_graph_are_refused():
+    ro, col = gen.random_graph(10, 30, 2)
+    g = host_graph(ro, col)
+    L = W.lib()
+    st = B.Stats()
+    o, _ = B.make_opts()
+    out = np.zeros(10, np.uint32)
+    assert L.wedge_bfs(g.handle, 0, out.ctypes.data, C.byref(o), None, C.byref(st)) == -6
+    assert L.wedge_pagerank(g.handle, 20, 0.85, out.ctypes.data, C.byref(o), None, C.byref(st)) == -6
+    assert L.wedge_graph_layout(g.handle, B.LAYOUT["pos"], out.ctypes.data, 3) == -1
+    assert L.wedge_graph_layout(g.handle, 99, out.ctypes.data, 4) == -1
+    assert L.wedge_graph_destroy(None) == 0

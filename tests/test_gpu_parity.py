@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer results (BFS levels, CC labels, SSSP distances) must be bit-exact, and
+so must every per-iteration record (frontier size, out-degree sum A, gate
+decision, marked chunks). PageRank (FP32) must be within 1e-5 relative L1 of
+the FP64 oracle. Sizes span many wave tiles and end in ragged tails.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a ROCm GPU", allow_module_level=True)
+
+import paper_1903_07754_amd as W  # noqa: E402
+
+THETA = {"bfs": 10_000, "cc": 200_000, "sssp": 200_000}
+CHUNK = {"bfs": 32, "cc": 16, "sssp": 16}
+
+
+def run_app(app, g, src, **kw):
+    print(f"  [{app} n={g.n} m={g.m} src={src} {kw}]", flush=True)
+    if app == "bfs":
+        out, st, tr = W.bfs(g, src, trace_cap=g.n + 2, **kw)
+    elif app == "cc":
+        out, st, tr = W.cc(g, trace_cap=g.n + 2, **kw)
+    else:
+        out, st, tr = W.sssp(g, src, trace_cap=g.n + 2, **kw)
+    torch.cuda.synchronize()
+    return W.u32(out), st, tr
+
+
+def check_trace(tr, ref, chunk):
+    assert len(tr) == ref.iters
+    for k, r in enumerate(tr):
+        assert r["frontier"] == ref.F[k], k
+        assert r["active_edges"] == ref.A[k], k
+        if r["mode"] == 1:
+            assert r["chunk_edges"] == chunk
+            assert r["marked_chunks"] == ref.K[k], k
+
+
+def parity(app, ro, col, w=None, src=0, gate="threshold", theta=None, chunk=None):
+    theta = THETA[app] if theta is None else theta
+    chunk = CHUNK[app] if chunk is None else chunk
+    if app == "cc":
+        sro, scol = oracle.symmetrize(ro, col)
+        g = W.Graph.from_csr(ro, col, symmetrize=True)
+        ref = oracle.pull_engine("cc", sro, scol, theta_ppm=theta, chunk=chunk)
+        want = oracle.cc(ro, col)
+    else:
+        g = W.Graph.from_csr(ro, col, w)
+        ref = oracle.pull_engine(app, ro, col, w, src, theta_ppm=theta, chunk=chunk)
+        want = oracle.bfs(ro, col, src) if app == "bfs" else oracle.sssp(ro, col, w, src)
+    np.testing.assert_array_equal(ref.values, want)
+    got, st, tr = run_app(app, g, src, gate=gate, theta_ppm=theta, chunk=chunk)
+    np.testing.assert_array_equal(got, want)
+    assert st["iterations"] == ref.iters
+    check_trace(tr, ref, chunk)
+    if gate == "threshold":
+        assert [r["mode"] for r in tr] == list(ref.mode)
+    elif gate == "wedge":
+        assert all(r["mode"] == 1 for r in tr)
+    else:
+        assert all(r["mode"] == 0 for r in tr)
+    g.close()
+    return tr
+
+
+GRAPHS = {
+    "er_small": lambda: gen.random_graph(1000, 6000, 11),
+    "er_ragged": lambda: gen.random_graph(4099, 37001, 12),
+    "rmat12": lambda: gen.rmat(12, 16, seed=13),
+    "rmat14": lambda: gen.rmat(14, 16, seed=14),
+    "grid": lambda: gen.grid2d(37, 53),
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("app", ["bfs", "cc", "sssp"])
+def test_parity_threshold_gate(app, name):
+    ro, col = GRAPHS[name]()
+    w = gen.edge_weights(ro, col, seed=4) if app == "sssp" else None
+    srcs = gen.pick_sources(ro, 2, seed=5) if app != "cc" else [0]
+    for s in srcs:
+        parity(app, ro, col, w, int(s))
+
+
+@pytest.mark.parametrize("gate", ["wedge", "full"])
+@pytest.mark.parametrize("chunk", [1, 4, 16, 32, 64, 128, 1024])
+@pytest.mark.parametrize("app", ["bfs", "cc", "sssp"])
+def test_mode_and_granularity_invariance(app, chunk, gate):
+    """Any chunk size and either forced mode gives the same values and the same
+    per-iteration frontiers (Frontier Transformation, Frontier Precision)."""
+    ro, col = gen.rmat(11, 16, seed=21)
+    w = gen.edge_weights(ro, col, seed=6) if app == "sssp" else None
+    s = int(gen.pick_sources(ro, 1, seed=7)[0])
+    parity(app, ro, col, w, s, gate=gate, chunk=chunk)
+
+
+def test_theta_extremes():
+    ro, col = gen.rmat(12, 8, seed=31)
+    w = gen.edge_weights(ro, col, seed=8)
+    s = int(gen.pick_sources(ro, 1, seed=9)[0])
+    for theta in (1, 50_000, 480_000, 1_000_000):
+        parity("sssp", ro, col, w, s, theta=theta)
+
+
+def test_wedge_frontier_bitmap_is_the_definition():
+    """The translated bitmap equals the full-scan definition bit for bit."""
+    ro, col = gen.rmat(13, 16, seed=41)
+    g = W.Graph.from_csr(ro, col)
+    co, src, _ = oracle.csc(ro, col)
+    n = len(ro) - 1
+    rng = np.random.default_rng(3)
+    for chunk in (1, 2, 16, 32, 64, 256):
+        for frac in (0.0005, 0.01, 0.3, 1.0):
+            fr = np.flatnonzero(rng.random(n) < frac).astype(np.uint32)
+            dev = torch.from_numpy(fr.view(np.int32)).cuda()
+            wbits, lst = W.frontier_translate(g, dev, chunk)
+            mask = np.zeros(n, np.uint8)
+            mask[fr] = 1
+            want, k = oracle.wedge_frontier(src, mask, chunk)
+            words = wbits.cpu().numpy().view(np.uint64)
+            got = np.unpackbits(words.view(np.uint8), bitorder="little")[:len(want)]
+            np.testing.assert_array_equal(got, want)
+            assert lst.numel() == k
+            assert np.array_equal(np.sort(lst.cpu().numpy().view(np.uint32)), np.flatnonzero(want))
+
+
+def test_worked_example_on_gpu():
+    """Design Requirements example: frontier {2, 4} marks exactly its 4 edges at
+    one edge per group and 3 groups at two edges per group."""
+    pairs = [(2, 4), (2, 6), (4, 8), (4, 9), (1, 6), (3, 8), (5, 9)]
+    ro, col = gen.csr_from_edges(10, np.array([p[0] for p in pairs], np.uint32),
+                                 np.array([p[1] for p in pairs], np.uint32))
+    g = W.Graph.from_csr(ro, col)
+    fr = torch.tensor([2, 4], dtype=torch.int32, device="cuda")
+    _, l1 = W.frontier_translate(g, fr, 1)
+    _, l2 = W.frontier_translate(g, fr, 2)
+    assert sorted(l1.cpu().tolist()) == [0, 2, 4, 5]
+    assert sorted(l2.cpu().tolist()) == [0, 1, 2]
+
+
+def test_edge_cases():
+    # single vertex, no edges
+    ro, col = np.zeros(2, np.uint64), np.zeros(0, np.uint32)
+    g = W.Graph.from_csr(ro, col, np.zeros(0, np.uint32))
+    assert W.u32(W.bfs(g, 0)[0]).tolist() == [0]
+    assert W.u32(W.sssp(g, 0)[0]).tolist() == [0]
+    r, _ = W.pagerank(g, 20, 0.85)
+    assert abs(float(r.cpu()[0]) - 1.0) < 1e-6
+    gs = W.Graph.from_csr(ro, col, symmetrize=True)
+    assert W.u32(W.cc(gs)[0]).tolist() == [0]
+    # source without out-edges, isolated vertices, self-loops and duplicates in input
+    src = np.array([0, 0, 1, 2, 3, 3, 5], np.uint32)
+    dst = np.array([1, 1, 2, 2, 3, 4, 5], np.uint32)
+    order = np.argsort(src, kind="stable")
+    ro = np.zeros(8, np.uint64)
+    np.add.at(ro, src.astype(np.int64) + 1, 1)
+    ro = np.cumsum(ro).astype(np.uint64)
+    col = dst[order]
+    g = W.Graph.from_csr(ro, col, np.ones(len(col), np.uint32))
+    np.testing.assert_array_equal(W.u32(W.bfs(g, 4)[0]), oracle.bfs(ro, col, 4))
+    np.testing.assert_array_equal(W.u32(W.bfs(g, 0)[0]), oracle.bfs(ro, col, 0))
+    np.testing.assert_array_equal(W.u32(W.sssp(g, 0)[0]),
+                                  oracle.sssp(ro, col, np.ones(len(col), np.uint32), 0))
+    rk, _ = W.pagerank(g, 20, 0.85)
+    ref = oracle.pagerank(ro, col, 20, 0.85)
+    assert np.abs(rk.cpu().numpy() - ref).sum() / ref.sum() < 1e-6
+    # errors reported through the ABI, before any device work
+    with pytest.raises(W.WedgeError) as e:
+        W.bfs(g, 99)
+    assert e.value.name == "WEDGE_ERR_INVALID_ARG"
+    gu = W.Graph.from_csr(ro, col)
+    with pytest.raises(W.WedgeError) as e:
+        W.sssp(gu, 0)
+    assert e.value.name == "WEDGE_ERR_NO_WEIGHTS"
+    with pytest.raises(W.WedgeError) as e:
+        W.cc(gu)
+    assert e.value.name == "WEDGE_ERR_UNSUPPORTED"
+    with pytest.raises(W.WedgeError) as e:
+        W.bfs(gu, 0, chunk=3)
+    assert e.value.name == "WEDGE_ERR_INVALID_ARG"
+    with pytest.raises(W.WedgeError) as e:
+        W.pagerank(gu, 20, 1.5)
+    assert e.value.name == "WEDGE_ERR_INVALID_ARG"
+
+
+def test_max_iters_reports_not_converged():
+    ro, col = gen.grid2d(30, 30)
+    g = W.Graph.from_csr(ro, col)
+    with pytest.raises(W.WedgeError) as e:
+        W.bfs(g, 0, max_iters=5)
+    assert e.value.name == "WEDGE_ERR_NOT_CONVERGED"
+    out, st, _ = W.bfs(g, 0, max_iters=60)
+    np.testing.assert_array_equal(W.u32(out), oracle.bfs(ro, col, 0))
+
+
+def rel_l1(got, ref):
+    return float(np.abs(got.astype(np.float64) - ref).sum() / np.abs(ref).sum())
+
+
+@pytest.mark.parametrize("name", ["er_ragged", "rmat12", "rmat14", "grid"])
+def test_pagerank_parity(name):
+    ro, col = GRAPHS[name]()
+    g = W.Graph.from_csr(ro, col)
+    r, st = W.pagerank(g, 20, 0.85)
+    ref = oracle.pagerank(ro, col, 20, 0.85)
+    got = r.cpu().numpy()
+    assert rel_l1(got, ref) <= 1e-5
+    assert abs(got.astype(np.float64).sum() - 1.0) < 1e-5
+    # deterministic: a second run is bitwise identical
+    r2, _ = W.pagerank(g, 20, 0.85)
+    assert torch.equal(r, r2)
+
+
+def test_pagerank_closed_forms():
+    n = 1000
+    cyc = gen.csr_from_edges(n, np.arange(n, dtype=np.uint32),
+                             ((np.arange(n) + 1) % n).astype(np.uint32))
+    g = W.Graph.from_csr(*cyc)
+    r, _ = W.pagerank(g, 20, 0.85)
+    assert np.allclose(r.cpu().numpy(), 1.0 / n, rtol=1e-6, atol=0)
+    star = gen.csr_from_edges(40, np.arange(1, 40, dtype=np.uint32), np.zeros(39, np.uint32))
+    g = W.Graph.from_csr(*star)
+    r, _ = W.pagerank(g, 400, 0.85)
+    x = (1 + 39 * 0.85) / (40 + 39 * 0.85)
+    assert abs(float(r.cpu()[0]) - x) < 1e-6
+
+
+def test_pagerank_hub_spans_many_tiles():
+    """A destination with tens of thousands of in-edges crosses many tiles."""
+    n = 70000
+    src = np.arange(1, n, dtype=np.uint32)
+    dst = np.zeros(n - 1, np.uint32)
+    extra_s = np.random.default_rng(1).integers(0, n, 200000).astype(np.uint32)
+    extra_d = np.random.default_rng(2).integers(1, n, 200000).astype(np.uint32)
+    ro, col = gen.csr_from_edges(n, np.concatenate([src, extra_s]), np.concatenate([dst, extra_d]))
+    g = W.Graph.from_csr(ro, col)
+    assert g.info["pr_spans"] > 0
+    r, _ = W.pagerank(g, 20, 0.85)
+    ref = oracle.pagerank(ro, col, 20, 0.85)
+    assert rel_l1(r.cpu().numpy(), ref) <= 1e-5
+
+
+def test_repeated_runs_reuse_workspace():
+    ro, col = gen.rmat(12, 16, seed=51)
+    w = gen.edge_weights(ro, col, seed=1)
+    g = W.Graph.from_csr(ro, col, w)
+    srcs = gen.pick_sources(ro, 4, seed=3)
+    for s in srcs:
+        for chunk in (64, 16, 1, 32):
+            np.testing.assert_array_equal(W.u32(W.bfs(g, int(s), chunk=chunk)[0]),
+                                          oracle.bfs(ro, col, int(s)))
+            np.testing.assert_array_equal(W.u32(W.sssp(g, int(s), chunk=chunk)[0]),
+                                          oracle.sssp(ro, col, w, int(s)))
