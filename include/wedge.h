@@ -64,6 +64,10 @@ typedef struct wedge_graph_s* wedge_graph_t;
 #define WEDGE_HOST_ONLY    0x4u /* build and keep the layout in host memory only, touching no
                                    GPU: the handle then serves wedge_graph_info/_layout and can
                                    not run applications (WEDGE_ERR_UNSUPPORTED) */
+#define WEDGE_KEEP_IDS     0x8u /* keep the caller's vertex order inside the library (by
+                                   default vertices are renumbered by decreasing out-degree,
+                                   which packs the most-gathered values into few cache lines;
+                                   results are always returned in the caller's ids) */
 
 /*
  * Create a graph from out-edges (CSR, Background, Graph Representation):
@@ -79,6 +83,9 @@ typedef struct wedge_graph_s* wedge_graph_t;
  *   - the edge index (Wedge Frontier; Implementation, Data Structures): for
  *     every CSR edge u->v, the position of that edge in the in-edge array,
  *     stored in CSR order so a vertex's entries are contiguous;
+ *   - an internal vertex order by decreasing out-degree (unless WEDGE_KEEP_IDS),
+ *     applied to every array below; inputs (sources, frontiers) and outputs use
+ *     the caller's ids;
  *   - per 64-position row of the in-edge array, a 64-bit mask of the positions
  *     where a destination's in-edge list begins, the index of the destination
  *     segment covering the row's first position, and the list of destinations
@@ -112,6 +119,8 @@ typedef struct {
     uint32_t pr_tile_edges;/* in-edges per PageRank pull tile */
     uint64_t pr_spans;     /* destinations whose in-edges cross a PageRank tile boundary */
     uint64_t device_bytes; /* device memory held by the graph (layout + cached workspace) */
+    uint64_t pr_short_spans; /* of pr_spans, those over at most 9 tiles (listed first) */
+    uint32_t relabeled;    /* 1 when the internal vertex order differs from the caller's */
 } wedge_graph_info;
 
 wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info);
@@ -126,8 +135,11 @@ typedef enum {
     WEDGE_LAYOUT_ROWMASK = 5, /* uint64[rows] segment-start bits per 64 positions */
     WEDGE_LAYOUT_ROWSEG = 6,  /* uint32[rows] segment index covering the row's first position */
     WEDGE_LAYOUT_NZDST = 7,   /* uint32[nonempty] destination of each segment */
-    WEDGE_LAYOUT_PR_SPANS = 8 /* uint32[3*pr_spans] (vertex, first tile, last tile) */
+    WEDGE_LAYOUT_PR_SPANS = 8,/* uint32[3*pr_spans] (vertex, first tile, last tile) */
+    WEDGE_LAYOUT_PERM = 9     /* uint32[n] internal id of each caller id (relabelled graphs) */
 } wedge_layout_array;
+
+/* Layout arrays are indexed and valued by internal vertex ids. */
 
 /* Copy one layout array into host memory `dst` of `bytes` bytes (must be exactly
  * the array's size). Synchronous. */

@@ -22,11 +22,11 @@ STATUS = {0: "WEDGE_OK", -1: "WEDGE_ERR_INVALID_ARG", -2: "WEDGE_ERR_BAD_GRAPH",
           -6: "WEDGE_ERR_UNSUPPORTED", -7: "WEDGE_ERR_MODEL", -8: "WEDGE_ERR_NOT_CONVERGED",
           -9: "WEDGE_ERR_BUSY"}
 
-INPUT_DEVICE, SYMMETRIZE, HOST_ONLY = 0x1, 0x2, 0x4
+INPUT_DEVICE, SYMMETRIZE, HOST_ONLY, KEEP_IDS = 0x1, 0x2, 0x4, 0x8
 GATE = {"threshold": 0, "wedge": 1, "full": 2, "learned": 3}
 RUN_TIME_PULL, RUN_TIME_ITERS = 0x1, 0x2
 LAYOUT = {"col_off": 0, "in_src": 1, "in_w": 2, "row_off": 3, "pos": 4, "rowmask": 5,
-          "rowseg": 6, "nzdst": 7, "pr_spans": 8}
+          "rowseg": 6, "nzdst": 7, "pr_spans": 8, "perm": 9}
 
 
 class WedgeError(RuntimeError):
@@ -40,7 +40,8 @@ class GraphInfo(C.Structure):
     _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("nonempty", C.c_uint32),
                 ("rows", C.c_uint64), ("flags", C.c_uint32), ("weighted", C.c_uint32),
                 ("dangling", C.c_uint32), ("pr_tile_edges", C.c_uint32),
-                ("pr_spans", C.c_uint64), ("device_bytes", C.c_uint64)]
+                ("pr_spans", C.c_uint64), ("device_bytes", C.c_uint64),
+                ("pr_short_spans", C.c_uint64), ("relabeled", C.c_uint32)]
 
 
 class IterRecord(C.Structure):
@@ -132,8 +133,9 @@ class Graph:
         self.n, self.m = info.n, info.m
 
     @staticmethod
-    def _make(fn, n, off, ids, w, symmetrize, host_only, stream):
-        flags = (SYMMETRIZE if symmetrize else 0) | (HOST_ONLY if host_only else 0)
+    def _make(fn, n, off, ids, w, symmetrize, host_only, stream, keep_ids=False):
+        flags = ((SYMMETRIZE if symmetrize else 0) | (HOST_ONLY if host_only else 0)
+                 | (KEEP_IDS if keep_ids else 0))
         arrs = [off, ids, w]
         if not all(a is None or isinstance(a, np.ndarray) for a in arrs):
             flags |= INPUT_DEVICE
@@ -149,20 +151,23 @@ class Graph:
         return Graph(h.value)
 
     @classmethod
-    def from_csr(cls, row_off, col, w=None, symmetrize=False, host_only=False, stream=None):
+    def from_csr(cls, row_off, col, w=None, symmetrize=False, host_only=False, stream=None,
+                 keep_ids=False):
         return cls._make(lib().wedge_graph_create_csr, len(row_off) - 1, row_off, col, w,
-                         symmetrize, host_only, stream)
+                         symmetrize, host_only, stream, keep_ids)
 
     @classmethod
-    def from_csc(cls, col_off, src, w=None, symmetrize=False, host_only=False, stream=None):
+    def from_csc(cls, col_off, src, w=None, symmetrize=False, host_only=False, stream=None,
+                 keep_ids=False):
         return cls._make(lib().wedge_graph_create_csc, len(col_off) - 1, col_off, src, w,
-                         symmetrize, host_only, stream)
+                         symmetrize, host_only, stream, keep_ids)
 
     def layout(self, name):
         dt = np.uint64 if name == "rowmask" else np.uint32
         sizes = {"col_off": self.n + 1, "in_src": self.m, "in_w": self.m, "row_off": self.n + 1,
                  "pos": self.m, "rowmask": self.info["rows"], "rowseg": self.info["rows"],
-                 "nzdst": self.info["nonempty"], "pr_spans": 3 * self.info["pr_spans"]}
+                 "nzdst": self.info["nonempty"], "pr_spans": 3 * self.info["pr_spans"],
+                 "perm": self.n}
         out = np.zeros(max(int(sizes[name]), 1), dt)
         nbytes = int(sizes[name]) * out.itemsize
         check(lib().wedge_graph_layout(self._h, LAYOUT[name], out.ctypes.data, nbytes))

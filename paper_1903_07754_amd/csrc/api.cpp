@@ -70,12 +70,14 @@ wedge_status upload(wedge_graph_s* g, T** dst, const std::vector<T>& src, hipStr
 
 void free_all(wedge_graph_s* g) {
     DevGraph& d = g->dev;
-    void* ptrs[] = {d.col_off, d.in_src, d.in_w, d.row_off, d.pos, d.rowmask, d.rowseg, d.nzdst, d.spans};
+    void* ptrs[] = {d.col_off, d.in_src, d.in_w, d.row_off, d.pos, d.rowmask, d.rowseg, d.nzdst, d.spans,
+                    d.perm, d.inv};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     Workspace& w = g->ws;
-    void* wp[] = {w.fbits, w.flist[0], w.flist[1], w.degpre[0], w.degpre[1], w.val_prev, w.wbits,
-                  w.chunks, w.ctl, w.pr_sum, w.pr_contrib, w.pr_head, w.pr_tail, w.pr_part, w.pr_d};
+    void* wp[] = {w.fbits, w.fcur, w.flist[0], w.flist[1], w.degpre[0], w.degpre[1], w.val_prev,
+                  w.val, w.wbits, w.chunks, w.ctl, w.pr_sum, w.pr_contrib, w.pr_rank, w.pr_head,
+                  w.pr_tail, w.pr_part, w.pr_d};
     for (void* p : wp)
         if (p) (void)hipFree(p);
     if (w.ctl_host) (void)hipHostFree(w.ctl_host);
@@ -102,7 +104,7 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
                     const uint32_t* w, uint32_t flags, hipStream_t stream, wedge_graph_t* out) {
     if (!out) return fail(WEDGE_ERR_INVALID_ARG, "out is null");
     *out = nullptr;
-    if (flags & ~(WEDGE_INPUT_DEVICE | WEDGE_SYMMETRIZE | WEDGE_HOST_ONLY))
+    if (flags & ~(WEDGE_INPUT_DEVICE | WEDGE_SYMMETRIZE | WEDGE_HOST_ONLY | WEDGE_KEEP_IDS))
         return fail(WEDGE_ERR_INVALID_ARG, "unknown flag bits");
     if ((flags & WEDGE_HOST_ONLY) && (flags & WEDGE_INPUT_DEVICE))
         return fail(WEDGE_ERR_INVALID_ARG, "WEDGE_HOST_ONLY cannot take device input");
@@ -124,8 +126,9 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     g->host_only = flags & WEDGE_HOST_ONLY;
     HostLayout& L = g->host;
     const bool sym = flags & WEDGE_SYMMETRIZE;
-    st = from_csr ? build_layout_from_csr(n, m, hoff, hids, hw, sym, &L, &g_err)
-                  : build_layout_from_csc(n, m, hoff, hids, hw, sym, &L, &g_err);
+    const bool relabel = !(flags & WEDGE_KEEP_IDS);
+    st = from_csr ? build_layout_from_csr(n, m, hoff, hids, hw, sym, relabel, &L, &g_err)
+                  : build_layout_from_csc(n, m, hoff, hids, hw, sym, relabel, &L, &g_err);
     if (st != WEDGE_OK) { delete g; return st; }
     g->weighted = !L.in_w.empty() || (w != nullptr);
     g->dangling = L.dangling;
@@ -136,6 +139,8 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     d.rows = (L.m + 63) / 64;
     d.nonempty = (uint32_t)L.nzdst.size();
     d.nspans = L.spans.size() / 3;
+    d.short_spans = L.short_spans;
+    g->perm_host = L.perm;
     if (g->host_only) { *out = g; return WEDGE_OK; }
     HIP_TRY(hipGetDevice(&g->device), "hipGetDevice");
     st = WEDGE_OK;
@@ -148,6 +153,8 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     if (st == WEDGE_OK) st = upload(g, &d.rowseg, L.rowseg, stream, "rowseg");
     if (st == WEDGE_OK) st = upload(g, &d.nzdst, L.nzdst, stream, "nzdst");
     if (st == WEDGE_OK) st = upload(g, &d.spans, L.spans, stream, "spans");
+    if (st == WEDGE_OK && !L.perm.empty()) st = upload(g, &d.perm, L.perm, stream, "perm");
+    if (st == WEDGE_OK && !L.inv.empty()) st = upload(g, &d.inv, L.inv, stream, "inv");
     if (st == WEDGE_OK) {
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) st = hip_fail(e, "uploading graph");
@@ -175,6 +182,8 @@ wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontie
         const uint64_t fw = ((uint64_t)d.n + 63) / 64;
         if ((st = dev_alloc(g, (void**)&w.fbits, fw * 8, "frontier bitmap")) != WEDGE_OK) return st;
         HIP_TRY(hipMemset(w.fbits, 0, fw ? fw * 8 : 8), "clearing frontier bitmap");
+        if ((st = dev_alloc(g, (void**)&w.fcur, fw * 8, "current frontier bitmap")) != WEDGE_OK) return st;
+        if (d.inv && (st = dev_alloc(g, (void**)&w.val, (size_t)d.n * 4, "values")) != WEDGE_OK) return st;
         for (int i = 0; i < 2; ++i) {
             if ((st = dev_alloc(g, (void**)&w.flist[i], (size_t)d.n * 4, "frontier list")) != WEDGE_OK) return st;
             if ((st = dev_alloc(g, (void**)&w.degpre[i], (size_t)d.n * 4, "degree prefix")) != WEDGE_OK) return st;
@@ -260,18 +269,27 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     HIP_TRY(hipMemsetAsync(w.fbits, 0, fwords * 8, s), "clearing frontier bitmap");
     if (may_wedge) HIP_TRY(hipMemsetAsync(w.wbits, 0, wwords * 8, s), "clearing Wedge bitmap");
 
+    // values are computed in internal vertex order; a relabelled graph works in
+    // a workspace array and scatters to the caller's order at the end
+    uint32_t* const out = val;
+    if (d.inv) val = w.val;
+    const uint32_t isrc = (app != kCc && !g->perm_host.empty()) ? g->perm_host[src] : src;
     uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
+    HIP_TRY(hipMemsetAsync(w.fcur, 0, fwords * 8, s), "clearing frontier bitmap");
     if (app == kCc) {
-        HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, val, w.val_prev, w.flist[0], w.degpre[0], w.ctl, s), "seeding CC");
+        HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, d.inv, val, w.val_prev, w.flist[0], w.degpre[0],
+                                w.fcur, w.ctl, s), "seeding CC");
     } else {
         HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
         if (vprev) HIP_TRY(launch_fill_u32(vprev, d.n, kInf, s), "initialising values");
-        HIP_TRY(launch_seed_source(src, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.ctl, s), "seeding source");
+        HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur,
+                                   w.ctl, s), "seeding source");
     }
     HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
     HIP_TRY(hipStreamSynchronize(s), "initialising run");
-    uint64_t fcount = w.ctl_host->fnext >> kDegBits;
-    uint64_t active = w.ctl_host->fnext & kDegMask;
+    uint64_t fcount = w.ctl_host->ftotal;               // |F_k|
+    uint64_t flisted = w.ctl_host->fnext >> kDegBits;   // of which have out-edges
+    uint64_t active = w.ctl_host->fnext & kDegMask;     // A_k
     const uint32_t max_iters = o.max_iters ? o.max_iters : d.n + 1;
     const bool time_pull = o.flags & WEDGE_RUN_TIME_PULL;
     const bool time_iter = o.flags & WEDGE_RUN_TIME_ITERS;
@@ -289,22 +307,22 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
             case WEDGE_GATE_ALWAYS_FULL: wedge_mode = false; break;
             default: wedge_mode = active < thr; break;  // the fullness threshold (strict <)
         }
-        HIP_TRY(hipMemsetAsync(w.ctl, 0, 16, s), "clearing counters");
+        HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
         if (time_iter) HIP_TRY(hipEventRecord(w.ev[2], s), "event");
         if (wedge_mode) {
-            HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)fcount, active, d.row_off,
+            HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)flisted, active, d.row_off,
                                      d.pos, lc, w.wbits, s), "frontier translation");
             HIP_TRY(launch_compact_chunks(w.wbits, wwords, w.chunks, w.ctl, s), "chunk compaction");
             if (time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
             const uint64_t maxk = active < nchunks ? active : nchunks;
-            HIP_TRY(launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev, w.fbits, s), "chunk pull");
+            HIP_TRY(launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev, w.fcur, w.fbits, s), "chunk pull");
         } else {
             if (time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
-            HIP_TRY(launch_pull_full(app, d, k, val, vprev, w.fbits, s), "full pull");
+            HIP_TRY(launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s), "full pull");
         }
         if (time_pull) HIP_TRY(hipEventRecord(w.ev[1], s), "event");
         HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                vprev, val, s), "frontier finalisation");
+                                vprev, val, w.fcur, s), "frontier finalisation");
         if (time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
         HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
         HIP_TRY(hipStreamSynchronize(s), "iteration");
@@ -328,9 +346,14 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         }
         if (wedge_mode) { local.wedge_iters++; local.edges_scanned += marked << lc; }
         else { local.full_iters++; local.edges_scanned += d.m; }
-        fcount = w.ctl_host->fnext >> kDegBits;
+        fcount = w.ctl_host->ftotal;
+        flisted = w.ctl_host->fnext >> kDegBits;
         active = w.ctl_host->fnext & kDegMask;
         cur ^= 1;
+    }
+    if (d.inv) {
+        HIP_TRY(launch_unpermute_u32(d.n, d.perm, val, out, s), "writing results");
+        HIP_TRY(hipStreamSynchronize(s), "writing results");
     }
     local.iterations = k;
     local.ms = now_ms() - t0;
@@ -381,6 +404,8 @@ wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info) {
     info->pr_tile_edges = 64u * kPrTileRows;
     info->pr_spans = g->dev.nspans;
     info->device_bytes = g->device_bytes;
+    info->pr_short_spans = g->dev.short_spans;
+    info->relabeled = g->perm_host.empty() ? 0u : 1u;
     return WEDGE_OK;
 }
 
@@ -404,6 +429,12 @@ wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void*
         case WEDGE_LAYOUT_ROWSEG: size = d.rows * 4; hsrc = L.rowseg.data(); dsrc = d.rowseg; break;
         case WEDGE_LAYOUT_NZDST: size = (uint64_t)d.nonempty * 4; hsrc = L.nzdst.data(); dsrc = d.nzdst; break;
         case WEDGE_LAYOUT_PR_SPANS: size = d.nspans * 12; hsrc = L.spans.data(); dsrc = d.spans; break;
+        case WEDGE_LAYOUT_PERM:
+            size = g->perm_host.empty() ? 0 : (uint64_t)d.n * 4;
+            if (!size) return fail(WEDGE_ERR_UNSUPPORTED, "graph keeps the caller's ids (no permutation)");
+            if (bytes != size) return fail(WEDGE_ERR_INVALID_ARG, "bytes does not match the array size");
+            std::memcpy(dst, g->perm_host.data(), size);
+            return WEDGE_OK;
         default: return fail(WEDGE_ERR_INVALID_ARG, "unknown layout array");
     }
     if (bytes != size) return fail(WEDGE_ERR_INVALID_ARG, "bytes does not match the array size " + std::to_string(size));
@@ -451,7 +482,9 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
         if ((st = dev_alloc(g, (void**)&w.pr_tail, w.pr_tiles * 4, "PageRank tile tails")) != WEDGE_OK) return st;
         if ((st = dev_alloc(g, (void**)&w.pr_part, (size_t)w.pr_parts * 8, "PageRank partials")) != WEDGE_OK) return st;
         if ((st = dev_alloc(g, (void**)&w.pr_d, 16, "dangling mass")) != WEDGE_OK) return st;
+        if (d.inv && (st = dev_alloc(g, (void**)&w.pr_rank, (size_t)d.n * 4, "ranks")) != WEDGE_OK) return st;
     }
+    float* rank = d.inv ? w.pr_rank : rank_dev;
     const bool time_pull = o.flags & WEDGE_RUN_TIME_PULL;
     std::vector<hipEvent_t> evs;
     if (time_pull) {
@@ -459,18 +492,23 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
         for (auto& e : evs) HIP_TRY(hipEventCreate(&e), "event");
     }
     auto cleanup = [&] { for (auto e : evs) if (e) (void)hipEventDestroy(e); };
-    hipError_t e = launch_pr_init(d.n, d.row_off, rank_dev, w.pr_contrib, w.pr_sum, s);
+    // D_0 comes from the host; D_k (k >= 1) is reduced from the previous
+    // epilogue's partials by the fix-up launch of iteration k
+    hipError_t e = launch_pr_init(d.n, d.row_off, rank, w.pr_contrib, w.pr_sum, s);
     if (e == hipSuccess) e = launch_set_f64(w.pr_d, (double)g->dangling / (double)d.n, s);
     for (uint32_t k = 0; k < iters && e == hipSuccess; ++k) {
+        double* dk = w.pr_d + (k & 1);
         if (time_pull) e = hipEventRecord(evs[2 * k], s);
         if (e == hipSuccess) e = launch_pr_pull(d, w.pr_contrib, w.pr_sum, w.pr_head, w.pr_tail, s);
         if (time_pull && e == hipSuccess) e = hipEventRecord(evs[2 * k + 1], s);
-        if (e == hipSuccess) e = launch_pr_fixup(d, w.pr_head, w.pr_tail, w.pr_sum, s);
         if (e == hipSuccess)
-            e = launch_pr_epilogue(d.n, d.row_off, w.pr_sum, (double)damping, w.pr_d + (k & 1),
-                                   rank_dev, w.pr_contrib, w.pr_part, w.pr_parts,
-                                   w.pr_d + ((k + 1) & 1), s);
+            e = launch_pr_fixup(d, w.pr_head, w.pr_tail, w.pr_sum, w.pr_part, w.pr_parts,
+                                k ? dk : nullptr, s);
+        if (e == hipSuccess)
+            e = launch_pr_epilogue(d.n, d.row_off, w.pr_sum, (double)damping, dk, rank,
+                                   w.pr_contrib, w.pr_part, w.pr_parts, s);
     }
+    if (e == hipSuccess && d.inv) e = launch_unpermute_f32(d.n, d.perm, rank, rank_dev, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { cleanup(); return hip_fail(e, "PageRank"); }
     for (uint32_t k = 0; k < iters && time_pull; ++k) {
@@ -520,15 +558,19 @@ wedge_status wedge_frontier_translate(wedge_graph_t g, const uint32_t* frontier_
         // set the bits on the host side copy, upload, and let the compaction
         // build the list and the out-degree prefix exactly as an iteration does
         std::vector<uint64_t> fb(((uint64_t)d.n + 63) / 64, 0);
-        for (uint32_t v : ids) fb[v >> 6] |= 1ull << (v & 63);
+        for (uint32_t v : ids) {
+            if (!g->perm_host.empty()) v = g->perm_host[v];
+            fb[v >> 6] |= 1ull << (v & 63);
+        }
         HIP_TRY(hipMemcpyAsync(w.fbits, fb.data(), fb.size() * 8, hipMemcpyHostToDevice, s), "uploading frontier");
-        HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr, s), "frontier list");
+        HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr,
+                                nullptr, s), "frontier list");
         HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
         HIP_TRY(hipStreamSynchronize(s), "frontier list");
-        const uint64_t fcount = w.ctl_host->fnext >> kDegBits;
+        const uint64_t flisted = w.ctl_host->fnext >> kDegBits;
         const uint64_t active = w.ctl_host->fnext & kDegMask;
         HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
-        HIP_TRY(launch_translate(w.flist[0], w.degpre[0], (uint32_t)fcount, active, d.row_off, d.pos,
+        HIP_TRY(launch_translate(w.flist[0], w.degpre[0], (uint32_t)flisted, active, d.row_off, d.pos,
                                  lc, wbits_dev, s), "frontier translation");
     }
     // compact a copy so the caller keeps the bitmap

@@ -18,9 +18,10 @@ namespace {
 
 constexpr int kBlock = 256;           // 4 waves
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kPullRows = 4;          // rows (64 positions each) per wave in the integer pulls
+constexpr int kPullRows = 8;          // rows (64 positions each) per wave in the integer pulls
 constexpr int kTranslateEpt = 4;      // frontier out-edges per lane in the translation
 constexpr int kCompactWords = 8;      // 64-bit bitmap words per wave in the compaction
+constexpr uint32_t kPrEpilogueVerts = 8192;  // vertices per PageRank epilogue block
 
 struct GraphArgs {
     uint32_t n;
@@ -88,6 +89,28 @@ __device__ __forceinline__ T wave_sum_tree(T x) {
     return x;
 }
 
+// Largest j in [L, H] with a[j] <= key, a non-decreasing and a[L] <= key;
+// key is the same in every lane. Each step probes 64 points at once, so the
+// search takes ceil(log64(H-L+1)) dependent loads.
+__device__ __forceinline__ uint32_t wave_last_le(const uint32_t* __restrict__ a, uint32_t L,
+                                                 uint32_t H, uint64_t key, int lane) {
+    while (H - L >= 64) {
+        const uint32_t step = (H - L + 63) / 64;
+        const uint64_t probe = (uint64_t)L + (uint64_t)lane * step;
+        const bool ok = probe <= H && a[probe] <= key;
+        const int last = 63 - __clzll(__ballot(ok));
+        L = L + (uint32_t)last * step;
+        H = min(H, L + step - 1);
+    }
+    const uint64_t probe = (uint64_t)L + lane;
+    const bool ok = probe <= H && a[probe] <= key;
+    return L + (uint32_t)(63 - __clzll(__ballot(ok)));
+}
+
+__device__ __forceinline__ bool test_bit(const uint64_t* bits, uint32_t i) {
+    return (reinterpret_cast<const uint32_t*>(bits)[i >> 5] >> (i & 31)) & 1u;
+}
+
 __device__ __forceinline__ void set_bit(uint64_t* bits, uint32_t i) {
     atomicOr(reinterpret_cast<uint32_t*>(bits) + (i >> 5), 1u << (i & 31));
 }
@@ -113,34 +136,56 @@ __global__ void k_iota_u32(uint32_t* __restrict__ p, uint32_t count) {
         p[i] = i;
 }
 
-// F_0 = {src}: value 0 at the source in one or two value arrays.
+// F_0 = {src}: value 0 at the source in one or two value arrays, and the
+// source's bit in the current-frontier bitmap.
 __global__ void k_seed_source(uint32_t src, const uint32_t* __restrict__ row_off,
                               uint32_t* val_a, uint32_t* val_b, uint32_t* flist, uint32_t* degpre,
-                              Ctl* ctl) {
+                              uint64_t* fcur, Ctl* ctl) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         val_a[src] = 0;
         if (val_b) val_b[src] = 0;
         flist[0] = src;
         degpre[0] = 0;
-        ctl->fnext = (1ull << kDegBits) | (unsigned long long)(row_off[src + 1] - row_off[src]);
+        set_bit(fcur, src);
+        const unsigned long long d = row_off[src + 1] - row_off[src];
+        ctl->fnext = ((d ? 1ull : 0ull) << kDegBits) | d;
+        ctl->ftotal = 1;
         ctl->marked = 0;
     }
 }
 
-// F_0 = V with label(v) = v; the out-degree prefix of the identity list is row_off.
+// F_0 = V with label(v) = the vertex's caller id (inv maps internal ids back;
+// null = identity); the out-degree prefix of the identity list is row_off.
 __global__ void k_seed_all(uint32_t n, uint32_t m, const uint32_t* __restrict__ row_off,
-                           uint32_t* __restrict__ label, uint32_t* __restrict__ val_prev,
-                           uint32_t* __restrict__ flist, uint32_t* __restrict__ degpre, Ctl* ctl) {
+                           const uint32_t* __restrict__ inv, uint32_t* __restrict__ label,
+                           uint32_t* __restrict__ val_prev, uint32_t* __restrict__ flist,
+                           uint32_t* __restrict__ degpre, uint64_t* __restrict__ fcur, Ctl* ctl) {
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        label[v] = v;
-        val_prev[v] = v;
+        const uint32_t id = inv ? inv[v] : v;
+        label[v] = id;
+        val_prev[v] = id;
         flist[v] = v;
         degpre[v] = row_off[v];
     }
+    const uint32_t words = (n + 63) / 64;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) {
+        const uint32_t left = n - i * 64;
+        fcur[i] = left >= 64 ? ~0ull : ((1ull << left) - 1ull);
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->fnext = ((unsigned long long)n << kDegBits) | (unsigned long long)m;
+        ctl->ftotal = n;
         ctl->marked = 0;
     }
+}
+
+// out[v] = val[perm[v]]: internal order back to the caller's ids (coalesced
+// writes, gathered reads).
+template <typename T>
+__global__ void k_unpermute(uint32_t n, const uint32_t* __restrict__ perm,
+                            const T* __restrict__ val, T* __restrict__ out) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        out[v] = val[perm[v]];
 }
 
 // ------------------------------------------------- frontier transformation
@@ -173,8 +218,8 @@ __global__ __launch_bounds__(kBlock) void k_translate(const uint32_t* __restrict
         }
         return L;
     };
-    const uint32_t lo = last_le(base, 0, fcount - 1);
-    const uint32_t hi = last_le(end - 1, lo, fcount - 1);
+    const uint32_t lo = wave_last_le(degpre, 0, fcount - 1, base, lane);
+    const uint32_t hi = wave_last_le(degpre, lo, fcount - 1, end - 1, lane);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
         const uint64_t a = base + (uint64_t)i * 64 + lane;
@@ -199,50 +244,60 @@ __global__ __launch_bounds__(kBlock) void k_translate(const uint32_t* __restrict
 // ------------------------------------------------------- bitmap compaction
 //
 // Turns a bitmap into a list of its set bit indices. Each wave owns G
-// consecutive 64-bit words; lane l stands for bit l of a word, so a ballot-free
-// popcount of the word and of its lanes below gives each set bit its rank.
-// One atomicAdd per block reserves the output range. Words are cleared after
-// reading so the bitmap is all-zero for its next use.
-//   DEG:    also write the exclusive out-degree prefix of the listed vertices
-//           and count their out-degrees (the next frontier's A).
+// consecutive 64-bit words; lane l stands for bit l of a word, so a popcount
+// of the word below the lane gives each set bit its rank. One atomicAdd per
+// block reserves the output range. Words are cleared after reading so the
+// bitmap is all-zero for its next use; *total counts every set bit.
+//   DEG:    list only vertices with out-edges (the only ones the translation
+//           needs), with the exclusive out-degree prefix, and sum their
+//           out-degrees (the next frontier's A).
 //   COMMIT: also copy val[v] to val_prev[v] for every listed vertex.
+//   COPY:   also copy every word to copy_to (the next-frontier bitmap becomes
+//           the current one while it is cleared).
 // Counter layout: (count << 33) | out-degree sum.
-template <bool DEG, bool COMMIT, int G>
+template <bool DEG, bool COMMIT, bool COPY, int G>
 __global__ __launch_bounds__(kBlock) void k_bitmap_compact(
     uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
-    uint32_t* __restrict__ degpre, unsigned long long* counter, uint32_t* __restrict__ val_prev,
-    const uint32_t* __restrict__ val) {
+    uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
+    uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
+    uint64_t* __restrict__ copy_to) {
     __shared__ unsigned long long s_wave[kWavesPerBlock];
+    __shared__ unsigned long long s_all[kWavesPerBlock];
     __shared__ unsigned long long s_base;
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const uint64_t w0 = ((uint64_t)blockIdx.x * kWavesPerBlock + wid) * G;
-    uint64_t mk[G];
+    uint64_t mk[G], lm[G];
     uint32_t deg[G];
-    uint64_t cnt = 0, dsum = 0;
+    uint64_t cnt = 0, all = 0, dsum = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const uint64_t wi = w0 + g;
         mk[g] = wi < words ? bits[wi] : 0ull;
+        lm[g] = mk[g];
         deg[g] = 0;
         if (mk[g]) {
-            cnt += __popcll(mk[g]);
+            all += __popcll(mk[g]);
             if (DEG) {
                 if ((mk[g] >> lane) & 1ull) {
                     uint32_t v = (uint32_t)(wi * 64 + lane);
                     deg[g] = row_off[v + 1] - row_off[v];
                 }
+                // vertices without out-edges are counted but not listed
+                lm[g] = __ballot(deg[g] != 0);
                 dsum += wave_sum_tree(deg[g]);
             }
+            cnt += __popcll(lm[g]);
         }
     }
-    if (lane == 0) s_wave[wid] = (cnt << kDegBits) | dsum;
+    if (lane == 0) { s_wave[wid] = (cnt << kDegBits) | dsum; s_all[wid] = all; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) t += s_wave[i];
+        unsigned long long t = 0, a = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) { t += s_wave[i]; a += s_all[i]; }
         s_base = t ? atomicAdd(counter, t) : 0ull;
+        if (total && a) atomicAdd(total, a);
     }
     __syncthreads();
     unsigned long long base = s_base;
@@ -251,41 +306,47 @@ __global__ __launch_bounds__(kBlock) void k_bitmap_compact(
     uint64_t db = base & kDegMask;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        if (!mk[g]) continue;
         const uint64_t wi = w0 + g;
-        const bool act = (mk[g] >> lane) & 1ull;
-        const uint32_t rank = (uint32_t)__popcll(mk[g] & mask_lt(lane));
+        if (COPY && lane == 0 && wi < words) copy_to[wi] = mk[g];
+        if (!mk[g]) continue;
+        const uint32_t v = (uint32_t)(wi * 64 + lane);
+        if (COMMIT && ((mk[g] >> lane) & 1ull) && v < limit) val_prev[v] = val[v];
+        if (lane == 0) bits[wi] = 0ull;
+        if (!lm[g]) continue;
+        const bool act = (lm[g] >> lane) & 1ull;
+        const uint32_t rank = (uint32_t)__popcll(lm[g] & mask_lt(lane));
         uint32_t dex = 0, dtot = 0;
         if (DEG) {
             uint32_t inc = wave_incl_scan(deg[g], lane);
             dex = inc - deg[g];
             dtot = __shfl(inc, 63, 64);
         }
-        if (act) {
-            uint32_t v = (uint32_t)(wi * 64 + lane);
-            if (v < limit) {
-                list[cb + rank] = v;
-                if (DEG) degpre[cb + rank] = (uint32_t)(db + dex);
-                if (COMMIT) val_prev[v] = val[v];
-            }
+        if (act && v < limit) {
+            list[cb + rank] = v;
+            if (DEG) degpre[cb + rank] = (uint32_t)(db + dex);
         }
-        cb += (uint32_t)__popcll(mk[g]);
+        cb += (uint32_t)__popcll(lm[g]);
         db += dtot;
-        if (lane == 0) bits[wi] = 0ull;
     }
 }
 
 // ------------------------------------------------------------- the pulls
 //
 // One lane per in-edge position. A lane reads its destination from the row
-// layout, its source from the streamed in-edge array, and forms the candidate
-// value the edge carries; lanes of one destination are reduced in the wave
-// (min), and the segment head applies the result:
+// layout and its source from the streamed in-edge array, and forms the
+// candidate value the edge carries. Lanes of one destination are reduced in
+// the wave (min), and the segment head applies the result:
 //   BFS  : destinations already visited are skipped before their in-edges are
 //          read (Evaluation, no-frontier BFS iterations get cheaper); an
-//          unvisited destination with an in-neighbour at level k gets k+1.
+//          unvisited destination with an in-neighbour in the current frontier
+//          (a bit test in the 1-bit-per-vertex frontier, the check a pull
+//          engine makes after reading an edge; Background, Push vs. Pull) gets
+//          k+1.
 //   CC   : candidate = label_prev[u].
 //   SSSP : candidate = dist_prev[u] + w (u reached).
+// CC and SSSP gather the source value without a frontier test: the value is
+// one random read either way, and an edge from outside the frontier cannot
+// lower its destination (below).
 // An improvement lowers val[v] with atomicMin (a destination can span several
 // chunks and waves) and sets v's bit in the next-frontier bitmap. Values are
 // read from val_prev, the copy committed at the end of the previous
@@ -299,6 +360,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                                            const bool (&valid)[R], uint32_t iter,
                                            uint32_t* __restrict__ val,
                                            const uint32_t* __restrict__ val_prev,
+                                           const uint64_t* __restrict__ fcur,
                                            uint64_t* __restrict__ fbits) {
     const int lane = lane_id();
     uint32_t dst[R];
@@ -314,7 +376,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
         for (int i = 0; i < R; ++i) u[i] = need[i] ? ld_stream(g.in_src + p[i]) : 0u;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const bool found = need[i] && val[u[i]] == iter;
+            const bool found = need[i] && test_bit(fcur, u[i]);
             const uint32_t prev = __shfl_up(dst[i], 1, 64);
             const bool head = lane == 0 || prev != dst[i];
             const uint64_t heads = __ballot(head);
@@ -362,6 +424,7 @@ template <int APP, int R>
 __global__ __launch_bounds__(kBlock) void k_pull_full(GraphArgs g, uint32_t iter,
                                                       uint32_t* __restrict__ val,
                                                       const uint32_t* __restrict__ val_prev,
+                                                      const uint64_t* __restrict__ fcur,
                                                       uint64_t* __restrict__ fbits) {
     const int lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -375,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_full(GraphArgs g, uint32_t iter
         valid[i] = pp < g.m;
         p[i] = (uint32_t)pp;
     }
-    pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fbits);
+    pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fcur, fbits);
 }
 
 // Pull over the marked chunks: the chunk list holds K = *marked chunk ids of
@@ -388,6 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_chunks(GraphArgs g, uint32_t it
                                                         const unsigned long long* marked,
                                                         uint32_t* __restrict__ val,
                                                         const uint32_t* __restrict__ val_prev,
+                                                        const uint64_t* __restrict__ fcur,
                                                         uint64_t* __restrict__ fbits) {
     const int lane = lane_id();
     const uint64_t K = *marked >> kDegBits;
@@ -413,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_chunks(GraphArgs g, uint32_t it
             valid[i] = pp < g.m;
             p[i] = (uint32_t)pp;
         }
-        pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fbits);
+        pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fcur, fbits);
     }
 }
 
@@ -493,12 +557,46 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull(GraphArgs g, const float* __
 }
 
 // S(v) = tail[first tile] + sum of head[t] over the later tiles v covers.
-__global__ __launch_bounds__(kBlock) void k_pr_fixup(const uint32_t* __restrict__ spans,
-                                                     uint64_t nspans,
-                                                     const float* __restrict__ head_part,
-                                                     const float* __restrict__ tail_part,
-                                                     float* __restrict__ sum) {
+// Short spans: one lane each, summed in tile order.
+__global__ __launch_bounds__(kBlock) void k_pr_fixup_short(const uint32_t* __restrict__ spans,
+                                                           uint64_t nspans,
+                                                           const float* __restrict__ head_part,
+                                                           const float* __restrict__ tail_part,
+                                                           float* __restrict__ sum) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nspans) return;
+    const uint32_t v = spans[3 * e], ta = spans[3 * e + 1], tb = spans[3 * e + 2];
+    float acc = tail_part[ta];
+    for (uint32_t t = ta + 1; t <= tb; ++t) acc += head_part[t];
+    sum[v] = acc;
+}
+
+// Long spans: one wave each, lane-strided partial sums then a fixed tree.
+// The grid's last block instead reduces the dangling-mass partials of the
+// previous epilogue into *dnext, in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_pr_fixup_long(const uint32_t* __restrict__ spans,
+                                                          uint64_t nspans,
+                                                          const float* __restrict__ head_part,
+                                                          const float* __restrict__ tail_part,
+                                                          float* __restrict__ sum,
+                                                          const double* __restrict__ partials,
+                                                          uint32_t parts, double* __restrict__ dnext) {
     const int lane = lane_id();
+    if (blockIdx.x == gridDim.x - 1) {
+        __shared__ double s_part[kWavesPerBlock];
+        if (!dnext) return;
+        double acc = 0.0;
+        for (uint32_t i = threadIdx.x; i < parts; i += blockDim.x) acc += partials[i];
+        acc = wave_sum_tree(acc);
+        if (lane == 0) s_part[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < kWavesPerBlock; ++i) t += s_part[i];
+            *dnext = t;
+        }
+        return;
+    }
     const uint64_t e = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (e >= nspans) return;
     const uint32_t v = spans[3 * e], ta = spans[3 * e + 1], tb = spans[3 * e + 2];
@@ -524,8 +622,10 @@ __global__ void k_set_f64(double* p, double v) {
 }
 
 // r'(v) = (1-d)/n + d (S(v) + D/n); contrib'(v) = r'/outdeg; per-block sum of
-// the new rank mass on out-degree-0 vertices (the next D), in FP64.
-__global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n,
+// the new rank mass on out-degree-0 vertices (the next D), in FP64. Each block
+// covers a fixed contiguous vertex range, so the partials (and their order)
+// do not depend on timing.
+__global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n, uint32_t per_block,
                                                         const uint32_t* __restrict__ row_off,
                                                         const float* __restrict__ sum, double d,
                                                         const double* __restrict__ dcur,
@@ -533,16 +633,17 @@ __global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n,
                                                         float* __restrict__ contrib,
                                                         double* __restrict__ partials) {
     __shared__ double s_part[kWavesPerBlock];
-    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     const double dn = *dcur / (double)n;
     const double base = (1.0 - d) / (double)n;
+    const uint32_t lo = blockIdx.x * per_block;
+    const uint32_t hi = min(n, lo + per_block);
     double acc = 0.0;
-    if (v < n) {
+    for (uint32_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
         const float r = (float)(base + d * ((double)sum[v] + dn));
         const uint32_t od = row_off[v + 1] - row_off[v];
         rank[v] = r;
         contrib[v] = od ? r / (float)od : 0.0f;
-        if (!od) acc = (double)r;
+        if (!od) acc += (double)r;
     }
     acc = wave_sum_tree(acc);
     if (lane_id() == 0) s_part[threadIdx.x >> 6] = acc;
@@ -551,22 +652,6 @@ __global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n,
         double t = 0.0;
         for (int i = 0; i < kWavesPerBlock; ++i) t += s_part[i];
         partials[blockIdx.x] = t;
-    }
-}
-
-// D_next = sum of the per-block partials, in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_pr_dsum(const double* __restrict__ partials,
-                                                    uint32_t parts, double* __restrict__ dnext) {
-    __shared__ double s_part[kWavesPerBlock];
-    double acc = 0.0;
-    for (uint32_t i = threadIdx.x; i < parts; i += blockDim.x) acc += partials[i];
-    acc = wave_sum_tree(acc);
-    if (lane_id() == 0) s_part[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kWavesPerBlock; ++i) t += s_part[i];
-        *dnext = t;
     }
 }
 
@@ -593,17 +678,31 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s) {
 }
 
 hipError_t launch_seed_source(uint32_t src, const uint32_t* row_off, uint32_t* val_a,
-                              uint32_t* val_b, uint32_t* flist, uint32_t* degpre, Ctl* ctl,
-                              hipStream_t s) {
-    k_seed_source<<<1, 64, 0, s>>>(src, row_off, val_a, val_b, flist, degpre, ctl);
+                              uint32_t* val_b, uint32_t* flist, uint32_t* degpre, uint64_t* fcur,
+                              Ctl* ctl, hipStream_t s) {
+    k_seed_source<<<1, 64, 0, s>>>(src, row_off, val_a, val_b, flist, degpre, fcur, ctl);
     return hipGetLastError();
 }
 
-hipError_t launch_seed_all(uint32_t n, uint64_t m, const uint32_t* row_off, uint32_t* label,
-                           uint32_t* val_prev, uint32_t* flist, uint32_t* degpre, Ctl* ctl,
-                           hipStream_t s) {
-    k_seed_all<<<grid_for(n, 8192), kBlock, 0, s>>>(n, (uint32_t)m, row_off, label, val_prev,
-                                                    flist, degpre, ctl);
+hipError_t launch_seed_all(uint32_t n, uint64_t m, const uint32_t* row_off, const uint32_t* inv,
+                           uint32_t* label, uint32_t* val_prev, uint32_t* flist, uint32_t* degpre,
+                           uint64_t* fcur, Ctl* ctl, hipStream_t s) {
+    k_seed_all<<<grid_for(n, 8192), kBlock, 0, s>>>(n, (uint32_t)m, row_off, inv, label, val_prev,
+                                                    flist, degpre, fcur, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute_u32(uint32_t n, const uint32_t* perm, const uint32_t* val,
+                                uint32_t* out, hipStream_t s) {
+    if (!n) return hipSuccess;
+    k_unpermute<uint32_t><<<grid_for(n, 16384), kBlock, 0, s>>>(n, perm, val, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute_f32(uint32_t n, const uint32_t* perm, const float* val, float* out,
+                                hipStream_t s) {
+    if (!n) return hipSuccess;
+    k_unpermute<float><<<grid_for(n, 16384), kBlock, 0, s>>>(n, perm, val, out);
     return hipGetLastError();
 }
 
@@ -619,56 +718,57 @@ hipError_t launch_translate(const uint32_t* flist, const uint32_t* degpre, uint3
     return hipGetLastError();
 }
 
-static hipError_t launch_compact(uint64_t* bits, uint64_t words, uint32_t limit,
-                                 const uint32_t* row_off, uint32_t* list, uint32_t* degpre,
-                                 unsigned long long* counter, uint32_t* val_prev,
-                                 const uint32_t* val, bool deg, bool commit, hipStream_t s) {
+hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list, Ctl* ctl,
+                                 hipStream_t s) {
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (!deg)
-        k_bitmap_compact<false, false, kCompactWords><<<blocks, kBlock, 0, s>>>(
-            bits, words, limit, row_off, list, degpre, counter, val_prev, val);
-    else if (!commit)
-        k_bitmap_compact<true, false, kCompactWords><<<blocks, kBlock, 0, s>>>(
-            bits, words, limit, row_off, list, degpre, counter, val_prev, val);
-    else
-        k_bitmap_compact<true, true, kCompactWords><<<blocks, kBlock, 0, s>>>(
-            bits, words, limit, row_off, list, degpre, counter, val_prev, val);
+    k_bitmap_compact<false, false, false, kCompactWords><<<blocks, kBlock, 0, s>>>(
+        wbits, words, 0xFFFFFFFFu, nullptr, list, nullptr, &ctl->marked, nullptr, nullptr, nullptr,
+        nullptr);
     return hipGetLastError();
-}
-
-hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list, Ctl* ctl,
-                                 hipStream_t s) {
-    return launch_compact(wbits, words, 0xFFFFFFFFu, nullptr, list, nullptr, &ctl->marked,
-                          nullptr, nullptr, false, false, s);
 }
 
 hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
                            uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
-                           hipStream_t s) {
-    return launch_compact(fbits, ((uint64_t)n + 63) / 64, n, row_off, flist, degpre, &ctl->fnext,
-                          val_prev, val, true, val_prev != nullptr, s);
+                           uint64_t* fcur, hipStream_t s) {
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    if (!words) return hipSuccess;
+    const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    unsigned long long* c = &ctl->fnext;
+    unsigned long long* t = &ctl->ftotal;
+    if (val_prev && fcur)
+        k_bitmap_compact<true, true, true, kCompactWords><<<blocks, kBlock, 0, s>>>(
+            fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur);
+    else if (fcur)
+        k_bitmap_compact<true, false, true, kCompactWords><<<blocks, kBlock, 0, s>>>(
+            fbits, words, n, row_off, flist, degpre, c, t, nullptr, nullptr, fcur);
+    else
+        k_bitmap_compact<true, false, false, kCompactWords><<<blocks, kBlock, 0, s>>>(
+            fbits, words, n, row_off, flist, degpre, c, t, nullptr, nullptr, nullptr);
+    return hipGetLastError();
 }
 
 hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
-                            const uint32_t* val_prev, uint64_t* fbits, hipStream_t s) {
+                            const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
+                            hipStream_t s) {
     if (!g.rows) return hipSuccess;
     const uint64_t waves = (g.rows + kPullRows - 1) / kPullRows;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     GraphArgs a = args_of(g);
     switch (app) {
-        case kBfs: k_pull_full<kBfs, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fbits); break;
-        case kCc: k_pull_full<kCc, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fbits); break;
-        default: k_pull_full<kSssp, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fbits); break;
+        case kBfs: k_pull_full<kBfs, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
+        case kCc: k_pull_full<kCc, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
+        default: k_pull_full<kSssp, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
                               const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
-                              uint32_t* val, const uint32_t* val_prev, uint64_t* fbits,
-                              hipStream_t s) {
+                              uint32_t* val, const uint32_t* val_prev, const uint64_t* fcur,
+                              uint64_t* fbits, hipStream_t s) {
     if (!max_chunks) return hipSuccess;
     const uint64_t slots = log_chunk <= 6
                                ? (max_chunks + (64u >> log_chunk) - 1) / (64u >> log_chunk)
@@ -680,9 +780,9 @@ hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log
     GraphArgs a = args_of(g);
     const unsigned long long* mk = &ctl->marked;
     switch (app) {
-        case kBfs: k_pull_chunks<kBfs, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fbits); break;
-        case kCc: k_pull_chunks<kCc, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fbits); break;
-        default: k_pull_chunks<kSssp, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fbits); break;
+        case kBfs: k_pull_chunks<kBfs, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits); break;
+        case kCc: k_pull_chunks<kCc, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits); break;
+        default: k_pull_chunks<kSssp, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits); break;
     }
     return hipGetLastError();
 }
@@ -704,24 +804,30 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
 }
 
 hipError_t launch_pr_fixup(const DevGraph& g, const float* head, const float* tail, float* sum,
-                           hipStream_t s) {
-    if (!g.nspans) return hipSuccess;
-    const uint32_t blocks = (uint32_t)((g.nspans + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_pr_fixup<<<blocks, kBlock, 0, s>>>(g.spans, g.nspans, head, tail, sum);
+                           const double* partials, uint32_t parts, double* d_next, hipStream_t s) {
+    const uint64_t ns = g.short_spans, nl = g.nspans - g.short_spans;
+    if (ns) {
+        k_pr_fixup_short<<<(uint32_t)((ns + kBlock - 1) / kBlock), kBlock, 0, s>>>(g.spans, ns, head, tail, sum);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const uint32_t blocks = (uint32_t)((nl + kWavesPerBlock - 1) / kWavesPerBlock) + 1;
+    k_pr_fixup_long<<<blocks, kBlock, 0, s>>>(g.spans + 3 * ns, nl, head, tail, sum, partials, parts,
+                                              d_next);
     return hipGetLastError();
 }
 
-uint32_t pr_epilogue_blocks(uint32_t n) { return (n + kBlock - 1) / kBlock; }
+uint32_t pr_epilogue_blocks(uint32_t n) {
+    uint32_t b = (n + kPrEpilogueVerts - 1) / kPrEpilogueVerts;
+    return b ? b : 1;
+}
 
 hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* sum,
                               double damping, const double* d_cur, float* rank, float* contrib,
-                              double* partials, uint32_t parts, double* d_next, hipStream_t s) {
+                              double* partials, uint32_t parts, hipStream_t s) {
     if (!n) return hipSuccess;
-    k_pr_epilogue<<<parts, kBlock, 0, s>>>(n, row_off, sum, damping, d_cur, rank, contrib,
-                                           partials);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_pr_dsum<<<1, kBlock, 0, s>>>(partials, parts, d_next);
+    k_pr_epilogue<<<parts, kBlock, 0, s>>>(n, kPrEpilogueVerts, row_off, sum, damping, d_cur, rank,
+                                           contrib, partials);
     return hipGetLastError();
 }
 

@@ -124,11 +124,53 @@ void symmetrize_csr(uint32_t n, const uint64_t* row_off, const uint32_t* col,
     });
 }
 
+
+// Relabel a CSR so that internal vertex i is the i-th vertex in order of
+// decreasing out-degree (ties by id): inv[i] = original id, perm[orig] = i.
+// Rows of the result list internal neighbour ids in ascending order (parallel
+// edges keep their input order); weights follow their edges.
+void relabel_csr(uint32_t n, const uint64_t* row_off, const uint32_t* col, const uint32_t* w,
+                 std::vector<uint32_t>* perm, std::vector<uint32_t>* inv,
+                 std::vector<uint64_t>* nro, std::vector<uint32_t>* ncol,
+                 std::vector<uint32_t>* nw) {
+    uint64_t maxdeg = 0;
+    for (uint32_t u = 0; u < n; ++u) maxdeg = std::max<uint64_t>(maxdeg, row_off[u + 1] - row_off[u]);
+    // counting sort by degree (descending), stable in id
+    std::vector<uint64_t> bucket(maxdeg + 2, 0);
+    for (uint32_t u = 0; u < n; ++u) bucket[maxdeg - (row_off[u + 1] - row_off[u]) + 1]++;
+    for (uint64_t d = 0; d <= maxdeg; ++d) bucket[d + 1] += bucket[d];
+    inv->resize(n);
+    perm->resize(n);
+    for (uint32_t u = 0; u < n; ++u) (*inv)[bucket[maxdeg - (row_off[u + 1] - row_off[u])]++] = u;
+    for (uint32_t i = 0; i < n; ++i) (*perm)[(*inv)[i]] = i;
+    nro->assign((size_t)n + 1, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t u = (*inv)[i];
+        (*nro)[i + 1] = (*nro)[i] + (row_off[u + 1] - row_off[u]);
+    }
+    const uint64_t m = (*nro)[n];
+    ncol->resize(m ? m : 1);
+    if (nw) nw->resize(m ? m : 1);
+    const std::vector<uint32_t>& P = *perm;
+    parallel_dynamic(n, 1024, [&](uint64_t i) {
+        const uint32_t u = (*inv)[i];
+        const uint64_t b = row_off[u], d = row_off[u + 1] - b, o = (*nro)[i];
+        if (!d) return;
+        std::vector<uint64_t> key(d);
+        for (uint64_t j = 0; j < d; ++j) key[j] = ((uint64_t)P[col[b + j]] << 32) | j;
+        std::sort(key.begin(), key.end());
+        for (uint64_t j = 0; j < d; ++j) {
+            (*ncol)[o + j] = (uint32_t)(key[j] >> 32);
+            if (nw) (*nw)[o + j] = w[b + (uint32_t)key[j]];
+        }
+    });
+}
+
 }  // namespace
 
 wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_off_in,
                                    const uint32_t* col_in, const uint32_t* w, bool symmetrize,
-                                   HostLayout* L, std::string* err) {
+                                   bool relabel, HostLayout* L, std::string* err) {
     wedge_status st = check_offsets(n, m, row_off_in, col_in, err);
     if (st != WEDGE_OK) return st;
     std::vector<uint64_t> sro;
@@ -142,6 +184,17 @@ wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_o
         col = scol.data();
         m = sro[n];
         if (m >= (1ull << 32)) { *err = "undirected view has >= 2^32 edges"; return WEDGE_ERR_BAD_GRAPH; }
+    }
+    // --- internal vertex order: out-degree descending (ties by id), so the
+    // values most often gathered by the pull (sources with many out-edges)
+    // share cache lines; the ABI keeps the caller's ids (perm maps them).
+    std::vector<uint64_t> rro;
+    std::vector<uint32_t> rcol, rw;
+    if (relabel && n) {
+        relabel_csr(n, row_off, col, w, &L->perm, &L->inv, &rro, &rcol, w ? &rw : nullptr);
+        row_off = rro.data();
+        col = rcol.data();
+        if (w) w = rw.data();
     }
     L->n = n;
     L->m = m;
@@ -220,24 +273,29 @@ wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_o
         }
     }
 
-    // --- PageRank tile spans
+    // --- PageRank tile spans (short ones first, then those over more than
+    // kPrShortSpan tiles; each group ordered by vertex)
     L->spans.clear();
+    std::vector<uint32_t> longs;
     const uint64_t T = 64ull * kPrTileRows;
     for (uint64_t t = 0; t < S; ++t) {
         uint32_t v = L->nzdst[t];
         uint64_t a = L->col_off[v], b = (uint64_t)L->col_off[v + 1] - 1;
         if (a / T != b / T) {
-            L->spans.push_back(v);
-            L->spans.push_back((uint32_t)(a / T));
-            L->spans.push_back((uint32_t)(b / T));
+            std::vector<uint32_t>& dst = (b / T - a / T <= kPrShortSpan) ? L->spans : longs;
+            dst.push_back(v);
+            dst.push_back((uint32_t)(a / T));
+            dst.push_back((uint32_t)(b / T));
         }
     }
+    L->short_spans = L->spans.size() / 3;
+    L->spans.insert(L->spans.end(), longs.begin(), longs.end());
     return WEDGE_OK;
 }
 
 wedge_status build_layout_from_csc(uint32_t n, uint64_t m, const uint64_t* col_off,
                                    const uint32_t* src, const uint32_t* w, bool symmetrize,
-                                   HostLayout* L, std::string* err) {
+                                   bool relabel, HostLayout* L, std::string* err) {
     wedge_status st = check_offsets(n, m, col_off, src, err);
     if (st != WEDGE_OK) return st;
     // transpose to CSR (stable: destinations ascend within each source's row)
@@ -254,7 +312,7 @@ wedge_status build_layout_from_csc(uint32_t n, uint64_t m, const uint64_t* col_o
             if (w) cw[q] = w[p];
         }
     return build_layout_from_csr(n, m, row_off.data(), col.data(), w ? cw.data() : nullptr,
-                                 symmetrize, L, err);
+                                 symmetrize, relabel, L, err);
 }
 
 }  // namespace wedge

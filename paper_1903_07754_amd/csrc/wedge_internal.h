@@ -18,6 +18,7 @@ namespace wedge {
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kWave = 64;
 constexpr uint32_t kPrTileRows = 8;  // PageRank pull tile: 8 rows of 64 in-edge positions
+constexpr uint32_t kPrShortSpan = 8; // spans over at most this many extra tiles are fixed up per lane
 
 enum App : int { kBfs = 1, kCc = 2, kSssp = 3 };
 
@@ -34,7 +35,10 @@ struct HostLayout {
     std::vector<uint64_t> rowmask;   // rows
     std::vector<uint32_t> rowseg;    // rows
     std::vector<uint32_t> nzdst;     // nonempty
-    std::vector<uint32_t> spans;     // 3 * pr_spans (v, first tile, last tile)
+    std::vector<uint32_t> spans;     // 3 * pr_spans (v, first tile, last tile); short ones first
+    uint64_t short_spans = 0;
+    std::vector<uint32_t> perm;      // original id -> internal id (empty: identity)
+    std::vector<uint32_t> inv;       // internal id -> original id
     uint32_t dangling = 0;
     uint32_t max_w = 0;
 };
@@ -43,10 +47,10 @@ struct HostLayout {
 // (grouped by destination). Returns WEDGE_OK or an error with *err set.
 wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_off,
                                    const uint32_t* col, const uint32_t* w, bool symmetrize,
-                                   HostLayout* out, std::string* err);
+                                   bool relabel, HostLayout* out, std::string* err);
 wedge_status build_layout_from_csc(uint32_t n, uint64_t m, const uint64_t* col_off,
                                    const uint32_t* src, const uint32_t* w, bool symmetrize,
-                                   HostLayout* out, std::string* err);
+                                   bool relabel, HostLayout* out, std::string* err);
 
 // ------------------------------------------------------- device structures
 struct DevGraph {
@@ -55,6 +59,7 @@ struct DevGraph {
     uint64_t rows = 0;
     uint32_t nonempty = 0;
     uint64_t nspans = 0;
+    uint64_t short_spans = 0;
     uint32_t* col_off = nullptr;
     uint32_t* in_src = nullptr;
     uint32_t* in_w = nullptr;
@@ -64,13 +69,16 @@ struct DevGraph {
     uint32_t* rowseg = nullptr;
     uint32_t* nzdst = nullptr;
     uint32_t* spans = nullptr;
+    uint32_t* perm = nullptr;  // original -> internal (null: identity)
+    uint32_t* inv = nullptr;   // internal -> original (null: identity)
 };
 
 // Iteration counters written by the kernels and read back by the host.
 struct Ctl {
-    unsigned long long fnext;  // (count << 33) | out-degree sum of the next frontier
-    unsigned long long marked; // chunks appended to the chunk list
-    unsigned long long pad[6];
+    unsigned long long fnext;  // (listed count << 33) | out-degree sum of the next frontier
+    unsigned long long marked; // (chunks appended to the chunk list) << 33
+    unsigned long long ftotal; // next-frontier size, including vertices without out-edges
+    unsigned long long pad[5];
 };
 
 constexpr int kDegBits = 33;
@@ -80,6 +88,8 @@ struct Workspace {
     uint32_t n = 0;
     uint64_t m = 0;
     uint64_t* fbits = nullptr;     // ceil(n/64) words: next-frontier bitmap (kept all-zero between uses)
+    uint64_t* fcur = nullptr;      // ceil(n/64) words: current-frontier bitmap
+    uint32_t* val = nullptr;       // n: values in internal order (relabelled graphs)
     uint32_t* flist[2] = {nullptr, nullptr};
     uint32_t* degpre[2] = {nullptr, nullptr};
     uint32_t* val_prev = nullptr;  // n
@@ -92,6 +102,7 @@ struct Workspace {
     // PageRank
     float* pr_sum = nullptr;       // n
     float* pr_contrib = nullptr;   // n
+    float* pr_rank = nullptr;      // n: ranks in internal order (relabelled graphs)
     float* pr_head = nullptr;      // tiles
     float* pr_tail = nullptr;      // tiles
     double* pr_part = nullptr;     // per-block dangling partials
@@ -110,6 +121,7 @@ struct wedge_graph_s {
     uint32_t dangling = 0;
     uint32_t max_w = 0;
     wedge::HostLayout host;        // kept only for WEDGE_HOST_ONLY graphs
+    std::vector<uint32_t> perm_host;  // original -> internal id (empty: identity)
     wedge::DevGraph dev;
     wedge::Workspace ws;
     uint64_t device_bytes = 0;
@@ -124,35 +136,46 @@ namespace wedge {
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
 hipError_t launch_seed_source(uint32_t src, const uint32_t* row_off, uint32_t* val_a,
-                              uint32_t* val_b, uint32_t* flist, uint32_t* degpre, Ctl* ctl,
-                              hipStream_t s);
-hipError_t launch_seed_all(uint32_t n, uint64_t m, const uint32_t* row_off, uint32_t* label,
-                           uint32_t* val_prev, uint32_t* flist, uint32_t* degpre, Ctl* ctl,
-                           hipStream_t s);
+                              uint32_t* val_b, uint32_t* flist, uint32_t* degpre, uint64_t* fcur,
+                              Ctl* ctl, hipStream_t s);
+hipError_t launch_seed_all(uint32_t n, uint64_t m, const uint32_t* row_off, const uint32_t* inv,
+                           uint32_t* label, uint32_t* val_prev, uint32_t* flist, uint32_t* degpre,
+                           uint64_t* fcur, Ctl* ctl, hipStream_t s);
+hipError_t launch_unpermute_u32(uint32_t n, const uint32_t* perm, const uint32_t* val,
+                                uint32_t* out, hipStream_t s);
+hipError_t launch_unpermute_f32(uint32_t n, const uint32_t* perm, const float* val, float* out,
+                                hipStream_t s);
+hipError_t launch_set_f64(double* p, double v, hipStream_t s);
 hipError_t launch_translate(const uint32_t* flist, const uint32_t* degpre, uint32_t fcount,
                             uint64_t active, const uint32_t* row_off, const uint32_t* pos,
                             int log_chunk, uint64_t* wbits, hipStream_t s);
 hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list, Ctl* ctl,
                                  hipStream_t s);
 hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
-                            const uint32_t* val_prev, uint64_t* fbits, hipStream_t s);
+                            const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
+                            hipStream_t s);
 hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
                               const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
-                              uint32_t* val, const uint32_t* val_prev, uint64_t* fbits,
-                              hipStream_t s);
+                              uint32_t* val, const uint32_t* val_prev, const uint64_t* fcur,
+                              uint64_t* fbits, hipStream_t s);
+// Lists the next-frontier bitmap (with out-degree prefix), commits val to
+// val_prev for listed vertices (when val_prev is set), moves the bitmap into
+// fcur (when set) and clears it.
 hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
                            uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
-                           hipStream_t s);
+                           uint64_t* fcur, hipStream_t s);
 // PageRank
 hipError_t launch_pr_init(uint32_t n, const uint32_t* row_off, float* rank, float* contrib,
                           float* sum, hipStream_t s);
 hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, float* head,
                           float* tail, hipStream_t s);
+// Completes S for destinations crossing tile boundaries, and reduces the
+// previous epilogue's dangling partials into *d_next (when d_next is set).
 hipError_t launch_pr_fixup(const DevGraph& g, const float* head, const float* tail, float* sum,
-                           hipStream_t s);
+                           const double* partials, uint32_t parts, double* d_next, hipStream_t s);
 hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* sum,
                               double damping, const double* d_cur, float* rank, float* contrib,
-                              double* partials, uint32_t parts, double* d_next, hipStream_t s);
+                              double* partials, uint32_t parts, hipStream_t s);
 uint32_t pr_epilogue_blocks(uint32_t n);
 
 }  // namespace wedge

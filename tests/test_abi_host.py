@@ -10,6 +10,7 @@ import gen
 import oracle
 import paper_1903_07754_amd as W
 from paper_1903_07754_amd import _binding as B
+from helpers import relabel
 
 
 def test_library_exports_every_header_function():
@@ -21,8 +22,28 @@ def test_library_exports_every_header_function():
     assert W.lib().wedge_status_string(-4) == b"out of memory"
 
 
-def host_graph(ro, col, w=None, symmetrize=False):
-    return W.Graph.from_csr(ro, col, w, symmetrize=symmetrize, host_only=True)
+def host_graph(ro, col, w=None, symmetrize=False, keep_ids=True):
+    return W.Graph.from_csr(ro, col, w, symmetrize=symmetrize, host_only=True, keep_ids=keep_ids)
+
+
+@pytest.mark.parametrize("seed,scale", [(1, 9), (2, 11)])
+def test_relabelled_layout_is_degree_order(seed, scale):
+    """Default layout: internal id = rank by decreasing out-degree (ties by id), and
+    every array is the canonical layout of the renamed graph."""
+    ro, col = gen.rmat(scale, 16, seed=seed)
+    w = gen.edge_weights(ro, col, seed=seed)
+    g = host_graph(ro, col, w, keep_ids=False)
+    assert g.info["relabeled"] == 1
+    perm = g.layout("perm")
+    n = len(ro) - 1
+    deg = np.diff(ro.astype(np.int64))
+    want_inv = np.lexsort((np.arange(n), -deg))
+    np.testing.assert_array_equal(np.argsort(perm), want_inv)
+    rro, rcol, rw = relabel(ro, col, perm, w)
+    ref = host_graph(rro, rcol, rw, keep_ids=True)
+    for name in ("col_off", "in_src", "in_w", "row_off", "pos", "rowmask", "rowseg", "nzdst",
+                 "pr_spans"):
+        np.testing.assert_array_equal(g.layout(name), ref.layout(name))
 
 
 @pytest.mark.parametrize("seed,scale", [(1, 8), (2, 10), (3, 12)])
@@ -67,7 +88,6 @@ def test_row_layout_names_every_position_destination(seed, scale):
     # destination = nz[seg[row] + number of segment starts in (row start, p]]
     cum = np.cumsum(starts)
     row_first = r * 64
-    cnt = cum - cum[row_first] + starts[row_first] * 0
     got = nz[seg[r] + (cum - cum[row_first])]
     assert np.array_equal(got, dst_of_pos)
     assert g.info["rows"] == (m + 63) // 64
@@ -80,12 +100,13 @@ def test_pagerank_tile_spans():
     co, _, _ = oracle.csc(ro, col)
     T = g.info["pr_tile_edges"]
     sp = g.layout("pr_spans").reshape(-1, 3).astype(np.int64)
-    want = []
+    short, long_ = [], []
     for v in range(len(ro) - 1):
         a, b = int(co[v]), int(co[v + 1]) - 1
         if b >= a and a // T != b // T:
-            want.append((v, a // T, b // T))
-    assert [tuple(x) for x in sp] == want
+            (short if b // T - a // T <= 8 else long_).append((v, a // T, b // T))
+    assert [tuple(x) for x in sp] == short + long_
+    assert g.info["pr_short_spans"] == len(short)
 
 
 def test_symmetrized_layout_is_oracle_undirected_view():
@@ -102,9 +123,10 @@ def test_from_csc_equals_from_csr():
     ro, col = gen.rmat(9, 16, seed=7)
     w = gen.edge_weights(ro, col, seed=3)
     co, src, iw = oracle.csc(ro, col, w)
-    a = host_graph(ro, col, w)
+    a = host_graph(ro, col, w, keep_ids=False)
     b = W.Graph.from_csc(co, src, iw, host_only=True)
-    for name in ("col_off", "in_src", "in_w", "row_off", "pos", "rowmask", "rowseg", "nzdst"):
+    for name in ("col_off", "in_src", "in_w", "row_off", "pos", "rowmask", "rowseg", "nzdst",
+                 "perm"):
         np.testing.assert_array_equal(a.layout(name), b.layout(name))
 
 

@@ -10,6 +10,7 @@ import pytest
 
 import gen
 import oracle
+from helpers import relabel
 
 pytestmark = pytest.mark.gpu
 
@@ -35,33 +36,53 @@ def run_app(app, g, src, **kw):
     return W.u32(out), st, tr
 
 
-def check_trace(tr, ref, chunk):
+def internal_marked(g, gro, gcol, frontiers, chunk):
+    """Wedge Frontier sizes of the oracle's frontiers, on the library's internal
+    vertex order (the canonical in-edge array of the renamed graph)."""
+    n = len(gro) - 1
+    perm = g.layout("perm") if g.info["relabeled"] else np.arange(n, dtype=np.uint32)
+    rro, rcol, _ = relabel(gro, gcol, perm)
+    _, isrc, _ = oracle.csc(rro, rcol)
+    out = []
+    for fr in frontiers:
+        fi = np.empty(n, np.uint8)
+        fi[perm] = fr
+        out.append(oracle.wedge_frontier(isrc, fi, chunk)[1])
+    return out
+
+
+def check_trace(tr, ref, chunk, K):
     assert len(tr) == ref.iters
     for k, r in enumerate(tr):
         assert r["frontier"] == ref.F[k], k
         assert r["active_edges"] == ref.A[k], k
         if r["mode"] == 1:
             assert r["chunk_edges"] == chunk
-            assert r["marked_chunks"] == ref.K[k], k
+            assert r["marked_chunks"] == K[k], k
 
 
-def parity(app, ro, col, w=None, src=0, gate="threshold", theta=None, chunk=None):
+def parity(app, ro, col, w=None, src=0, gate="threshold", theta=None, chunk=None, keep_ids=False):
     theta = THETA[app] if theta is None else theta
     chunk = CHUNK[app] if chunk is None else chunk
     if app == "cc":
-        sro, scol = oracle.symmetrize(ro, col)
-        g = W.Graph.from_csr(ro, col, symmetrize=True)
-        ref = oracle.pull_engine("cc", sro, scol, theta_ppm=theta, chunk=chunk)
+        gro, gcol = oracle.symmetrize(ro, col)
+        g = W.Graph.from_csr(ro, col, symmetrize=True, keep_ids=keep_ids)
+        ref = oracle.pull_engine("cc", gro, gcol, theta_ppm=theta, chunk=chunk, keep_frontiers=True)
         want = oracle.cc(ro, col)
     else:
-        g = W.Graph.from_csr(ro, col, w)
-        ref = oracle.pull_engine(app, ro, col, w, src, theta_ppm=theta, chunk=chunk)
+        gro, gcol = ro, col
+        g = W.Graph.from_csr(ro, col, w, keep_ids=keep_ids)
+        ref = oracle.pull_engine(app, ro, col, w, src, theta_ppm=theta, chunk=chunk,
+                                 keep_frontiers=True)
         want = oracle.bfs(ro, col, src) if app == "bfs" else oracle.sssp(ro, col, w, src)
+    K = internal_marked(g, gro, gcol, ref.frontiers, chunk)
+    if keep_ids:
+        np.testing.assert_array_equal(K, ref.K)
     np.testing.assert_array_equal(ref.values, want)
     got, st, tr = run_app(app, g, src, gate=gate, theta_ppm=theta, chunk=chunk)
     np.testing.assert_array_equal(got, want)
     assert st["iterations"] == ref.iters
-    check_trace(tr, ref, chunk)
+    check_trace(tr, ref, chunk, K)
     if gate == "threshold":
         assert [r["mode"] for r in tr] == list(ref.mode)
     elif gate == "wedge":
@@ -89,6 +110,7 @@ def test_parity_threshold_gate(app, name):
     srcs = gen.pick_sources(ro, 2, seed=5) if app != "cc" else [0]
     for s in srcs:
         parity(app, ro, col, w, int(s))
+        parity(app, ro, col, w, int(s), keep_ids=True)
 
 
 @pytest.mark.parametrize("gate", ["wedge", "full"])
@@ -114,7 +136,7 @@ def test_theta_extremes():
 def test_wedge_frontier_bitmap_is_the_definition():
     """The translated bitmap equals the full-scan definition bit for bit."""
     ro, col = gen.rmat(13, 16, seed=41)
-    g = W.Graph.from_csr(ro, col)
+    g = W.Graph.from_csr(ro, col, keep_ids=True)
     co, src, _ = oracle.csc(ro, col)
     n = len(ro) - 1
     rng = np.random.default_rng(3)
@@ -133,13 +155,34 @@ def test_wedge_frontier_bitmap_is_the_definition():
             assert np.array_equal(np.sort(lst.cpu().numpy().view(np.uint32)), np.flatnonzero(want))
 
 
+def test_wedge_frontier_bitmap_relabelled_layout():
+    """Frontier given in caller ids; the bitmap is over the internal in-edge order."""
+    ro, col = gen.rmat(12, 16, seed=42)
+    g = W.Graph.from_csr(ro, col)
+    assert g.info["relabeled"] == 1
+    n = len(ro) - 1
+    perm = g.layout("perm")
+    rro, rcol, _ = relabel(ro, col, perm)
+    _, isrc, _ = oracle.csc(rro, rcol)
+    rng = np.random.default_rng(5)
+    for chunk in (1, 16, 64):
+        fr = np.flatnonzero(rng.random(n) < 0.02).astype(np.uint32)
+        wbits, lst = W.frontier_translate(g, torch.from_numpy(fr.view(np.int32)).cuda(), chunk)
+        mask = np.zeros(n, np.uint8)
+        mask[perm[fr]] = 1
+        want, k = oracle.wedge_frontier(isrc, mask, chunk)
+        got = np.unpackbits(wbits.cpu().numpy().view(np.uint8), bitorder="little")[:len(want)]
+        np.testing.assert_array_equal(got, want)
+        assert lst.numel() == k
+
+
 def test_worked_example_on_gpu():
     """Design Requirements example: frontier {2, 4} marks exactly its 4 edges at
     one edge per group and 3 groups at two edges per group."""
     pairs = [(2, 4), (2, 6), (4, 8), (4, 9), (1, 6), (3, 8), (5, 9)]
     ro, col = gen.csr_from_edges(10, np.array([p[0] for p in pairs], np.uint32),
                                  np.array([p[1] for p in pairs], np.uint32))
-    g = W.Graph.from_csr(ro, col)
+    g = W.Graph.from_csr(ro, col, keep_ids=True)
     fr = torch.tensor([2, 4], dtype=torch.int32, device="cuda")
     _, l1 = W.frontier_translate(g, fr, 1)
     _, l2 = W.frontier_translate(g, fr, 2)
@@ -206,10 +249,11 @@ def rel_l1(got, ref):
     return float(np.abs(got.astype(np.float64) - ref).sum() / np.abs(ref).sum())
 
 
+@pytest.mark.parametrize("keep_ids", [False, True])
 @pytest.mark.parametrize("name", ["er_ragged", "rmat12", "rmat14", "grid"])
-def test_pagerank_parity(name):
+def test_pagerank_parity(name, keep_ids):
     ro, col = GRAPHS[name]()
-    g = W.Graph.from_csr(ro, col)
+    g = W.Graph.from_csr(ro, col, keep_ids=keep_ids)
     r, st = W.pagerank(g, 20, 0.85)
     ref = oracle.pagerank(ro, col, 20, 0.85)
     got = r.cpu().numpy()
