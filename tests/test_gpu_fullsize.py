@@ -1,0 +1,158 @@
+"""GPU parity at the benchmark's full sizes and launch configuration.
+
+R-MAT scale 16 (BFS, 8 sources) and the scale-24 R-MAT and Erdos-Renyi graphs
+(BFS, SSSP, CC, PageRank) are checked against the CPU oracle computed in full:
+bit-exact for integers, per-iteration frontier size, out-degree sum and gate
+decision for one BFS and one SSSP run, and <= 1e-5 relative L1 for PageRank.
+The scale-26 PageRank case is opt-in (WEDGE_FULLSCALE=1).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a ROCm GPU", allow_module_level=True)
+
+import paper_1903_07754_amd as W  # noqa: E402
+
+
+def say(msg):
+    print(f"  [fullsize] {msg}", flush=True)
+
+
+def rel_l1(got, ref):
+    return float(np.abs(got.astype(np.float64) - ref).sum() / np.abs(ref).sum())
+
+
+@pytest.mark.timeout(600)
+def test_config1_rmat16_bfs_eight_sources():
+    ro, col = gen.rmat(16, 16, seed=1)
+    g = W.Graph.from_csr(ro, col)
+    for s in gen.pick_sources(ro, 8, seed=2):
+        s = int(s)
+        out, st, tr = W.bfs(g, s, theta_ppm=10_000, chunk=32, trace_cap=64)
+        np.testing.assert_array_equal(W.u32(out), oracle.bfs(ro, col, s))
+        ref = oracle.pull_engine("bfs", ro, col, None, s, theta_ppm=10_000, chunk=0)
+        assert [r["frontier"] for r in tr] == list(ref.F)
+        assert [r["active_edges"] for r in tr] == list(ref.A)
+        assert [r["mode"] for r in tr] == list(ref.mode)
+
+
+class Big:
+    """One scale-24 graph held for the tests of its kind."""
+
+    def __init__(self, kind):
+        t = time.time()
+        if kind == "rmat":
+            self.ro, self.col = gen.rmat(24, 16, seed=1)
+        else:
+            m = _m_rmat24.get("m") or int(gen.rmat(24, 16, seed=1)[0][-1])
+            self.ro, self.col = gen.erdos_renyi(1 << 24, m, seed=2)
+        if kind == "rmat":
+            _m_rmat24["m"] = len(self.col)
+        self.w = gen.edge_weights(self.ro, self.col, seed=4)
+        self.srcs = [int(s) for s in gen.pick_sources(self.ro, 4, seed=3)]
+        say(f"{kind} n={len(self.ro) - 1} m={len(self.col)} generated in {time.time() - t:.1f}s")
+        t = time.time()
+        self.g = W.Graph.from_csr(self.ro, self.col, self.w)
+        say(f"{kind} directed layout in {time.time() - t:.1f}s")
+        self._gs = None
+
+    @property
+    def gs(self):
+        if self._gs is None:
+            t = time.time()
+            self._gs = W.Graph.from_csr(self.ro, self.col, symmetrize=True)
+            say(f"undirected layout in {time.time() - t:.1f}s")
+        return self._gs
+
+
+_cache = {}
+_m_rmat24 = {}
+
+
+def big(kind):
+    if kind not in _cache:
+        _cache.clear()
+        _cache[kind] = Big(kind)
+    return _cache[kind]
+
+
+def check_bfs_sssp(kind):
+    b = big(kind)
+    for i, s in enumerate(b.srcs[:2]):
+        out, st, tr = W.bfs(b.g, s, trace_cap=256)
+        want = oracle.bfs(b.ro, b.col, s)
+        np.testing.assert_array_equal(W.u32(out), want)
+        say(f"{kind} bfs src={s} ok ({st['iterations']} iters, {st['ms']:.2f} ms)")
+        d, st, trs = W.sssp(b.g, s, trace_cap=4096)
+        np.testing.assert_array_equal(W.u32(d), oracle.sssp(b.ro, b.col, b.w, s))
+        say(f"{kind} sssp src={s} ok ({st['iterations']} iters, {st['ms']:.2f} ms)")
+        if i == 0:
+            for app, t in (("bfs", tr), ("sssp", trs)):
+                theta = 10_000 if app == "bfs" else 200_000
+                ref = oracle.pull_engine(app, b.ro, b.col, b.w if app == "sssp" else None, s,
+                                         theta_ppm=theta, chunk=0)
+                assert [r["frontier"] for r in t] == list(ref.F)
+                assert [r["active_edges"] for r in t] == list(ref.A)
+                assert [r["mode"] for r in t] == list(ref.mode)
+                say(f"{kind} {app} per-iteration trace matches ({ref.iters} iters)")
+
+
+def check_cc(kind):
+    b = big(kind)
+    out, st, _ = W.cc(b.gs)
+    np.testing.assert_array_equal(W.u32(out), oracle.cc(b.ro, b.col))
+    say(f"{kind} cc ok ({st['iterations']} iters, {st['ms']:.2f} ms)")
+
+
+@pytest.mark.timeout(900)
+def test_config2_rmat24_bfs_sssp():
+    check_bfs_sssp("rmat")
+
+
+@pytest.mark.timeout(900)
+def test_config2_rmat24_cc():
+    check_cc("rmat")
+
+
+@pytest.mark.timeout(900)
+def test_rmat24_pagerank():
+    b = big("rmat")
+    r, st = W.pagerank(b.g, 20, 0.85)
+    ref = oracle.pagerank(b.ro, b.col, 20, 0.85)
+    e = rel_l1(r.cpu().numpy(), ref)
+    say(f"pagerank s24 rel L1 {e:.3e} ({st['ms']:.1f} ms)")
+    assert e <= 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_config2_er24_bfs_sssp():
+    check_bfs_sssp("er")
+
+
+@pytest.mark.timeout(900)
+def test_config2_er24_cc():
+    check_cc("er")
+    _cache.clear()
+
+
+@pytest.mark.fullscale
+@pytest.mark.timeout(1500)
+def test_config3_pagerank_rmat26():
+    ro, col = gen.rmat(26, 16, seed=1)
+    g = W.Graph.from_csr(ro, col)
+    r, st = W.pagerank(g, 20, 0.85)
+    got = r.cpu().numpy()
+    del g
+    ref = oracle.pagerank(ro, col, 20, 0.85)
+    e = rel_l1(got, ref)
+    say(f"pagerank s26 rel L1 {e:.3e} ({st['ms']:.1f} ms)")
+    assert e <= 1e-5
