@@ -172,6 +172,10 @@ typedef struct {
 /* wedge_opts.flags */
 #define WEDGE_RUN_TIME_PULL  0x1u /* HIP events around each pull launch; sums into stats */
 #define WEDGE_RUN_TIME_ITERS 0x2u /* HIP events around each iteration; into trace[k].ms */
+#define WEDGE_RUN_PERSISTENT 0x4u /* BFS kinds only: run the whole traversal as one persistent
+                                     kernel (grid barriers between steps, the fullness gate
+                                     evaluated on the device), captured once in a hipGraph and
+                                     replayed; per-iteration times are not available */
 
 typedef struct {
     uint32_t gate;           /* wedge_gate */
@@ -184,6 +188,10 @@ typedef struct {
     uint32_t trace_cap;      /* entries available at trace */
     wedge_iter_record* trace;/* host array, nullable */
     const void* model;       /* wedge_model_t for WEDGE_GATE_LEARNED, nullable */
+    uint32_t blocks_per_cu;  /* WEDGE_RUN_PERSISTENT: resident blocks of 256 threads per compute
+                                unit; 0 = as many as the kernel's occupancy allows (the value is
+                                clamped to that maximum so every block is co-resident) */
+    uint32_t reserved;
 } wedge_opts;
 
 typedef struct {
@@ -230,6 +238,69 @@ wedge_status wedge_sssp(wedge_graph_t g, uint32_t src, uint32_t* dist_dev, const
  */
 wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, float* rank_dev,
                             const wedge_opts* opts, hipStream_t stream, wedge_stats* stats);
+
+/* ------------------------------------------------------------- batching */
+
+/*
+ * Multi-source BFS: `count` (1..64) BFS runs from srcs[0..count) (host array of
+ * caller ids) in one traversal, each vertex holding a 64-bit mask per state
+ * (bit s = source s), after Then et al., "The More the Merrier" (PVLDB 8(4),
+ * 2014). The Wedge machinery runs on the union frontier {v : some source
+ * reached v in the last iteration} with the usual gate and chunk options.
+ * levels_dev[s*n + v] receives the level of v from srcs[s] (0xFFFFFFFF when
+ * unreachable); the caller provides count*n entries.
+ */
+wedge_status wedge_bfs_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t count,
+                                   uint32_t* levels_dev, const wedge_opts* opts,
+                                   hipStream_t stream, wedge_stats* stats);
+
+/*
+ * One graph holding `count` independent graphs as a disjoint union: part i has
+ * n_each[i] vertices and out-edges row_off[i], col[i] (host arrays, part-local
+ * ids), and becomes vertices [first_i, first_i + n_each[i]) of the union.
+ * Flags as for wedge_graph_create_csr (weights are not supported).
+ */
+wedge_status wedge_graph_create_batch_csr(uint32_t count, const uint32_t* n_each,
+                                          const uint64_t* const* row_off,
+                                          const uint32_t* const* col, uint32_t flags,
+                                          hipStream_t stream, wedge_graph_t* out);
+
+/* First vertex of each part of a batch graph: first[0..count] (first[count] = n). */
+wedge_status wedge_graph_batch_parts(wedge_graph_t g, uint64_t* first, uint32_t cap,
+                                     uint32_t* count);
+
+/*
+ * One BFS per part of a batch graph in a single traversal: srcs[i] (host) is
+ * the part-local source of part i. The union is traversed from all sources at
+ * once; parts share no edges, so each vertex gets its own part's level.
+ * levels_dev[n] receives the levels in union order.
+ */
+wedge_status wedge_bfs_batch(wedge_graph_t g, const uint32_t* srcs, uint32_t* levels_dev,
+                             const wedge_opts* opts, hipStream_t stream, wedge_stats* stats);
+
+/* kinds for wedge_tune_bfs */
+#define WEDGE_TUNE_SINGLE 0u      /* wedge_bfs from srcs[0] */
+#define WEDGE_TUNE_MULTISOURCE 1u /* wedge_bfs_multisource over srcs[0..count) */
+#define WEDGE_TUNE_BATCH 2u       /* wedge_bfs_batch with srcs[0..parts) */
+
+/*
+ * Autotuner: times the BFS kind on this graph and these sources for every
+ * combination of edges per Wedge bit {16, 32, 64}, host-driven or persistent
+ * launch, and persistent blocks per compute unit {1, 2, 4, occupancy max}
+ * (best of two runs each), and writes the fastest options to *best (its gate
+ * and threshold are taken from *best on entry). Results do not depend on the
+ * choice. out_dev is scratch output of the kind's size. The winner is also
+ * kept in a process-wide table keyed by (kind, source count, ceil(log2 m)),
+ * which wedge_tune_lookup reads.
+ */
+wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs, uint32_t count,
+                            uint32_t* out_dev, hipStream_t stream, wedge_opts* best,
+                            double* best_ms);
+
+/* Tuned options for (kind, count, edge count m), if wedge_tune_bfs has
+ * recorded them in this process: copies chunk_edges, flags' persistent bit and
+ * blocks_per_cu into *opts and returns WEDGE_OK; else WEDGE_ERR_UNSUPPORTED. */
+wedge_status wedge_tune_lookup(uint32_t kind, uint32_t count, uint64_t m, wedge_opts* opts);
 
 /* ------------------------------------------------------- single steps */
 

@@ -24,7 +24,8 @@ STATUS = {0: "WEDGE_OK", -1: "WEDGE_ERR_INVALID_ARG", -2: "WEDGE_ERR_BAD_GRAPH",
 
 INPUT_DEVICE, SYMMETRIZE, HOST_ONLY, KEEP_IDS = 0x1, 0x2, 0x4, 0x8
 GATE = {"threshold": 0, "wedge": 1, "full": 2, "learned": 3}
-RUN_TIME_PULL, RUN_TIME_ITERS = 0x1, 0x2
+RUN_TIME_PULL, RUN_TIME_ITERS, RUN_PERSISTENT = 0x1, 0x2, 0x4
+TUNE = {"single": 0, "multisource": 1, "batch": 2}
 LAYOUT = {"col_off": 0, "in_src": 1, "in_w": 2, "row_off": 3, "pos": 4, "rowmask": 5,
           "rowseg": 6, "nzdst": 7, "pr_spans": 8, "perm": 9}
 
@@ -53,7 +54,8 @@ class IterRecord(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("gate", C.c_uint32), ("threshold_ppm", C.c_uint32), ("chunk_edges", C.c_uint32),
                 ("max_iters", C.c_uint32), ("flags", C.c_uint32), ("trace_cap", C.c_uint32),
-                ("trace", C.POINTER(IterRecord)), ("model", C.c_void_p)]
+                ("trace", C.POINTER(IterRecord)), ("model", C.c_void_p),
+                ("blocks_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Stats(C.Structure):
@@ -88,13 +90,21 @@ def lib():
     L.wedge_sssp.argtypes = [vp, u32, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
     L.wedge_pagerank.argtypes = [vp, u32, C.c_float, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
     L.wedge_frontier_translate.argtypes = [vp, vp, u32, u32, vp, vp, C.POINTER(u64), vp]
+    L.wedge_bfs_multisource.argtypes = [vp, vp, u32, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
+    L.wedge_graph_create_batch_csr.argtypes = [u32, vp, vp, vp, u32, vp, C.POINTER(vp)]
+    L.wedge_graph_batch_parts.argtypes = [vp, vp, u32, C.POINTER(u32)]
+    L.wedge_bfs_batch.argtypes = [vp, vp, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
+    L.wedge_tune_bfs.argtypes = [vp, u32, vp, u32, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double)]
+    L.wedge_tune_lookup.argtypes = [u32, u32, u64, C.POINTER(Opts)]
     L.wedge_status_string.argtypes = [C.c_int]
     L.wedge_status_string.restype = C.c_char_p
     L.wedge_last_error.restype = C.c_char_p
     L.wedge_version.restype = C.c_char_p
     for name in ("wedge_graph_create_csr", "wedge_graph_create_csc", "wedge_graph_destroy",
                  "wedge_graph_get_info", "wedge_graph_layout", "wedge_bfs", "wedge_cc",
-                 "wedge_sssp", "wedge_pagerank", "wedge_frontier_translate"):
+                 "wedge_sssp", "wedge_pagerank", "wedge_frontier_translate",
+                 "wedge_bfs_multisource", "wedge_graph_create_batch_csr", "wedge_graph_batch_parts",
+                 "wedge_bfs_batch", "wedge_tune_bfs", "wedge_tune_lookup"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -162,6 +172,28 @@ class Graph:
         return cls._make(lib().wedge_graph_create_csc, len(col_off) - 1, col_off, src, w,
                          symmetrize, host_only, stream, keep_ids)
 
+    @classmethod
+    def from_batch_csr(cls, parts, host_only=False, stream=None, keep_ids=False):
+        """Disjoint union of [(row_off, col), ...] (host arrays, part-local ids)."""
+        count = len(parts)
+        keep = [(np.ascontiguousarray(r, np.uint64), np.ascontiguousarray(c, np.uint32)) for r, c in parts]
+        n_each = np.array([len(r) - 1 for r, _ in keep], np.uint32)
+        ros = (C.c_void_p * count)(*[r.ctypes.data for r, _ in keep])
+        cols = (C.c_void_p * count)(*[c.ctypes.data if len(c) else None for _, c in keep])
+        flags = (HOST_ONLY if host_only else 0) | (KEEP_IDS if keep_ids else 0)
+        h = C.c_void_p()
+        check(lib().wedge_graph_create_batch_csr(count, n_each.ctypes.data, ros, cols, flags,
+                                                 None if host_only else _stream_handle(stream),
+                                                 C.byref(h)))
+        return Graph(h.value)
+
+    def parts(self):
+        cnt = C.c_uint32()
+        check(lib().wedge_graph_batch_parts(self._h, None, 0, C.byref(cnt)))
+        first = np.zeros(cnt.value + 1, np.uint64)
+        check(lib().wedge_graph_batch_parts(self._h, first.ctypes.data, cnt.value + 1, C.byref(cnt)))
+        return first
+
     def layout(self, name):
         dt = np.uint64 if name == "rowmask" else np.uint32
         sizes = {"col_off": self.n + 1, "in_src": self.m, "in_w": self.m, "row_off": self.n + 1,
@@ -190,11 +222,13 @@ class Graph:
 
 
 def make_opts(gate="threshold", theta_ppm=0, chunk=0, max_iters=0, time_pull=False,
-              time_iters=False, trace_cap=0, model=None):
+              time_iters=False, trace_cap=0, model=None, persistent=False, blocks_per_cu=0):
     o = Opts()
     o.gate = GATE[gate] if isinstance(gate, str) else int(gate)
     o.threshold_ppm, o.chunk_edges, o.max_iters = theta_ppm, chunk, max_iters
-    o.flags = (RUN_TIME_PULL if time_pull else 0) | (RUN_TIME_ITERS if time_iters else 0)
+    o.flags = ((RUN_TIME_PULL if time_pull else 0) | (RUN_TIME_ITERS if time_iters else 0)
+               | (RUN_PERSISTENT if persistent else 0))
+    o.blocks_per_cu = blocks_per_cu
     trace = (IterRecord * trace_cap)() if trace_cap else None
     o.trace_cap = trace_cap
     o.trace = C.cast(trace, C.POINTER(IterRecord)) if trace is not None else None
@@ -246,6 +280,52 @@ def pagerank(g, iters=20, damping=0.85, out=None, stream=None, time_pull=False):
     check(lib().wedge_pagerank(g.handle, iters, damping, _ptr(out), C.byref(o),
                                _stream_handle(stream), C.byref(st)))
     return out[:g.n], st.as_dict()
+
+
+def bfs_multisource(g, srcs, out=None, stream=None, trace_cap=0, **kw):
+    """Levels [len(srcs), n] (int32 tensor viewed as uint32), stats, trace."""
+    import torch
+    srcs = np.ascontiguousarray(srcs, np.uint32)
+    k = len(srcs)
+    if out is None:
+        out = torch.empty(max(k * g.n, 1), dtype=torch.int32, device="cuda")
+    o, trace = make_opts(trace_cap=trace_cap, **kw)
+    st = Stats()
+    check(lib().wedge_bfs_multisource(g.handle, srcs.ctypes.data, k, _ptr(out), C.byref(o),
+                                      _stream_handle(stream), C.byref(st)))
+    return out[:k * g.n].view(k, g.n), st.as_dict(), _trace_list(trace, st.iterations)
+
+
+def bfs_batch(g, srcs, out=None, stream=None, trace_cap=0, **kw):
+    """Union-order levels of one BFS per part (srcs: part-local sources)."""
+    srcs = np.ascontiguousarray(srcs, np.uint32)
+    o, trace = make_opts(trace_cap=trace_cap, **kw)
+    out = _out_u32(g.n, out)
+    st = Stats()
+    check(lib().wedge_bfs_batch(g.handle, srcs.ctypes.data, _ptr(out), C.byref(o),
+                                _stream_handle(stream), C.byref(st)))
+    return out[:g.n], st.as_dict(), _trace_list(trace, st.iterations)
+
+
+def tune_bfs(g, kind, srcs, out, stream=None, gate="threshold", theta_ppm=0):
+    """Autotune a BFS kind; returns (best options dict, best ms)."""
+    srcs = np.ascontiguousarray(srcs, np.uint32)
+    o, _ = make_opts(gate=gate, theta_ppm=theta_ppm)
+    ms = C.c_double()
+    check(lib().wedge_tune_bfs(g.handle, TUNE[kind], srcs.ctypes.data, len(srcs), _ptr(out),
+                               _stream_handle(stream), C.byref(o), C.byref(ms)))
+    best = {"chunk": o.chunk_edges, "persistent": bool(o.flags & RUN_PERSISTENT),
+            "blocks_per_cu": o.blocks_per_cu, "gate": o.gate, "theta_ppm": o.threshold_ppm}
+    return best, ms.value
+
+
+def tune_lookup(kind, count, m):
+    o, _ = make_opts()
+    st = lib().wedge_tune_lookup(TUNE[kind], count, m, C.byref(o))
+    if st != OK:
+        return None
+    return {"chunk": o.chunk_edges, "persistent": bool(o.flags & RUN_PERSISTENT),
+            "blocks_per_cu": o.blocks_per_cu}
 
 
 def frontier_translate(g, frontier, chunk, stream=None):

@@ -1,6 +1,10 @@
 // C ABI of the Wedge-Frontier pull engine: argument checks, graph upload, the
 // per-iteration control loop (Wedge Overview, Fig. 5) and PageRank.
+#include <algorithm>
+#include <map>
+#include <tuple>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -81,6 +85,15 @@ void free_all(wedge_graph_s* g) {
     for (void* p : wp)
         if (p) (void)hipFree(p);
     if (w.ctl_host) (void)hipHostFree(w.ctl_host);
+    void* bp[] = {w.visited, w.masks[0], w.masks[1], w.lev, w.roots, w.ps, w.trace};
+    for (void* p : bp)
+        if (p) (void)hipFree(p);
+    void* hp[] = {w.roots_host, w.ps_host, w.trace_host};
+    for (void* p : hp)
+        if (p) (void)hipHostFree(p);
+    if (w.graph_exec) (void)hipGraphExecDestroy(w.graph_exec);
+    if (w.graph) (void)hipGraphDestroy(w.graph);
+    if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
     for (hipEvent_t e : w.ev)
         if (e) (void)hipEventDestroy(e);
     d = DevGraph{};
@@ -219,7 +232,7 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-const wedge_opts kDefaultOpts = {WEDGE_GATE_THRESHOLD, 0, 0, 0, 0, 0, nullptr, nullptr};
+const wedge_opts kDefaultOpts = {WEDGE_GATE_THRESHOLD, 0, 0, 0, 0, 0, nullptr, nullptr, 0, 0};
 
 wedge_status check_run(wedge_graph_t g, const void* out, const wedge_opts* o) {
     if (!g) return fail(WEDGE_ERR_INVALID_ARG, "graph is null");
@@ -229,13 +242,125 @@ wedge_status check_run(wedge_graph_t g, const void* out, const wedge_opts* o) {
     if (o->chunk_edges && (!is_pow2(o->chunk_edges) || o->chunk_edges > 4096))
         return fail(WEDGE_ERR_INVALID_ARG, "chunk_edges must be a power of two in [1, 4096]");
     if (o->trace_cap && !o->trace) return fail(WEDGE_ERR_INVALID_ARG, "trace_cap set but trace is null");
-    if (o->flags & ~(WEDGE_RUN_TIME_PULL | WEDGE_RUN_TIME_ITERS))
+    if (o->flags & ~(WEDGE_RUN_TIME_PULL | WEDGE_RUN_TIME_ITERS | WEDGE_RUN_PERSISTENT))
         return fail(WEDGE_ERR_INVALID_ARG, "unknown run flag bits");
     return WEDGE_OK;
 }
 
-// BFS, CC and SSSP share one control loop; they differ in the pull kernel, the
-// initial frontier and whether values need a committed copy.
+wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t count, uint32_t* out,
+                           const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats);
+
+// ------------------------------------------------------------ the loop
+//
+// The control loop of one traversal (Wedge Overview, Fig. 5): with the
+// frontier's size, listed count and A read back from the device, choose the
+// mode, build the Wedge Frontier when chosen, pull, finalise, repeat until the
+// frontier is empty. The app supplies the pull and finalise launches.
+struct LoopCfg {
+    int lc = 5;
+    uint64_t thr = 0;
+    uint32_t gate = WEDGE_GATE_THRESHOLD;
+    uint32_t max_iters = 0;
+    bool time_pull = false, time_iter = false;
+    uint64_t nchunks = 0, wwords = 0;
+};
+
+template <class Pull, class Fin>
+wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hipStream_t s,
+                     wedge_stats& local, double t0, wedge_stats* stats, Pull pull, Fin fin) {
+    Workspace& w = g->ws;
+    const DevGraph& d = g->dev;
+    HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
+    HIP_TRY(hipStreamSynchronize(s), "initialising run");
+    uint64_t fcount = w.ctl_host->ftotal;               // |F_k|
+    uint64_t flisted = w.ctl_host->fnext >> kDegBits;   // of which have out-edges
+    uint64_t active = w.ctl_host->fnext & kDegMask;     // A_k
+    int cur = 0;
+    uint32_t k = 0;
+    for (; fcount > 0; ++k) {
+        if (k >= c.max_iters) {
+            local.iterations = k;
+            if (stats) { local.ms = now_ms() - t0; *stats = local; }
+            return fail(WEDGE_ERR_NOT_CONVERGED, "max_iters reached with a non-empty frontier");
+        }
+        bool wedge_mode;
+        switch (c.gate) {
+            case WEDGE_GATE_ALWAYS_WEDGE: wedge_mode = true; break;
+            case WEDGE_GATE_ALWAYS_FULL: wedge_mode = false; break;
+            default: wedge_mode = active < c.thr; break;  // the fullness threshold (strict <)
+        }
+        HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
+        if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[2], s), "event");
+        uint64_t maxk = 0;
+        if (wedge_mode) {
+            HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)flisted, active, d.row_off,
+                                     d.pos, c.lc, w.wbits, s), "frontier translation");
+            HIP_TRY(launch_compact_chunks(w.wbits, c.wwords, w.chunks, w.ctl, s), "chunk compaction");
+            maxk = active < c.nchunks ? active : c.nchunks;
+        }
+        if (c.time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
+        HIP_TRY(pull(k, wedge_mode, maxk, cur), wedge_mode ? "chunk pull" : "full pull");
+        if (c.time_pull) HIP_TRY(hipEventRecord(w.ev[1], s), "event");
+        HIP_TRY(fin(k, cur), "frontier finalisation");
+        if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
+        HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
+        HIP_TRY(hipStreamSynchronize(s), "iteration");
+        float pms = 0.f, ims = 0.f;
+        if (c.time_pull) HIP_TRY(hipEventElapsedTime(&pms, w.ev[0], w.ev[1]), "event time");
+        if (c.time_iter) HIP_TRY(hipEventElapsedTime(&ims, w.ev[2], w.ev[3]), "event time");
+        local.pull_ms += pms;
+        local.pull_launches++;
+        const uint64_t marked = wedge_mode ? (w.ctl_host->marked >> kDegBits) : 0;
+        if (o.trace && k < o.trace_cap) {
+            wedge_iter_record& r = o.trace[k];
+            r.iter = k;
+            r.mode = wedge_mode ? 1u : 0u;
+            r.chunk_edges = wedge_mode ? (1u << c.lc) : 0u;
+            r.reserved = 0;
+            r.frontier = fcount;
+            r.active_edges = active;
+            r.marked_chunks = marked;
+            r.ms = ims;
+            r.reserved2 = 0.f;
+        }
+        if (wedge_mode) { local.wedge_iters++; local.edges_scanned += marked << c.lc; }
+        else { local.full_iters++; local.edges_scanned += d.m; }
+        fcount = w.ctl_host->ftotal;
+        flisted = w.ctl_host->fnext >> kDegBits;
+        active = w.ctl_host->fnext & kDegMask;
+        cur ^= 1;
+    }
+    local.iterations = k;
+    return WEDGE_OK;
+}
+
+LoopCfg loop_cfg(const wedge_opts& o, const DevGraph& d, uint32_t theta_default,
+                 uint32_t chunk_default) {
+    LoopCfg c;
+    const uint32_t theta = o.threshold_ppm ? o.threshold_ppm : theta_default;
+    const uint32_t chunk = o.chunk_edges ? o.chunk_edges : chunk_default;
+    c.lc = log2u(chunk);
+    c.thr = ((uint64_t)theta * d.m) / 1000000ull;
+    c.gate = o.gate;
+    c.max_iters = o.max_iters ? o.max_iters : d.n + 1;
+    c.time_pull = o.flags & WEDGE_RUN_TIME_PULL;
+    c.time_iter = o.flags & WEDGE_RUN_TIME_ITERS;
+    c.nchunks = (d.m + chunk - 1) >> c.lc;
+    c.wwords = (c.nchunks + 63) / 64;
+    return c;
+}
+
+// Clears both frontier bitmaps (and the Wedge bitmap when it may be used).
+wedge_status clear_bitmaps(wedge_graph_t g, const LoopCfg& c, hipStream_t s) {
+    Workspace& w = g->ws;
+    const uint64_t fwords = ((uint64_t)g->dev.n + 63) / 64;
+    HIP_TRY(hipMemsetAsync(w.fbits, 0, fwords * 8, s), "clearing frontier bitmap");
+    HIP_TRY(hipMemsetAsync(w.fcur, 0, fwords * 8, s), "clearing frontier bitmap");
+    if (c.gate != WEDGE_GATE_ALWAYS_FULL) HIP_TRY(hipMemsetAsync(w.wbits, 0, c.wwords * 8, s), "clearing Wedge bitmap");
+    return WEDGE_OK;
+}
+
+// BFS, CC and SSSP from one source (or all vertices for CC).
 wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* val,
                               const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
     const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
@@ -250,32 +375,23 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     }
     if (app == kCc && !(g->flags & WEDGE_SYMMETRIZE))
         return fail(WEDGE_ERR_UNSUPPORTED, "CC runs on the undirected view: create the graph with WEDGE_SYMMETRIZE");
+    if (app == kBfs && (o.flags & WEDGE_RUN_PERSISTENT))
+        return run_bfs_roots(g, &src, 1, val, opts_in, s, stats);
     RunGuard guard(g->busy);
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
     wedge_stats local{};
     const double t0 = now_ms();
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
-
-    const uint32_t theta = o.threshold_ppm ? o.threshold_ppm : (app == kBfs ? 10000u : 200000u);
-    const uint32_t chunk = o.chunk_edges ? o.chunk_edges : (app == kBfs ? 32u : 16u);
-    const int lc = log2u(chunk);
-    const uint64_t thr = ((uint64_t)theta * d.m) / 1000000ull;
-    const bool may_wedge = o.gate != WEDGE_GATE_ALWAYS_FULL;
-    if ((st = ensure_workspace(g, lc, true, may_wedge)) != WEDGE_OK) return st;
+    const LoopCfg c = loop_cfg(o, d, app == kBfs ? 10000u : 200000u, app == kBfs ? 32u : 16u);
+    if ((st = ensure_workspace(g, c.lc, true, c.gate != WEDGE_GATE_ALWAYS_FULL)) != WEDGE_OK) return st;
     Workspace& w = g->ws;
-    const uint64_t nchunks = (d.m + chunk - 1) >> lc;
-    const uint64_t wwords = (nchunks + 63) / 64;
-    const uint64_t fwords = ((uint64_t)d.n + 63) / 64;
-    HIP_TRY(hipMemsetAsync(w.fbits, 0, fwords * 8, s), "clearing frontier bitmap");
-    if (may_wedge) HIP_TRY(hipMemsetAsync(w.wbits, 0, wwords * 8, s), "clearing Wedge bitmap");
-
+    if ((st = clear_bitmaps(g, c, s)) != WEDGE_OK) return st;
     // values are computed in internal vertex order; a relabelled graph works in
-    // a workspace array and scatters to the caller's order at the end
+    // a workspace array and is mapped to the caller's order at the end
     uint32_t* const out = val;
     if (d.inv) val = w.val;
     const uint32_t isrc = (app != kCc && !g->perm_host.empty()) ? g->perm_host[src] : src;
     uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
-    HIP_TRY(hipMemsetAsync(w.fcur, 0, fwords * 8, s), "clearing frontier bitmap");
     if (app == kCc) {
         HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, d.inv, val, w.val_prev, w.flist[0], w.degpre[0],
                                 w.fcur, w.ctl, s), "seeding CC");
@@ -285,80 +401,310 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur,
                                    w.ctl, s), "seeding source");
     }
-    HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
-    HIP_TRY(hipStreamSynchronize(s), "initialising run");
-    uint64_t fcount = w.ctl_host->ftotal;               // |F_k|
-    uint64_t flisted = w.ctl_host->fnext >> kDegBits;   // of which have out-edges
-    uint64_t active = w.ctl_host->fnext & kDegMask;     // A_k
-    const uint32_t max_iters = o.max_iters ? o.max_iters : d.n + 1;
-    const bool time_pull = o.flags & WEDGE_RUN_TIME_PULL;
-    const bool time_iter = o.flags & WEDGE_RUN_TIME_ITERS;
-    int cur = 0;
-    uint32_t k = 0;
-    for (; fcount > 0; ++k) {
-        if (k >= max_iters) {
-            local.iterations = k;
-            if (stats) { local.ms = now_ms() - t0; *stats = local; }
-            return fail(WEDGE_ERR_NOT_CONVERGED, "max_iters reached with a non-empty frontier");
-        }
-        bool wedge_mode;
-        switch (o.gate) {
-            case WEDGE_GATE_ALWAYS_WEDGE: wedge_mode = true; break;
-            case WEDGE_GATE_ALWAYS_FULL: wedge_mode = false; break;
-            default: wedge_mode = active < thr; break;  // the fullness threshold (strict <)
-        }
-        HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
-        if (time_iter) HIP_TRY(hipEventRecord(w.ev[2], s), "event");
-        if (wedge_mode) {
-            HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)flisted, active, d.row_off,
-                                     d.pos, lc, w.wbits, s), "frontier translation");
-            HIP_TRY(launch_compact_chunks(w.wbits, wwords, w.chunks, w.ctl, s), "chunk compaction");
-            if (time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
-            const uint64_t maxk = active < nchunks ? active : nchunks;
-            HIP_TRY(launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev, w.fcur, w.fbits, s), "chunk pull");
-        } else {
-            if (time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
-            HIP_TRY(launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s), "full pull");
-        }
-        if (time_pull) HIP_TRY(hipEventRecord(w.ev[1], s), "event");
-        HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                vprev, val, w.fcur, s), "frontier finalisation");
-        if (time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
-        HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
-        HIP_TRY(hipStreamSynchronize(s), "iteration");
-        float pms = 0.f, ims = 0.f;
-        if (time_pull) HIP_TRY(hipEventElapsedTime(&pms, w.ev[0], w.ev[1]), "event time");
-        if (time_iter) HIP_TRY(hipEventElapsedTime(&ims, w.ev[2], w.ev[3]), "event time");
-        local.pull_ms += pms;
-        local.pull_launches++;
-        const uint64_t marked = wedge_mode ? (w.ctl_host->marked >> kDegBits) : 0;
-        if (o.trace && k < o.trace_cap) {
-            wedge_iter_record& r = o.trace[k];
-            r.iter = k;
-            r.mode = wedge_mode ? 1u : 0u;
-            r.chunk_edges = wedge_mode ? chunk : 0u;
-            r.reserved = 0;
-            r.frontier = fcount;
-            r.active_edges = active;
-            r.marked_chunks = marked;
-            r.ms = ims;
-            r.reserved2 = 0.f;
-        }
-        if (wedge_mode) { local.wedge_iters++; local.edges_scanned += marked << lc; }
-        else { local.full_iters++; local.edges_scanned += d.m; }
-        fcount = w.ctl_host->ftotal;
-        flisted = w.ctl_host->fnext >> kDegBits;
-        active = w.ctl_host->fnext & kDegMask;
-        cur ^= 1;
-    }
+    st = iterate(
+        g, o, c, s, local, t0, stats,
+        [&](uint32_t k, bool wedge_mode, uint64_t maxk, int) {
+            return wedge_mode ? launch_pull_chunks(app, d, k, c.lc, w.chunks, w.ctl, maxk, val, vprev,
+                                                   w.fcur, w.fbits, s)
+                              : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s);
+        },
+        [&](uint32_t, int cur) {
+            return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
+                                   vprev, val, w.fcur, s);
+        });
+    if (st != WEDGE_OK) return st;
     if (d.inv) {
         HIP_TRY(launch_unpermute_u32(d.n, d.perm, val, out, s), "writing results");
         HIP_TRY(hipStreamSynchronize(s), "writing results");
     }
-    local.iterations = k;
     local.ms = now_ms() - t0;
     if (stats) *stats = local;
     return WEDGE_OK;
+}
+
+// ---------------------------------------------------------------- batching
+
+wedge_status ensure_batch(wedge_graph_t g, uint32_t nroots, uint32_t K) {
+    Workspace& w = g->ws;
+    const DevGraph& d = g->dev;
+    wedge_status st;
+    if (nroots > w.roots_cap) {
+        if (w.roots) { (void)hipFree(w.roots); g->device_bytes -= (uint64_t)w.roots_cap * 4; w.roots = nullptr; }
+        if (w.roots_host) { (void)hipHostFree(w.roots_host); w.roots_host = nullptr; }
+        if ((st = dev_alloc(g, (void**)&w.roots, (size_t)nroots * 4, "sources")) != WEDGE_OK) return st;
+        HIP_TRY(hipHostMalloc((void**)&w.roots_host, (size_t)nroots * 4, hipHostMallocDefault), "pinned sources");
+        w.roots_cap = nroots;
+        w.generation++;
+    }
+    if (K && !w.visited) {
+        if ((st = dev_alloc(g, (void**)&w.visited, (size_t)d.n * 8, "visited masks")) != WEDGE_OK) return st;
+        for (int i = 0; i < 2; ++i)
+            if ((st = dev_alloc(g, (void**)&w.masks[i], (size_t)d.n * 8, "frontier masks")) != WEDGE_OK) return st;
+        w.generation++;
+    }
+    if (K > w.lev_k) {
+        if (w.lev) { (void)hipFree(w.lev); g->device_bytes -= (uint64_t)d.n * w.lev_k * 4; w.lev = nullptr; }
+        if ((st = dev_alloc(g, (void**)&w.lev, (size_t)d.n * K * 4, "multi-source levels")) != WEDGE_OK) return st;
+        w.lev_k = K;
+        w.generation++;
+    }
+    if (!w.ps) {
+        if ((st = dev_alloc(g, (void**)&w.ps, sizeof(PersistState), "persistent state")) != WEDGE_OK) return st;
+        HIP_TRY(hipHostMalloc((void**)&w.ps_host, sizeof(PersistState), hipHostMallocDefault), "pinned state");
+        w.trace_cap = 4096;
+        if ((st = dev_alloc(g, (void**)&w.trace, (size_t)w.trace_cap * sizeof(wedge_iter_record), "trace")) != WEDGE_OK) return st;
+        HIP_TRY(hipHostMalloc((void**)&w.trace_host, (size_t)w.trace_cap * sizeof(wedge_iter_record), hipHostMallocDefault), "pinned trace");
+        w.generation++;
+    }
+    return WEDGE_OK;
+}
+
+// Copy the (caller-id) sources into the device buffer in internal ids.
+wedge_status upload_roots(wedge_graph_t g, const uint32_t* roots, uint32_t count, hipStream_t s) {
+    Workspace& w = g->ws;
+    for (uint32_t i = 0; i < count; ++i)
+        w.roots_host[i] = g->perm_host.empty() ? roots[i] : g->perm_host[roots[i]];
+    if (count) HIP_TRY(hipMemcpyAsync(w.roots, w.roots_host, (size_t)count * 4, hipMemcpyHostToDevice, s), "uploading sources");
+    return WEDGE_OK;
+}
+
+int device_cus(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
+    return p.multiProcessorCount;
+}
+
+uint64_t barrier_timeout_ticks(int dev) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;
+    double ms = 10000.0;  // a traversal step never waits this long on a healthy device
+    if (const char* e = std::getenv("WEDGE_BARRIER_TIMEOUT_MS")) ms = std::strtod(e, nullptr);
+    return (uint64_t)(ms * (double)khz);
+}
+
+// The persistent form of a BFS-kind traversal, recorded in a hipGraph (on a
+// library stream: the legacy default stream cannot be captured) and replayed
+// on the caller's stream.
+wedge_status run_persistent(wedge_graph_t g, bool ms, uint32_t count, uint32_t* out,
+                            const wedge_opts& o, const LoopCfg& c, hipStream_t s,
+                            wedge_stats& local) {
+    Workspace& w = g->ws;
+    const DevGraph& d = g->dev;
+    int bpc_max = 0;
+    HIP_TRY(persistent_max_blocks(ms, &bpc_max), "occupancy query");
+    if (bpc_max <= 0) return fail(WEDGE_ERR_UNSUPPORTED, "persistent kernel cannot be resident");
+    const int cus = device_cus(g->device);
+    if (cus <= 0) return fail(WEDGE_ERR_HIP, "cannot read the compute unit count");
+    const uint32_t bpc = o.blocks_per_cu ? std::min<uint32_t>(o.blocks_per_cu, (uint32_t)bpc_max)
+                                         : (uint32_t)bpc_max;
+    const uint32_t blocks = bpc * (uint32_t)cus;
+    uint32_t* level = d.inv ? w.val : out;
+    const uint64_t timeout = barrier_timeout_ticks(g->device);
+    char keybuf[256];
+    std::snprintf(keybuf, sizeof keybuf, "%d|%u|%p|%u|%u|%d|%llu|%u|%llu|%llu", ms ? 1 : 0, count,
+                  (void*)out, blocks, c.gate, c.lc, (unsigned long long)c.thr, c.max_iters,
+                  (unsigned long long)w.generation, (unsigned long long)timeout);
+    const std::string key(keybuf);
+    if (key != w.graph_key || !w.graph_exec) {
+        if (w.graph_exec) { (void)hipGraphExecDestroy(w.graph_exec); w.graph_exec = nullptr; }
+        if (w.graph) { (void)hipGraphDestroy(w.graph); w.graph = nullptr; }
+        w.graph_key.clear();
+        if (!w.capture_stream) HIP_TRY(hipStreamCreateWithFlags(&w.capture_stream, hipStreamNonBlocking), "capture stream");
+        hipStream_t cs = w.capture_stream;
+        PersistParams P{};
+        P.g = args_of(d);
+        P.n = d.n;
+        P.row_off = d.row_off;
+        P.pos = d.pos;
+        P.level = level;
+        P.visited = w.visited;
+        P.masks[0] = w.masks[0];
+        P.masks[1] = w.masks[1];
+        P.lev = w.lev;
+        P.K = ms ? count : 0;
+        P.all = ms ? (count == 64 ? ~0ull : ((1ull << count) - 1ull)) : 0ull;
+        P.fbits = w.fbits;
+        P.fcur = w.fcur;
+        P.flist[0] = w.flist[0];
+        P.flist[1] = w.flist[1];
+        P.degpre[0] = w.degpre[0];
+        P.degpre[1] = w.degpre[1];
+        P.wbits = w.wbits;
+        P.wwords = c.wwords;
+        P.chunks = w.chunks;
+        P.lc = c.lc;
+        P.ctl = w.ctl;
+        P.ps = w.ps;
+        P.trace = w.trace;
+        P.trace_cap = w.trace_cap;
+        P.thr = c.thr;
+        P.gate = c.gate;
+        P.max_iters = c.max_iters;
+        P.timeout_ticks = timeout;
+        const uint64_t fwords = ((uint64_t)d.n + 63) / 64;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "graph capture");
+        hipError_t e = hipSuccess;
+        // every buffer is reset by kernels (no memset nodes in the graph)
+        if (e == hipSuccess) e = launch_fill_u64(w.fbits, fwords, 0, cs);
+        if (e == hipSuccess) e = launch_fill_u64(w.fcur, fwords, 0, cs);
+        if (e == hipSuccess && c.gate != WEDGE_GATE_ALWAYS_FULL) e = launch_fill_u64(w.wbits, c.wwords, 0, cs);
+        if (e == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t*>(w.ctl), sizeof(Ctl) / 8, 0, cs);
+        if (e == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t*>(w.ps), sizeof(PersistState) / 8, 0, cs);
+        if (ms) {
+            if (e == hipSuccess) e = launch_fill_u64(w.visited, d.n, 0, cs);
+            if (e == hipSuccess) e = launch_fill_u64(w.masks[0], d.n, 0, cs);
+            if (e == hipSuccess) e = launch_fill_u64(w.masks[1], d.n, 0, cs);
+            if (e == hipSuccess) e = launch_fill_u32_kernel(w.lev, (uint64_t)d.n * count, kInf, cs);
+            if (e == hipSuccess) e = launch_ms_seed(w.roots, count, w.masks[0], w.fbits, cs);
+        } else {
+            if (e == hipSuccess) e = launch_fill_u32_kernel(level, d.n, kInf, cs);
+            if (e == hipSuccess) e = launch_roots_seed(w.roots, count, level, w.fbits, cs);
+        }
+        if (e == hipSuccess) e = launch_bfs_persistent(ms, P, blocks, cs);
+        if (e == hipSuccess) {
+            if (ms) e = launch_ms_output(d.n, count, d.perm, w.lev, out, cs);
+            else if (d.inv) e = launch_unpermute_u32(d.n, d.perm, level, out, cs);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(e, "recording the persistent traversal"); }
+        if (e2 != hipSuccess) return hip_fail(e2, "graph capture");
+        w.graph = graph;
+        HIP_TRY(hipGraphInstantiate(&w.graph_exec, w.graph, nullptr, nullptr, 0), "graph instantiation");
+        w.graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(w.graph_exec, s), "graph launch");
+    HIP_TRY(hipMemcpyAsync(w.ps_host, w.ps, sizeof(PersistState), hipMemcpyDeviceToHost, s), "reading state");
+    HIP_TRY(hipStreamSynchronize(s), "persistent traversal");
+    if (w.ps_host->error)
+        return fail(WEDGE_ERR_HIP, "persistent traversal: a grid barrier passed its deadline "
+                                   "(blocks not co-resident or WEDGE_BARRIER_TIMEOUT_MS too small)");
+    const uint32_t iters = w.ps_host->iters;
+    const uint32_t nrec = std::min(iters, w.trace_cap);
+    if (nrec) {
+        HIP_TRY(hipMemcpy(w.trace_host, w.trace, (size_t)nrec * sizeof(wedge_iter_record), hipMemcpyDeviceToHost), "reading trace");
+    }
+    for (uint32_t k = 0; k < nrec; ++k) {
+        const wedge_iter_record& r = w.trace_host[k];
+        if (r.mode) { local.wedge_iters++; local.edges_scanned += r.marked_chunks << c.lc; }
+        else { local.full_iters++; local.edges_scanned += d.m; }
+        if (o.trace && k < o.trace_cap) o.trace[k] = r;
+    }
+    local.iterations = iters;
+    local.pull_launches = 1;
+    if (w.ps_host->not_converged) return fail(WEDGE_ERR_NOT_CONVERGED, "max_iters reached with a non-empty frontier");
+    return WEDGE_OK;
+}
+
+// BFS from every root at once (one traversal; with disjoint parts, the level
+// of each vertex is the one from its own part's root).
+wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t count, uint32_t* out,
+                           const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
+    const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
+    wedge_status st = check_run(g, out, &o);
+    if (st != WEDGE_OK) return st;
+    const DevGraph& d = g->dev;
+    if (count && !roots) return fail(WEDGE_ERR_INVALID_ARG, "sources pointer is null");
+    for (uint32_t i = 0; i < count; ++i)
+        if (roots[i] >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
+    RunGuard guard(g->busy);
+    if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
+    wedge_stats local{};
+    const double t0 = now_ms();
+    if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
+    const LoopCfg c = loop_cfg(o, d, 10000u, 32u);
+    if ((st = ensure_workspace(g, c.lc, true, true)) != WEDGE_OK) return st;
+    if ((st = ensure_batch(g, count ? count : 1, 0)) != WEDGE_OK) return st;
+    Workspace& w = g->ws;
+    if ((st = upload_roots(g, roots, count, s)) != WEDGE_OK) return st;
+    if (o.flags & WEDGE_RUN_PERSISTENT) {
+        st = run_persistent(g, false, count, out, o, c, s, local);
+    } else {
+        if ((st = clear_bitmaps(g, c, s)) != WEDGE_OK) return st;
+        uint32_t* val = d.inv ? w.val : out;
+        HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
+        HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
+        HIP_TRY(launch_roots_seed(w.roots, count, val, w.fbits, s), "seeding roots");
+        HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr,
+                                w.fcur, s), "listing roots");
+        st = iterate(
+            g, o, c, s, local, t0, stats,
+            [&](uint32_t k, bool wedge_mode, uint64_t maxk, int) {
+                return wedge_mode ? launch_pull_chunks(kBfs, d, k, c.lc, w.chunks, w.ctl, maxk, val,
+                                                       nullptr, w.fcur, w.fbits, s)
+                                  : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, s);
+            },
+            [&](uint32_t, int cur) {
+                return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1],
+                                       w.ctl, nullptr, val, w.fcur, s);
+            });
+        if (st == WEDGE_OK && d.inv) {
+            HIP_TRY(launch_unpermute_u32(d.n, d.perm, val, out, s), "writing results");
+            HIP_TRY(hipStreamSynchronize(s), "writing results");
+        }
+    }
+    local.ms = now_ms() - t0;
+    if (stats) *stats = local;
+    return st;
+}
+
+// Multi-source BFS with 64-bit masks.
+wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t count, uint32_t* out,
+                             const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
+    const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
+    wedge_status st = check_run(g, out, &o);
+    if (st != WEDGE_OK) return st;
+    const DevGraph& d = g->dev;
+    if (count < 1 || count > 64) return fail(WEDGE_ERR_INVALID_ARG, "count must be in [1, 64]");
+    if (!srcs) return fail(WEDGE_ERR_INVALID_ARG, "sources pointer is null");
+    for (uint32_t i = 0; i < count; ++i)
+        if (srcs[i] >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
+    RunGuard guard(g->busy);
+    if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
+    wedge_stats local{};
+    const double t0 = now_ms();
+    if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
+    const LoopCfg c = loop_cfg(o, d, 10000u, 32u);
+    if ((st = ensure_workspace(g, c.lc, true, true)) != WEDGE_OK) return st;
+    if ((st = ensure_batch(g, count, count)) != WEDGE_OK) return st;
+    Workspace& w = g->ws;
+    if ((st = upload_roots(g, srcs, count, s)) != WEDGE_OK) return st;
+    const uint64_t all = count == 64 ? ~0ull : ((1ull << count) - 1ull);
+    if (o.flags & WEDGE_RUN_PERSISTENT) {
+        st = run_persistent(g, true, count, out, o, c, s, local);
+    } else {
+        if ((st = clear_bitmaps(g, c, s)) != WEDGE_OK) return st;
+        HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
+        HIP_TRY(hipMemsetAsync(w.visited, 0, (size_t)d.n * 8, s), "clearing masks");
+        HIP_TRY(hipMemsetAsync(w.masks[0], 0, (size_t)d.n * 8, s), "clearing masks");
+        HIP_TRY(hipMemsetAsync(w.masks[1], 0, (size_t)d.n * 8, s), "clearing masks");
+        HIP_TRY(launch_fill_u32_kernel(w.lev, (uint64_t)d.n * count, kInf, s), "initialising levels");
+        HIP_TRY(launch_ms_seed(w.roots, count, w.masks[0], w.fbits, s), "seeding sources");
+        HIP_TRY(launch_ms_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, w.fcur,
+                                   w.visited, w.masks[1], w.masks[0], w.lev, count, 0, s), "listing sources");
+        st = iterate(
+            g, o, c, s, local, t0, stats,
+            [&](uint32_t k, bool wedge_mode, uint64_t maxk, int) {
+                const uint64_t* mc = w.masks[k & 1];
+                uint64_t* mn = w.masks[(k & 1) ^ 1];
+                return wedge_mode ? launch_ms_pull_chunks(d, c.lc, w.chunks, w.ctl, maxk, all, w.visited,
+                                                          mc, mn, w.fbits, s)
+                                  : launch_ms_pull_full(d, all, w.visited, mc, mn, w.fbits, s);
+            },
+            [&](uint32_t k, int cur) {
+                return launch_ms_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1],
+                                          w.ctl, w.fcur, w.visited, w.masks[k & 1],
+                                          w.masks[(k & 1) ^ 1], w.lev, count, k + 1, s);
+            });
+        if (st == WEDGE_OK) {
+            HIP_TRY(launch_ms_output(d.n, count, d.perm, w.lev, out, s), "writing results");
+            HIP_TRY(hipStreamSynchronize(s), "writing results");
+        }
+    }
+    local.ms = now_ms() - t0;
+    if (stats) *stats = local;
+    return st;
 }
 
 }  // namespace
@@ -582,6 +928,144 @@ wedge_status wedge_frontier_translate(wedge_graph_t g, const uint32_t* frontier_
     HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
     HIP_TRY(hipStreamSynchronize(s), "frontier translation");
     *marked = w.ctl_host->marked >> kDegBits;
+    return WEDGE_OK;
+}
+
+wedge_status wedge_bfs_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t count,
+                                   uint32_t* levels_dev, const wedge_opts* opts,
+                                   hipStream_t stream, wedge_stats* stats) {
+    return run_multisource(g, srcs, count, levels_dev, opts, stream, stats);
+}
+
+wedge_status wedge_graph_create_batch_csr(uint32_t count, const uint32_t* n_each,
+                                          const uint64_t* const* row_off,
+                                          const uint32_t* const* col, uint32_t flags,
+                                          hipStream_t stream, wedge_graph_t* out) {
+    if (!out) return fail(WEDGE_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!count || !n_each || !row_off || !col) return fail(WEDGE_ERR_INVALID_ARG, "null argument or empty batch");
+    if (flags & WEDGE_INPUT_DEVICE) return fail(WEDGE_ERR_INVALID_ARG, "batch parts must be host arrays");
+    try {
+        std::vector<uint64_t> first(count + 1, 0);
+        uint64_t m = 0;
+        for (uint32_t i = 0; i < count; ++i) {
+            if (!row_off[i]) return fail(WEDGE_ERR_INVALID_ARG, "part offsets pointer is null");
+            first[i + 1] = first[i] + n_each[i];
+            m += row_off[i][n_each[i]];
+        }
+        if (first[count] >= (1ull << 31)) return fail(WEDGE_ERR_BAD_GRAPH, "batch has >= 2^31 vertices");
+        if (m >= (1ull << 32)) return fail(WEDGE_ERR_BAD_GRAPH, "batch has >= 2^32 edges");
+        const uint32_t n = (uint32_t)first[count];
+        std::vector<uint64_t> ro((size_t)n + 1, 0);
+        std::vector<uint32_t> cl(m ? m : 1);
+        uint64_t e = 0;
+        for (uint32_t i = 0; i < count; ++i) {
+            const uint64_t* r = row_off[i];
+            const uint32_t ni = n_each[i];
+            if (r[0] != 0) return fail(WEDGE_ERR_BAD_GRAPH, "part offsets must start at 0");
+            if (r[ni] && !col[i]) return fail(WEDGE_ERR_INVALID_ARG, "part edge array pointer is null");
+            for (uint32_t v = 0; v < ni; ++v) {
+                if (r[v + 1] < r[v]) return fail(WEDGE_ERR_BAD_GRAPH, "part offsets are not non-decreasing");
+                ro[first[i] + v + 1] = e + r[v + 1];
+            }
+            for (uint64_t j = 0; j < r[ni]; ++j) {
+                if (col[i][j] >= ni) return fail(WEDGE_ERR_BAD_GRAPH, "part neighbour id out of range");
+                cl[e + j] = (uint32_t)first[i] + col[i][j];
+            }
+            e += r[ni];
+        }
+        wedge_status st = create(true, n, m, ro.data(), cl.data(), nullptr, flags, stream, out);
+        if (st != WEDGE_OK) return st;
+        (*out)->parts = first;
+        return WEDGE_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(WEDGE_ERR_OOM, "host allocation failed while building the batch");
+    }
+}
+
+wedge_status wedge_graph_batch_parts(wedge_graph_t g, uint64_t* first, uint32_t cap,
+                                     uint32_t* count) {
+    if (!g || !count) return fail(WEDGE_ERR_INVALID_ARG, "null argument");
+    if (g->parts.empty()) return fail(WEDGE_ERR_UNSUPPORTED, "not a batch graph");
+    *count = (uint32_t)g->parts.size() - 1;
+    if (first) {
+        if (cap < g->parts.size()) return fail(WEDGE_ERR_INVALID_ARG, "cap must be at least count + 1");
+        std::memcpy(first, g->parts.data(), g->parts.size() * sizeof(uint64_t));
+    }
+    return WEDGE_OK;
+}
+
+wedge_status wedge_bfs_batch(wedge_graph_t g, const uint32_t* srcs, uint32_t* levels_dev,
+                             const wedge_opts* opts, hipStream_t stream, wedge_stats* stats) {
+    if (!g) return fail(WEDGE_ERR_INVALID_ARG, "graph is null");
+    if (g->parts.empty()) return fail(WEDGE_ERR_UNSUPPORTED, "not a batch graph (wedge_graph_create_batch_csr)");
+    if (!srcs) return fail(WEDGE_ERR_INVALID_ARG, "sources pointer is null");
+    const uint32_t count = (uint32_t)g->parts.size() - 1;
+    std::vector<uint32_t> roots(count);
+    for (uint32_t i = 0; i < count; ++i) {
+        if ((uint64_t)srcs[i] >= g->parts[i + 1] - g->parts[i])
+            return fail(WEDGE_ERR_INVALID_ARG, "source out of range in part " + std::to_string(i));
+        roots[i] = (uint32_t)(g->parts[i] + srcs[i]);
+    }
+    return run_bfs_roots(g, roots.data(), count, levels_dev, opts, stream, stats);
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<uint32_t, uint32_t, int>, wedge_opts> g_tune;
+
+int size_bucket(uint64_t m) { int b = 0; while ((1ull << b) < m) ++b; return b; }
+}  // namespace
+
+wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs, uint32_t count,
+                            uint32_t* out_dev, hipStream_t stream, wedge_opts* best,
+                            double* best_ms) {
+    if (!g || !srcs || !out_dev || !best) return fail(WEDGE_ERR_INVALID_ARG, "null argument");
+    if (kind > WEDGE_TUNE_BATCH) return fail(WEDGE_ERR_INVALID_ARG, "unknown kind");
+    const wedge_opts base = *best;
+    struct Cand { uint32_t chunk, persistent, bpc; };
+    std::vector<Cand> cands;
+    for (uint32_t c : {16u, 32u, 64u}) {
+        cands.push_back({c, 0, 0});
+        for (uint32_t b : {1u, 2u, 4u, 0u}) cands.push_back({c, 1, b});
+    }
+    double best_t = 1e300;
+    wedge_opts win = base;
+    for (const Cand& cd : cands) {
+        wedge_opts o = base;
+        o.chunk_edges = cd.chunk;
+        o.flags = (base.flags & ~(WEDGE_RUN_PERSISTENT | WEDGE_RUN_TIME_ITERS | WEDGE_RUN_TIME_PULL)) |
+                  (cd.persistent ? WEDGE_RUN_PERSISTENT : 0u);
+        o.blocks_per_cu = cd.bpc;
+        o.trace = nullptr;
+        o.trace_cap = 0;
+        double t = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            wedge_stats st{};
+            wedge_status r;
+            if (kind == WEDGE_TUNE_SINGLE) r = wedge_bfs(g, srcs[0], out_dev, &o, stream, &st);
+            else if (kind == WEDGE_TUNE_MULTISOURCE) r = wedge_bfs_multisource(g, srcs, count, out_dev, &o, stream, &st);
+            else r = wedge_bfs_batch(g, srcs, out_dev, &o, stream, &st);
+            if (r != WEDGE_OK) return r;
+            t = std::min(t, st.ms);
+        }
+        if (t < best_t) { best_t = t; win = o; }
+    }
+    *best = win;
+    if (best_ms) *best_ms = best_t;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(kind, count, size_bucket(g->dev.m))] = win;
+    return WEDGE_OK;
+}
+
+wedge_status wedge_tune_lookup(uint32_t kind, uint32_t count, uint64_t m, wedge_opts* opts) {
+    if (!opts) return fail(WEDGE_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(kind, count, size_bucket(m)));
+    if (it == g_tune.end()) return fail(WEDGE_ERR_UNSUPPORTED, "no tuned entry for this kind and size");
+    opts->chunk_edges = it->second.chunk_edges;
+    opts->flags = (opts->flags & ~WEDGE_RUN_PERSISTENT) | (it->second.flags & WEDGE_RUN_PERSISTENT);
+    opts->blocks_per_cu = it->second.blocks_per_cu;
     return WEDGE_OK;
 }
 

@@ -1,0 +1,472 @@
+// Batched BFS on gfx950: many sources as 64-bit masks, many graphs as one
+// disjoint union, and a persistent kernel that runs a whole traversal in one
+// launch.
+//
+// Multi-source BFS follows the bit-parallel formulation of Then et al. ("The
+// More the Merrier", PVLDB 8(4), 2014) on top of the Wedge pull: vertex v
+// keeps visited[v], cur[v] and nxt[v] as 64-bit masks (bit s = source s), and
+// one pull sets nxt[v] |= OR over in-edges of cur[u], minus visited[v]. The
+// vertex frontier the Wedge machinery sees is {v : cur[v] != 0}, so gating,
+// translation and compaction are exactly those of single-source BFS.
+#include "device_common.h"
+
+namespace wedge {
+namespace {
+
+using namespace dev;
+
+// ------------------------------------------------------------ pull (masks)
+template <int R>
+__device__ __forceinline__ void ms_pull_lanes(const GraphArgs& g, const uint32_t (&p)[R],
+                                              const bool (&valid)[R], uint64_t all,
+                                              const uint64_t* __restrict__ visited,
+                                              const uint64_t* __restrict__ cur,
+                                              uint64_t* __restrict__ nxt,
+                                              uint64_t* __restrict__ fbits) {
+    const int lane = lane_id();
+    uint32_t dst[R], u[R];
+    uint64_t vis[R], x[R];
+    bool need[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst_of(g, p[i]) : kInf;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        vis[i] = valid[i] ? visited[dst[i]] : all;
+        need[i] = (vis[i] & all) != all;  // a destination seen by every source is skipped
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) u[i] = need[i] ? ld_stream(g.in_src + p[i]) : 0u;
+#pragma unroll
+    for (int i = 0; i < R; ++i) x[i] = need[i] ? cur[u[i]] : 0ull;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t prev = __shfl_up(dst[i], 1, 64);
+        const bool head = lane == 0 || prev != dst[i];
+        const uint64_t heads = __ballot(head);
+        const uint64_t orv = seg_reduce(x[i], seg_span(heads, lane),
+                                        [](uint64_t a, uint64_t b) { return a | b; });
+        if (head && dst[i] != kInf) {
+            const uint64_t nb = orv & ~vis[i] & all;
+            if (nb) {
+                atomicOr(reinterpret_cast<unsigned long long*>(nxt + dst[i]),
+                         (unsigned long long)nb);
+                set_bit(fbits, dst[i]);
+            }
+        }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void ms_pull_rows(const GraphArgs& g, uint64_t r0, uint64_t all,
+                                             const uint64_t* visited, const uint64_t* cur,
+                                             uint64_t* nxt, uint64_t* fbits) {
+    const int lane = lane_id();
+    uint32_t p[R];
+    bool valid[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint64_t pp = (r0 + i) * 64 + lane;
+        valid[i] = pp < g.m;
+        p[i] = (uint32_t)pp;
+    }
+    ms_pull_lanes<R>(g, p, valid, all, visited, cur, nxt, fbits);
+}
+
+template <int R>
+__device__ __forceinline__ void ms_pull_slots(const GraphArgs& g, uint64_t s0, uint64_t slots,
+                                              int lc, const uint32_t* list, uint64_t K,
+                                              uint64_t all, const uint64_t* visited,
+                                              const uint64_t* cur, uint64_t* nxt,
+                                              uint64_t* fbits) {
+    const int lane = lane_id();
+    uint32_t p[R];
+    bool valid[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint64_t pp = s0 + i < slots ? chunk_slot_pos(s0 + i, lane, lc, list, K) : ~0ull;
+        valid[i] = pp < g.m;
+        p[i] = (uint32_t)pp;
+    }
+    ms_pull_lanes<R>(g, p, valid, all, visited, cur, nxt, fbits);
+}
+
+// Commit of one multi-source iteration, over the next-frontier bitmap: list the
+// vertices (with out-degree prefix), add the new masks to visited, write level
+// `level` for every newly set (vertex, source) bit into lev[v*K + s], clear
+// the masks of the frontier being retired, and move the bitmap to fcur.
+__device__ __forceinline__ void ms_finalize_block(
+    uint64_t vblock, uint64_t* bits, uint64_t words, uint32_t n, const uint32_t* row_off,
+    uint32_t* list, uint32_t* degpre, Ctl* ctl, uint64_t* fcur, uint64_t* visited,
+    uint64_t* retire, const uint64_t* nxt, uint32_t* lev, uint32_t K, uint32_t level) {
+    bitmap_compact_block_ex<true, true, kCompactWords>(
+        vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
+        [&](uint32_t v) {
+            const uint64_t nb = nxt[v];
+            visited[v] |= nb;
+            uint64_t b = nb;
+            uint32_t* row = lev + (uint64_t)v * K;
+            while (b) {
+                const int s = __builtin_ctzll(b);
+                row[s] = level;
+                b &= b - 1;
+            }
+        },
+        [&](uint32_t v) { retire[v] = 0ull; });
+}
+
+__device__ __forceinline__ void bfs_finalize_block(uint64_t vblock, uint64_t* bits,
+                                                   uint64_t words, uint32_t n,
+                                                   const uint32_t* row_off, uint32_t* list,
+                                                   uint32_t* degpre, Ctl* ctl, uint64_t* fcur) {
+    bitmap_compact_block_ex<true, true, kCompactWords>(
+        vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
+        [](uint32_t) {}, [](uint32_t) {});
+}
+
+// --------------------------------------------------- per-iteration kernels
+
+__global__ __launch_bounds__(kBlock) void k_ms_pull_full(GraphArgs g, uint64_t all,
+                                                         const uint64_t* __restrict__ visited,
+                                                         const uint64_t* __restrict__ cur,
+                                                         uint64_t* __restrict__ nxt,
+                                                         uint64_t* __restrict__ fbits) {
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t r0 = wave * kPullRows;
+    if (r0 >= g.rows) return;
+    ms_pull_rows<kPullRows>(g, r0, all, visited, cur, nxt, fbits);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ms_pull_chunks(GraphArgs g, int lc,
+                                                           const uint32_t* __restrict__ list,
+                                                           const unsigned long long* marked,
+                                                           uint64_t all,
+                                                           const uint64_t* __restrict__ visited,
+                                                           const uint64_t* __restrict__ cur,
+                                                           uint64_t* __restrict__ nxt,
+                                                           uint64_t* __restrict__ fbits) {
+    const uint64_t K = *marked >> kDegBits;
+    const uint64_t slots = chunk_slots(K, lc);
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t s0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kPullRows;
+         s0 < slots; s0 += nwaves * kPullRows)
+        ms_pull_slots<kPullRows>(g, s0, slots, lc, list, K, all, visited, cur, nxt, fbits);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ms_finalize(uint64_t* bits, uint64_t words,
+                                                        uint32_t n, const uint32_t* row_off,
+                                                        uint32_t* list, uint32_t* degpre,
+                                                        Ctl* ctl, uint64_t* fcur,
+                                                        uint64_t* visited, uint64_t* retire,
+                                                        const uint64_t* nxt, uint32_t* lev,
+                                                        uint32_t K, uint32_t level) {
+    ms_finalize_block(blockIdx.x, bits, words, n, row_off, list, degpre, ctl, fcur, visited,
+                      retire, nxt, lev, K, level);
+}
+
+// Sources of a multi-source run: bit s of nxt[src[s]], and the vertex bit.
+__global__ void k_ms_seed(const uint32_t* __restrict__ srcs, uint32_t K, uint64_t* nxt,
+                          uint64_t* fbits) {
+    const uint32_t s = threadIdx.x;
+    if (blockIdx.x == 0 && s < K) {
+        atomicOr(reinterpret_cast<unsigned long long*>(nxt + srcs[s]), 1ull << s);
+        set_bit(fbits, srcs[s]);
+    }
+}
+
+// Roots of a multi-root BFS: level 0 and the vertex bit.
+__global__ void k_roots_seed(const uint32_t* __restrict__ roots, uint32_t count,
+                             uint32_t* __restrict__ level, uint64_t* fbits) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        level[roots[i]] = 0;
+        set_bit(fbits, roots[i]);
+    }
+}
+
+// Caller layout of multi-source levels: out[s*n + v] = lev[perm[v]*K + s].
+__global__ void k_ms_output(uint32_t n, uint32_t K, const uint32_t* __restrict__ perm,
+                            const uint32_t* __restrict__ lev, uint32_t* __restrict__ out) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t* row = lev + (uint64_t)(perm ? perm[v] : v) * K;
+        for (uint32_t s = 0; s < K; ++s) out[(uint64_t)s * n + v] = row[s];
+    }
+}
+
+__global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t count, uint64_t value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_fill_u32b(uint32_t* __restrict__ p, uint64_t count, uint32_t value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// ------------------------------------------------------- persistent kernel
+//
+// One launch runs every iteration: the blocks stride over each phase's work,
+// separated by grid-wide barriers, and block 0 evaluates the fullness gate
+// between iterations from the device counters, so no host round trip is
+// needed. The grid is sized from the occupancy API so that every block is
+// resident; each barrier wait is additionally bounded by a wall-clock
+// deadline, after which the kernel records an error and every block exits.
+
+__device__ __forceinline__ unsigned ld_acq(unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ bool grid_sync(PersistState* ps, uint64_t timeout_ticks) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        const unsigned gen = ld_acq(&ps->bar_gen);
+        const unsigned arrived = atomicAdd(&ps->bar_count, 1u);
+        if (arrived == gridDim.x - 1) {
+            atomicExch(&ps->bar_count, 0u);
+            __threadfence();
+            atomicAdd(&ps->bar_gen, 1u);
+        } else {
+            const uint64_t deadline = wall_clock64() + timeout_ticks;
+            while (ld_acq(&ps->bar_gen) == gen) {
+                if (ld_acq(&ps->error)) { ok = 0; break; }
+                if (wall_clock64() > deadline) {
+                    atomicExch(&ps->error, 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        if (ld_acq(&ps->error)) ok = 0;
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <bool MS>
+__global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
+    const GraphArgs g = P.g;
+    const uint64_t fwords = ((uint64_t)P.n + 63) / 64;
+    const uint64_t fblocks = (fwords + kCompactWords * kWavesPerBlock - 1) / (kCompactWords * kWavesPerBlock);
+    const uint64_t gwave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    PersistState* ps = P.ps;
+    Ctl* ctl = P.ctl;
+    uint64_t* ma = P.masks[0];
+    uint64_t* mb = P.masks[1];
+
+    // the seeds were written as the output of "iteration -1": list them
+    for (uint64_t vb = blockIdx.x; vb < fblocks; vb += gridDim.x) {
+        if (MS) ms_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0], ctl,
+                                  P.fcur, P.visited, mb, ma, P.lev, P.K, 0u);
+        else bfs_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0], ctl,
+                                P.fcur);
+    }
+    if (!grid_sync(ps, P.timeout_ticks)) return;
+
+    for (uint32_t k = 0;; ++k) {
+        const int cur = k & 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            // close the previous iteration's record, then decide this one
+            if (k > 0 && k - 1 < P.trace_cap && ps->mode)
+                P.trace[k - 1].marked_chunks = ctl->marked >> kDegBits;
+            const unsigned long long fcount = ctl->ftotal;
+            const unsigned long long flisted = ctl->fnext >> kDegBits;
+            const unsigned long long active = ctl->fnext & kDegMask;
+            unsigned done = 0, mode = 0;
+            if (fcount == 0) {
+                done = 1;
+            } else if (k >= P.max_iters) {
+                done = 1;
+                ps->not_converged = 1;
+            } else {
+                mode = P.gate == WEDGE_GATE_ALWAYS_WEDGE ? 1u
+                     : P.gate == WEDGE_GATE_ALWAYS_FULL ? 0u
+                     : (active < P.thr ? 1u : 0u);
+                if (k < P.trace_cap) {
+                    wedge_iter_record r;
+                    r.iter = k;
+                    r.mode = mode;
+                    r.chunk_edges = mode ? (1u << P.lc) : 0u;
+                    r.reserved = 0;
+                    r.frontier = fcount;
+                    r.active_edges = active;
+                    r.marked_chunks = 0;
+                    r.ms = 0.f;
+                    r.reserved2 = 0.f;
+                    P.trace[k] = r;
+                }
+            }
+            ps->iters = k;
+            ps->done = done;
+            ps->mode = mode;
+            ps->flisted = flisted;
+            ps->active = active;
+            ctl->fnext = 0;
+            ctl->ftotal = 0;
+            ctl->marked = 0;
+            __threadfence();
+        }
+        if (!grid_sync(ps, P.timeout_ticks)) return;
+        if (__hip_atomic_load(&ps->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        const unsigned mode = __hip_atomic_load(&ps->mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t* mcur = cur ? mb : ma;   // masks of F_k (multi-source)
+        uint64_t* mnxt = cur ? ma : mb;   // masks being built for F_{k+1}
+        if (mode) {
+            const unsigned long long flisted = ps->flisted, active = ps->active;
+            const uint64_t twaves = (active + 64ull * kTranslateEpt - 1) / (64ull * kTranslateEpt);
+            for (uint64_t w = gwave; w < twaves; w += nwaves)
+                translate_wave<kTranslateEpt>(w, P.flist[cur], P.degpre[cur], (uint32_t)flisted,
+                                              (uint32_t)active, P.row_off, P.pos, P.lc,
+                                              reinterpret_cast<uint32_t*>(P.wbits));
+            if (!grid_sync(ps, P.timeout_ticks)) return;
+            const uint64_t cblocks = (P.wwords + kCompactWords * kWavesPerBlock - 1) / (kCompactWords * kWavesPerBlock);
+            for (uint64_t vb = blockIdx.x; vb < cblocks; vb += gridDim.x)
+                bitmap_compact_block<false, false, false, kCompactWords>(
+                    vb, P.wbits, P.wwords, 0xFFFFFFFFu, nullptr, P.chunks, nullptr, &ctl->marked,
+                    nullptr, nullptr, nullptr, nullptr);
+            if (!grid_sync(ps, P.timeout_ticks)) return;
+            const uint64_t K = __hip_atomic_load(&ctl->marked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> kDegBits;
+            const uint64_t slots = chunk_slots(K, P.lc);
+            for (uint64_t s0 = gwave * kPullRows; s0 < slots; s0 += nwaves * kPullRows) {
+                if (MS) {
+                    ms_pull_slots<kPullRows>(g, s0, slots, P.lc, P.chunks, K, P.all, P.visited, mcur,
+                                             mnxt, P.fbits);
+                } else {
+                    const int lane = lane_id();
+                    uint32_t p[kPullRows];
+                    bool valid[kPullRows];
+#pragma unroll
+                    for (int i = 0; i < kPullRows; ++i) {
+                        const uint64_t pp = s0 + i < slots ? chunk_slot_pos(s0 + i, lane, P.lc, P.chunks, K) : ~0ull;
+                        valid[i] = pp < g.m;
+                        p[i] = (uint32_t)pp;
+                    }
+                    pull_lanes<kBfs, kPullRows>(g, p, valid, k, P.level, nullptr, P.fcur, P.fbits);
+                }
+            }
+        } else {
+            for (uint64_t r0 = gwave * kPullRows; r0 < g.rows; r0 += nwaves * kPullRows) {
+                if (MS) {
+                    ms_pull_rows<kPullRows>(g, r0, P.all, P.visited, mcur, mnxt, P.fbits);
+                } else {
+                    const int lane = lane_id();
+                    uint32_t p[kPullRows];
+                    bool valid[kPullRows];
+#pragma unroll
+                    for (int i = 0; i < kPullRows; ++i) {
+                        const uint64_t pp = (r0 + i) * 64 + lane;
+                        valid[i] = pp < g.m;
+                        p[i] = (uint32_t)pp;
+                    }
+                    pull_lanes<kBfs, kPullRows>(g, p, valid, k, P.level, nullptr, P.fcur, P.fbits);
+                }
+            }
+        }
+        if (!grid_sync(ps, P.timeout_ticks)) return;
+        for (uint64_t vb = blockIdx.x; vb < fblocks; vb += gridDim.x) {
+            if (MS) ms_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[cur ^ 1],
+                                      P.degpre[cur ^ 1], ctl, P.fcur, P.visited, mcur, mnxt, P.lev,
+                                      P.K, k + 1);
+            else bfs_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[cur ^ 1],
+                                    P.degpre[cur ^ 1], ctl, P.fcur);
+        }
+        if (!grid_sync(ps, P.timeout_ticks)) return;
+    }
+}
+
+uint32_t grid_for(uint64_t threads, uint32_t cap) {
+    uint64_t b = (threads + kBlock - 1) / kBlock;
+    if (b == 0) b = 1;
+    return (uint32_t)(b < cap ? b : cap);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_ms_pull_full(const DevGraph& g, uint64_t all, const uint64_t* visited,
+                               const uint64_t* cur, uint64_t* nxt, uint64_t* fbits,
+                               hipStream_t s) {
+    if (!g.rows) return hipSuccess;
+    const uint64_t waves = (g.rows + kPullRows - 1) / kPullRows;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    k_ms_pull_full<<<blocks, kBlock, 0, s>>>(args_of(g), all, visited, cur, nxt, fbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_pull_chunks(const DevGraph& g, int lc, const uint32_t* list, const Ctl* ctl,
+                                 uint64_t max_chunks, uint64_t all, const uint64_t* visited,
+                                 const uint64_t* cur, uint64_t* nxt, uint64_t* fbits,
+                                 hipStream_t s) {
+    if (!max_chunks) return hipSuccess;
+    uint64_t waves = (chunk_slots_count(max_chunks, lc) + kPullRows - 1) / kPullRows;
+    if (waves > 256ull * 32) waves = 256ull * 32;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    k_ms_pull_chunks<<<blocks, kBlock, 0, s>>>(args_of(g), lc, list, &ctl->marked, all, visited,
+                                               cur, nxt, fbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
+                              uint32_t* flist, uint32_t* degpre, Ctl* ctl, uint64_t* fcur,
+                              uint64_t* visited, uint64_t* retire, const uint64_t* nxt,
+                              uint32_t* lev, uint32_t K, uint32_t level, hipStream_t s) {
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    if (!words) return hipSuccess;
+    const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    k_ms_finalize<<<blocks, kBlock, 0, s>>>(fbits, words, n, row_off, flist, degpre, ctl, fcur,
+                                            visited, retire, nxt, lev, K, level);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_seed(const uint32_t* srcs, uint32_t K, uint64_t* nxt, uint64_t* fbits,
+                          hipStream_t s) {
+    k_ms_seed<<<1, 64, 0, s>>>(srcs, K, nxt, fbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_roots_seed(const uint32_t* roots, uint32_t count, uint32_t* level,
+                             uint64_t* fbits, hipStream_t s) {
+    if (!count) return hipSuccess;
+    k_roots_seed<<<grid_for(count, 1024), kBlock, 0, s>>>(roots, count, level, fbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_output(uint32_t n, uint32_t K, const uint32_t* perm, const uint32_t* lev,
+                            uint32_t* out, hipStream_t s) {
+    if (!n) return hipSuccess;
+    k_ms_output<<<grid_for(n, 16384), kBlock, 0, s>>>(n, K, perm, lev, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s) {
+    if (!count) return hipSuccess;
+    k_fill_u64<<<grid_for(count, 8192), kBlock, 0, s>>>(p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32_kernel(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s) {
+    if (!count) return hipSuccess;
+    k_fill_u32b<<<grid_for(count, 8192), kBlock, 0, s>>>(p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t persistent_max_blocks(bool ms, int* blocks_per_cu) {
+    return ms ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bfs_persistent<true>, kBlock, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bfs_persistent<false>, kBlock, 0);
+}
+
+hipError_t launch_bfs_persistent(bool ms, const PersistParams& P, uint32_t blocks, hipStream_t s) {
+    if (ms) k_bfs_persistent<true><<<blocks, kBlock, 0, s>>>(P);
+    else k_bfs_persistent<false><<<blocks, kBlock, 0, s>>>(P);
+    return hipGetLastError();
+}
+
+}  // namespace wedge

@@ -11,117 +11,13 @@
 // Every kernel is memory-bound: nothing here is a dense contraction.
 #include <hip/hip_runtime.h>
 
-#include "wedge_internal.h"
+#include "device_common.h"
 
 namespace wedge {
 namespace {
 
-constexpr int kBlock = 256;           // 4 waves
-constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kPullRows = 8;          // rows (64 positions each) per wave in the integer pulls
-constexpr int kTranslateEpt = 4;      // frontier out-edges per lane in the translation
-constexpr int kCompactWords = 8;      // 64-bit bitmap words per wave in the compaction
-constexpr uint32_t kPrEpilogueVerts = 8192;  // vertices per PageRank epilogue block
+using namespace dev;
 
-struct GraphArgs {
-    uint32_t n;
-    uint32_t m;
-    uint32_t rows;
-    const uint32_t* __restrict__ in_src;
-    const uint32_t* __restrict__ in_w;
-    const uint64_t* __restrict__ rowmask;
-    const uint32_t* __restrict__ rowseg;
-    const uint32_t* __restrict__ nzdst;
-};
-
-GraphArgs args_of(const DevGraph& g) {
-    GraphArgs a;
-    a.n = g.n;
-    a.m = (uint32_t)g.m;
-    a.rows = (uint32_t)g.rows;
-    a.in_src = g.in_src;
-    a.in_w = g.in_w;
-    a.rowmask = g.rowmask;
-    a.rowseg = g.rowseg;
-    a.nzdst = g.nzdst;
-    return a;
-}
-
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
-__device__ __forceinline__ uint64_t mask_le(int l) { return l == 63 ? ~0ull : ((2ull << l) - 1ull); }
-__device__ __forceinline__ uint64_t mask_lt(int l) { return (1ull << l) - 1ull; }
-
-template <typename T>
-__device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
-
-// Lanes from `l` up to (excluding) the next segment head.
-__device__ __forceinline__ int seg_span(uint64_t heads, int l) {
-    uint64_t rest = l == 63 ? 0ull : (heads >> (l + 1));
-    return rest ? (int)__builtin_ctzll(rest) + 1 : 64 - l;
-}
-
-// Suffix-doubling reduction restricted to the lane's segment: on return the
-// head lane of each segment holds the reduction of its whole segment, combined
-// in a fixed tree order.
-template <typename T, typename Op>
-__device__ __forceinline__ T seg_reduce(T v, int span, Op op) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        T w = __shfl_down(v, o, 64);
-        if (o < span) v = op(v, w);
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum_tree(T x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-// Largest j in [L, H] with a[j] <= key, a non-decreasing and a[L] <= key;
-// key is the same in every lane. Each step probes 64 points at once, so the
-// search takes ceil(log64(H-L+1)) dependent loads.
-__device__ __forceinline__ uint32_t wave_last_le(const uint32_t* __restrict__ a, uint32_t L,
-                                                 uint32_t H, uint64_t key, int lane) {
-    while (H - L >= 64) {
-        const uint32_t step = (H - L + 63) / 64;
-        const uint64_t probe = (uint64_t)L + (uint64_t)lane * step;
-        const bool ok = probe <= H && a[probe] <= key;
-        const int last = 63 - __clzll(__ballot(ok));
-        L = L + (uint32_t)last * step;
-        H = min(H, L + step - 1);
-    }
-    const uint64_t probe = (uint64_t)L + lane;
-    const bool ok = probe <= H && a[probe] <= key;
-    return L + (uint32_t)(63 - __clzll(__ballot(ok)));
-}
-
-__device__ __forceinline__ bool test_bit(const uint64_t* bits, uint32_t i) {
-    return (reinterpret_cast<const uint32_t*>(bits)[i >> 5] >> (i & 31)) & 1u;
-}
-
-__device__ __forceinline__ void set_bit(uint64_t* bits, uint32_t i) {
-    atomicOr(reinterpret_cast<uint32_t*>(bits) + (i >> 5), 1u << (i & 31));
-}
-
-// Destination owning in-edge position p (valid p < m): the row mask marks
-// where destination segments start; rowseg is the segment at the row start.
-__device__ __forceinline__ uint32_t dst_of(const GraphArgs& g, uint32_t p) {
-    uint32_t r = p >> 6, b = p & 63;
-    uint64_t mk = g.rowmask[r];
-    return g.nzdst[g.rowseg[r] + (uint32_t)__popcll(mk & ~1ull & mask_le((int)b))];
-}
 
 // ------------------------------------------------------------ small kernels
 
@@ -205,40 +101,8 @@ __global__ __launch_bounds__(kBlock) void k_translate(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ row_off,
                                                       const uint32_t* __restrict__ pos, int lc,
                                                       uint32_t* __restrict__ wbits32) {
-    const int lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t base = wave * 64ull * EPT;
-    if (base >= active) return;
-    const uint64_t end = min<uint64_t>(base + 64ull * EPT, active);
-    // frontier index range [lo, hi] covering edges [base, end)
-    auto last_le = [&](uint64_t a, uint32_t L, uint32_t H) {
-        while (L < H) {
-            uint32_t M = (L + H + 1) >> 1;
-            if (degpre[M] <= a) L = M; else H = M - 1;
-        }
-        return L;
-    };
-    const uint32_t lo = wave_last_le(degpre, 0, fcount - 1, base, lane);
-    const uint32_t hi = wave_last_le(degpre, lo, fcount - 1, end - 1, lane);
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const uint64_t a = base + (uint64_t)i * 64 + lane;
-        const bool valid = a < end;
-        uint32_t key = kInf, bit = 0;
-        if (valid) {
-            uint32_t j = last_le(a, lo, hi);
-            uint32_t u = flist[j];
-            uint32_t q = row_off[u] + (uint32_t)(a - degpre[j]);
-            uint32_t c = pos[q] >> lc;
-            key = c >> 5;
-            bit = 1u << (c & 31);
-        }
-        uint32_t prev = __shfl_up(key, 1, 64);
-        bool head = lane == 0 || prev != key;
-        uint64_t heads = __ballot(head);
-        bit = seg_reduce(bit, seg_span(heads, lane), [](uint32_t x, uint32_t y) { return x | y; });
-        if (head && valid) atomicOr(wbits32 + key, bit);
-    }
+    translate_wave<EPT>(wave, flist, degpre, fcount, active, row_off, pos, lc, wbits32);
 }
 
 // ------------------------------------------------------- bitmap compaction
@@ -262,72 +126,8 @@ __global__ __launch_bounds__(kBlock) void k_bitmap_compact(
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
     uint64_t* __restrict__ copy_to) {
-    __shared__ unsigned long long s_wave[kWavesPerBlock];
-    __shared__ unsigned long long s_all[kWavesPerBlock];
-    __shared__ unsigned long long s_base;
-    const int lane = lane_id();
-    const int wid = threadIdx.x >> 6;
-    const uint64_t w0 = ((uint64_t)blockIdx.x * kWavesPerBlock + wid) * G;
-    uint64_t mk[G], lm[G];
-    uint32_t deg[G];
-    uint64_t cnt = 0, all = 0, dsum = 0;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const uint64_t wi = w0 + g;
-        mk[g] = wi < words ? bits[wi] : 0ull;
-        lm[g] = mk[g];
-        deg[g] = 0;
-        if (mk[g]) {
-            all += __popcll(mk[g]);
-            if (DEG) {
-                if ((mk[g] >> lane) & 1ull) {
-                    uint32_t v = (uint32_t)(wi * 64 + lane);
-                    deg[g] = row_off[v + 1] - row_off[v];
-                }
-                // vertices without out-edges are counted but not listed
-                lm[g] = __ballot(deg[g] != 0);
-                dsum += wave_sum_tree(deg[g]);
-            }
-            cnt += __popcll(lm[g]);
-        }
-    }
-    if (lane == 0) { s_wave[wid] = (cnt << kDegBits) | dsum; s_all[wid] = all; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0, a = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) { t += s_wave[i]; a += s_all[i]; }
-        s_base = t ? atomicAdd(counter, t) : 0ull;
-        if (total && a) atomicAdd(total, a);
-    }
-    __syncthreads();
-    unsigned long long base = s_base;
-    for (int i = 0; i < wid; ++i) base += s_wave[i];
-    uint32_t cb = (uint32_t)(base >> kDegBits);
-    uint64_t db = base & kDegMask;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const uint64_t wi = w0 + g;
-        if (COPY && lane == 0 && wi < words) copy_to[wi] = mk[g];
-        if (!mk[g]) continue;
-        const uint32_t v = (uint32_t)(wi * 64 + lane);
-        if (COMMIT && ((mk[g] >> lane) & 1ull) && v < limit) val_prev[v] = val[v];
-        if (lane == 0) bits[wi] = 0ull;
-        if (!lm[g]) continue;
-        const bool act = (lm[g] >> lane) & 1ull;
-        const uint32_t rank = (uint32_t)__popcll(lm[g] & mask_lt(lane));
-        uint32_t dex = 0, dtot = 0;
-        if (DEG) {
-            uint32_t inc = wave_incl_scan(deg[g], lane);
-            dex = inc - deg[g];
-            dtot = __shfl(inc, 63, 64);
-        }
-        if (act && v < limit) {
-            list[cb + rank] = v;
-            if (DEG) degpre[cb + rank] = (uint32_t)(db + dex);
-        }
-        cb += (uint32_t)__popcll(lm[g]);
-        db += dtot;
-    }
+    bitmap_compact_block<DEG, COMMIT, COPY, G>(blockIdx.x, bits, words, limit, row_off, list,
+                                               degpre, counter, total, val_prev, val, copy_to);
 }
 
 // ------------------------------------------------------------- the pulls
@@ -355,70 +155,6 @@ __global__ __launch_bounds__(kBlock) void k_bitmap_compact(
 // Superfluous edges (chunk members that are not active) never lower a value,
 // which is why any chunk granularity, or none, gives the same result
 // (Frontier Transformation, "Frontier Precision").
-template <int APP, int R>
-__device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&p)[R],
-                                           const bool (&valid)[R], uint32_t iter,
-                                           uint32_t* __restrict__ val,
-                                           const uint32_t* __restrict__ val_prev,
-                                           const uint64_t* __restrict__ fcur,
-                                           uint64_t* __restrict__ fbits) {
-    const int lane = lane_id();
-    uint32_t dst[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst_of(g, p[i]) : kInf;
-
-    if (APP == kBfs) {
-        bool need[R];
-        uint32_t u[R];
-#pragma unroll
-        for (int i = 0; i < R; ++i) need[i] = valid[i] && val[dst[i]] == kInf;
-#pragma unroll
-        for (int i = 0; i < R; ++i) u[i] = need[i] ? ld_stream(g.in_src + p[i]) : 0u;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const bool found = need[i] && test_bit(fcur, u[i]);
-            const uint32_t prev = __shfl_up(dst[i], 1, 64);
-            const bool head = lane == 0 || prev != dst[i];
-            const uint64_t heads = __ballot(head);
-            const uint64_t fm = __ballot(found);
-            if (head && dst[i] != kInf) {
-                const int span = seg_span(heads, lane);
-                const uint64_t seg = span >= 64 ? ~0ull : ((1ull << span) - 1ull);
-                if ((fm >> lane) & seg) {
-                    val[dst[i]] = iter + 1;
-                    set_bit(fbits, dst[i]);
-                }
-            }
-        }
-    } else {
-        uint32_t u[R], x[R], cand[R];
-#pragma unroll
-        for (int i = 0; i < R; ++i) u[i] = valid[i] ? ld_stream(g.in_src + p[i]) : 0u;
-#pragma unroll
-        for (int i = 0; i < R; ++i) x[i] = valid[i] ? val_prev[u[i]] : kInf;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            if (APP == kCc) cand[i] = x[i];
-            else cand[i] = x[i] != kInf ? x[i] + ld_stream(g.in_w + p[i]) : kInf;
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const uint32_t prev = __shfl_up(dst[i], 1, 64);
-            const bool head = lane == 0 || prev != dst[i];
-            const uint64_t heads = __ballot(head);
-            const uint32_t best = seg_reduce(cand[i], seg_span(heads, lane),
-                                             [](uint32_t a, uint32_t b) { return a < b ? a : b; });
-            if (head && best != kInf) {
-                const uint32_t v = dst[i];
-                if (best < val[v]) {
-                    const uint32_t old = atomicMin(val + v, best);
-                    if (best < old) set_bit(fbits, v);
-                }
-            }
-        }
-    }
-}
-
 // Full pull: wave w covers rows [w*R, w*R + R), i.e. every in-edge once.
 template <int APP, int R>
 __global__ __launch_bounds__(kBlock) void k_pull_full(GraphArgs g, uint32_t iter,
@@ -455,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_chunks(GraphArgs g, uint32_t it
                                                         uint64_t* __restrict__ fbits) {
     const int lane = lane_id();
     const uint64_t K = *marked >> kDegBits;
-    const uint64_t slots = lc <= 6 ? (K + (64u >> lc) - 1) / (64u >> lc) : K << (lc - 6);
+    const uint64_t slots = chunk_slots(K, lc);
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     for (uint64_t s0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * R; s0 < slots;
          s0 += nwaves * R) {
@@ -463,17 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_chunks(GraphArgs g, uint32_t it
         bool valid[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const uint64_t s = s0 + i;
-            uint64_t ci, off;
-            if (lc <= 6) {
-                ci = s * (64u >> lc) + ((uint32_t)lane >> lc);
-                off = (uint32_t)lane & ((1u << lc) - 1u);
-            } else {
-                ci = s >> (lc - 6);
-                off = ((s & ((1ull << (lc - 6)) - 1ull)) << 6) + lane;
-            }
-            uint64_t pp = ~0ull;
-            if (s < slots && ci < K) pp = ((uint64_t)list[ci] << lc) + off;
+            const uint64_t pp = s0 + i < slots ? chunk_slot_pos(s0 + i, lane, lc, list, K) : ~0ull;
             valid[i] = pp < g.m;
             p[i] = (uint32_t)pp;
         }

@@ -73,6 +73,39 @@ struct DevGraph {
     uint32_t* inv = nullptr;   // internal -> original (null: identity)
 };
 
+// Kernel view of a device graph.
+struct GraphArgs {
+    uint32_t n;
+    uint32_t m;
+    uint32_t rows;
+    const uint32_t* __restrict__ in_src;
+    const uint32_t* __restrict__ in_w;
+    const uint64_t* __restrict__ rowmask;
+    const uint32_t* __restrict__ rowseg;
+    const uint32_t* __restrict__ nzdst;
+};
+
+inline GraphArgs args_of(const DevGraph& g) {
+    GraphArgs a;
+    a.n = g.n;
+    a.m = (uint32_t)g.m;
+    a.rows = (uint32_t)g.rows;
+    a.in_src = g.in_src;
+    a.in_w = g.in_w;
+    a.rowmask = g.rowmask;
+    a.rowseg = g.rowseg;
+    a.nzdst = g.nzdst;
+    return a;
+}
+
+// 64-lane slots needed to cover K chunks of 2^lc positions.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline uint64_t chunk_slots_count(uint64_t K, int lc) {
+    return lc <= 6 ? (K + (64u >> lc) - 1) / (64u >> lc) : K << (lc - 6);
+}
+
 // Iteration counters written by the kernels and read back by the host.
 struct Ctl {
     unsigned long long fnext;  // (listed count << 33) | out-degree sum of the next frontier
@@ -83,6 +116,49 @@ struct Ctl {
 
 constexpr int kDegBits = 33;
 constexpr unsigned long long kDegMask = (1ull << kDegBits) - 1;
+
+// Control block of the persistent traversal kernel (device memory).
+struct PersistState {
+    unsigned bar_count;      // grid barrier arrivals
+    unsigned bar_gen;        // grid barrier generation
+    unsigned error;          // set when a barrier wait passed its deadline
+    unsigned done;           // traversal finished
+    unsigned mode;           // current iteration: 1 Wedge Frontier, 0 full pull
+    unsigned iters;          // iterations run
+    unsigned not_converged;  // stopped by max_iters with a non-empty frontier
+    unsigned pad;
+    unsigned long long flisted;  // listed frontier vertices (with out-edges)
+    unsigned long long active;   // A of the current frontier
+};
+
+struct PersistParams {
+    GraphArgs g;
+    uint32_t n;
+    const uint32_t* row_off;
+    const uint32_t* pos;
+    uint32_t* level;            // single-level BFS values (internal order)
+    uint64_t* visited;          // multi-source masks
+    uint64_t* masks[2];
+    uint32_t* lev;              // multi-source levels, lev[v*K + s]
+    uint32_t K;
+    uint64_t all;               // mask of the K sources
+    uint64_t* fbits;
+    uint64_t* fcur;
+    uint32_t* flist[2];
+    uint32_t* degpre[2];
+    uint64_t* wbits;
+    uint64_t wwords;
+    uint32_t* chunks;
+    int lc;
+    Ctl* ctl;
+    PersistState* ps;
+    wedge_iter_record* trace;
+    uint32_t trace_cap;
+    uint64_t thr;
+    uint32_t gate;
+    uint32_t max_iters;
+    uint64_t timeout_ticks;
+};
 
 struct Workspace {
     uint32_t n = 0;
@@ -110,6 +186,24 @@ struct Workspace {
     uint64_t pr_tiles = 0;
     uint32_t pr_parts = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // batched BFS
+    uint64_t* visited = nullptr;   // n multi-source masks
+    uint64_t* masks[2] = {nullptr, nullptr};
+    uint32_t* lev = nullptr;       // n * lev_k multi-source levels
+    uint32_t lev_k = 0;
+    uint32_t* roots = nullptr;     // device copy of sources / roots
+    uint32_t* roots_host = nullptr;// pinned staging
+    uint32_t roots_cap = 0;
+    PersistState* ps = nullptr;
+    PersistState* ps_host = nullptr;
+    wedge_iter_record* trace = nullptr;
+    wedge_iter_record* trace_host = nullptr;
+    uint32_t trace_cap = 0;
+    uint64_t generation = 0;       // bumped whenever a buffer above moves
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::string graph_key;
 };
 
 }  // namespace wedge
@@ -122,6 +216,7 @@ struct wedge_graph_s {
     uint32_t max_w = 0;
     wedge::HostLayout host;        // kept only for WEDGE_HOST_ONLY graphs
     std::vector<uint32_t> perm_host;  // original -> internal id (empty: identity)
+    std::vector<uint64_t> parts;      // batch graphs: first vertex of each part (+ total)
     wedge::DevGraph dev;
     wedge::Workspace ws;
     uint64_t device_bytes = 0;
@@ -177,5 +272,27 @@ hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* 
                               double damping, const double* d_cur, float* rank, float* contrib,
                               double* partials, uint32_t parts, hipStream_t s);
 uint32_t pr_epilogue_blocks(uint32_t n);
+// Batched BFS (batch.hip)
+hipError_t launch_ms_pull_full(const DevGraph& g, uint64_t all, const uint64_t* visited,
+                               const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s);
+hipError_t launch_ms_pull_chunks(const DevGraph& g, int lc, const uint32_t* list, const Ctl* ctl,
+                                 uint64_t max_chunks, uint64_t all, const uint64_t* visited,
+                                 const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s);
+// Commit of a multi-source iteration (see ms_finalize_block); `retire` holds
+// the masks of the frontier being replaced, `nxt` those just built.
+hipError_t launch_ms_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
+                              uint32_t* flist, uint32_t* degpre, Ctl* ctl, uint64_t* fcur,
+                              uint64_t* visited, uint64_t* retire, const uint64_t* nxt,
+                              uint32_t* lev, uint32_t K, uint32_t level, hipStream_t s);
+hipError_t launch_ms_seed(const uint32_t* srcs, uint32_t K, uint64_t* nxt, uint64_t* fbits,
+                          hipStream_t s);
+hipError_t launch_roots_seed(const uint32_t* roots, uint32_t count, uint32_t* level,
+                             uint64_t* fbits, hipStream_t s);
+hipError_t launch_ms_output(uint32_t n, uint32_t K, const uint32_t* perm, const uint32_t* lev,
+                            uint32_t* out, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);
+hipError_t launch_fill_u32_kernel(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
+hipError_t persistent_max_blocks(bool ms, int* blocks_per_cu);
+hipError_t launch_bfs_persistent(bool ms, const PersistParams& P, uint32_t blocks, hipStream_t s);
 
 }  // namespace wedge

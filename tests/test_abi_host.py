@@ -184,3 +184,19 @@ def test_runs_on_host_only_graph_are_refused():
     assert L.wedge_graph_layout(g.handle, B.LAYOUT["pos"], out.ctypes.data, 3) == -1
     assert L.wedge_graph_layout(g.handle, 99, out.ctypes.data, 4) == -1
     assert L.wedge_graph_destroy(None) == 0
+
+
+def test_batch_union_is_the_concatenation():
+    parts = [gen.rmat(s, 16, seed=70 + s) for s in (3, 6, 5, 2)]
+    g = W.Graph.from_batch_csr(parts, host_only=True, keep_ids=True)
+    first = g.parts()
+    assert list(first) == list(np.cumsum([0] + [len(r) - 1 for r, _ in parts]))
+    ro = np.concatenate([[0]] + [r[1:] + sum(int(p[0][-1]) for p in parts[:i])
+                                 for i, (r, _) in enumerate(parts)]).astype(np.uint64)
+    col = np.concatenate([c + first[i] for i, (_, c) in enumerate(parts)]).astype(np.uint32)
+    co, src, _ = oracle.csc(ro, col)
+    np.testing.assert_array_equal(g.layout("row_off"), ro.astype(np.uint32))
+    np.testing.assert_array_equal(g.layout("in_src"), src)
+    with pytest.raises(W.WedgeError):
+        bad = [(parts[0][0], parts[0][1] + 100)]
+        W.Graph.from_batch_csr(bad, host_only=True)

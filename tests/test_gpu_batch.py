@@ -1,0 +1,177 @@
+"""GPU parity of the batched BFS kinds against the CPU oracle.
+
+Multi-source BFS (64-bit masks) must equal one oracle BFS per source, and its
+per-iteration union frontier must equal {v : some source reaches v at level
+k}. The many-graph batch must equal one oracle BFS per part. The persistent
+launch (one kernel, grid barriers, captured in a hipGraph and replayed) must
+give exactly the host-driven results and records.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a ROCm GPU", allow_module_level=True)
+
+import paper_1903_07754_amd as W  # noqa: E402
+
+INF = oracle.INF
+
+
+def union_trace(levels, outdeg):
+    """|F_k| and A_k of the union frontier implied by per-source levels."""
+    lv = np.asarray(levels)
+    F, A = [], []
+    k = 0
+    while True:
+        fr = (lv == k).any(axis=0)
+        if not fr.any():
+            break
+        F.append(int(fr.sum()))
+        A.append(int(outdeg[fr].sum()))
+        k += 1
+    return F, A
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("k", [1, 7, 63, 64])
+def test_multisource_equals_per_source_bfs(k, persistent):
+    ro, col = gen.rmat(13, 16, seed=61)
+    g = W.Graph.from_csr(ro, col)
+    srcs = gen.pick_sources(ro, k, seed=k)
+    print(f"  [multisource k={k} persistent={persistent}]", flush=True)
+    lv, st, tr = W.bfs_multisource(g, srcs, trace_cap=256, persistent=persistent)
+    got = lv.cpu().numpy().view(np.uint32)
+    want = np.stack([oracle.bfs(ro, col, int(s)) for s in srcs])
+    np.testing.assert_array_equal(got, want)
+    F, A = union_trace(want, np.diff(ro.astype(np.int64)))
+    assert [r["frontier"] for r in tr] == F
+    assert [r["active_edges"] for r in tr] == A
+    thr = (10_000 * len(col)) // 1_000_000
+    assert [r["mode"] for r in tr] == [1 if a < thr else 0 for a in A]
+
+
+@pytest.mark.parametrize("gate,chunk", [("wedge", 1), ("wedge", 64), ("full", 32), ("threshold", 16)])
+def test_multisource_gate_and_chunk_invariance(gate, chunk):
+    ro, col = gen.random_graph(5000, 40000, 62)
+    g = W.Graph.from_csr(ro, col)
+    srcs = gen.pick_sources(ro, 40, seed=5)
+    want = np.stack([oracle.bfs(ro, col, int(s)) for s in srcs])
+    for persistent in (False, True):
+        lv, _, _ = W.bfs_multisource(g, srcs, gate=gate, chunk=chunk, persistent=persistent)
+        np.testing.assert_array_equal(lv.cpu().numpy().view(np.uint32), want)
+
+
+def make_parts(count, seed, lo=4, hi=11):
+    rng = np.random.default_rng(seed)
+    scales = rng.integers(lo, hi + 1, count)
+    parts = [gen.rmat(int(s), 16, seed=3000 + i) for i, s in enumerate(scales)]
+    srcs = np.array([int(gen.pick_sources(r, 1, seed=i)[0]) for i, (r, _) in enumerate(parts)],
+                    np.uint32)
+    return parts, srcs
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("keep_ids", [False, True])
+def test_batch_equals_per_part_bfs(persistent, keep_ids):
+    parts, srcs = make_parts(40, 7)
+    g = W.Graph.from_batch_csr(parts, keep_ids=keep_ids)
+    first = g.parts()
+    lv, st, tr = W.bfs_batch(g, srcs, trace_cap=256, persistent=persistent)
+    got = W.u32(lv)
+    for i, (r, c) in enumerate(parts):
+        np.testing.assert_array_equal(got[first[i]:first[i + 1]], oracle.bfs(r, c, int(srcs[i])))
+    # union frontier of the batch = union over parts of their level-k sets
+    F = []
+    k = 0
+    while (got == k).any():
+        F.append(int((got == k).sum()))
+        k += 1
+    assert [r["frontier"] for r in tr] == F
+
+
+def test_persistent_bfs_matches_host_driven_records():
+    ro, col = gen.rmat(14, 16, seed=63)
+    g = W.Graph.from_csr(ro, col)
+    for s in gen.pick_sources(ro, 3, seed=9):
+        s = int(s)
+        a, sa, ta = W.bfs(g, s, trace_cap=128)
+        b, sb, tb = W.bfs(g, s, trace_cap=128, persistent=True)
+        np.testing.assert_array_equal(W.u32(a), oracle.bfs(ro, col, s))
+        np.testing.assert_array_equal(W.u32(b), W.u32(a))
+        assert sa["iterations"] == sb["iterations"]
+        for ra, rb in zip(ta, tb):
+            for key in ("frontier", "active_edges", "mode", "marked_chunks", "chunk_edges"):
+                assert ra[key] == rb[key], (key, ra, rb)
+
+
+def test_graph_replays_with_eager_work_between():
+    """The captured traversal is replayed many times (new sources each time, same
+    graph), with the program's own device work and synchronisations between
+    replays; every replay must equal the oracle."""
+    ro, col = gen.rmat(12, 16, seed=64)
+    g = W.Graph.from_csr(ro, col)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    x = torch.randn(1 << 20, device="cuda")
+    for rep, s in enumerate(gen.pick_sources(ro, 6, seed=10)):
+        W.bfs(g, int(s), out=out, persistent=True)
+        y = (x * rep).sum()          # eager work between replays
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(W.u32(out), oracle.bfs(ro, col, int(s)))
+        assert torch.isfinite(y)
+    srcs = gen.pick_sources(ro, 64, seed=11)
+    want = np.stack([oracle.bfs(ro, col, int(s)) for s in srcs])
+    for rep in range(3):
+        lv, _, _ = W.bfs_multisource(g, srcs, persistent=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(lv.cpu().numpy().view(np.uint32), want)
+
+
+def test_barrier_deadline_is_reported_not_hung(monkeypatch):
+    """With a zero barrier deadline forced from the host, the persistent kernel
+    gives up at its first wait, every block exits, and the call reports an
+    error; the next run (default deadline) is correct again."""
+    ro, col = gen.rmat(11, 16, seed=65)
+    g = W.Graph.from_csr(ro, col)
+    s = int(gen.pick_sources(ro, 1, seed=12)[0])
+    monkeypatch.setenv("WEDGE_BARRIER_TIMEOUT_MS", "0")
+    with pytest.raises(W.WedgeError) as e:
+        W.bfs(g, s, persistent=True)
+    assert e.value.name == "WEDGE_ERR_HIP"
+    monkeypatch.delenv("WEDGE_BARRIER_TIMEOUT_MS")
+    out, _, _ = W.bfs(g, s, persistent=True)
+    np.testing.assert_array_equal(W.u32(out), oracle.bfs(ro, col, s))
+
+
+def test_autotuner_picks_a_candidate_and_results_hold():
+    ro, col = gen.rmat(12, 16, seed=66)
+    g = W.Graph.from_csr(ro, col)
+    srcs = gen.pick_sources(ro, 64, seed=13)
+    out = torch.empty(64 * g.n, dtype=torch.int32, device="cuda")
+    best, ms = W.tune_bfs(g, "multisource", srcs, out)
+    assert best["chunk"] in (16, 32, 64) and best["blocks_per_cu"] in (0, 1, 2, 4)
+    assert ms > 0
+    assert W.tune_lookup("multisource", 64, g.m) == {k: best[k] for k in ("chunk", "persistent", "blocks_per_cu")}
+    lv, _, _ = W.bfs_multisource(g, srcs, chunk=best["chunk"], persistent=best["persistent"],
+                                 blocks_per_cu=best["blocks_per_cu"])
+    want = np.stack([oracle.bfs(ro, col, int(s)) for s in srcs])
+    np.testing.assert_array_equal(lv.cpu().numpy().view(np.uint32), want)
+
+
+def test_multisource_errors():
+    ro, col = gen.random_graph(100, 400, 3)
+    g = W.Graph.from_csr(ro, col)
+    with pytest.raises(W.WedgeError):
+        W.bfs_multisource(g, np.arange(65, dtype=np.uint32) % 100)
+    with pytest.raises(W.WedgeError):
+        W.bfs_multisource(g, np.array([100], np.uint32))
+    with pytest.raises(W.WedgeError) as e:
+        W.bfs_batch(g, np.array([0], np.uint32))
+    assert e.value.name == "WEDGE_ERR_UNSUPPORTED"
