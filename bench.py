@@ -84,6 +84,88 @@ def cpu_baseline(ro, col, w, srcs, m):
             "seconds": {k: round(v, 3) for k, v in t.items()}}
 
 
+def timed(fn, reps):
+    """Best wall time of `reps` synchronous calls (seconds)."""
+    import torch
+    best = 1e30
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best
+
+
+def batched_section(reps=3):
+    """Batched BFS against the plain threshold-gated single-query path on the
+    same GPU: 64 sources on R-MAT scale 22 as 64-bit masks in one traversal,
+    and 256 R-MAT graphs of scales drawn from 10..16 as one disjoint union.
+    Both batched forms run the autotuned configuration (chunk size, host-driven
+    or persistent hipGraph launch, blocks per CU)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1903_07754_amd as W
+
+    res = {}
+    ro, col = gen.rmat(22, 16, seed=5)
+    srcs = gen.pick_sources(ro, 64, seed=6)
+    n, m = len(ro) - 1, len(col)
+    g = W.Graph.from_csr(ro, col)
+    out1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    outk = torch.empty(64 * n, dtype=torch.int32, device="cuda")
+    log("batched: 64 sources on R-MAT s22")
+    t_seq = timed(lambda: [W.bfs(g, int(s), out=out1) for s in srcs], reps)
+    t_ms = timed(lambda: W.bfs_multisource(g, srcs, out=outk), reps)
+    best, _ = W.tune_bfs(g, "multisource", srcs, outk)
+    t_tuned = timed(lambda: W.bfs_multisource(g, srcs, out=outk, chunk=best["chunk"],
+                                              persistent=best["persistent"],
+                                              blocks_per_cu=best["blocks_per_cu"]), reps)
+    lv = outk.view(64, n)
+    for i in (0, 31, 63):
+        W.bfs(g, int(srcs[i]), out=out1)
+        assert torch.equal(lv[i], out1), "multi-source row differs from the single-source run"
+    res["multisource_s22"] = {
+        "n": n, "m": m, "sources": 64, "unit": "GTEPS (64*M/t)",
+        "single_query_threshold_ms": round(t_seq * 1e3, 3),
+        "single_query_threshold_gteps": round(64 * m / t_seq / 1e9, 2),
+        "batched_host_loop_ms": round(t_ms * 1e3, 3),
+        "batched_tuned_ms": round(t_tuned * 1e3, 3),
+        "batched_tuned_gteps": round(64 * m / t_tuned / 1e9, 2),
+        "tuned": best, "speedup_vs_single_query": round(t_seq / t_tuned, 2)}
+    del g, lv, outk
+    log("batched: 256 R-MAT graphs of scales 10..16")
+    scales = gen.batch_scales(256, 10, 16, seed=7)
+    parts = [gen.rmat(s, 16, seed=3000 + i) for i, s in enumerate(scales)]
+    bsrcs = np.array([int(gen.pick_sources(r, 1, seed=4000 + i)[0]) for i, (r, _) in enumerate(parts)],
+                     np.uint32)
+    mtot = sum(len(c) for _, c in parts)
+    gb = W.Graph.from_batch_csr(parts)
+    singles = [W.Graph.from_csr(r, c) for r, c in parts]
+    outs = [torch.empty(len(r) - 1, dtype=torch.int32, device="cuda") for r, _ in parts]
+    outb = torch.empty(gb.n, dtype=torch.int32, device="cuda")
+    t_seq = timed(lambda: [W.bfs(sg, int(s), out=o) for sg, s, o in zip(singles, bsrcs, outs)], reps)
+    t_b = timed(lambda: W.bfs_batch(gb, bsrcs, out=outb), reps)
+    best, _ = W.tune_bfs(gb, "batch", bsrcs, outb)
+    t_tuned = timed(lambda: W.bfs_batch(gb, bsrcs, out=outb, chunk=best["chunk"],
+                                        persistent=best["persistent"],
+                                        blocks_per_cu=best["blocks_per_cu"]), reps)
+    first = gb.parts()
+    for i in (0, 100, 255):
+        assert torch.equal(outb[int(first[i]):int(first[i + 1])], outs[i]), "batch part differs"
+    res["batch256_s10_16"] = {
+        "graphs": 256, "n": gb.n, "m": mtot, "unit": "GTEPS (sum M_g / t)",
+        "single_query_threshold_ms": round(t_seq * 1e3, 3),
+        "single_query_threshold_gteps": round(mtot / t_seq / 1e9, 2),
+        "batched_host_loop_ms": round(t_b * 1e3, 3),
+        "batched_tuned_ms": round(t_tuned * 1e3, 3),
+        "batched_tuned_gteps": round(mtot / t_tuned / 1e9, 2),
+        "tuned": best, "speedup_vs_single_query": round(t_seq / t_tuned, 2)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +174,7 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--sources", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -188,6 +271,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ro, col, w, srcs, m)
+    if not args.no_batched:
+        del g, gs, lev, lab, dist, rank
+        out["batched"] = batched_section()
     print(json.dumps(out), flush=True)
 
 

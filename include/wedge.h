@@ -239,6 +239,89 @@ wedge_status wedge_sssp(wedge_graph_t g, uint32_t src, uint32_t* dist_dev, const
 wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, float* rank_dev,
                             const wedge_opts* opts, hipStream_t stream, wedge_stats* stats);
 
+/* ---------------------------------------------------------- learned gate */
+
+/*
+ * A small learned cost model for the fullness decision: an FP32 MLP
+ * 8 -> 32 -> 32 -> 4 (ReLU) predicting log(1 + microseconds) of the next
+ * iteration in each mode, mode 0 = full pull and modes 1, 2, 3 = Wedge
+ * Frontier at 16, 32, 64 edges per bit. With WEDGE_GATE_LEARNED the decision
+ * is the mode of smallest prediction (ties to the lower index), computed on
+ * the device between iterations. The paper's threshold rule (Frontier
+ * Transformation, Frontier Fullness Threshold) decides instead when no model
+ * is given or a feature lies outside the model's training envelope. The
+ * choice never changes results (any mode visits a superset of the active
+ * edges).
+ *
+ * Features of the frontier F_k about to be consumed (float, in this order):
+ * |F_k|/n, A_k/m, 1 - exp(-A_k/ceil(m/16)), log2(n)/32, log2(m)/32,
+ * min(k,255)/64, log(1 + previous iteration's device time in us)/16,
+ * previous mode index / 3.
+ */
+typedef struct wedge_model_s* wedge_model_t;
+
+#define WEDGE_APP_BFS 1u
+#define WEDGE_APP_CC 2u
+#define WEDGE_APP_SSSP 3u
+
+/* One iteration of a counterfactual trace (what the model learns from). */
+typedef struct {
+    uint32_t app;            /* WEDGE_APP_* */
+    uint32_t iter;           /* k */
+    uint32_t prev_mode;      /* mode index taken at k-1 by the threshold rule (0 at k = 0) */
+    uint32_t threshold_mode; /* mode index the threshold rule takes at k */
+    uint64_t n, m;           /* traversed graph size */
+    uint64_t frontier;       /* |F_k| */
+    uint64_t active;         /* A_k */
+    float prev_us;           /* device time of iteration k-1 in prev_mode (0 at k = 0) */
+    float t_us[4];           /* device time of iteration k in each mode, all from the same state */
+    float reserved;
+} wedge_trace_sample;
+
+/* New model with uniform(+-1/sqrt(fan_in)) weights from `seed`, zero biases,
+ * and an unbounded envelope. Host-only until first used on a GPU. */
+wedge_status wedge_model_create(uint64_t seed, wedge_model_t* out);
+wedge_status wedge_model_free(wedge_model_t m);
+/* Versioned binary file: magic "WEDGEMLP", version, shape, envelope, 1476
+ * parameters, FNV-1a-64 checksum. Load returns WEDGE_ERR_MODEL for a missing,
+ * truncated, corrupt or mismatched file. */
+wedge_status wedge_model_load(const char* path, wedge_model_t* out);
+wedge_status wedge_model_save(wedge_model_t m, const char* path);
+/* Copy the 1476 parameters (W1[32x8] b1 W2[32x32] b2 W3[4x32] b3, row-major)
+ * out (set = 0) or in (set = 1). */
+wedge_status wedge_model_params(wedge_model_t m, float* params, uint32_t count, int set);
+/* Copy the per-feature envelope lo[8], hi[8] out (set = 0) or in (set = 1). */
+wedge_status wedge_model_envelope(wedge_model_t m, float* lo, float* hi, int set);
+/* Features of samples (host): x[count*8]. */
+wedge_status wedge_model_features(const wedge_trace_sample* s, uint32_t count, float* x);
+/* y[count*4] = model(x[count*8]) on the device (host arrays). */
+wedge_status wedge_model_predict(wedge_model_t m, const float* x, uint32_t count, float* y,
+                                 hipStream_t stream);
+/* Gradient of mean_b sum_j mask[b,j] (y[b,j] - t[b,j])^2 with respect to the
+ * parameters, and the loss, on the device (host arrays). */
+wedge_status wedge_model_grad(wedge_model_t m, const float* x, const float* t, const float* mask,
+                              uint32_t count, float* grad, float* loss, hipStream_t stream);
+/* Full-batch Adam (lr, 0.9, 0.999, 1e-8) on log(1 + t_us) targets for
+ * `epochs` steps on the device; sets the envelope to the samples' feature
+ * range widened by 5%, except for the graph-size and previous-time features
+ * (3, 4, 6), which stay unbounded so that a model trained on small graphs is
+ * used on larger ones. */
+wedge_status wedge_model_train(wedge_model_t m, const wedge_trace_sample* s, uint32_t count,
+                               uint32_t epochs, float lr, hipStream_t stream, float* final_loss);
+
+/*
+ * Counterfactual per-iteration trace (the profiling method of the paper's
+ * Evaluation, Frontier Fullness Threshold: per-iteration times with and
+ * without the Wedge Frontier): the app runs as under the threshold rule, and
+ * at every iteration the state is saved, the iteration is run and timed in all
+ * four modes from that same state (restoring between runs), and the traversal
+ * advances. Writes up to cap samples to out (host) and their number to *count.
+ * opts supplies theta and the default chunk size of the threshold rule.
+ */
+wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t src,
+                                        const wedge_opts* opts, wedge_trace_sample* out,
+                                        uint32_t cap, uint32_t* count, hipStream_t stream);
+
 /* ------------------------------------------------------------- batching */
 
 /*

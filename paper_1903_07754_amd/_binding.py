@@ -51,6 +51,17 @@ class IterRecord(C.Structure):
                 ("marked_chunks", C.c_uint64), ("ms", C.c_float), ("reserved2", C.c_float)]
 
 
+class TraceSample(C.Structure):
+    _fields_ = [("app", C.c_uint32), ("iter", C.c_uint32), ("prev_mode", C.c_uint32),
+                ("threshold_mode", C.c_uint32), ("n", C.c_uint64), ("m", C.c_uint64),
+                ("frontier", C.c_uint64), ("active", C.c_uint64), ("prev_us", C.c_float),
+                ("t_us", C.c_float * 4), ("reserved", C.c_float)]
+
+
+APP = {"bfs": 1, "cc": 2, "sssp": 3}
+MLP_PARAMS = 1476
+
+
 class Opts(C.Structure):
     _fields_ = [("gate", C.c_uint32), ("threshold_ppm", C.c_uint32), ("chunk_edges", C.c_uint32),
                 ("max_iters", C.c_uint32), ("flags", C.c_uint32), ("trace_cap", C.c_uint32),
@@ -78,6 +89,9 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    # the library must share PyTorch's HIP runtime (same streams and allocations):
+    # load torch first so that libamdhip64.so.7 resolves to the copy it ships
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
     L.wedge_graph_create_csr.argtypes = [u32, u64, vp, vp, vp, u32, vp, C.POINTER(vp)]
@@ -96,6 +110,18 @@ def lib():
     L.wedge_bfs_batch.argtypes = [vp, vp, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
     L.wedge_tune_bfs.argtypes = [vp, u32, vp, u32, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double)]
     L.wedge_tune_lookup.argtypes = [u32, u32, u64, C.POINTER(Opts)]
+    L.wedge_model_create.argtypes = [u64, C.POINTER(vp)]
+    L.wedge_model_free.argtypes = [vp]
+    L.wedge_model_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+    L.wedge_model_save.argtypes = [vp, C.c_char_p]
+    L.wedge_model_params.argtypes = [vp, vp, u32, C.c_int]
+    L.wedge_model_envelope.argtypes = [vp, vp, vp, C.c_int]
+    L.wedge_model_features.argtypes = [vp, u32, vp]
+    L.wedge_model_predict.argtypes = [vp, vp, u32, vp, vp]
+    L.wedge_model_grad.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp]
+    L.wedge_model_train.argtypes = [vp, vp, u32, u32, C.c_float, vp, C.POINTER(C.c_float)]
+    L.wedge_trace_counterfactual.argtypes = [vp, u32, u32, C.POINTER(Opts), vp, u32,
+                                             C.POINTER(u32), vp]
     L.wedge_status_string.argtypes = [C.c_int]
     L.wedge_status_string.restype = C.c_char_p
     L.wedge_last_error.restype = C.c_char_p
@@ -104,7 +130,10 @@ def lib():
                  "wedge_graph_get_info", "wedge_graph_layout", "wedge_bfs", "wedge_cc",
                  "wedge_sssp", "wedge_pagerank", "wedge_frontier_translate",
                  "wedge_bfs_multisource", "wedge_graph_create_batch_csr", "wedge_graph_batch_parts",
-                 "wedge_bfs_batch", "wedge_tune_bfs", "wedge_tune_lookup"):
+                 "wedge_bfs_batch", "wedge_tune_bfs", "wedge_tune_lookup", "wedge_model_create",
+                 "wedge_model_free", "wedge_model_load", "wedge_model_save", "wedge_model_params",
+                 "wedge_model_envelope", "wedge_model_features", "wedge_model_predict",
+                 "wedge_model_grad", "wedge_model_train", "wedge_trace_counterfactual"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -340,6 +369,113 @@ def frontier_translate(g, frontier, chunk, stream=None):
                                          _ptr(wbits), _ptr(lst), C.byref(marked),
                                          _stream_handle(stream)))
     return wbits[:words], lst[:marked.value]
+
+
+class Model:
+    """Learned-gate model (FP32 MLP 8 -> 32 -> 32 -> 4) held by the library."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+
+    @classmethod
+    def create(cls, seed=0):
+        h = C.c_void_p()
+        check(lib().wedge_model_create(seed, C.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def load(cls, path):
+        h = C.c_void_p()
+        check(lib().wedge_model_load(os.fsencode(path), C.byref(h)))
+        return cls(h.value)
+
+    def save(self, path):
+        check(lib().wedge_model_save(self._h, os.fsencode(path)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self, new=None):
+        p = np.zeros(MLP_PARAMS, np.float32)
+        if new is not None:
+            p[:] = np.asarray(new, np.float32)
+            check(lib().wedge_model_params(self._h, p.ctypes.data, MLP_PARAMS, 1))
+        else:
+            check(lib().wedge_model_params(self._h, p.ctypes.data, MLP_PARAMS, 0))
+        return p
+
+    def envelope(self, lo=None, hi=None):
+        a = np.zeros(8, np.float32)
+        b = np.zeros(8, np.float32)
+        if lo is not None:
+            a[:] = lo
+            b[:] = hi
+            check(lib().wedge_model_envelope(self._h, a.ctypes.data, b.ctypes.data, 1))
+        else:
+            check(lib().wedge_model_envelope(self._h, a.ctypes.data, b.ctypes.data, 0))
+        return a, b
+
+    def predict(self, x, stream=None):
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.zeros((len(x), 4), np.float32)
+        check(lib().wedge_model_predict(self._h, x.ctypes.data, len(x), y.ctypes.data,
+                                        _stream_handle(stream)))
+        return y
+
+    def grad(self, x, t, mask, stream=None):
+        x = np.ascontiguousarray(x, np.float32)
+        t = np.ascontiguousarray(t, np.float32)
+        mask = np.ascontiguousarray(mask, np.float32)
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = C.c_float()
+        check(lib().wedge_model_grad(self._h, x.ctypes.data, t.ctypes.data, mask.ctypes.data,
+                                     len(x), g.ctypes.data, C.byref(loss),
+                                     _stream_handle(stream)))
+        return g, loss.value
+
+    def train(self, samples, epochs=2000, lr=1e-3, stream=None):
+        loss = C.c_float()
+        check(lib().wedge_model_train(self._h, samples, len(samples), epochs, lr,
+                                      _stream_handle(stream), C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().wedge_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def features(samples):
+    """Gate features (host formula) of a TraceSample array: float32 [count, 8]."""
+    x = np.zeros((len(samples), 8), np.float32)
+    if len(samples):
+        check(lib().wedge_model_features(samples, len(samples), x.ctypes.data))
+    return x
+
+
+def trace_counterfactual(g, app, src=0, cap=4096, stream=None, theta_ppm=0, chunk=0):
+    """Per-iteration times of all four modes from each iteration's state (TraceSample array)."""
+    o, _ = make_opts(theta_ppm=theta_ppm, chunk=chunk)
+    out = (TraceSample * cap)()
+    cnt = C.c_uint32()
+    check(lib().wedge_trace_counterfactual(g.handle, APP[app], src, C.byref(o), out, cap,
+                                           C.byref(cnt), _stream_handle(stream)))
+    res = (TraceSample * cnt.value)()
+    C.memmove(res, out, C.sizeof(TraceSample) * cnt.value)
+    return res
+
+
+def samples_to_dicts(samples):
+    return [{"app": s.app, "iter": s.iter, "prev_mode": s.prev_mode,
+             "threshold_mode": s.threshold_mode, "n": s.n, "m": s.m, "frontier": s.frontier,
+             "active": s.active, "prev_us": s.prev_us, "t_us": list(s.t_us)} for s in samples]
 
 
 def u32(t):

@@ -36,11 +36,11 @@ def build(verbose: bool = False) -> str:
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     objs = []
-    for src in ("api.cpp", "layout.cpp"):
+    for src in ("api.cpp", "layout.cpp", "model.cpp"):
         o = os.path.join(obj_dir, src + ".o")
         _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)
-    for src in ("kernels.hip", "batch.hip"):
+    for src in ("kernels.hip", "batch.hip", "mlp.hip"):
         o = os.path.join(obj_dir, src + ".o")
         _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

@@ -28,6 +28,14 @@ wedge_status fail(wedge_status st, const std::string& msg) {
     return st;
 }
 
+}  // namespace
+
+namespace wedge {
+wedge_status set_error(wedge_status st, const std::string& msg) { return fail(st, msg); }
+}  // namespace wedge
+
+namespace {
+
 wedge_status hip_fail(hipError_t e, const char* what) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
     return WEDGE_ERR_HIP;
@@ -263,6 +271,16 @@ struct LoopCfg {
     uint32_t max_iters = 0;
     bool time_pull = false, time_iter = false;
     uint64_t nchunks = 0, wwords = 0;
+    // learned gate: decisions come from the device (model may be null: threshold rule)
+    bool learned = false;
+    const float* P = nullptr;
+    const float* lo = nullptr;
+    const float* hi = nullptr;
+    double ticks_per_us = 100.0;
+    uint64_t m = 0;
+    // the smallest chunk exponent this run may use (bitmap and list sizes)
+    int min_lc() const { return learned ? std::min(lc, 4) : lc; }
+    uint64_t chunks_of(int l) const { return (m + (1ull << l) - 1) >> l; }
 };
 
 template <class Pull, class Fin>
@@ -270,6 +288,9 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
                      wedge_stats& local, double t0, wedge_stats* stats, Pull pull, Fin fin) {
     Workspace& w = g->ws;
     const DevGraph& d = g->dev;
+    if (c.learned)
+        HIP_TRY(launch_mlp_infer(c.P, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr, (uint32_t)c.lc,
+                                 c.ticks_per_us, s), "gate inference");
     HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
     HIP_TRY(hipStreamSynchronize(s), "initialising run");
     uint64_t fcount = w.ctl_host->ftotal;               // |F_k|
@@ -284,25 +305,36 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
             return fail(WEDGE_ERR_NOT_CONVERGED, "max_iters reached with a non-empty frontier");
         }
         bool wedge_mode;
-        switch (c.gate) {
-            case WEDGE_GATE_ALWAYS_WEDGE: wedge_mode = true; break;
-            case WEDGE_GATE_ALWAYS_FULL: wedge_mode = false; break;
-            default: wedge_mode = active < c.thr; break;  // the fullness threshold (strict <)
+        int lc = c.lc;
+        if (c.learned) {
+            wedge_mode = w.ctl_host->gate.mode != 0;
+            lc = (int)w.ctl_host->gate.lc;
+        } else {
+            switch (c.gate) {
+                case WEDGE_GATE_ALWAYS_WEDGE: wedge_mode = true; break;
+                case WEDGE_GATE_ALWAYS_FULL: wedge_mode = false; break;
+                default: wedge_mode = active < c.thr; break;  // the fullness threshold (strict <)
+            }
         }
         HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
+        if (c.learned) HIP_TRY(launch_gate_stamp(w.ctl, s), "gate stamp");
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[2], s), "event");
         uint64_t maxk = 0;
         if (wedge_mode) {
+            const uint64_t nch = c.chunks_of(lc);
             HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)flisted, active, d.row_off,
-                                     d.pos, c.lc, w.wbits, s), "frontier translation");
-            HIP_TRY(launch_compact_chunks(w.wbits, c.wwords, w.chunks, w.ctl, s), "chunk compaction");
-            maxk = active < c.nchunks ? active : c.nchunks;
+                                     d.pos, lc, w.wbits, s), "frontier translation");
+            HIP_TRY(launch_compact_chunks(w.wbits, (nch + 63) / 64, w.chunks, w.ctl, s), "chunk compaction");
+            maxk = active < nch ? active : nch;
         }
         if (c.time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
-        HIP_TRY(pull(k, wedge_mode, maxk, cur), wedge_mode ? "chunk pull" : "full pull");
+        HIP_TRY(pull(k, wedge_mode, maxk, cur, lc), wedge_mode ? "chunk pull" : "full pull");
         if (c.time_pull) HIP_TRY(hipEventRecord(w.ev[1], s), "event");
         HIP_TRY(fin(k, cur), "frontier finalisation");
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
+        if (c.learned)
+            HIP_TRY(launch_mlp_infer(c.P, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr,
+                                     (uint32_t)c.lc, c.ticks_per_us, s), "gate inference");
         HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
         HIP_TRY(hipStreamSynchronize(s), "iteration");
         float pms = 0.f, ims = 0.f;
@@ -315,7 +347,7 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
             wedge_iter_record& r = o.trace[k];
             r.iter = k;
             r.mode = wedge_mode ? 1u : 0u;
-            r.chunk_edges = wedge_mode ? (1u << c.lc) : 0u;
+            r.chunk_edges = wedge_mode ? (1u << lc) : 0u;
             r.reserved = 0;
             r.frontier = fcount;
             r.active_edges = active;
@@ -323,7 +355,7 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
             r.ms = ims;
             r.reserved2 = 0.f;
         }
-        if (wedge_mode) { local.wedge_iters++; local.edges_scanned += marked << c.lc; }
+        if (wedge_mode) { local.wedge_iters++; local.edges_scanned += marked << lc; }
         else { local.full_iters++; local.edges_scanned += d.m; }
         fcount = w.ctl_host->ftotal;
         flisted = w.ctl_host->fnext >> kDegBits;
@@ -347,7 +379,35 @@ LoopCfg loop_cfg(const wedge_opts& o, const DevGraph& d, uint32_t theta_default,
     c.time_iter = o.flags & WEDGE_RUN_TIME_ITERS;
     c.nchunks = (d.m + chunk - 1) >> c.lc;
     c.wwords = (c.nchunks + 63) / 64;
+    c.m = d.m;
+    if (o.gate == WEDGE_GATE_LEARNED) {
+        c.learned = true;
+        const wedge_model_s* md = static_cast<const wedge_model_s*>(o.model);
+        if (md && md->dev_params) { c.P = md->dev_params; c.lo = md->dev_lo; c.hi = md->dev_hi; }
+    }
     return c;
+}
+
+double wall_ticks_per_us(int dev) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;
+    return (double)khz / 1000.0;
+}
+
+// Learned gate: upload the model (if any) and fill the device pointers.
+wedge_status prepare_gate(wedge_graph_t g, const wedge_opts& o, LoopCfg* c) {
+    if (!c->learned) return WEDGE_OK;
+    c->ticks_per_us = wall_ticks_per_us(g->device);
+    if (o.model) {
+        wedge_model_s* md = const_cast<wedge_model_s*>(static_cast<const wedge_model_s*>(o.model));
+        wedge_status st = model_to_device(md);
+        if (st != WEDGE_OK) return st;
+        c->P = md->dev_params;
+        c->lo = md->dev_lo;
+        c->hi = md->dev_hi;
+    }
+    return WEDGE_OK;
 }
 
 // Clears both frontier bitmaps (and the Wedge bitmap when it may be used).
@@ -356,7 +416,8 @@ wedge_status clear_bitmaps(wedge_graph_t g, const LoopCfg& c, hipStream_t s) {
     const uint64_t fwords = ((uint64_t)g->dev.n + 63) / 64;
     HIP_TRY(hipMemsetAsync(w.fbits, 0, fwords * 8, s), "clearing frontier bitmap");
     HIP_TRY(hipMemsetAsync(w.fcur, 0, fwords * 8, s), "clearing frontier bitmap");
-    if (c.gate != WEDGE_GATE_ALWAYS_FULL) HIP_TRY(hipMemsetAsync(w.wbits, 0, c.wwords * 8, s), "clearing Wedge bitmap");
+    if (c.gate != WEDGE_GATE_ALWAYS_FULL)
+        HIP_TRY(hipMemsetAsync(w.wbits, 0, (c.chunks_of(c.min_lc()) + 63) / 64 * 8, s), "clearing Wedge bitmap");
     return WEDGE_OK;
 }
 
@@ -382,8 +443,9 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     wedge_stats local{};
     const double t0 = now_ms();
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
-    const LoopCfg c = loop_cfg(o, d, app == kBfs ? 10000u : 200000u, app == kBfs ? 32u : 16u);
-    if ((st = ensure_workspace(g, c.lc, true, c.gate != WEDGE_GATE_ALWAYS_FULL)) != WEDGE_OK) return st;
+    LoopCfg c = loop_cfg(o, d, app == kBfs ? 10000u : 200000u, app == kBfs ? 32u : 16u);
+    if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
+    if ((st = ensure_workspace(g, c.min_lc(), true, c.gate != WEDGE_GATE_ALWAYS_FULL)) != WEDGE_OK) return st;
     Workspace& w = g->ws;
     if ((st = clear_bitmaps(g, c, s)) != WEDGE_OK) return st;
     // values are computed in internal vertex order; a relabelled graph works in
@@ -392,6 +454,7 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     if (d.inv) val = w.val;
     const uint32_t isrc = (app != kCc && !g->perm_host.empty()) ? g->perm_host[src] : src;
     uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
+    HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
     if (app == kCc) {
         HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, d.inv, val, w.val_prev, w.flist[0], w.degpre[0],
                                 w.fcur, w.ctl, s), "seeding CC");
@@ -403,8 +466,8 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     }
     st = iterate(
         g, o, c, s, local, t0, stats,
-        [&](uint32_t k, bool wedge_mode, uint64_t maxk, int) {
-            return wedge_mode ? launch_pull_chunks(app, d, k, c.lc, w.chunks, w.ctl, maxk, val, vprev,
+        [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
+            return wedge_mode ? launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev,
                                                    w.fcur, w.fbits, s)
                               : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s);
         },
@@ -613,8 +676,11 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
     wedge_stats local{};
     const double t0 = now_ms();
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
-    const LoopCfg c = loop_cfg(o, d, 10000u, 32u);
-    if ((st = ensure_workspace(g, c.lc, true, true)) != WEDGE_OK) return st;
+    LoopCfg c = loop_cfg(o, d, 10000u, 32u);
+    if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
+    if ((o.flags & WEDGE_RUN_PERSISTENT) && c.learned)
+        return fail(WEDGE_ERR_UNSUPPORTED, "the learned gate runs with the host-driven loop");
+    if ((st = ensure_workspace(g, c.min_lc(), true, true)) != WEDGE_OK) return st;
     if ((st = ensure_batch(g, count ? count : 1, 0)) != WEDGE_OK) return st;
     Workspace& w = g->ws;
     if ((st = upload_roots(g, roots, count, s)) != WEDGE_OK) return st;
@@ -630,8 +696,8 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
                                 w.fcur, s), "listing roots");
         st = iterate(
             g, o, c, s, local, t0, stats,
-            [&](uint32_t k, bool wedge_mode, uint64_t maxk, int) {
-                return wedge_mode ? launch_pull_chunks(kBfs, d, k, c.lc, w.chunks, w.ctl, maxk, val,
+            [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
+                return wedge_mode ? launch_pull_chunks(kBfs, d, k, lc, w.chunks, w.ctl, maxk, val,
                                                        nullptr, w.fcur, w.fbits, s)
                                   : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, s);
             },
@@ -665,8 +731,11 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
     wedge_stats local{};
     const double t0 = now_ms();
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
-    const LoopCfg c = loop_cfg(o, d, 10000u, 32u);
-    if ((st = ensure_workspace(g, c.lc, true, true)) != WEDGE_OK) return st;
+    LoopCfg c = loop_cfg(o, d, 10000u, 32u);
+    if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
+    if ((o.flags & WEDGE_RUN_PERSISTENT) && c.learned)
+        return fail(WEDGE_ERR_UNSUPPORTED, "the learned gate runs with the host-driven loop");
+    if ((st = ensure_workspace(g, c.min_lc(), true, true)) != WEDGE_OK) return st;
     if ((st = ensure_batch(g, count, count)) != WEDGE_OK) return st;
     Workspace& w = g->ws;
     if ((st = upload_roots(g, srcs, count, s)) != WEDGE_OK) return st;
@@ -685,10 +754,10 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
                                    w.visited, w.masks[1], w.masks[0], w.lev, count, 0, s), "listing sources");
         st = iterate(
             g, o, c, s, local, t0, stats,
-            [&](uint32_t k, bool wedge_mode, uint64_t maxk, int) {
+            [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
                 const uint64_t* mc = w.masks[k & 1];
                 uint64_t* mn = w.masks[(k & 1) ^ 1];
-                return wedge_mode ? launch_ms_pull_chunks(d, c.lc, w.chunks, w.ctl, maxk, all, w.visited,
+                return wedge_mode ? launch_ms_pull_chunks(d, lc, w.chunks, w.ctl, maxk, all, w.visited,
                                                           mc, mn, w.fbits, s)
                                   : launch_ms_pull_full(d, all, w.visited, mc, mn, w.fbits, s);
             },
@@ -1008,6 +1077,121 @@ wedge_status wedge_bfs_batch(wedge_graph_t g, const uint32_t* srcs, uint32_t* le
         roots[i] = (uint32_t)(g->parts[i] + srcs[i]);
     }
     return run_bfs_roots(g, roots.data(), count, levels_dev, opts, stream, stats);
+}
+
+wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t src,
+                                        const wedge_opts* opts_in, wedge_trace_sample* out,
+                                        uint32_t cap, uint32_t* count, hipStream_t s) {
+    if (!count || (cap && !out)) return fail(WEDGE_ERR_INVALID_ARG, "null argument");
+    *count = 0;
+    const wedge_opts& o0 = opts_in ? *opts_in : kDefaultOpts;
+    if (app < WEDGE_APP_BFS || app > WEDGE_APP_SSSP) return fail(WEDGE_ERR_INVALID_ARG, "unknown app");
+    wedge_opts o = o0;
+    o.gate = WEDGE_GATE_THRESHOLD;
+    o.flags = 0;
+    o.trace = nullptr;
+    o.trace_cap = 0;
+    if (!g) return fail(WEDGE_ERR_INVALID_ARG, "graph is null");
+    if (g->host_only) return fail(WEDGE_ERR_UNSUPPORTED, "graph was created with WEDGE_HOST_ONLY");
+    const DevGraph& d = g->dev;
+    if (app != kCc && src >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
+    if (app == kSssp && !g->weighted) return fail(WEDGE_ERR_NO_WEIGHTS, "SSSP needs weights");
+    if (app == kCc && !(g->flags & WEDGE_SYMMETRIZE)) return fail(WEDGE_ERR_UNSUPPORTED, "CC needs WEDGE_SYMMETRIZE");
+    RunGuard guard(g->busy);
+    if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
+    if (d.n == 0) return WEDGE_OK;
+    const uint32_t def_chunk = app == kBfs ? 32u : 16u;
+    const LoopCfg c = loop_cfg(o, d, app == kBfs ? 10000u : 200000u, def_chunk);
+    wedge_status st;
+    if ((st = ensure_workspace(g, 4, true, true)) != WEDGE_OK) return st;
+    Workspace& w = g->ws;
+    LoopCfg c16 = c;
+    c16.lc = 4;
+    if ((st = clear_bitmaps(g, c16, s)) != WEDGE_OK) return st;
+    const uint64_t fwords = ((uint64_t)d.n + 63) / 64;
+    struct Tmp { void* p = nullptr; ~Tmp() { if (p) (void)hipFree(p); } } tval, sv, sp, sf;
+    uint32_t* val = d.inv ? w.val : nullptr;
+    if (!val) { HIP_TRY(hipMalloc(&tval.p, (size_t)d.n * 4), "trace values"); val = (uint32_t*)tval.p; }
+    HIP_TRY(hipMalloc(&sv.p, (size_t)d.n * 4), "snapshot");
+    HIP_TRY(hipMalloc(&sp.p, (size_t)d.n * 4), "snapshot");
+    HIP_TRY(hipMalloc(&sf.p, fwords * 8), "snapshot");
+    uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
+    const uint32_t isrc = (app != kCc && !g->perm_host.empty()) ? g->perm_host[src] : src;
+    HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
+    if (app == kCc) {
+        HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, d.inv, val, w.val_prev, w.flist[0], w.degpre[0],
+                                w.fcur, w.ctl, s), "seeding CC");
+    } else {
+        HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
+        if (vprev) HIP_TRY(launch_fill_u32(vprev, d.n, kInf, s), "initialising values");
+        HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur, w.ctl, s),
+                "seeding source");
+    }
+    HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
+    HIP_TRY(hipStreamSynchronize(s), "initialising trace");
+    uint64_t fcount = w.ctl_host->ftotal, flisted = w.ctl_host->fnext >> kDegBits;
+    uint64_t active = w.ctl_host->fnext & kDegMask;
+    const uint32_t def_mode = def_chunk == 16 ? 1u : def_chunk == 32 ? 2u : 3u;
+    uint32_t prev_mode = 0;
+    float prev_us = 0.f;
+    int cur = 0;
+    for (uint32_t k = 0; fcount > 0; ++k) {
+        if (k >= c.max_iters) return fail(WEDGE_ERR_NOT_CONVERGED, "max_iters reached");
+        const uint32_t tmode = active < c.thr ? def_mode : 0u;
+        HIP_TRY(hipMemcpyAsync(sv.p, val, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s), "snapshot");
+        if (vprev) HIP_TRY(hipMemcpyAsync(sp.p, vprev, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s), "snapshot");
+        HIP_TRY(hipMemcpyAsync(sf.p, w.fcur, fwords * 8, hipMemcpyDeviceToDevice, s), "snapshot");
+        float t[4] = {0, 0, 0, 0};
+        for (uint32_t mi = 0; mi < 4; ++mi) {
+            if (mi) {
+                HIP_TRY(hipMemcpyAsync(val, sv.p, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s), "restore");
+                if (vprev) HIP_TRY(hipMemcpyAsync(vprev, sp.p, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s), "restore");
+                HIP_TRY(hipMemcpyAsync(w.fcur, sf.p, fwords * 8, hipMemcpyDeviceToDevice, s), "restore");
+            }
+            HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
+            HIP_TRY(hipEventRecord(w.ev[0], s), "event");
+            if (mi == 0) {
+                HIP_TRY(launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s), "full pull");
+            } else {
+                const int lc = 3 + (int)mi;
+                const uint64_t nch = c.chunks_of(lc);
+                HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)flisted, active, d.row_off,
+                                         d.pos, lc, w.wbits, s), "frontier translation");
+                HIP_TRY(launch_compact_chunks(w.wbits, (nch + 63) / 64, w.chunks, w.ctl, s), "chunk compaction");
+                HIP_TRY(launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, active < nch ? active : nch, val,
+                                           vprev, w.fcur, w.fbits, s), "chunk pull");
+            }
+            HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
+                                    vprev, val, w.fcur, s), "frontier finalisation");
+            HIP_TRY(hipEventRecord(w.ev[1], s), "event");
+            HIP_TRY(hipEventSynchronize(w.ev[1]), "trace iteration");
+            HIP_TRY(hipEventElapsedTime(&t[mi], w.ev[0], w.ev[1]), "event time");
+            t[mi] *= 1000.f;
+        }
+        HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
+        HIP_TRY(hipStreamSynchronize(s), "trace iteration");
+        if (*count < cap) {
+            wedge_trace_sample& r = out[(*count)++];
+            r.app = app;
+            r.iter = k;
+            r.prev_mode = prev_mode;
+            r.threshold_mode = tmode;
+            r.n = d.n;
+            r.m = d.m;
+            r.frontier = fcount;
+            r.active = active;
+            r.prev_us = prev_us;
+            for (int j = 0; j < 4; ++j) r.t_us[j] = t[j];
+            r.reserved = 0.f;
+        }
+        prev_mode = tmode;
+        prev_us = t[tmode];
+        fcount = w.ctl_host->ftotal;
+        flisted = w.ctl_host->fnext >> kDegBits;
+        active = w.ctl_host->fnext & kDegMask;
+        cur ^= 1;
+    }
+    return WEDGE_OK;
 }
 
 namespace {

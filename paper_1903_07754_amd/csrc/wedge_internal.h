@@ -106,13 +106,31 @@ inline uint64_t chunk_slots_count(uint64_t K, int lc) {
     return lc <= 6 ? (K + (64u >> lc) - 1) / (64u >> lc) : K << (lc - 6);
 }
 
+// Learned-gate sizes: 8 features -> 32 -> 32 -> 4 predicted log-times.
+constexpr int kMlpIn = 8, kMlpHidden = 32, kMlpOut = 4;
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpOut * kMlpHidden + kMlpOut;  // 1476
+
+// Decision state of the device-side gate, carried across iterations.
+struct GateState {
+    unsigned long long stamp;  // wall clock at the start of the current iteration
+    uint32_t k;                // index of the iteration being decided
+    uint32_t prev_mode;        // mode index of the previous iteration (0 full, 1..3 Wedge 16/32/64)
+    uint32_t mode;             // decision: 1 Wedge Frontier, 0 full pull
+    uint32_t lc;               // decision: log2 of edges per Wedge bit
+    uint32_t learned;          // decisions taken by the model
+    uint32_t fallback;         // decisions taken by the threshold rule
+    uint32_t pad[2];
+};
+
 // Iteration counters written by the kernels and read back by the host.
 struct Ctl {
     unsigned long long fnext;  // (listed count << 33) | out-degree sum of the next frontier
     unsigned long long marked; // (chunks appended to the chunk list) << 33
     unsigned long long ftotal; // next-frontier size, including vertices without out-edges
-    unsigned long long pad[5];
+    GateState gate;
 };
+static_assert(sizeof(Ctl) == 64, "counter block layout");
 
 constexpr int kDegBits = 33;
 constexpr unsigned long long kDegMask = (1ull << kDegBits) - 1;
@@ -208,6 +226,18 @@ struct Workspace {
 
 }  // namespace wedge
 
+// Learned-gate model: FP32 parameters, the training envelope of each feature,
+// and their device copies (made on first use on a GPU).
+struct wedge_model_s {
+    std::vector<float> params;   // kMlpParams, layout W1 b1 W2 b2 W3 b3 (row-major out x in)
+    std::vector<float> lo, hi;   // per-feature envelope
+    float* dev_params = nullptr;
+    float* dev_lo = nullptr;
+    float* dev_hi = nullptr;
+    int device = -1;
+    bool dirty = true;           // host copy changed since the last upload
+};
+
 struct wedge_graph_s {
     uint32_t flags = 0;
     bool weighted = false;
@@ -225,6 +255,11 @@ struct wedge_graph_s {
 };
 
 namespace wedge {
+
+// Records msg as the thread's last error and returns st.
+wedge_status set_error(wedge_status st, const std::string& msg);
+// Uploads the model to the current device if needed.
+wedge_status model_to_device(wedge_model_s* m);
 
 // ------------------------------------------------------ kernel launchers
 // (kernels.hip). Every launcher enqueues on `s` and returns the launch status.
@@ -293,6 +328,21 @@ hipError_t launch_ms_output(uint32_t n, uint32_t K, const uint32_t* perm, const 
 hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u32_kernel(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
 hipError_t persistent_max_blocks(bool ms, int* blocks_per_cu);
+// Learned gate (mlp.hip)
+hipError_t launch_mlp_forward(const float* P, const float* X, float* Y, uint32_t count,
+                              hipStream_t s);
+hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const float* Mk,
+                           uint32_t count, float scale, float* G, float* loss, hipStream_t s);
+hipError_t launch_adam(float* P, float* G, float* M1, float* M2, float lr, float b1, float b2,
+                       float eps, uint32_t step, hipStream_t s);
+// P null: the threshold rule decides (no model)
+hipError_t launch_mlp_infer(const float* P, const float* lo, const float* hi, Ctl* ctl, double n,
+                            double m, uint64_t thr, uint32_t fallback_lc, double ticks_per_us,
+                            hipStream_t s);
+hipError_t launch_gate_stamp(Ctl* ctl, hipStream_t s);
+// Host form of the gate features (same formula as the device).
+void mlp_features(float* x, double fcount, double active, double n, double m, double k,
+                  double prev_us, double prev_mode);
 hipError_t launch_bfs_persistent(bool ms, const PersistParams& P, uint32_t blocks, hipStream_t s);
 
 }  // namespace wedge

@@ -1,0 +1,118 @@
+"""Pins of the gate-MLP oracle and host-side checks of the model API (no GPU).
+
+The oracle's gradient is pinned by central finite differences, its forward
+pass by torch's CPU Linear/ReLU stack, its Adam step by torch.optim.Adam; the
+library's host feature formula must equal the oracle's; model files must
+round-trip and corrupt ones must be refused.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+import paper_1903_07754_amd as W
+from paper_1903_07754_amd import _binding as B
+
+
+def rand_params(seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0, 0.3, mlp.NPARAMS)
+
+
+def test_param_count():
+    assert mlp.NPARAMS == 1476 == B.MLP_PARAMS
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_gradient_matches_central_differences(seed):
+    rng = np.random.default_rng(100 + seed)
+    p = rand_params(seed)
+    x = rng.normal(0, 1, (7, 8))
+    t = rng.normal(0, 1, (7, 4))
+    mask = (rng.random((7, 4)) < 0.8).astype(float)
+    g = mlp.grad(p, x, t, mask)
+    h = 1e-6
+    idx = rng.choice(mlp.NPARAMS, 60, replace=False)
+    for i in idx:
+        e = np.zeros_like(p); e[i] = h
+        fd = (mlp.loss(p + e, x, t, mask) - mlp.loss(p - e, x, t, mask)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def torch_net(p):
+    W1, b1, W2, b2, W3, b3 = [torch.tensor(a) for a in mlp.unpack(p)]
+    net = torch.nn.Sequential(torch.nn.Linear(8, 32), torch.nn.ReLU(), torch.nn.Linear(32, 32),
+                              torch.nn.ReLU(), torch.nn.Linear(32, 4)).double()
+    with torch.no_grad():
+        for layer, (w, b) in zip([net[0], net[2], net[4]], [(W1, b1), (W2, b2), (W3, b3)]):
+            layer.weight.copy_(w)
+            layer.bias.copy_(b)
+    return net
+
+
+def test_forward_matches_torch():
+    p = rand_params(5)
+    x = np.random.default_rng(6).normal(0, 1, (33, 8))
+    want = torch_net(p)(torch.tensor(x)).detach().numpy()
+    np.testing.assert_allclose(mlp.forward(p, x), want, rtol=1e-12, atol=1e-12)
+
+
+def test_adam_matches_torch():
+    p = rand_params(7)
+    g = np.random.default_rng(8).normal(0, 1, mlp.NPARAMS)
+    tp = torch.tensor(p.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    m1 = np.zeros_like(p); m2 = np.zeros_like(p)
+    q = p.copy()
+    for step in range(1, 4):
+        tp.grad = torch.tensor(g * step)
+        opt.step()
+        q, m1, m2 = mlp.adam_step(q, g * step, m1, m2, step)
+    np.testing.assert_allclose(q, tp.detach().numpy(), rtol=1e-10, atol=1e-12)
+
+
+def test_library_features_equal_oracle():
+    rows = [(1, 1, 2**10, 2**14, 0, 0.0, 0), (500, 123456, 2**20, 2**24, 7, 350.5, 2),
+            (2**18, 2**22, 2**18, 2**22, 300, 1e5, 3)]
+    S = (B.TraceSample * len(rows))()
+    for s, (f, a, n, m, k, pu, pm) in zip(S, rows):
+        s.frontier, s.active, s.n, s.m, s.iter, s.prev_us, s.prev_mode = f, a, n, m, k, pu, pm
+    got = W.features(S)
+    want = np.stack([mlp.features(*r) for r in rows]).astype(np.float32)
+    np.testing.assert_allclose(got, want, rtol=2e-7, atol=0)
+
+
+def test_model_file_roundtrip_and_corruption(tmp_path):
+    m = W.Model.create(seed=42)
+    p = m.params()
+    assert p.shape == (1476,) and np.isfinite(p).all() and np.any(p != 0)
+    # weights in +-1/sqrt(fan_in), biases zero
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(p)
+    assert np.abs(W1).max() <= 1 / np.sqrt(8) and np.abs(W2).max() <= 1 / np.sqrt(32)
+    assert not b1.any() and not b2.any() and not b3.any()
+    m.envelope(np.arange(8) - 10.0, np.arange(8) + 10.0)
+    f = tmp_path / "gate.bin"
+    m.save(str(f))
+    m2 = W.Model.load(str(f))
+    np.testing.assert_array_equal(m2.params(), p)
+    np.testing.assert_array_equal(m2.envelope()[0], np.arange(8) - 10.0)
+    raw = bytearray(f.read_bytes())
+    for pos in (0, 20, 200, len(raw) - 3):
+        bad = bytearray(raw); bad[pos] ^= 0x40
+        g = tmp_path / f"bad{pos}.bin"
+        g.write_bytes(bytes(bad))
+        with pytest.raises(W.WedgeError) as e:
+            W.Model.load(str(g))
+        assert e.value.name == "WEDGE_ERR_MODEL"
+    (tmp_path / "short.bin").write_bytes(bytes(raw[:100]))
+    with pytest.raises(W.WedgeError) as e:
+        W.Model.load(str(tmp_path / "short.bin"))
+    assert e.value.name == "WEDGE_ERR_MODEL"
+    with pytest.raises(W.WedgeError) as e:
+        W.Model.load(str(tmp_path / "missing.bin"))
+    assert e.value.name == "WEDGE_ERR_MODEL"
+    q = np.linspace(-1, 1, 1476).astype(np.float32)
+    np.testing.assert_array_equal(m.params(q), q)
+    np.testing.assert_array_equal(m.params(), q)
