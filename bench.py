@@ -97,6 +97,36 @@ def timed(fn, reps):
     return best
 
 
+def learned_section(W, g, gs, srcs, m, outs, reps=2):
+    """BFS, SSSP (the bench's sources) and CC on the bench graph under the
+    threshold rule and under the learned gate (the committed model, trained on
+    scales 18-22 only): best-of-reps wall time per application."""
+    import torch
+    path = os.path.join(ROOT, "paper_1903_07754_amd", "models", "gate.bin")
+    if not os.path.exists(path):
+        return None
+    model = W.Model.load(path)
+    lev, dist, lab = outs
+    res = {"model": "paper_1903_07754_amd/models/gate.bin", "unit": "GTEPS (runs*M/t)"}
+    for app in ("bfs", "sssp", "cc"):
+        row = {}
+        for gate in ("threshold", "learned"):
+            kw = {"gate": gate, "model": model.handle if gate == "learned" else None}
+            if app == "bfs":
+                fn = lambda: [W.bfs(g, s, out=lev, **kw) for s in srcs]
+            elif app == "sssp":
+                fn = lambda: [W.sssp(g, s, out=dist, **kw) for s in srcs]
+            else:
+                fn = lambda: W.cc(gs, out=lab, **kw)
+            runs = 1 if app == "cc" else len(srcs)
+            row[gate] = round(runs * m / timed(fn, reps) / 1e9, 3)
+        row["learned_over_threshold"] = round(row["learned"] / row["threshold"], 3)
+        res[app] = row
+    torch.cuda.synchronize()
+    model.close()
+    return res
+
+
 def batched_section(reps=3):
     """Batched BFS against the plain threshold-gated single-query path on the
     same GPU: 64 sources on R-MAT scale 22 as 64-bit masks in one traversal,
@@ -175,6 +205,10 @@ def main():
     ap.add_argument("--sources", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB 3 times (a known-size "
+                         "kernel for calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -269,12 +303,23 @@ def main():
         "per_app_gteps": per_app, "per_app_ms": per_app_ms,
         "roofline": roof,
     }
+    if not args.no_learned:
+        log("learned gate vs threshold rule on the bench graph")
+        out["learned_gate"] = learned_section(W, g, gs, srcs, m, (lev, dist, lab))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ro, col, w, srcs, m)
     if not args.no_batched:
         del g, gs, lev, lab, dist, rank
         out["batched"] = batched_section()
     print(json.dumps(out), flush=True)
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {nbytes} bytes")
 
 
 if __name__ == "__main__":

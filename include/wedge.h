@@ -243,9 +243,9 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
 
 /*
  * A small learned cost model for the fullness decision: an FP32 MLP
- * 8 -> 32 -> 32 -> 4 (ReLU) predicting log(1 + microseconds) of the next
- * iteration in each mode, mode 0 = full pull and modes 1, 2, 3 = Wedge
- * Frontier at 16, 32, 64 edges per bit. With WEDGE_GATE_LEARNED the decision
+ * 8 -> 32 -> 32 -> 4 (ReLU) predicting, for each mode, log(1 + microseconds)
+ * of the next iteration minus that of the full pull (mode 0 = full pull,
+ * modes 1, 2, 3 = Wedge Frontier at 16, 32, 64 edges per bit). With WEDGE_GATE_LEARNED the decision
  * is the mode of smallest prediction (ties to the lower index), computed on
  * the device between iterations. The paper's threshold rule (Frontier
  * Transformation, Frontier Fullness Threshold) decides instead when no model
@@ -254,7 +254,7 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
  * edges).
  *
  * Features of the frontier F_k about to be consumed (float, in this order):
- * |F_k|/n, A_k/m, 1 - exp(-A_k/ceil(m/16)), log2(n)/32, log2(m)/32,
+ * |F_k|/n, A_k/m, 1 - exp(-A_k/ceil(m/16)), WEDGE_APP_* / 3, log2(m)/32,
  * min(k,255)/64, log(1 + previous iteration's device time in us)/16,
  * previous mode index / 3.
  */
@@ -283,7 +283,7 @@ typedef struct {
 wedge_status wedge_model_create(uint64_t seed, wedge_model_t* out);
 wedge_status wedge_model_free(wedge_model_t m);
 /* Versioned binary file: magic "WEDGEMLP", version, shape, envelope, 1476
- * parameters, FNV-1a-64 checksum. Load returns WEDGE_ERR_MODEL for a missing,
+ * parameters, FNV-1a-64 checksum (version 2: feature 3 is the application). Load returns WEDGE_ERR_MODEL for a missing,
  * truncated, corrupt or mismatched file. */
 wedge_status wedge_model_load(const char* path, wedge_model_t* out);
 wedge_status wedge_model_save(wedge_model_t m, const char* path);
@@ -301,10 +301,11 @@ wedge_status wedge_model_predict(wedge_model_t m, const float* x, uint32_t count
  * parameters, and the loss, on the device (host arrays). */
 wedge_status wedge_model_grad(wedge_model_t m, const float* x, const float* t, const float* mask,
                               uint32_t count, float* grad, float* loss, hipStream_t stream);
-/* Full-batch Adam (lr, 0.9, 0.999, 1e-8) on log(1 + t_us) targets for
+/* Full-batch Adam (lr, 0.9, 0.999, 1e-8) on log(1 + t_us[j]) - log(1 + t_us[0])
+ * targets (samples without a full-pull time are ignored) for
  * `epochs` steps on the device; sets the envelope to the samples' feature
  * range widened by 5%, except for the graph-size and previous-time features
- * (3, 4, 6), which stay unbounded so that a model trained on small graphs is
+ * (4, 6), which stay unbounded so that a model trained on small graphs is
  * used on larger ones. */
 wedge_status wedge_model_train(wedge_model_t m, const wedge_trace_sample* s, uint32_t count,
                                uint32_t epochs, float lr, hipStream_t stream, float* final_loss);

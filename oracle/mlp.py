@@ -69,8 +69,8 @@ def adam_step(p, g, m1, m2, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m1, m2
 
 
-def features(frontier, active, n, m, k, prev_us, prev_mode):
+def features(frontier, active, n, m, k, prev_us, prev_mode, app):
     """The gate's 8 input features (same definitions as the library header)."""
     return np.array([frontier / n, active / m, 1.0 - np.exp(-active / np.ceil(m / 16.0)),
-                     np.log2(n) / 32.0, np.log2(m) / 32.0, min(k, 255) / 64.0,
+                     app / 3.0, np.log2(m) / 32.0, min(k, 255) / 64.0,
                      np.log1p(prev_us) / 16.0, prev_mode / 3.0])

@@ -278,6 +278,7 @@ struct LoopCfg {
     const float* hi = nullptr;
     double ticks_per_us = 100.0;
     uint64_t m = 0;
+    uint32_t app = kBfs;       // application (a gate feature)
     // the smallest chunk exponent this run may use (bitmap and list sizes)
     int min_lc() const { return learned ? std::min(lc, 4) : lc; }
     uint64_t chunks_of(int l) const { return (m + (1ull << l) - 1) >> l; }
@@ -290,7 +291,7 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
     const DevGraph& d = g->dev;
     if (c.learned)
         HIP_TRY(launch_mlp_infer(c.P, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr, (uint32_t)c.lc,
-                                 c.ticks_per_us, s), "gate inference");
+                                 c.ticks_per_us, c.app, s), "gate inference");
     HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
     HIP_TRY(hipStreamSynchronize(s), "initialising run");
     uint64_t fcount = w.ctl_host->ftotal;               // |F_k|
@@ -316,8 +317,8 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
                 default: wedge_mode = active < c.thr; break;  // the fullness threshold (strict <)
             }
         }
-        HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
-        if (c.learned) HIP_TRY(launch_gate_stamp(w.ctl, s), "gate stamp");
+        if (c.learned) HIP_TRY(launch_gate_stamp(w.ctl, s), "clearing counters");
+        else HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[2], s), "event");
         uint64_t maxk = 0;
         if (wedge_mode) {
@@ -334,7 +335,7 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
         if (c.learned)
             HIP_TRY(launch_mlp_infer(c.P, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr,
-                                     (uint32_t)c.lc, c.ticks_per_us, s), "gate inference");
+                                     (uint32_t)c.lc, c.ticks_per_us, c.app, s), "gate inference");
         HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
         HIP_TRY(hipStreamSynchronize(s), "iteration");
         float pms = 0.f, ims = 0.f;
@@ -366,9 +367,10 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
     return WEDGE_OK;
 }
 
-LoopCfg loop_cfg(const wedge_opts& o, const DevGraph& d, uint32_t theta_default,
+LoopCfg loop_cfg(const wedge_opts& o, const DevGraph& d, App app, uint32_t theta_default,
                  uint32_t chunk_default) {
     LoopCfg c;
+    c.app = (uint32_t)app;
     const uint32_t theta = o.threshold_ppm ? o.threshold_ppm : theta_default;
     const uint32_t chunk = o.chunk_edges ? o.chunk_edges : chunk_default;
     c.lc = log2u(chunk);
@@ -443,7 +445,7 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     wedge_stats local{};
     const double t0 = now_ms();
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
-    LoopCfg c = loop_cfg(o, d, app == kBfs ? 10000u : 200000u, app == kBfs ? 32u : 16u);
+    LoopCfg c = loop_cfg(o, d, (App)app, app == kBfs ? 10000u : 200000u, app == kBfs ? 32u : 16u);
     if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
     if ((st = ensure_workspace(g, c.min_lc(), true, c.gate != WEDGE_GATE_ALWAYS_FULL)) != WEDGE_OK) return st;
     Workspace& w = g->ws;
@@ -676,7 +678,7 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
     wedge_stats local{};
     const double t0 = now_ms();
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
-    LoopCfg c = loop_cfg(o, d, 10000u, 32u);
+    LoopCfg c = loop_cfg(o, d, kBfs, 10000u, 32u);
     if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
     if ((o.flags & WEDGE_RUN_PERSISTENT) && c.learned)
         return fail(WEDGE_ERR_UNSUPPORTED, "the learned gate runs with the host-driven loop");
@@ -731,7 +733,7 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
     wedge_stats local{};
     const double t0 = now_ms();
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
-    LoopCfg c = loop_cfg(o, d, 10000u, 32u);
+    LoopCfg c = loop_cfg(o, d, kBfs, 10000u, 32u);
     if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
     if ((o.flags & WEDGE_RUN_PERSISTENT) && c.learned)
         return fail(WEDGE_ERR_UNSUPPORTED, "the learned gate runs with the host-driven loop");
@@ -1101,7 +1103,7 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
     if (d.n == 0) return WEDGE_OK;
     const uint32_t def_chunk = app == kBfs ? 32u : 16u;
-    const LoopCfg c = loop_cfg(o, d, app == kBfs ? 10000u : 200000u, def_chunk);
+    const LoopCfg c = loop_cfg(o, d, (App)app, app == kBfs ? 10000u : 200000u, def_chunk);
     wedge_status st;
     if ((st = ensure_workspace(g, 4, true, true)) != WEDGE_OK) return st;
     Workspace& w = g->ws;

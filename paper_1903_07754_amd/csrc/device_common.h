@@ -92,7 +92,13 @@ __device__ __forceinline__ uint32_t dst_of(const GraphArgs& g, uint32_t p) {
 }
 
 
-// Frontier transformation work of one wave (see k_translate).
+// Frontier transformation work of one wave (see k_translate). The wave covers
+// out-edges [base, base + 64*EPT) of the concatenated lists of the listed
+// frontier vertices (each has at least one out-edge), one 64-edge row at a
+// time. 64 consecutive edges lie in at most 64 consecutive list entries, so
+// lane l holds entry j0 + l of a window (its out-degree prefix and CSR row
+// start) and every lane finds the owner of its edge by a 6-step shuffle
+// search of that window; the only per-edge global load is the edge index.
 template <int EPT>
 __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __restrict__ flist,
                                                const uint32_t* __restrict__ degpre,
@@ -104,32 +110,41 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
     const uint64_t base = wave * 64ull * EPT;
     if (base >= active) return;
     const uint64_t end = min<uint64_t>(base + 64ull * EPT, active);
-    // frontier index range [lo, hi] covering edges [base, end)
-    auto last_le = [&](uint64_t a, uint32_t L, uint32_t H) {
-        while (L < H) {
-            uint32_t M = (L + H + 1) >> 1;
-            if (degpre[M] <= a) L = M; else H = M - 1;
-        }
-        return L;
-    };
-    const uint32_t lo = wave_last_le(degpre, 0, fcount - 1, base, lane);
-    const uint32_t hi = wave_last_le(degpre, lo, fcount - 1, end - 1, lane);
+    uint32_t j0 = wave_last_le(degpre, 0, fcount - 1, base, lane);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        const uint64_t a = base + (uint64_t)i * 64 + lane;
+        const uint64_t row = base + (uint64_t)i * 64;
+        if (row >= end) break;
+        const uint32_t jw = j0 + lane;
+        const uint32_t dw = jw < fcount ? degpre[jw] : 0xFFFFFFFFu;
+        const uint32_t rw = jw < fcount ? row_off[flist[jw]] : 0u;
+        const uint64_t a = row + lane;
         const bool valid = a < end;
+        int t = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int cand = t + step;
+            const uint32_t d = __shfl(dw, cand & 63, 64);
+            if (cand < 64 && d <= a) t = cand;
+        }
         uint32_t key = kInf, bit = 0;
+        const uint32_t dt = __shfl(dw, t, 64);
+        const uint32_t rt = __shfl(rw, t, 64);
         if (valid) {
-            uint32_t j = last_le(a, lo, hi);
-            uint32_t u = flist[j];
-            uint32_t q = row_off[u] + (uint32_t)(a - degpre[j]);
-            uint32_t c = pos[q] >> lc;
+            const uint32_t q = rt + (uint32_t)(a - dt);
+            const uint32_t c = pos[q] >> lc;
             key = c >> 5;
             bit = 1u << (c & 31);
         }
-        uint32_t prev = __shfl_up(key, 1, 64);
-        bool head = lane == 0 || prev != key;
-        uint64_t heads = __ballot(head);
+        // next row's window starts at the vertex holding edge row + 64: the one
+        // holding edge row + 63, or the next one when that begins exactly there
+        // (every listed vertex has at least one edge, so a window of 64 vertices
+        // from there covers the whole next row)
+        j0 += (uint32_t)__shfl(t, 63, 64);
+        if (j0 + 1 < fcount && degpre[j0 + 1] <= row + 64) ++j0;
+        const uint32_t prev = __shfl_up(key, 1, 64);
+        const bool head = lane == 0 || prev != key;
+        const uint64_t heads = __ballot(head);
         bit = seg_reduce(bit, seg_span(heads, lane), [](uint32_t x, uint32_t y) { return x | y; });
         if (head && valid) atomicOr(wbits32 + key, bit);
     }

@@ -1,6 +1,7 @@
 // Learned gate: a small FP32 MLP (8 -> 32 -> 32 -> 4, ReLU) that predicts the
 // log-time of the next iteration in each mode {full pull, Wedge Frontier at 16,
-// 32, 64 edges per bit}; the gate picks the smallest prediction. Inference
+// 32, 64 edges per bit} relative to the full pull; the gate picks the smallest
+// prediction. Inference
 // runs on one wave between iterations from the device counters; training is a
 // per-sample forward/backward with LDS-reduced gradients and an Adam update.
 // The paper's threshold rule (Frontier Transformation, Frontier Fullness
@@ -51,11 +52,11 @@ __device__ __forceinline__ void mlp_forward(const float* __restrict__ P, const f
 // Features of the frontier the next iteration will consume (see mlp_features).
 __device__ __forceinline__ void make_features(float (&x)[kMlpIn], double fcount, double active,
                                               double n, double m, double k, double prev_us,
-                                              double prev_mode) {
+                                              double prev_mode, double app) {
     x[0] = (float)(fcount / n);
     x[1] = (float)(active / m);
     x[2] = (float)(1.0 - exp(-active / ceil(m / 16.0)));
-    x[3] = (float)(log2(n) / 32.0);
+    x[3] = (float)(app / 3.0);
     x[4] = (float)(log2(m) / 32.0);
     x[5] = (float)(fmin(k, 255.0) / 64.0);
     x[6] = (float)(log1p(prev_us) / 16.0);
@@ -169,16 +170,22 @@ __device__ __forceinline__ uint32_t mode_of_lc(uint32_t lc) {
     return lc <= 4 ? 1u : lc == 5 ? 2u : 3u;
 }
 
-// Start-of-iteration time stamp (the previous-iteration-time feature is the
-// device time from this stamp to the next decision).
+// Start of an iteration: clear the iteration counters and stamp the time (the
+// previous-iteration-time feature is the device time from this stamp to the
+// next decision).
 __global__ void k_gate_stamp(Ctl* ctl) {
-    if (threadIdx.x == 0) ctl->gate.stamp = wall_clock64();
+    if (threadIdx.x == 0) {
+        ctl->fnext = 0;
+        ctl->marked = 0;
+        ctl->ftotal = 0;
+        ctl->gate.stamp = wall_clock64();
+    }
 }
 
 __global__ void k_mlp_infer(const float* __restrict__ P, const float* __restrict__ env_lo,
                             const float* __restrict__ env_hi, Ctl* ctl,
                             double n, double m, uint64_t thr, uint32_t fallback_lc,
-                            double ticks_per_us) {
+                            double ticks_per_us, uint32_t app) {
     GateState* gs = &ctl->gate;
     __shared__ float h1[kMlpHidden], h2[kMlpHidden], xs[kMlpIn];
     __shared__ int s_in;
@@ -189,7 +196,8 @@ __global__ void k_mlp_infer(const float* __restrict__ P, const float* __restrict
     if (lane == 0) {
         const double prev_us = gs->stamp ? (double)(now - gs->stamp) / ticks_per_us : 0.0;
         float x[kMlpIn];
-        make_features(x, fcount, (double)active, n, m, (double)gs->k, prev_us, (double)gs->prev_mode);
+        make_features(x, fcount, (double)active, n, m, (double)gs->k, prev_us, (double)gs->prev_mode,
+                      (double)app);
         int in = P != nullptr;
         for (int i = 0; i < kMlpIn; ++i) {
             xs[i] = x[i];
@@ -259,8 +267,8 @@ hipError_t launch_adam(float* P, float* G, float* M1, float* M2, float lr, float
 
 hipError_t launch_mlp_infer(const float* P, const float* lo, const float* hi, Ctl* ctl, double n,
                             double m, uint64_t thr, uint32_t fallback_lc, double ticks_per_us,
-                            hipStream_t s) {
-    k_mlp_infer<<<1, 64, 0, s>>>(P, lo, hi, ctl, n, m, thr, fallback_lc, ticks_per_us);
+                            uint32_t app, hipStream_t s) {
+    k_mlp_infer<<<1, 64, 0, s>>>(P, lo, hi, ctl, n, m, thr, fallback_lc, ticks_per_us, app);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ using namespace wedge;
 namespace {
 
 constexpr char kMagic[8] = {'W', 'E', 'D', 'G', 'E', 'M', 'L', 'P'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 wedge_status err(wedge_status st, const std::string& m) { return set_error(st, m); }
 
@@ -56,11 +56,11 @@ struct DevBuf {
 namespace wedge {
 
 void mlp_features(float* x, double fcount, double active, double n, double m, double k,
-                  double prev_us, double prev_mode) {
+                  double prev_us, double prev_mode, double app) {
     x[0] = (float)(fcount / n);
     x[1] = (float)(active / m);
     x[2] = (float)(1.0 - std::exp(-active / std::ceil(m / 16.0)));
-    x[3] = (float)(std::log2(n) / 32.0);
+    x[3] = (float)(app / 3.0);
     x[4] = (float)(std::log2(m) / 32.0);
     x[5] = (float)(std::fmin(k, 255.0) / 64.0);
     x[6] = (float)(std::log1p(prev_us) / 16.0);
@@ -211,7 +211,7 @@ wedge_status wedge_model_features(const wedge_trace_sample* s, uint32_t count, f
     for (uint32_t i = 0; i < count; ++i)
         mlp_features(x + (size_t)i * kMlpIn, (double)s[i].frontier, (double)s[i].active,
                      (double)s[i].n, (double)s[i].m, (double)s[i].iter, (double)s[i].prev_us,
-                     (double)s[i].prev_mode);
+                     (double)s[i].prev_mode, (double)s[i].app);
     return WEDGE_OK;
 }
 
@@ -261,17 +261,23 @@ wedge_status wedge_model_train(wedge_model_t m, const wedge_trace_sample* s, uin
     if (!(lr > 0.f)) return err(WEDGE_ERR_INVALID_ARG, "lr must be > 0");
     std::vector<float> X((size_t)count * kMlpIn), T((size_t)count * kMlpOut), M((size_t)count * kMlpOut);
     wedge_model_features(s, count, X.data());
-    for (uint32_t i = 0; i < count; ++i)
+    // targets relative to the full pull of the same iteration: only differences
+    // between modes decide, and they carry over across graph sizes far better
+    // than absolute times
+    for (uint32_t i = 0; i < count; ++i) {
+        const double ref = s[i].t_us[0] > 0.f ? std::log1p((double)s[i].t_us[0]) : 0.0;
         for (int j = 0; j < kMlpOut; ++j) {
             const float tu = s[i].t_us[j];
-            M[(size_t)i * kMlpOut + j] = tu > 0.f ? 1.f : 0.f;
-            T[(size_t)i * kMlpOut + j] = tu > 0.f ? (float)std::log1p((double)tu) : 0.f;
+            const bool ok = tu > 0.f && s[i].t_us[0] > 0.f;
+            M[(size_t)i * kMlpOut + j] = ok ? 1.f : 0.f;
+            T[(size_t)i * kMlpOut + j] = ok ? (float)(std::log1p((double)tu) - ref) : 0.f;
         }
+    }
     // training envelope: per-feature range widened by 5% on each side, for the
-    // scale-free features only; graph size (3, 4) and the previous time (6) are
+    // scale-free features only; graph size (4) and the previous time (6) are
     // left open so a model trained on small graphs serves larger ones
     for (int f = 0; f < kMlpIn; ++f) {
-        if (f == 3 || f == 4 || f == 6) {
+        if (f == 4 || f == 6) {
             m->lo[f] = -std::numeric_limits<float>::infinity();
             m->hi[f] = std::numeric_limits<float>::infinity();
             continue;

@@ -338,11 +338,11 @@ hipError_t launch_adam(float* P, float* G, float* M1, float* M2, float lr, float
 // P null: the threshold rule decides (no model)
 hipError_t launch_mlp_infer(const float* P, const float* lo, const float* hi, Ctl* ctl, double n,
                             double m, uint64_t thr, uint32_t fallback_lc, double ticks_per_us,
-                            hipStream_t s);
+                            uint32_t app, hipStream_t s);
 hipError_t launch_gate_stamp(Ctl* ctl, hipStream_t s);
 // Host form of the gate features (same formula as the device).
 void mlp_features(float* x, double fcount, double active, double n, double m, double k,
-                  double prev_us, double prev_mode);
+                  double prev_us, double prev_mode, double app);
 hipError_t launch_bfs_persistent(bool ms, const PersistParams& P, uint32_t blocks, hipStream_t s);
 
 }  // namespace wedge

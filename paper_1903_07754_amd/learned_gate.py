@@ -34,6 +34,7 @@ import gen  # noqa: E402
 from . import _binding as B  # noqa: E402
 
 DEFAULT_MODEL = os.path.join(HERE, "models", "gate.bin")
+DEFAULT_TRACES = os.path.join(HERE, "models", "gate_traces.npz")
 APPS = ("bfs", "cc", "sssp")
 FIELDS = ("app", "iter", "prev_mode", "threshold_mode", "n", "m", "frontier", "active", "prev_us")
 
@@ -128,10 +129,22 @@ def regret(samples, pick):
             "best_total_us": float(best.sum())}
 
 
-def train(samples, epochs=3000, lr=3e-3, seed=7):
-    m = B.Model.create(seed=seed)
-    loss = m.train(samples, epochs=epochs, lr=lr)
-    return m, loss
+def train(samples, epochs=3000, lr=3e-3, seed=7, restarts=1):
+    """Train `restarts` models from seeds seed, seed+1, ...; keep the one with the
+    smallest regret on the training samples themselves."""
+    best = None
+    for r in range(restarts):
+        m = B.Model.create(seed=seed + r)
+        loss = m.train(samples, epochs=epochs, lr=lr)
+        reg = regret(samples, choices(m, samples)[0])["regret_us"]
+        log(f"restart {r}: seed {seed + r} loss {loss:.4f} training-set regret {reg:.0f} us")
+        if best is None or reg < best[2]:
+            if best is not None:
+                best[0].close()
+            best = (m, loss, reg)
+        else:
+            m.close()
+    return best[0], best[1]
 
 
 def eval_graphs(seeds=(2000, 2001, 2002, 2003), scale=24):
@@ -174,7 +187,7 @@ def end_to_end(model, ro, col, seed, reps=3):
     return res
 
 
-def evaluate(model, seeds=(2000, 2001, 2002, 2003), scale=24):
+def evaluate(model, seeds=(2000, 2001, 2002, 2003), scale=24, traces_out=None):
     report = {"graphs": []}
     all_samples = []
     for kind, seed, ro, col in eval_graphs(seeds, scale):
@@ -193,6 +206,8 @@ def evaluate(model, seeds=(2000, 2001, 2002, 2003), scale=24):
             "end_to_end_gteps": {app: {k: round(m / v / 1e6, 3) for k, v in t.items()}
                                  for app, t in e2e.items()}})
     samples = concat(all_samples)
+    if traces_out:
+        np.savez_compressed(traces_out, **to_arrays(samples))
     pick, inside = choices(model, samples)
     thr = np.array([s.threshold_mode for s in samples])
     report["all"] = {"iterations": len(samples), "model_decided": float(inside.mean()),
@@ -208,15 +223,17 @@ def main(argv=None):
     c.add_argument("--first-seed", type=int, default=1000)
     c.add_argument("--out", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--traces", required=True)
+    t.add_argument("--traces", default=DEFAULT_TRACES)
     t.add_argument("--out", required=True)
     t.add_argument("--epochs", type=int, default=3000)
     t.add_argument("--lr", type=float, default=3e-3)
     t.add_argument("--seed", type=int, default=7)
+    t.add_argument("--restarts", type=int, default=4)
     e = sub.add_parser("evaluate")
     e.add_argument("--model", default=DEFAULT_MODEL)
     e.add_argument("--out", required=True)
     e.add_argument("--scale", type=int, default=24)
+    e.add_argument("--traces-out", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
         samples = collect(a.count, a.first_seed)
@@ -224,7 +241,7 @@ def main(argv=None):
         log(f"{len(samples)} samples -> {a.out}")
     elif a.cmd == "train":
         samples = from_arrays(dict(np.load(a.traces)))
-        m, loss = train(samples, a.epochs, a.lr, a.seed)
+        m, loss = train(samples, a.epochs, a.lr, a.seed, a.restarts)
         m.save(a.out)
         pick, inside = choices(m, samples)
         thr = np.array([s.threshold_mode for s in samples])
@@ -233,7 +250,7 @@ def main(argv=None):
             f"learned {regret(samples, pick)['regret_us']:.0f} us -> {a.out}")
     else:
         model = B.Model.load(a.model)
-        rep = evaluate(model, scale=a.scale)
+        rep = evaluate(model, scale=a.scale, traces_out=a.traces_out)
         with open(a.out, "w") as f:
             json.dump(rep, f, indent=1)
         log(json.dumps(rep["all"]))

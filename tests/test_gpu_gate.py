@@ -47,6 +47,7 @@ def synthetic_samples(n, seed):
     S = (B.TraceSample * n)()
     for s in S:
         s.n, s.m = 1 << 20, 1 << 24
+        s.app = int(rng.integers(1, 4))
         s.frontier = int(rng.integers(1, 1 << 20))
         s.active = int(rng.integers(1, 1 << 24))
         s.iter = int(rng.integers(0, 30))
@@ -63,7 +64,8 @@ def test_training_lowers_the_loss_and_learns_the_crossover():
     S = synthetic_samples(3000, 2)
     m = W.Model.create(seed=4)
     x = W.features(S)
-    t = np.log1p(np.array([list(s.t_us) for s in S], np.float32))
+    t = np.log1p(np.array([list(s.t_us) for s in S], np.float64))
+    t = (t - t[:, :1]).astype(np.float32)        # training targets: relative to the full pull
     _, l0 = m.grad(x, t, np.ones_like(t))
     l1 = m.train(S, epochs=1500, lr=3e-3)
     assert l1 < l0 / 20, (l0, l1)
@@ -71,10 +73,11 @@ def test_training_lowers_the_loss_and_learns_the_crossover():
     choice = y.argmin(1)
     best = np.array([np.argmin(s.t_us) for s in S])
     assert (choice == best).mean() > 0.9
+    assert np.abs(y[:, 0]).mean() < 0.05         # the full pull's own relative target is 0
     lo, hi = m.envelope()
     assert np.all(lo <= x.min(0)) and np.all(hi >= x.max(0))
-    assert np.isinf(lo[[3, 4, 6]]).all() and np.isinf(hi[[3, 4, 6]]).all()
-    assert np.isfinite(lo[[0, 1, 2, 5, 7]]).all()
+    assert np.isinf(lo[[4, 6]]).all() and np.isinf(hi[[4, 6]]).all()
+    assert np.isfinite(lo[[0, 1, 2, 3, 5, 7]]).all()
 
 
 @pytest.mark.parametrize("app", ["bfs", "cc", "sssp"])

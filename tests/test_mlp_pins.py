@@ -74,11 +74,11 @@ def test_adam_matches_torch():
 
 
 def test_library_features_equal_oracle():
-    rows = [(1, 1, 2**10, 2**14, 0, 0.0, 0), (500, 123456, 2**20, 2**24, 7, 350.5, 2),
-            (2**18, 2**22, 2**18, 2**22, 300, 1e5, 3)]
+    rows = [(1, 1, 2**10, 2**14, 0, 0.0, 0, 1), (500, 123456, 2**20, 2**24, 7, 350.5, 2, 2),
+            (2**18, 2**22, 2**18, 2**22, 300, 1e5, 3, 3)]
     S = (B.TraceSample * len(rows))()
-    for s, (f, a, n, m, k, pu, pm) in zip(S, rows):
-        s.frontier, s.active, s.n, s.m, s.iter, s.prev_us, s.prev_mode = f, a, n, m, k, pu, pm
+    for s, (f, a, n, m, k, pu, pm, app) in zip(S, rows):
+        s.frontier, s.active, s.n, s.m, s.iter, s.prev_us, s.prev_mode, s.app = f, a, n, m, k, pu, pm, app
     got = W.features(S)
     want = np.stack([mlp.features(*r) for r in rows]).astype(np.float32)
     np.testing.assert_allclose(got, want, rtol=2e-7, atol=0)
