@@ -1,6 +1,7 @@
 // C ABI of the Wedge-Frontier pull engine: argument checks, graph upload, the
 // per-iteration control loop (Wedge Overview, Fig. 5) and PageRank.
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <tuple>
 #include <chrono>
@@ -534,9 +535,16 @@ wedge_status upload_roots(wedge_graph_t g, const uint32_t* roots, uint32_t count
 }
 
 int device_cus(int dev) {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
-    return p.multiProcessorCount;
+    static std::atomic<int> cache[64];
+    if (dev >= 0 && dev < 64) {
+        const int c = cache[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+        return 0;
+    if (dev >= 0 && dev < 64) cache[dev].store(c, std::memory_order_relaxed);
+    return c;
 }
 
 uint64_t barrier_timeout_ticks(int dev) {
@@ -903,6 +911,7 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
     }
     float* rank = d.inv ? w.pr_rank : rank_dev;
     const bool time_pull = o.flags & WEDGE_RUN_TIME_PULL;
+    const int cus = device_cus(g->device);
     std::vector<hipEvent_t> evs;
     if (time_pull) {
         evs.resize(2 * (size_t)iters);
@@ -916,7 +925,7 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
     for (uint32_t k = 0; k < iters && e == hipSuccess; ++k) {
         double* dk = w.pr_d + (k & 1);
         if (time_pull) e = hipEventRecord(evs[2 * k], s);
-        if (e == hipSuccess) e = launch_pr_pull(d, w.pr_contrib, w.pr_sum, w.pr_head, w.pr_tail, s);
+        if (e == hipSuccess) e = launch_pr_pull(d, w.pr_contrib, w.pr_sum, w.pr_head, w.pr_tail, cus, s);
         if (time_pull && e == hipSuccess) e = hipEventRecord(evs[2 * k + 1], s);
         if (e == hipSuccess)
             e = launch_pr_fixup(d, w.pr_head, w.pr_tail, w.pr_sum, w.pr_part, w.pr_parts,

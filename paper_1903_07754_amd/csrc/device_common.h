@@ -11,6 +11,20 @@ namespace dev {
 constexpr int kBlock = 256;           // 4 waves
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kPullRows = 8;          // rows (64 positions each) per wave in the integer pulls
+// LDS copy of the highest-out-degree vertices' values in the full pulls
+#ifndef WEDGE_HOT_BLOCK
+#define WEDGE_HOT_BLOCK 768
+#endif
+#ifndef WEDGE_HOT_VERTS
+#define WEDGE_HOT_VERTS 16384
+#endif
+#ifndef WEDGE_HOT_BATCH
+#define WEDGE_HOT_BATCH 4
+#endif
+constexpr int kHotBlock = WEDGE_HOT_BLOCK;          // threads per block
+constexpr uint32_t kHotVerts = WEDGE_HOT_VERTS;     // values held in LDS (4 B each)
+constexpr int kHotBatch = WEDGE_HOT_BATCH;          // rows loaded at a time per wave
+constexpr uint32_t kHotMinVerts = 4096;
 constexpr int kTranslateEpt = 4;      // frontier out-edges per lane in the translation
 constexpr int kCompactWords = 8;      // 64-bit bitmap words per wave in the compaction
 constexpr uint32_t kPrEpilogueVerts = 8192;  // vertices per PageRank epilogue block
@@ -270,29 +284,46 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
             }
         }
     } else {
-        uint32_t u[R], x[R], cand[R];
+        // All loads of the R rows are issued before any result is used, and
+        // the commit waits for nothing: within an iteration val[v] only falls
+        // from val_prev[v], so best < (any value of val[v] read now) already
+        // proves that v changes this iteration and belongs to the next
+        // frontier, whatever the min-atomic finds when it lands. A destination
+        // whose segment runs on into the next row is carried there, so each
+        // destination is committed at most once per wave (a hub spanning many
+        // rows would otherwise send one atomic per row to the same address).
+        uint32_t u[R], x[R], wt[R], cur[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) u[i] = valid[i] ? ld_stream(g.in_src + p[i]) : 0u;
 #pragma unroll
         for (int i = 0; i < R; ++i) x[i] = valid[i] ? val_prev[u[i]] : kInf;
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            if (APP == kCc) cand[i] = x[i];
-            else cand[i] = x[i] != kInf ? x[i] + ld_stream(g.in_w + p[i]) : kInf;
-        }
+        for (int i = 0; i < R; ++i) wt[i] = (APP == kSssp && valid[i]) ? ld_stream(g.in_w + p[i]) : 0u;
+#pragma unroll
+        for (int i = 0; i < R; ++i) cur[i] = valid[i] ? val[dst[i]] : 0u;
+        uint32_t carry = kInf;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
+            const uint32_t cand = (APP == kCc || x[i] == kInf) ? x[i] : x[i] + wt[i];
             const uint32_t prev = __shfl_up(dst[i], 1, 64);
             const bool head = lane == 0 || prev != dst[i];
             const uint64_t heads = __ballot(head);
-            const uint32_t best = seg_reduce(cand[i], seg_span(heads, lane),
-                                             [](uint32_t a, uint32_t b) { return a < b ? a : b; });
-            if (head && best != kInf) {
-                const uint32_t v = dst[i];
-                if (best < val[v]) {
-                    const uint32_t old = atomicMin(val + v, best);
-                    if (best < old) set_bit(fbits, v);
+            const uint64_t hv = heads & __ballot(valid[i]);
+            uint32_t best = seg_reduce(cand, seg_span(heads, lane),
+                                       [](uint32_t a, uint32_t b) { return a < b ? a : b; });
+            if (lane == 0 && carry < best) best = carry;
+            carry = kInf;
+            int defer = -1;
+            if (hv && i + 1 < R) {
+                const int h_last = 63 - __clzll(hv);
+                if (__shfl(dst[i + 1], 0, 64) == __shfl(dst[i], h_last, 64)) {
+                    defer = h_last;
+                    carry = __shfl(best, h_last, 64);
                 }
+            }
+            if (head && valid[i] && lane != defer && best < cur[i]) {
+                atomicMin(val + dst[i], best);
+                set_bit(fbits, dst[i]);
             }
         }
     }

@@ -298,7 +298,7 @@ hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
 hipError_t launch_pr_init(uint32_t n, const uint32_t* row_off, float* rank, float* contrib,
                           float* sum, hipStream_t s);
 hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, float* head,
-                          float* tail, hipStream_t s);
+                          float* tail, int cus, hipStream_t s);
 // Completes S for destinations crossing tile boundaries, and reduces the
 // previous epilogue's dangling partials into *d_next (when d_next is set).
 hipError_t launch_pr_fixup(const DevGraph& g, const float* head, const float* tail, float* sum,

@@ -264,6 +264,24 @@ def test_pagerank_parity(name, keep_ids):
     assert torch.equal(r, r2)
 
 
+@pytest.mark.parametrize("kind", ["rmat", "er"])
+def test_pagerank_large_graph_lds_pull(kind):
+    """Scale 20 is large enough for the pull that keeps the highest-degree
+    vertices' contributions in LDS and strides over the tiles (at least four
+    tiles per resident wave on 256 CUs); its result must still be the oracle's
+    and deterministic."""
+    ro, col = gen.rmat(20, 16, seed=81)
+    if kind == "er":
+        ro, col = gen.erdos_renyi(1 << 20, len(col), seed=81)
+    g = W.Graph.from_csr(ro, col)
+    assert (g.info["rows"] + 7) // 8 >= 4 * 2 * 256 * 12
+    r, _ = W.pagerank(g, 20, 0.85)
+    ref = oracle.pagerank(ro, col, 20, 0.85)
+    assert rel_l1(r.cpu().numpy(), ref) <= 1e-5
+    r2, _ = W.pagerank(g, 20, 0.85)
+    assert torch.equal(r, r2)
+
+
 def test_pagerank_closed_forms():
     n = 1000
     cyc = gen.csr_from_edges(n, np.arange(n, dtype=np.uint32),
