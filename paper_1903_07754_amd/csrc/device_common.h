@@ -248,6 +248,26 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
     }
 }
 
+// Destinations of R positions per lane, every load issued before any is
+// used. Positions must be valid (< m); lanes without an edge pass position 0
+// and mask the result themselves. A guarded load (valid ? load : default)
+// would become a branch per row, and the wait at each branch join would
+// serialise the rows' memory round trips.
+template <int R>
+__device__ __forceinline__ void dst_of_rows(const GraphArgs& g, const uint32_t (&pc)[R],
+                                            uint32_t (&dst)[R]) {
+    uint64_t mk[R];
+    uint32_t sg[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        mk[i] = g.rowmask[pc[i] >> 6];
+        sg[i] = g.rowseg[pc[i] >> 6];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+        dst[i] = g.nzdst[sg[i] + (uint32_t)__popcll(mk[i] & ~1ull & mask_le((int)(pc[i] & 63)))];
+}
+
 template <int APP, int R>
 __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&p)[R],
                                            const bool (&valid)[R], uint32_t iter,
@@ -256,20 +276,44 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                                            const uint64_t* __restrict__ fcur,
                                            uint64_t* __restrict__ fbits) {
     const int lane = lane_id();
-    uint32_t dst[R];
+    // loads are branch-free: a lane without an edge reads position 0 (its
+    // results are masked), so all rows' loads of one step are in flight at once
+    uint32_t pc[R], dst[R], u[R], wt[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst_of(g, p[i]) : kInf;
+    for (int i = 0; i < R; ++i) pc[i] = valid[i] ? p[i] : 0u;
+    if (APP != kBfs) {
+        // the edge streams do not depend on the destinations: issue them first
+#pragma unroll
+        for (int i = 0; i < R; ++i) u[i] = ld_stream(g.in_src + pc[i]);
+#pragma unroll
+        for (int i = 0; i < R; ++i) wt[i] = APP == kSssp ? ld_stream(g.in_w + pc[i]) : 0u;
+    }
+    dst_of_rows<R>(g, pc, dst);
+#pragma unroll
+    for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst[i] : kInf;
 
     if (APP == kBfs) {
+        // only unvisited destinations read their in-edges: the others point
+        // their loads at one shared address (one request per wave)
         bool need[R];
-        uint32_t u[R];
+        uint32_t vd[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) need[i] = valid[i] && val[dst[i]] == kInf;
+        for (int i = 0; i < R; ++i) vd[i] = val[valid[i] ? dst[i] : 0u];
 #pragma unroll
-        for (int i = 0; i < R; ++i) u[i] = need[i] ? ld_stream(g.in_src + p[i]) : 0u;
+        for (int i = 0; i < R; ++i) need[i] = valid[i] & (vd[i] == kInf);
+#pragma unroll
+        for (int i = 0; i < R; ++i) u[i] = ld_stream(g.in_src + (need[i] ? pc[i] : 0u));
+        uint32_t fw[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const bool found = need[i] && test_bit(fcur, u[i]);
+            const uint32_t q = need[i] ? u[i] : 0u;
+            fw[i] = reinterpret_cast<const uint32_t*>(fcur)[q >> 5] >> (q & 31);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) need[i] = need[i] & ((fw[i] & 1u) != 0u);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const bool found = need[i];
             const uint32_t prev = __shfl_up(dst[i], 1, 64);
             const bool head = lane == 0 || prev != dst[i];
             const uint64_t heads = __ballot(head);
@@ -292,15 +336,13 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
         // whose segment runs on into the next row is carried there, so each
         // destination is committed at most once per wave (a hub spanning many
         // rows would otherwise send one atomic per row to the same address).
-        uint32_t u[R], x[R], wt[R], cur[R];
+        uint32_t x[R], cur[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) u[i] = valid[i] ? ld_stream(g.in_src + p[i]) : 0u;
+        for (int i = 0; i < R; ++i) x[i] = val_prev[u[i]];
 #pragma unroll
-        for (int i = 0; i < R; ++i) x[i] = valid[i] ? val_prev[u[i]] : kInf;
+        for (int i = 0; i < R; ++i) cur[i] = val[valid[i] ? dst[i] : 0u];
 #pragma unroll
-        for (int i = 0; i < R; ++i) wt[i] = (APP == kSssp && valid[i]) ? ld_stream(g.in_w + p[i]) : 0u;
-#pragma unroll
-        for (int i = 0; i < R; ++i) cur[i] = valid[i] ? val[dst[i]] : 0u;
+        for (int i = 0; i < R; ++i) x[i] = valid[i] ? x[i] : kInf;
         uint32_t carry = kInf;
 #pragma unroll
         for (int i = 0; i < R; ++i) {

@@ -223,44 +223,58 @@ __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gathe
                                         float* __restrict__ tail_part) {
     static_assert(R % B == 0, "rows are loaded in batches of B");
     const int lane = lane_id();
-    const uint64_t r0 = tile * R;
+    const uint64_t r0 = tile * R;  // wave-uniform
     if (r0 >= g.rows) return;
     float carry = 0.0f;
     bool from_before = false;
-    // rows are loaded B at a time (B gathers in flight per lane) and reduced
-    // in order; the carry links segments across rows and batches
+    // Rows are loaded B at a time and reduced in order; the carry links
+    // segments across rows and batches. Loads are branch-free (a lane past
+    // the last edge reads position 0 and is masked) so that the batch's
+    // memory round trips overlap.
 #pragma unroll
     for (int i0 = 0; i0 < R; i0 += B) {
         if (r0 + i0 >= g.rows) break;
-        uint32_t u[B], dst[B];
+        uint32_t pc[B], u[B], dst[B];
+        uint64_t mk[B + 1];
         bool valid[B];
         float x[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             const uint64_t pp = (r0 + i0 + j) * 64 + lane;
             valid[j] = (r0 + i0 + j) < g.rows && pp < g.m;
-            u[j] = valid[j] ? ld_stream(g.in_src + pp) : 0u;
+            pc[j] = valid[j] ? (uint32_t)pp : 0u;
         }
 #pragma unroll
-        for (int j = 0; j < B; ++j)
-            dst[j] = valid[j] ? dst_of(g, (uint32_t)((r0 + i0 + j) * 64 + lane)) : kInf;
+        for (int j = 0; j < B; ++j) u[j] = ld_stream(g.in_src + pc[j]);
 #pragma unroll
-        for (int j = 0; j < B; ++j) x[j] = valid[j] ? gather(u[j]) : 0.0f;
+        for (int j = 0; j <= B; ++j) {
+            const uint64_t r = r0 + i0 + j;
+            const uint64_t w = g.rowmask[r < g.rows ? r : g.rows - 1];
+            mk[j] = r < g.rows ? w : 1ull;  // past the last row: a segment start
+        }
+        dst_of_rows<B>(g, pc, dst);
+        // dst is only used by the head lanes' stores; pinning it here keeps
+        // the compiler from sinking its loads into those branches, which
+        // would serialise them row by row
+#pragma unroll
+        for (int j = 0; j < B; ++j) __asm__ volatile("" : "+v"(dst[j]));
+#pragma unroll
+        for (int j = 0; j < B; ++j) x[j] = gather(u[j]);
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             const int i = i0 + j;
             const uint64_t r = r0 + i;
             if (r >= g.rows) break;
-            const uint64_t mk = g.rowmask[r];
             const uint64_t row_end = min<uint64_t>(r * 64 + 64, g.m);
-            const bool cont_in = !(mk & 1ull);
-            const bool cont_out = row_end < g.m && !(g.rowmask[r + 1] & 1ull);
+            const bool cont_in = !(mk[j] & 1ull);
+            const bool cont_out = row_end < g.m && !(mk[j + 1] & 1ull);
             const bool last_row = (i == R - 1) || (r + 1 >= g.rows);
             const uint64_t pp = r * 64 + lane;
-            const bool head = lane == 0 || ((mk >> lane) & 1ull) || pp == g.m;
+            const bool head = lane == 0 || ((mk[j] >> lane) & 1ull) || pp == g.m;
             const uint64_t heads = __ballot(head);
             const uint64_t vmask = __ballot(valid[j]);
-            float s = seg_reduce(x[j], seg_span(heads, lane), [](float a, float b) { return a + b; });
+            float s = seg_reduce(valid[j] ? x[j] : 0.0f, seg_span(heads, lane),
+                                 [](float a, float b) { return a + b; });
             if (i == 0) from_before = cont_in;
             if (lane == 0 && cont_in) s = carry + s;
             const uint64_t hv = heads & vmask;
@@ -293,31 +307,59 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull(GraphArgs g, const float* __
                                                     float* __restrict__ sum,
                                                     float* __restrict__ head_part,
                                                     float* __restrict__ tail_part) {
-    const uint64_t tile = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t tile = (uint64_t)blockIdx.x * kWavesPerBlock +
+                          __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     pr_tile<R, R>(g, tile, [&](uint32_t u) { return contrib[u]; }, sum, head_part, tail_part);
 }
 
 // The same pull with the first `hot` contributions held in LDS. Vertices are
 // numbered by descending out-degree, so the lowest ids are the sources of the
-// most in-edges (on R-MAT scale 24 the first 16384 source about 29% of them):
-// their gathers are served by LDS instead of the L1/L2 request path, which
-// bounds this kernel. Each block copies contrib[0, hot) once and then strides
-// over the tiles; tile results are the same as k_pr_pull's.
+// most in-edges (on R-MAT scale 24 the first 16384 source about 29% of them);
+// their gathers are served by LDS, and the global gather of such a lane is
+// pointed at one shared address. Each block copies contrib[0, hot) once and
+// then strides over the tiles; tile results are the same as k_pr_pull's.
 template <int R>
 __global__ __launch_bounds__(kHotBlock) void k_pr_pull_hot(GraphArgs g, const float* __restrict__ contrib,
                                                            float* __restrict__ sum,
                                                            float* __restrict__ head_part,
                                                            float* __restrict__ tail_part,
                                                            uint32_t hot, uint64_t tiles) {
-    extern __shared__ float s_hot[];
-    for (uint32_t i = threadIdx.x; i < hot; i += blockDim.x) s_hot[i] = contrib[i];
+    extern __shared__ float s_hot[];  // hot values + one spare 16-byte slot
+    {
+        // all of a thread's 16-byte loads are issued before its first store;
+        // the stores are unconditional, a thread past the end writing the
+        // spare slot
+        constexpr int kPer = (int)((kHotVerts / 4 + kHotBlock - 1) / kHotBlock);
+        const uint32_t hot4 = hot / 4;
+        const float4* src4 = reinterpret_cast<const float4*>(contrib);
+        float4* dst4 = reinterpret_cast<float4*>(s_hot);
+        const uint32_t spare = (hot + 3) / 4;
+        float4 t[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
+            t[k] = src4[i < hot4 ? i : 0u];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
+            dst4[i < hot4 ? i : spare] = t[k];
+        }
+        for (uint32_t i = hot4 * 4 + threadIdx.x; i < hot; i += kHotBlock) s_hot[i] = contrib[i];
+    }
     __syncthreads();
-    const uint64_t wpb = blockDim.x >> 6;
+    const uint64_t wpb = kHotBlock / 64;
     const uint64_t stride = (uint64_t)gridDim.x * wpb;
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint64_t t = blockIdx.x * wpb + wib; t < tiles; t += stride)
-        pr_tile<R, kHotBatch>(g, t, [&](uint32_t u) { return u < hot ? s_hot[u] : contrib[u]; }, sum, head_part,
-                   tail_part);
+        pr_tile<R, kHotBatch>(
+            g, t,
+            [&](uint32_t u) {
+                const float gv = contrib[u < hot ? 0u : u];
+                const float lv = s_hot[u < hot ? u : 0u];
+                return u < hot ? lv : gv;
+            },
+            sum, head_part, tail_part);
 }
 
 // S(v) = tail[first tile] + sum of head[t] over the later tiles v covers.
@@ -569,14 +611,14 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
         if (per_cu < 0) {
             int b = 0;
             hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &b, k_pr_pull_hot<kPrTileRows>, kHotBlock, kHotVerts * sizeof(float));
+                &b, k_pr_pull_hot<kPrTileRows>, kHotBlock, (kHotVerts + 8) * sizeof(float));
             if (e != hipSuccess) return e;
             per_cu = b;
         }
         const uint64_t blocks = (uint64_t)cus * (uint64_t)per_cu;
         // the LDS copy pays off once every wave has several tiles to stride over
         if (per_cu > 0 && tiles >= 4 * blocks * (kHotBlock / 64)) {
-            k_pr_pull_hot<kPrTileRows><<<(uint32_t)blocks, kHotBlock, hot * sizeof(float), s>>>(
+            k_pr_pull_hot<kPrTileRows><<<(uint32_t)blocks, kHotBlock, (hot + 8) * sizeof(float), s>>>(
                 args_of(g), contrib, sum, head, tail, hot, tiles);
             return hipGetLastError();
         }
