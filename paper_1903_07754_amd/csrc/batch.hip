@@ -24,20 +24,36 @@ __device__ __forceinline__ void ms_pull_lanes(const GraphArgs& g, const uint32_t
                                               uint64_t* __restrict__ nxt,
                                               uint64_t* __restrict__ fbits) {
     const int lane = lane_id();
-    uint32_t dst[R], u[R];
+    // branch-free loads (see pull_lanes): lanes without an edge read position
+    // 0, lanes that need no edge point at one shared address, and loaded
+    // values are pinned so the loads are not turned back into branches
+    uint32_t pc[R], dst[R], u[R];
     uint64_t vis[R], x[R];
     bool need[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst_of(g, p[i]) : kInf;
+    for (int i = 0; i < R; ++i) pc[i] = valid[i] ? p[i] : 0u;
+    dst_of_rows<R>(g, pc, dst);
+#pragma unroll
+    for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst[i] : kInf;
+#pragma unroll
+    for (int i = 0; i < R; ++i) vis[i] = visited[valid[i] ? dst[i] : 0u];
+#pragma unroll
+    for (int i = 0; i < R; ++i) __asm__ volatile("" : "+v"(vis[i]));
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        vis[i] = valid[i] ? visited[dst[i]] : all;
+        vis[i] = valid[i] ? vis[i] : all;
         need[i] = (vis[i] & all) != all;  // a destination seen by every source is skipped
     }
 #pragma unroll
-    for (int i = 0; i < R; ++i) u[i] = need[i] ? ld_stream(g.in_src + p[i]) : 0u;
+    for (int i = 0; i < R; ++i) u[i] = ld_stream(g.in_src + (need[i] ? pc[i] : 0u));
 #pragma unroll
-    for (int i = 0; i < R; ++i) x[i] = need[i] ? cur[u[i]] : 0ull;
+    for (int i = 0; i < R; ++i) __asm__ volatile("" : "+v"(u[i]));
+#pragma unroll
+    for (int i = 0; i < R; ++i) x[i] = cur[need[i] ? u[i] : 0u];
+#pragma unroll
+    for (int i = 0; i < R; ++i) __asm__ volatile("" : "+v"(x[i]));
+#pragma unroll
+    for (int i = 0; i < R; ++i) x[i] = need[i] ? x[i] : 0ull;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const uint32_t prev = __shfl_up(dst[i], 1, 64);
@@ -81,12 +97,7 @@ __device__ __forceinline__ void ms_pull_slots(const GraphArgs& g, uint64_t s0, u
     const int lane = lane_id();
     uint32_t p[R];
     bool valid[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const uint64_t pp = s0 + i < slots ? chunk_slot_pos(s0 + i, lane, lc, list, K) : ~0ull;
-        valid[i] = pp < g.m;
-        p[i] = (uint32_t)pp;
-    }
+    chunk_slot_rows<R>(s0, slots, lane, lc, list, K, g.m, p, valid);
     ms_pull_lanes<R>(g, p, valid, all, visited, cur, nxt, fbits);
 }
 
@@ -100,9 +111,9 @@ __device__ __forceinline__ void ms_finalize_block(
     uint64_t* retire, const uint64_t* nxt, uint32_t* lev, uint32_t K, uint32_t level) {
     bitmap_compact_block_ex<true, true, kCompactWords>(
         vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
-        [&](uint32_t v) {
-            const uint64_t nb = nxt[v];
-            visited[v] |= nb;
+        [&](uint32_t v) -> uint64_t { return nxt[v]; },
+        [&](uint32_t v, uint64_t nb) {
+            atomicOr(reinterpret_cast<unsigned long long*>(visited + v), (unsigned long long)nb);
             uint64_t b = nb;
             uint32_t* row = lev + (uint64_t)v * K;
             while (b) {
@@ -120,7 +131,7 @@ __device__ __forceinline__ void bfs_finalize_block(uint64_t vblock, uint64_t* bi
                                                    uint32_t* degpre, Ctl* ctl, uint64_t* fcur) {
     bitmap_compact_block_ex<true, true, kCompactWords>(
         vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
-        [](uint32_t) {}, [](uint32_t) {});
+        [](uint32_t) -> uint64_t { return 0ull; }, [](uint32_t, uint64_t) {}, [](uint32_t) {});
 }
 
 // --------------------------------------------------- per-iteration kernels
@@ -341,12 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
                     const int lane = lane_id();
                     uint32_t p[kPullRows];
                     bool valid[kPullRows];
-#pragma unroll
-                    for (int i = 0; i < kPullRows; ++i) {
-                        const uint64_t pp = s0 + i < slots ? chunk_slot_pos(s0 + i, lane, P.lc, P.chunks, K) : ~0ull;
-                        valid[i] = pp < g.m;
-                        p[i] = (uint32_t)pp;
-                    }
+                    chunk_slot_rows<kPullRows>(s0, slots, lane, P.lc, P.chunks, K, g.m, p, valid);
                     pull_lanes<kBfs, kPullRows>(g, p, valid, k, P.level, nullptr, P.fcur, P.fbits);
                 }
             }

@@ -165,14 +165,18 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
 }
 
 // Bitmap compaction work of one (virtual) block (see k_bitmap_compact).
-// on_set(v) runs for every set bit v < limit of the word; on_old(v) for every
-// set bit of the word copy_to held before it is overwritten (COPY only).
-template <bool DEG, bool COPY, int G, class OnSet, class OnOld>
+// For every set bit v < limit of a word, load_set(v) is read first (the
+// reads of all the wave's words in flight together) and on_set(v, value)
+// runs afterwards; on_old(v) runs for every set bit of the word copy_to held
+// before it is overwritten (COPY only). A wave's loads are issued word-batch
+// by word-batch, never one word at a time: bitmap words (and the words being
+// replaced), then the out-degree bounds and load_set of every set bit.
+template <bool DEG, bool COPY, int G, class LoadSet, class OnSet, class OnOld>
 __device__ __forceinline__ void bitmap_compact_block_ex(
     uint64_t vblock, uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
-    uint64_t* __restrict__ copy_to, OnSet on_set, OnOld on_old) {
+    uint64_t* __restrict__ copy_to, LoadSet load_set, OnSet on_set, OnOld on_old) {
     __shared__ unsigned long long s_wave[kWavesPerBlock];
     __shared__ unsigned long long s_all[kWavesPerBlock];
     __shared__ unsigned long long s_base;
@@ -182,22 +186,51 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const uint64_t w0 = (vblock * kWavesPerBlock + wid) * G;
-    uint64_t mk[G], lm[G];
-    uint32_t deg[G];
+    uint64_t mk[G], lm[G], old[G], pre[G];
+    uint32_t deg[G], r0[G], r1[G];
     uint64_t cnt = 0, all = 0, dsum = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const uint64_t wi = w0 + g;
-        mk[g] = wi < words ? bits[wi] : 0ull;
+        const uint64_t wc = wi < words ? wi : words - 1;
+        mk[g] = bits[wc];
+        old[g] = COPY ? copy_to[wc] : 0ull;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        __asm__ volatile("" : "+v"(mk[g]));
+        if (COPY) __asm__ volatile("" : "+v"(old[g]));
+        mk[g] = w0 + g < words ? mk[g] : 0ull;
+    }
+    // per set bit: out-degree bounds and the caller's value (a lane whose bit
+    // is clear reads vertex 0's, which is then ignored)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t v = (uint32_t)((w0 + g) * 64 + lane);
+        const bool set = ((mk[g] >> lane) & 1ull) && v < limit;
+        const uint32_t vs = set ? v : 0u;
+        if (DEG) {
+            r0[g] = row_off[vs];
+            r1[g] = row_off[vs + 1];
+        }
+        pre[g] = load_set(vs);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (DEG) {
+            __asm__ volatile("" : "+v"(r0[g]));
+            __asm__ volatile("" : "+v"(r1[g]));
+        }
+        __asm__ volatile("" : "+v"(pre[g]));
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
         lm[g] = mk[g];
         deg[g] = 0;
         if (mk[g]) {
             all += __popcll(mk[g]);
             if (DEG) {
-                if ((mk[g] >> lane) & 1ull) {
-                    uint32_t v = (uint32_t)(wi * 64 + lane);
-                    deg[g] = row_off[v + 1] - row_off[v];
-                }
+                if ((mk[g] >> lane) & 1ull) deg[g] = r1[g] - r0[g];
                 // vertices without out-edges are counted but not listed
                 lm[g] = __ballot(deg[g] != 0);
                 dsum += wave_sum_tree(deg[g]);
@@ -223,12 +256,11 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
         const uint64_t wi = w0 + g;
         const uint32_t v = (uint32_t)(wi * 64 + lane);
         if (COPY && wi < words) {
-            const uint64_t old = copy_to[wi];
-            if (((old >> lane) & 1ull) && v < limit) on_old(v);
+            if (((old[g] >> lane) & 1ull) && v < limit) on_old(v);
             if (lane == 0) copy_to[wi] = mk[g];
         }
         if (!mk[g]) continue;
-        if (((mk[g] >> lane) & 1ull) && v < limit) on_set(v);
+        if (((mk[g] >> lane) & 1ull) && v < limit) on_set(v, pre[g]);
         if (lane == 0) bits[wi] = 0ull;
         if (!lm[g]) continue;
         const bool act = (lm[g] >> lane) & 1ull;
@@ -380,23 +412,53 @@ __device__ __forceinline__ void bitmap_compact_block(
     uint64_t* __restrict__ copy_to) {
     bitmap_compact_block_ex<DEG, COPY, G>(
         vblock, bits, words, limit, row_off, list, degpre, counter, total, copy_to,
-        [&](uint32_t v) { if (COMMIT) val_prev[v] = val[v]; }, [](uint32_t) {});
+        [&](uint32_t v) -> uint64_t { return COMMIT ? val[v] : 0u; },
+        [&](uint32_t v, uint64_t x) { if (COMMIT) val_prev[v] = (uint32_t)x; }, [](uint32_t) {});
 }
 
-// Position covered by lane `lane` of chunk-list slot s: a slot is 64 lanes
-// over 64 >> lc chunks (lc <= 6) or one 64-position part of a chunk (lc > 6).
-// Returns ~0 when the slot runs past the K listed chunks.
-__device__ __forceinline__ uint64_t chunk_slot_pos(uint64_t s, int lane, int lc,
-                                                   const uint32_t* __restrict__ list, uint64_t K) {
-    uint64_t ci, off;
-    if (lc <= 6) {
-        ci = s * (64u >> lc) + ((uint32_t)lane >> lc);
-        off = (uint32_t)lane & ((1u << lc) - 1u);
+// Positions covered by lane `lane` of the chunk-list slots s0 .. s0+R-1: a
+// slot is 64 lanes over 64 >> lc chunks (lc <= 6) or one 64-position part of
+// a chunk (lc > 6). Lanes past the `slots` slots or the K >= 1 listed chunks
+// get valid = false. When the R slots cover at most 64 consecutive list
+// entries (chunks of 8 or more edges), the wave reads them with one
+// coalesced load and every lane takes its entry by a shuffle; otherwise each
+// slot reads its own entries.
+template <int R>
+__device__ __forceinline__ void chunk_slot_rows(uint64_t s0, uint64_t slots, int lane, int lc,
+                                                const uint32_t* __restrict__ list, uint64_t K,
+                                                uint64_t m, uint32_t (&p)[R], bool (&valid)[R]) {
+    if (lc > 6 || (R << (6 - lc)) <= 64) {
+        const int hi = lc > 6 ? lc - 6 : 0;
+        const int per = lc > 6 ? 0 : 64 >> lc;  // chunks per slot (lc <= 6)
+        const uint64_t first = lc > 6 ? s0 >> hi : s0 * (uint64_t)per;
+        const uint64_t e = first + (uint64_t)lane;
+        const uint32_t mine = list[e < K ? e : K - 1];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const uint64_t s = s0 + i;
+            const uint32_t idx = lc > 6 ? (uint32_t)((s >> hi) - first)
+                                        : (uint32_t)(i * per + (lane >> lc));
+            const uint32_t c = __shfl(mine, (int)idx, 64);
+            const uint64_t ci = first + idx;
+            const uint64_t off = lc > 6 ? ((s & ((1ull << hi) - 1ull)) << 6) + (uint64_t)lane
+                                        : (uint64_t)((uint32_t)lane & ((1u << lc) - 1u));
+            const uint64_t pp = ((uint64_t)c << lc) + off;
+            valid[i] = (s < slots) & (ci < K) & (pp < m);
+            p[i] = valid[i] ? (uint32_t)pp : 0u;
+        }
     } else {
-        ci = s >> (lc - 6);
-        off = ((s & ((1ull << (lc - 6)) - 1ull)) << 6) + lane;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            uint64_t pp = ~0ull;
+            if (s0 + i < slots) {
+                const uint64_t ci = (s0 + i) * (64u >> lc) + ((uint32_t)lane >> lc);
+                const uint64_t off = (uint32_t)lane & ((1u << lc) - 1u);
+                if (ci < K) pp = ((uint64_t)list[ci] << lc) + off;
+            }
+            valid[i] = pp < m;
+            p[i] = valid[i] ? (uint32_t)pp : 0u;
+        }
     }
-    return ci < K ? ((uint64_t)list[ci] << lc) + off : ~0ull;
 }
 
 __device__ __forceinline__ uint64_t chunk_slots(uint64_t K, int lc) { return chunk_slots_count(K, lc); }

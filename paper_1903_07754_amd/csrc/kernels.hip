@@ -197,12 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_chunks(GraphArgs g, uint32_t it
          s0 += nwaves * R) {
         uint32_t p[R];
         bool valid[R];
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const uint64_t pp = s0 + i < slots ? chunk_slot_pos(s0 + i, lane, lc, list, K) : ~0ull;
-            valid[i] = pp < g.m;
-            p[i] = (uint32_t)pp;
-        }
+        chunk_slot_rows<R>(s0, slots, lane, lc, list, K, g.m, p, valid);
         pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fcur, fbits);
     }
 }
