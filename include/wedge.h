@@ -202,6 +202,9 @@ typedef struct {
     uint64_t edges_scanned;  /* in-edge positions the pull kernels covered */
     double ms;               /* host wall time of the run, sync to sync */
     double pull_ms;          /* sum of event-timed pull kernel durations */
+    double full_pull_ms;     /* of which the pulls over every in-edge */
+    uint32_t full_pull_launches; /* timed pulls over every in-edge */
+    uint32_t reserved;
 } wedge_stats;
 
 /*

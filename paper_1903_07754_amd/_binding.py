@@ -72,7 +72,9 @@ class Opts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iterations", C.c_uint32), ("wedge_iters", C.c_uint32),
                 ("full_iters", C.c_uint32), ("pull_launches", C.c_uint32),
-                ("edges_scanned", C.c_uint64), ("ms", C.c_double), ("pull_ms", C.c_double)]
+                ("edges_scanned", C.c_uint64), ("ms", C.c_double), ("pull_ms", C.c_double),
+                ("full_pull_ms", C.c_double), ("full_pull_launches", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -344,6 +344,10 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
         if (c.time_iter) HIP_TRY(hipEventElapsedTime(&ims, w.ev[2], w.ev[3]), "event time");
         local.pull_ms += pms;
         local.pull_launches++;
+        if (!wedge_mode) {
+            local.full_pull_ms += pms;
+            local.full_pull_launches++;
+        }
         const uint64_t marked = wedge_mode ? (w.ctl_host->marked >> kDegBits) : 0;
         if (o.trace && k < o.trace_cap) {
             wedge_iter_record& r = o.trace[k];
@@ -945,6 +949,8 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
     local.iterations = iters;
     local.full_iters = iters;
     local.pull_launches = iters;
+    local.full_pull_ms = local.pull_ms;
+    local.full_pull_launches = iters;
     local.edges_scanned = (uint64_t)iters * d.m;
     local.ms = now_ms() - t0;
     if (stats) *stats = local;
