@@ -97,7 +97,7 @@ __device__ __forceinline__ void ms_pull_slots(const GraphArgs& g, uint64_t s0, u
     const int lane = lane_id();
     uint32_t p[R];
     bool valid[R];
-    chunk_slot_rows<R>(s0, slots, lane, lc, list, K, g.m, p, valid);
+    chunk_slot_rows_any<R>(s0, slots, lane, lc, list, K, g.m, p, valid);
     ms_pull_lanes<R>(g, p, valid, all, visited, cur, nxt, fbits);
 }
 
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
                     const int lane = lane_id();
                     uint32_t p[kPullRows];
                     bool valid[kPullRows];
-                    chunk_slot_rows<kPullRows>(s0, slots, lane, P.lc, P.chunks, K, g.m, p, valid);
+                    chunk_slot_rows_any<kPullRows>(s0, slots, lane, P.lc, P.chunks, K, g.m, p, valid);
                     pull_lanes<kBfs, kPullRows>(g, p, valid, k, P.level, nullptr, P.fcur, P.fbits);
                 }
             }

@@ -25,6 +25,18 @@ constexpr int kHotBlock = WEDGE_HOT_BLOCK;          // threads per block
 constexpr uint32_t kHotVerts = WEDGE_HOT_VERTS;     // values held in LDS (4 B each)
 constexpr int kHotBatch = WEDGE_HOT_BATCH;          // rows loaded at a time per wave
 constexpr uint32_t kHotMinVerts = 4096;
+// minimum resident waves per SIMD requested for the integer pulls (caps their
+// registers so that many rows' loads stay in flight per compute unit)
+#ifdef WEDGE_PULL_WAVES
+#define WEDGE_PULL_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WEDGE_PULL_WAVES)))
+#else
+#define WEDGE_PULL_OCCUPANCY
+#endif
+#ifdef WEDGE_CHUNK_WAVES
+#define WEDGE_CHUNK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WEDGE_CHUNK_WAVES)))
+#else
+#define WEDGE_CHUNK_OCCUPANCY
+#endif
 constexpr int kTranslateEpt = 4;      // frontier out-edges per lane in the translation
 constexpr int kCompactWords = 8;      // 64-bit bitmap words per wave in the compaction
 constexpr uint32_t kPrEpilogueVerts = 8192;  // vertices per PageRank epilogue block
@@ -300,7 +312,30 @@ __device__ __forceinline__ void dst_of_rows(const GraphArgs& g, const uint32_t (
         dst[i] = g.nzdst[sg[i] + (uint32_t)__popcll(mk[i] & ~1ull & mask_le((int)(pc[i] & 63)))];
 }
 
-template <int APP, int R>
+// Next-frontier bits of one row: every destination segment whose head lane
+// has `commit` set gets its bit, with one atomicOr per distinct bitmap word
+// (consecutive destinations share words, so a row of 64 positions needs one
+// or two atomics instead of one per destination). All lanes must call it.
+__device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint32_t dst, bool commit,
+                                             uint64_t heads, int lane) {
+    if (!__ballot(commit)) return;  // most rows of a late iteration change nothing
+    const int hl = 63 - __clzll(heads & mask_le(lane));  // head lane of this lane's segment
+    const bool c = __shfl((int)commit, hl, 64) != 0;
+    const uint32_t key = c ? (dst >> 5) : kInf;
+    const uint32_t bit = (c && lane == hl) ? (1u << (dst & 31)) : 0u;
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || prev != key;
+    const uint64_t wheads = __ballot(head);
+    const uint32_t orv = seg_reduce(bit, seg_span(wheads, lane), [](uint32_t a, uint32_t b) { return a | b; });
+    if (head && key != kInf) atomicOr(reinterpret_cast<uint32_t*>(fbits) + key, orv);
+}
+
+// ROWS: the R positions of each lane are the lanes of R consecutive rows
+// starting at a row the wave owns alone (the full pull). Then a destination
+// whose in-edges all lie in the wave is written by this wave only, and takes
+// a plain store instead of a min-atomic; only the wave's first and last
+// segments can be shared with the neighbouring waves.
+template <int APP, int R, bool ROWS = false>
 __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&p)[R],
                                            const bool (&valid)[R], uint32_t iter,
                                            uint32_t* __restrict__ val,
@@ -350,14 +385,14 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
             const bool head = lane == 0 || prev != dst[i];
             const uint64_t heads = __ballot(head);
             const uint64_t fm = __ballot(found);
+            bool commit = false;
             if (head && dst[i] != kInf) {
                 const int span = seg_span(heads, lane);
                 const uint64_t seg = span >= 64 ? ~0ull : ((1ull << span) - 1ull);
-                if ((fm >> lane) & seg) {
-                    val[dst[i]] = iter + 1;
-                    set_bit(fbits, dst[i]);
-                }
+                commit = ((fm >> lane) & seg) != 0;
+                if (commit) val[dst[i]] = iter + 1;
             }
+            set_bits_row(fbits, dst[i], commit, heads, lane);
         }
     } else {
         // All loads of the R rows are issued before any result is used, and
@@ -376,6 +411,13 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
 #pragma unroll
         for (int i = 0; i < R; ++i) x[i] = valid[i] ? x[i] : kInf;
         uint32_t carry = kInf;
+        bool first_shared = true, last_shared = true, lane0_first = true;
+        if (ROWS) {
+            const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane(pc[0]) >> 6;
+            first_shared = !(g.rowmask[r0] & 1ull);
+            const uint64_t rn = (uint64_t)r0 + R;
+            last_shared = rn < g.rows && !(g.rowmask[rn < g.rows ? rn : r0] & 1ull);
+        }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const uint32_t cand = (APP == kCc || x[i] == kInf) ? x[i] : x[i] + wt[i];
@@ -388,17 +430,22 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
             if (lane == 0 && carry < best) best = carry;
             carry = kInf;
             int defer = -1;
+            const int h_last = hv ? 63 - __clzll(hv) : -1;
             if (hv && i + 1 < R) {
-                const int h_last = 63 - __clzll(hv);
                 if (__shfl(dst[i + 1], 0, 64) == __shfl(dst[i], h_last, 64)) {
                     defer = h_last;
                     carry = __shfl(best, h_last, 64);
                 }
             }
-            if (head && valid[i] && lane != defer && best < cur[i]) {
-                atomicMin(val + dst[i], best);
-                set_bit(fbits, dst[i]);
+            const bool commit = head && valid[i] && lane != defer && best < cur[i];
+            if (commit) {
+                const bool shared = !ROWS || (lane == 0 && lane0_first && first_shared) ||
+                                    (i == R - 1 && lane == h_last && last_shared);
+                if (shared) atomicMin(val + dst[i], best);
+                else val[dst[i]] = best;
             }
+            set_bits_row(fbits, dst[i], commit, heads, lane);
+            lane0_first = lane0_first && defer == 0;
         }
     }
 }
@@ -422,28 +469,49 @@ __device__ __forceinline__ void bitmap_compact_block(
 // get valid = false. When the R slots cover at most 64 consecutive list
 // entries (chunks of 8 or more edges), the wave reads them with one
 // coalesced load and every lane takes its entry by a shuffle; otherwise each
-// slot reads its own entries.
+// slot reads its own entries. Positions are 32-bit, so slot and chunk
+// indices are too. FORM (see slot_form) picks one of the three cases at
+// compile time, so a kernel carries the registers of one case only.
+enum SlotForm : int { kSlotsShared = 0, kSlotsLong = 1, kSlotsEach = 2 };
+
 template <int R>
-__device__ __forceinline__ void chunk_slot_rows(uint64_t s0, uint64_t slots, int lane, int lc,
-                                                const uint32_t* __restrict__ list, uint64_t K,
+__host__ __device__ constexpr int slot_form(int lc) {
+    return lc > 6 ? kSlotsLong : ((R << (6 - lc)) <= 64 ? kSlotsShared : kSlotsEach);
+}
+
+template <int R, int FORM>
+__device__ __forceinline__ void chunk_slot_rows(uint64_t s0w, uint64_t slotsw, int lane, int lc,
+                                                const uint32_t* __restrict__ list, uint64_t Kw,
                                                 uint64_t m, uint32_t (&p)[R], bool (&valid)[R]) {
-    if (lc > 6 || (R << (6 - lc)) <= 64) {
-        const int hi = lc > 6 ? lc - 6 : 0;
-        const int per = lc > 6 ? 0 : 64 >> lc;  // chunks per slot (lc <= 6)
-        const uint64_t first = lc > 6 ? s0 >> hi : s0 * (uint64_t)per;
-        const uint64_t e = first + (uint64_t)lane;
+    const uint32_t s0 = (uint32_t)s0w, slots = (uint32_t)slotsw, K = (uint32_t)Kw;
+    const uint32_t ul = (uint32_t)lane;
+    if (FORM == kSlotsShared) {
+        const uint32_t per = 64u >> lc;
+        const uint32_t first = s0 * per;
+        const uint32_t e = first + ul;
+        const uint32_t mine = list[e < K ? e : K - 1];
+        const uint32_t sub = ul >> lc;
+        const uint32_t off = ul & ((1u << lc) - 1u);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const uint32_t idx = (uint32_t)i * per + sub;
+            const uint32_t c = __shfl(mine, (int)idx, 64);
+            const uint64_t pp = ((uint64_t)c << lc) + off;
+            valid[i] = (s0 + i < slots) & (first + idx < K) & (pp < m);
+            p[i] = valid[i] ? (uint32_t)pp : 0u;
+        }
+    } else if (FORM == kSlotsLong) {
+        const int hi = lc - 6;
+        const uint32_t first = s0 >> hi;
+        const uint32_t e = first + ul;
         const uint32_t mine = list[e < K ? e : K - 1];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const uint64_t s = s0 + i;
-            const uint32_t idx = lc > 6 ? (uint32_t)((s >> hi) - first)
-                                        : (uint32_t)(i * per + (lane >> lc));
+            const uint32_t s = s0 + (uint32_t)i;
+            const uint32_t idx = (s >> hi) - first;
             const uint32_t c = __shfl(mine, (int)idx, 64);
-            const uint64_t ci = first + idx;
-            const uint64_t off = lc > 6 ? ((s & ((1ull << hi) - 1ull)) << 6) + (uint64_t)lane
-                                        : (uint64_t)((uint32_t)lane & ((1u << lc) - 1u));
-            const uint64_t pp = ((uint64_t)c << lc) + off;
-            valid[i] = (s < slots) & (ci < K) & (pp < m);
+            const uint64_t pp = ((uint64_t)c << lc) + ((uint64_t)(s & ((1u << hi) - 1u)) << 6) + ul;
+            valid[i] = (s < slots) & (first + idx < K) & (pp < m);
             p[i] = valid[i] ? (uint32_t)pp : 0u;
         }
     } else {
@@ -451,14 +519,26 @@ __device__ __forceinline__ void chunk_slot_rows(uint64_t s0, uint64_t slots, int
         for (int i = 0; i < R; ++i) {
             uint64_t pp = ~0ull;
             if (s0 + i < slots) {
-                const uint64_t ci = (s0 + i) * (64u >> lc) + ((uint32_t)lane >> lc);
-                const uint64_t off = (uint32_t)lane & ((1u << lc) - 1u);
+                const uint32_t ci = (s0 + (uint32_t)i) * (64u >> lc) + (ul >> lc);
+                const uint32_t off = ul & ((1u << lc) - 1u);
                 if (ci < K) pp = ((uint64_t)list[ci] << lc) + off;
             }
             valid[i] = pp < m;
             p[i] = valid[i] ? (uint32_t)pp : 0u;
         }
     }
+}
+
+// The same with the case chosen at run time (kernels that serve every group
+// size from one instantiation).
+template <int R>
+__device__ __forceinline__ void chunk_slot_rows_any(uint64_t s0, uint64_t slots, int lane, int lc,
+                                                    const uint32_t* __restrict__ list, uint64_t K,
+                                                    uint64_t m, uint32_t (&p)[R], bool (&valid)[R]) {
+    const int form = slot_form<R>(lc);
+    if (form == kSlotsShared) chunk_slot_rows<R, kSlotsShared>(s0, slots, lane, lc, list, K, m, p, valid);
+    else if (form == kSlotsLong) chunk_slot_rows<R, kSlotsLong>(s0, slots, lane, lc, list, K, m, p, valid);
+    else chunk_slot_rows<R, kSlotsEach>(s0, slots, lane, lc, list, K, m, p, valid);
 }
 
 __device__ __forceinline__ uint64_t chunk_slots(uint64_t K, int lc) { return chunk_slots_count(K, lc); }

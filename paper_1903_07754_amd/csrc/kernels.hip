@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_bitmap_compact(
 // (Frontier Transformation, "Frontier Precision").
 // Full pull: wave w covers rows [w*R, w*R + R), i.e. every in-edge once.
 template <int APP, int R>
-__global__ __launch_bounds__(kBlock) void k_pull_full(GraphArgs g, uint32_t iter,
+__global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_full(GraphArgs g, uint32_t iter,
                                                       uint32_t* __restrict__ val,
                                                       const uint32_t* __restrict__ val_prev,
                                                       const uint64_t* __restrict__ fcur,
@@ -174,15 +174,15 @@ __global__ __launch_bounds__(kBlock) void k_pull_full(GraphArgs g, uint32_t iter
         valid[i] = pp < g.m;
         p[i] = (uint32_t)pp;
     }
-    pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fcur, fbits);
+    pull_lanes<APP, R, true>(g, p, valid, iter, val, val_prev, fcur, fbits);
 }
 
 // Pull over the marked chunks: the chunk list holds K = *marked chunk ids of
 // 2^lc positions each. A 64-lane slot covers 64 >> lc chunks (lc <= 6) or one
 // 64-position part of a chunk (lc > 6). Waves stride over the slots, R slots at
 // a time; K is read on the device, so the launch needs no host round trip.
-template <int APP, int R>
-__global__ __launch_bounds__(kBlock) void k_pull_chunks(GraphArgs g, uint32_t iter, int lc,
+template <int APP, int R, int FORM>
+__global__ __launch_bounds__(kBlock) WEDGE_CHUNK_OCCUPANCY void k_pull_chunks(GraphArgs g, uint32_t iter, int lc,
                                                         const uint32_t* __restrict__ list,
                                                         const unsigned long long* marked,
                                                         uint32_t* __restrict__ val,
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_chunks(GraphArgs g, uint32_t it
          s0 += nwaves * R) {
         uint32_t p[R];
         bool valid[R];
-        chunk_slot_rows<R>(s0, slots, lane, lc, list, K, g.m, p, valid);
+        chunk_slot_rows<R, FORM>(s0, slots, lane, lc, list, K, g.m, p, valid);
         pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fcur, fbits);
     }
 }
@@ -566,6 +566,18 @@ hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t*
     return hipGetLastError();
 }
 
+template <int FORM>
+void launch_chunks_form(int app, uint32_t blocks, const GraphArgs& a, uint32_t iter, int lc,
+                        const uint32_t* list, const unsigned long long* mk, uint32_t* val,
+                        const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
+                        hipStream_t s) {
+    switch (app) {
+        case kBfs: k_pull_chunks<kBfs, kPullRows, FORM><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits); break;
+        case kCc: k_pull_chunks<kCc, kPullRows, FORM><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits); break;
+        default: k_pull_chunks<kSssp, kPullRows, FORM><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits); break;
+    }
+}
+
 hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
                               const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
                               uint32_t* val, const uint32_t* val_prev, const uint64_t* fcur,
@@ -580,11 +592,10 @@ hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     GraphArgs a = args_of(g);
     const unsigned long long* mk = &ctl->marked;
-    switch (app) {
-        case kBfs: k_pull_chunks<kBfs, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits); break;
-        case kCc: k_pull_chunks<kCc, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits); break;
-        default: k_pull_chunks<kSssp, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits); break;
-    }
+    const int form = slot_form<kPullRows>(log_chunk);
+    if (form == kSlotsShared) launch_chunks_form<kSlotsShared>(app, blocks, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
+    else if (form == kSlotsLong) launch_chunks_form<kSlotsLong>(app, blocks, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
+    else launch_chunks_form<kSlotsEach>(app, blocks, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
     return hipGetLastError();
 }
 

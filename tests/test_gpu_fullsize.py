@@ -124,6 +124,28 @@ def test_config2_rmat24_cc():
 
 
 @pytest.mark.timeout(900)
+def test_rmat24_every_iteration_wedge():
+    """Every iteration on the Wedge Frontier, at each group size the learned
+    gate can pick: at scale 24 the chunk pulls stride over millions of marked
+    chunks per launch, which the default gate only reaches in a few sparse
+    iterations. Results must still be the oracle's."""
+    b = big("rmat")
+    s = b.srcs[1]
+    want_bfs = oracle.bfs(b.ro, b.col, s)
+    want_sssp = oracle.sssp(b.ro, b.col, b.w, s)
+    want_cc = oracle.cc(b.ro, b.col)
+    for chunk in (16, 32, 64):
+        out, st, _ = W.bfs(b.g, s, gate="wedge", chunk=chunk)
+        np.testing.assert_array_equal(W.u32(out), want_bfs)
+        assert st["full_iters"] == 0
+        out, st, _ = W.sssp(b.g, s, gate="wedge", chunk=chunk)
+        np.testing.assert_array_equal(W.u32(out), want_sssp)
+        out, st, _ = W.cc(b.gs, gate="wedge", chunk=chunk)
+        np.testing.assert_array_equal(W.u32(out), want_cc)
+        say(f"rmat wedge-only chunk={chunk} bfs/sssp/cc ok")
+
+
+@pytest.mark.timeout(900)
 def test_rmat24_pagerank():
     b = big("rmat")
     r, st = W.pagerank(b.g, 20, 0.85)
