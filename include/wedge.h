@@ -284,14 +284,23 @@ typedef struct {
 /* New model with uniform(+-1/sqrt(fan_in)) weights from `seed`, zero biases,
  * and an unbounded envelope. Host-only until first used on a GPU. */
 wedge_status wedge_model_create(uint64_t seed, wedge_model_t* out);
+/* New ensemble of `members` (1..8) such MLPs, drawn one after another from
+ * `seed` (member 0 equals wedge_model_create's model). The ensemble predicts
+ * the mean of its members' outputs, on the device and in wedge_model_predict;
+ * training trains every member on its own. WEDGE_ERR_INVALID_ARG outside 1..8. */
+wedge_status wedge_model_create_ensemble(uint64_t seed, uint32_t members, wedge_model_t* out);
+/* Number of ensemble members of m. */
+wedge_status wedge_model_members(wedge_model_t m, uint32_t* members);
 wedge_status wedge_model_free(wedge_model_t m);
 /* Versioned binary file: magic "WEDGEMLP", version, shape, envelope, 1476
- * parameters, FNV-1a-64 checksum (version 2: feature 3 is the application). Load returns WEDGE_ERR_MODEL for a missing,
+ * parameters per member, FNV-1a-64 checksum (version 3: member count in the
+ * header; version 2 files, one MLP, still load). Load returns WEDGE_ERR_MODEL for a missing,
  * truncated, corrupt or mismatched file. */
 wedge_status wedge_model_load(const char* path, wedge_model_t* out);
 wedge_status wedge_model_save(wedge_model_t m, const char* path);
-/* Copy the 1476 parameters (W1[32x8] b1 W2[32x32] b2 W3[4x32] b3, row-major)
- * out (set = 0) or in (set = 1). */
+/* Copy the 1476 x members parameters (per member W1[32x8] b1 W2[32x32] b2
+ * W3[4x32] b3, row-major; members one after another) out (set = 0) or in
+ * (set = 1); count must equal 1476 x members. */
 wedge_status wedge_model_params(wedge_model_t m, float* params, uint32_t count, int set);
 /* Copy the per-feature envelope lo[8], hi[8] out (set = 0) or in (set = 1). */
 wedge_status wedge_model_envelope(wedge_model_t m, float* lo, float* hi, int set);
@@ -301,12 +310,14 @@ wedge_status wedge_model_features(const wedge_trace_sample* s, uint32_t count, f
 wedge_status wedge_model_predict(wedge_model_t m, const float* x, uint32_t count, float* y,
                                  hipStream_t stream);
 /* Gradient of mean_b sum_j mask[b,j] (y[b,j] - t[b,j])^2 with respect to the
- * parameters, and the loss, on the device (host arrays). */
+ * parameters, and the loss, on the device (host arrays). One-member models
+ * only (WEDGE_ERR_UNSUPPORTED otherwise). */
 wedge_status wedge_model_grad(wedge_model_t m, const float* x, const float* t, const float* mask,
                               uint32_t count, float* grad, float* loss, hipStream_t stream);
 /* Full-batch Adam (lr, 0.9, 0.999, 1e-8) on log(1 + t_us[j]) - log(1 + t_us[0])
  * targets (samples without a full-pull time are ignored) for
- * `epochs` steps on the device; sets the envelope to the samples' feature
+ * `epochs` steps on the device, each ensemble member on its own from its own
+ * initial parameters (final_loss: the members' mean); sets the envelope to the samples' feature
  * range widened by 5%, except for the graph-size and previous-time features
  * (4, 6), which stay unbounded so that a model trained on small graphs is
  * used on larger ones. */

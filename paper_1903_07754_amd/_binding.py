@@ -113,6 +113,8 @@ def lib():
     L.wedge_tune_bfs.argtypes = [vp, u32, vp, u32, vp, vp, C.POINTER(Opts), C.POINTER(C.c_double)]
     L.wedge_tune_lookup.argtypes = [u32, u32, u64, C.POINTER(Opts)]
     L.wedge_model_create.argtypes = [u64, C.POINTER(vp)]
+    L.wedge_model_create_ensemble.argtypes = [u64, u32, C.POINTER(vp)]
+    L.wedge_model_members.argtypes = [vp, C.POINTER(u32)]
     L.wedge_model_free.argtypes = [vp]
     L.wedge_model_load.argtypes = [C.c_char_p, C.POINTER(vp)]
     L.wedge_model_save.argtypes = [vp, C.c_char_p]
@@ -133,6 +135,7 @@ def lib():
                  "wedge_sssp", "wedge_pagerank", "wedge_frontier_translate",
                  "wedge_bfs_multisource", "wedge_graph_create_batch_csr", "wedge_graph_batch_parts",
                  "wedge_bfs_batch", "wedge_tune_bfs", "wedge_tune_lookup", "wedge_model_create",
+                 "wedge_model_create_ensemble", "wedge_model_members",
                  "wedge_model_free", "wedge_model_load", "wedge_model_save", "wedge_model_params",
                  "wedge_model_envelope", "wedge_model_features", "wedge_model_predict",
                  "wedge_model_grad", "wedge_model_train", "wedge_trace_counterfactual"):
@@ -380,10 +383,20 @@ class Model:
         self._h = C.c_void_p(handle)
 
     @classmethod
-    def create(cls, seed=0):
+    def create(cls, seed=0, members=1):
+        """New model; members > 1 gives an ensemble whose prediction is the mean."""
         h = C.c_void_p()
-        check(lib().wedge_model_create(seed, C.byref(h)))
+        if members == 1:
+            check(lib().wedge_model_create(seed, C.byref(h)))
+        else:
+            check(lib().wedge_model_create_ensemble(seed, members, C.byref(h)))
         return cls(h.value)
+
+    @property
+    def members(self):
+        n = C.c_uint32()
+        check(lib().wedge_model_members(self._h, C.byref(n)))
+        return n.value
 
     @classmethod
     def load(cls, path):
@@ -399,12 +412,14 @@ class Model:
         return self._h
 
     def params(self, new=None):
-        p = np.zeros(MLP_PARAMS, np.float32)
+        """All members' parameters, members one after another (1476 each)."""
+        count = MLP_PARAMS * self.members
+        p = np.zeros(count, np.float32)
         if new is not None:
-            p[:] = np.asarray(new, np.float32)
-            check(lib().wedge_model_params(self._h, p.ctypes.data, MLP_PARAMS, 1))
+            p[:] = np.asarray(new, np.float32).ravel()
+            check(lib().wedge_model_params(self._h, p.ctypes.data, count, 1))
         else:
-            check(lib().wedge_model_params(self._h, p.ctypes.data, MLP_PARAMS, 0))
+            check(lib().wedge_model_params(self._h, p.ctypes.data, count, 0))
         return p
 
     def envelope(self, lo=None, hi=None):

@@ -275,6 +275,7 @@ struct LoopCfg {
     // learned gate: decisions come from the device (model may be null: threshold rule)
     bool learned = false;
     const float* P = nullptr;
+    uint32_t members = 1;
     const float* lo = nullptr;
     const float* hi = nullptr;
     double ticks_per_us = 100.0;
@@ -291,7 +292,7 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
     Workspace& w = g->ws;
     const DevGraph& d = g->dev;
     if (c.learned)
-        HIP_TRY(launch_mlp_infer(c.P, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr, (uint32_t)c.lc,
+        HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr, (uint32_t)c.lc,
                                  c.ticks_per_us, c.app, s), "gate inference");
     HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
     HIP_TRY(hipStreamSynchronize(s), "initialising run");
@@ -335,7 +336,7 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
         HIP_TRY(fin(k, cur), "frontier finalisation");
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
         if (c.learned)
-            HIP_TRY(launch_mlp_infer(c.P, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr,
+            HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr,
                                      (uint32_t)c.lc, c.ticks_per_us, c.app, s), "gate inference");
         HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
         HIP_TRY(hipStreamSynchronize(s), "iteration");
@@ -390,7 +391,12 @@ LoopCfg loop_cfg(const wedge_opts& o, const DevGraph& d, App app, uint32_t theta
     if (o.gate == WEDGE_GATE_LEARNED) {
         c.learned = true;
         const wedge_model_s* md = static_cast<const wedge_model_s*>(o.model);
-        if (md && md->dev_params) { c.P = md->dev_params; c.lo = md->dev_lo; c.hi = md->dev_hi; }
+        if (md && md->dev_params) {
+            c.P = md->dev_params;
+            c.members = md->members;
+            c.lo = md->dev_lo;
+            c.hi = md->dev_hi;
+        }
     }
     return c;
 }
@@ -411,6 +417,7 @@ wedge_status prepare_gate(wedge_graph_t g, const wedge_opts& o, LoopCfg* c) {
         wedge_status st = model_to_device(md);
         if (st != WEDGE_OK) return st;
         c->P = md->dev_params;
+        c->members = md->members;
         c->lo = md->dev_lo;
         c->hi = md->dev_hi;
     }

@@ -1,7 +1,8 @@
 // Learned gate: a small FP32 MLP (8 -> 32 -> 32 -> 4, ReLU) that predicts the
 // log-time of the next iteration in each mode {full pull, Wedge Frontier at 16,
-// 32, 64 edges per bit} relative to the full pull; the gate picks the smallest
-// prediction. Inference
+// 32, 64 edges per bit} relative to the full pull; a model is an ensemble of
+// such MLPs (independently initialised and trained) whose predictions are
+// averaged, and the gate picks the smallest mean prediction. Inference
 // runs on one wave between iterations from the device counters; training is a
 // per-sample forward/backward with LDS-reduced gradients and an Adam update.
 // The paper's threshold rule (Frontier Transformation, Frontier Fullness
@@ -63,18 +64,25 @@ __device__ __forceinline__ void make_features(float (&x)[kMlpIn], double fcount,
     x[7] = (float)(prev_mode / 3.0);
 }
 
-// Batched forward for evaluation: Y[b] = MLP(X[b]).
-__global__ __launch_bounds__(kBlock) void k_mlp_forward(const float* __restrict__ P,
+// Batched forward for evaluation: Y[b] = mean over the ensemble's members of
+// MLP_e(X[b]).
+__global__ __launch_bounds__(kBlock) void k_mlp_forward(const float* __restrict__ P, uint32_t members,
                                                         const float* __restrict__ X,
                                                         float* __restrict__ Y, uint32_t count) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
-    float x[kMlpIn], h1[kMlpHidden], h2[kMlpHidden], y[kMlpOut];
+    float x[kMlpIn], h1[kMlpHidden], h2[kMlpHidden], y[kMlpOut], acc[kMlpOut];
 #pragma unroll
     for (int i = 0; i < kMlpIn; ++i) x[i] = X[(uint64_t)b * kMlpIn + i];
-    mlp_forward(P, x, h1, h2, y);
 #pragma unroll
-    for (int j = 0; j < kMlpOut; ++j) Y[(uint64_t)b * kMlpOut + j] = y[j];
+    for (int j = 0; j < kMlpOut; ++j) acc[j] = 0.f;
+    for (uint32_t e = 0; e < members; ++e) {
+        mlp_forward(P + (size_t)e * kMlpParams, x, h1, h2, y);
+#pragma unroll
+        for (int j = 0; j < kMlpOut; ++j) acc[j] += y[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kMlpOut; ++j) Y[(uint64_t)b * kMlpOut + j] = acc[j] / (float)members;
 }
 
 // Gradient of the mean squared error over the sample's target outputs
@@ -182,7 +190,8 @@ __global__ void k_gate_stamp(Ctl* ctl) {
     }
 }
 
-__global__ void k_mlp_infer(const float* __restrict__ P, const float* __restrict__ env_lo,
+__global__ void k_mlp_infer(const float* __restrict__ P, uint32_t members,
+                            const float* __restrict__ env_lo,
                             const float* __restrict__ env_hi, Ctl* ctl,
                             double n, double m, uint64_t thr, uint32_t fallback_lc,
                             double ticks_per_us, uint32_t app) {
@@ -206,29 +215,38 @@ __global__ void k_mlp_infer(const float* __restrict__ P, const float* __restrict
         s_in = in;
     }
     __syncthreads();
+    // the ensemble's summed outputs (argmin of the sum = argmin of the mean)
+    float acc[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
     if (s_in) {
-        if (lane < kMlpHidden) {
-            float a = P[kB1 + lane];
-            for (int i = 0; i < kMlpIn; ++i) a += P[kW1 + lane * kMlpIn + i] * xs[i];
-            h1[lane] = a > 0.f ? a : 0.f;
+        for (uint32_t e = 0; e < members; ++e) {
+            const float* Q = P + (size_t)e * kMlpParams;
+            if (lane < kMlpHidden) {
+                float a = Q[kB1 + lane];
+                for (int i = 0; i < kMlpIn; ++i) a += Q[kW1 + lane * kMlpIn + i] * xs[i];
+                h1[lane] = a > 0.f ? a : 0.f;
+            }
+            __syncthreads();
+            if (lane < kMlpHidden) {
+                float a = Q[kB2 + lane];
+                for (int i = 0; i < kMlpHidden; ++i) a += Q[kW2 + lane * kMlpHidden + i] * h1[i];
+                h2[lane] = a > 0.f ? a : 0.f;
+            }
+            __syncthreads();
+            if (lane == 0)
+                for (int j = 0; j < kMlpOut; ++j) {
+                    float a = Q[kB3 + j];
+                    for (int i = 0; i < kMlpHidden; ++i) a += Q[kW3 + j * kMlpHidden + i] * h2[i];
+                    acc[j] += a;
+                }
+            __syncthreads();
         }
-        __syncthreads();
-        if (lane < kMlpHidden) {
-            float a = P[kB2 + lane];
-            for (int i = 0; i < kMlpHidden; ++i) a += P[kW2 + lane * kMlpHidden + i] * h1[i];
-            h2[lane] = a > 0.f ? a : 0.f;
-        }
-        __syncthreads();
     }
     if (lane == 0) {
         uint32_t mode = 0, lc = fallback_lc;
         if (s_in) {
             float best = 0.f;
-            for (int j = 0; j < kMlpOut; ++j) {
-                float a = P[kB3 + j];
-                for (int i = 0; i < kMlpHidden; ++i) a += P[kW3 + j * kMlpHidden + i] * h2[i];
-                if (j == 0 || a < best) { best = a; mode = j; }
-            }
+            for (int j = 0; j < kMlpOut; ++j)
+                if (j == 0 || acc[j] < best) { best = acc[j]; mode = j; }
             lc = mode ? 3 + mode : fallback_lc;  // modes 1, 2, 3 = 16, 32, 64 edges per bit
             gs->learned++;
         } else {
@@ -244,10 +262,10 @@ __global__ void k_mlp_infer(const float* __restrict__ P, const float* __restrict
 
 }  // namespace
 
-hipError_t launch_mlp_forward(const float* P, const float* X, float* Y, uint32_t count,
-                              hipStream_t s) {
+hipError_t launch_mlp_forward(const float* P, uint32_t members, const float* X, float* Y,
+                              uint32_t count, hipStream_t s) {
     if (!count) return hipSuccess;
-    k_mlp_forward<<<(count + kBlock - 1) / kBlock, kBlock, 0, s>>>(P, X, Y, count);
+    k_mlp_forward<<<(count + kBlock - 1) / kBlock, kBlock, 0, s>>>(P, members, X, Y, count);
     return hipGetLastError();
 }
 
@@ -265,10 +283,10 @@ hipError_t launch_adam(float* P, float* G, float* M1, float* M2, float lr, float
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_infer(const float* P, const float* lo, const float* hi, Ctl* ctl, double n,
-                            double m, uint64_t thr, uint32_t fallback_lc, double ticks_per_us,
-                            uint32_t app, hipStream_t s) {
-    k_mlp_infer<<<1, 64, 0, s>>>(P, lo, hi, ctl, n, m, thr, fallback_lc, ticks_per_us, app);
+hipError_t launch_mlp_infer(const float* P, uint32_t members, const float* lo, const float* hi,
+                            Ctl* ctl, double n, double m, uint64_t thr, uint32_t fallback_lc,
+                            double ticks_per_us, uint32_t app, hipStream_t s) {
+    k_mlp_infer<<<1, 64, 0, s>>>(P, members, lo, hi, ctl, n, m, thr, fallback_lc, ticks_per_us, app);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ using namespace wedge;
 namespace {
 
 constexpr char kMagic[8] = {'W', 'E', 'D', 'G', 'E', 'M', 'L', 'P'};
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;  // 3: ensemble (member count in the header); 2: one MLP
 
 wedge_status err(wedge_status st, const std::string& m) { return set_error(st, m); }
 
@@ -71,15 +71,16 @@ wedge_status model_to_device(wedge_model_s* m) {
     int dev = 0;
     HTRY(hipGetDevice(&dev), "hipGetDevice");
     if (m->dev_params && m->device != dev) free_device(m);
+    const size_t np = (size_t)m->members * kMlpParams;
     if (!m->dev_params) {
-        HTRY(hipMalloc((void**)&m->dev_params, kMlpParams * sizeof(float)), "model parameters");
+        HTRY(hipMalloc((void**)&m->dev_params, np * sizeof(float)), "model parameters");
         HTRY(hipMalloc((void**)&m->dev_lo, kMlpIn * sizeof(float)), "model envelope");
         HTRY(hipMalloc((void**)&m->dev_hi, kMlpIn * sizeof(float)), "model envelope");
         m->device = dev;
         m->dirty = true;
     }
     if (m->dirty) {
-        HTRY(hipMemcpy(m->dev_params, m->params.data(), kMlpParams * sizeof(float), hipMemcpyHostToDevice), "model upload");
+        HTRY(hipMemcpy(m->dev_params, m->params.data(), np * sizeof(float), hipMemcpyHostToDevice), "model upload");
         HTRY(hipMemcpy(m->dev_lo, m->lo.data(), kMlpIn * sizeof(float), hipMemcpyHostToDevice), "model upload");
         HTRY(hipMemcpy(m->dev_hi, m->hi.data(), kMlpIn * sizeof(float), hipMemcpyHostToDevice), "model upload");
         m->dirty = false;
@@ -91,32 +92,48 @@ wedge_status model_to_device(wedge_model_s* m) {
 
 extern "C" {
 
-wedge_status wedge_model_create(uint64_t seed, wedge_model_t* out) {
+wedge_status wedge_model_create_ensemble(uint64_t seed, uint32_t members, wedge_model_t* out) {
     if (!out) return err(WEDGE_ERR_INVALID_ARG, "out is null");
+    if (members < 1 || members > kMlpMaxMembers) return err(WEDGE_ERR_INVALID_ARG, "members must be 1..8");
     try {
         auto* m = new wedge_model_s();
-        m->params.assign(kMlpParams, 0.f);
+        m->members = members;
+        m->params.assign((size_t)members * kMlpParams, 0.f);
         m->lo.assign(kMlpIn, -std::numeric_limits<float>::infinity());
         m->hi.assign(kMlpIn, std::numeric_limits<float>::infinity());
-        // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases
+        // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases; the
+        // members draw one after another from the same stream
         uint64_t s = seed;
-        auto fill = [&](int off, int rows, int cols) {
-            const double b = 1.0 / std::sqrt((double)cols);
-            for (int i = 0; i < rows * cols; ++i) {
-                double u = (double)(splitmix(s) >> 11) * (1.0 / 9007199254740992.0);
-                m->params[off + i] = (float)((2.0 * u - 1.0) * b);
-            }
-        };
-        const int w1 = 0, b1 = w1 + kMlpHidden * kMlpIn, w2 = b1 + kMlpHidden;
-        const int b2 = w2 + kMlpHidden * kMlpHidden, w3 = b2 + kMlpHidden;
-        fill(w1, kMlpHidden, kMlpIn);
-        fill(w2, kMlpHidden, kMlpHidden);
-        fill(w3, kMlpOut, kMlpHidden);
+        for (uint32_t e = 0; e < members; ++e) {
+            float* P = m->params.data() + (size_t)e * kMlpParams;
+            auto fill = [&](int off, int rows, int cols) {
+                const double b = 1.0 / std::sqrt((double)cols);
+                for (int i = 0; i < rows * cols; ++i) {
+                    double u = (double)(splitmix(s) >> 11) * (1.0 / 9007199254740992.0);
+                    P[off + i] = (float)((2.0 * u - 1.0) * b);
+                }
+            };
+            const int w1 = 0, b1 = w1 + kMlpHidden * kMlpIn, w2 = b1 + kMlpHidden;
+            const int b2 = w2 + kMlpHidden * kMlpHidden, w3 = b2 + kMlpHidden;
+            fill(w1, kMlpHidden, kMlpIn);
+            fill(w2, kMlpHidden, kMlpHidden);
+            fill(w3, kMlpOut, kMlpHidden);
+        }
         *out = m;
         return WEDGE_OK;
     } catch (const std::bad_alloc&) {
         return err(WEDGE_ERR_OOM, "host allocation failed");
     }
+}
+
+wedge_status wedge_model_create(uint64_t seed, wedge_model_t* out) {
+    return wedge_model_create_ensemble(seed, 1, out);
+}
+
+wedge_status wedge_model_members(wedge_model_t m, uint32_t* members) {
+    if (!m || !members) return err(WEDGE_ERR_INVALID_ARG, "null argument");
+    *members = m->members;
+    return WEDGE_OK;
 }
 
 wedge_status wedge_model_free(wedge_model_t m) {
@@ -128,9 +145,10 @@ wedge_status wedge_model_free(wedge_model_t m) {
 
 wedge_status wedge_model_params(wedge_model_t m, float* params, uint32_t count, int set) {
     if (!m || !params) return err(WEDGE_ERR_INVALID_ARG, "null argument");
-    if (count != (uint32_t)kMlpParams) return err(WEDGE_ERR_INVALID_ARG, "count must be 1476");
-    if (set) { std::memcpy(m->params.data(), params, kMlpParams * sizeof(float)); m->dirty = true; }
-    else std::memcpy(params, m->params.data(), kMlpParams * sizeof(float));
+    const size_t np = (size_t)m->members * kMlpParams;
+    if (count != np) return err(WEDGE_ERR_INVALID_ARG, "count must be 1476 x members");
+    if (set) { std::memcpy(m->params.data(), params, np * sizeof(float)); m->dirty = true; }
+    else std::memcpy(params, m->params.data(), np * sizeof(float));
     return WEDGE_OK;
 }
 
@@ -154,13 +172,13 @@ wedge_status wedge_model_save(wedge_model_t m, const char* path) {
         const unsigned char* c = static_cast<const unsigned char*>(p);
         buf.insert(buf.end(), c, c + n);
     };
-    const uint32_t hdr[5] = {kVersion, (uint32_t)kMlpParams, (uint32_t)kMlpIn, (uint32_t)kMlpHidden,
-                             (uint32_t)kMlpOut};
+    const uint32_t hdr[6] = {kVersion, (uint32_t)kMlpParams, (uint32_t)kMlpIn, (uint32_t)kMlpHidden,
+                             (uint32_t)kMlpOut, m->members};
     put(kMagic, 8);
     put(hdr, sizeof hdr);
     put(m->lo.data(), kMlpIn * sizeof(float));
     put(m->hi.data(), kMlpIn * sizeof(float));
-    put(m->params.data(), kMlpParams * sizeof(float));
+    put(m->params.data(), (size_t)m->members * kMlpParams * sizeof(float));
     const uint64_t sum = fnv1a(buf.data(), buf.size());
     put(&sum, sizeof sum);
     FILE* f = std::fopen(path, "wb");
@@ -181,25 +199,32 @@ wedge_status wedge_model_load(const char* path, wedge_model_t* out) {
     size_t r;
     while ((r = std::fread(tmp, 1, sizeof tmp, f)) > 0) buf.insert(buf.end(), tmp, tmp + r);
     std::fclose(f);
-    const size_t want = 8 + 5 * 4 + 2 * kMlpIn * 4 + kMlpParams * 4 + 8;
-    if (buf.size() != want) return err(WEDGE_ERR_MODEL, "model file has the wrong size");
-    if (std::memcmp(buf.data(), kMagic, 8) != 0) return err(WEDGE_ERR_MODEL, "not a model file");
-    uint32_t hdr[5];
-    std::memcpy(hdr, buf.data() + 8, sizeof hdr);
-    if (hdr[0] != kVersion || hdr[1] != (uint32_t)kMlpParams || hdr[2] != (uint32_t)kMlpIn ||
-        hdr[3] != (uint32_t)kMlpHidden || hdr[4] != (uint32_t)kMlpOut)
+    if (buf.size() < 8 + 5 * 4 || std::memcmp(buf.data(), kMagic, 8) != 0)
+        return err(WEDGE_ERR_MODEL, "not a model file");
+    uint32_t hdr[6] = {0, 0, 0, 0, 0, 1};
+    std::memcpy(hdr, buf.data() + 8, 5 * 4);
+    // version 2 files hold one MLP and a five-word header
+    const size_t hwords = hdr[0] == 2 ? 5 : 6;
+    if (hdr[0] == kVersion && buf.size() >= 8 + 6 * 4) std::memcpy(hdr, buf.data() + 8, 6 * 4);
+    if ((hdr[0] != kVersion && hdr[0] != 2) || hdr[1] != (uint32_t)kMlpParams ||
+        hdr[2] != (uint32_t)kMlpIn || hdr[3] != (uint32_t)kMlpHidden || hdr[4] != (uint32_t)kMlpOut ||
+        hdr[5] < 1 || hdr[5] > kMlpMaxMembers)
         return err(WEDGE_ERR_MODEL, "model version or shape mismatch");
+    const size_t np = (size_t)hdr[5] * kMlpParams;
+    const size_t want = 8 + hwords * 4 + 2 * kMlpIn * 4 + np * 4 + 8;
+    if (buf.size() != want) return err(WEDGE_ERR_MODEL, "model file has the wrong size");
     uint64_t sum;
     std::memcpy(&sum, buf.data() + want - 8, 8);
     if (fnv1a(buf.data(), want - 8) != sum) return err(WEDGE_ERR_MODEL, "model checksum mismatch");
     auto* m = new wedge_model_s();
-    const unsigned char* p = buf.data() + 8 + sizeof hdr;
+    const unsigned char* p = buf.data() + 8 + hwords * 4;
+    m->members = hdr[5];
     m->lo.resize(kMlpIn);
     m->hi.resize(kMlpIn);
-    m->params.resize(kMlpParams);
+    m->params.resize(np);
     std::memcpy(m->lo.data(), p, kMlpIn * 4); p += kMlpIn * 4;
     std::memcpy(m->hi.data(), p, kMlpIn * 4); p += kMlpIn * 4;
-    std::memcpy(m->params.data(), p, kMlpParams * 4);
+    std::memcpy(m->params.data(), p, np * 4);
     for (float v : m->params)
         if (!std::isfinite(v)) { delete m; return err(WEDGE_ERR_MODEL, "model has non-finite parameters"); }
     *out = m;
@@ -225,7 +250,8 @@ wedge_status wedge_model_predict(wedge_model_t m, const float* x, uint32_t count
     HTRY(hipMalloc(&dx.p, (size_t)count * kMlpIn * 4), "features");
     HTRY(hipMalloc(&dy.p, (size_t)count * kMlpOut * 4), "predictions");
     HTRY(hipMemcpyAsync(dx.p, x, (size_t)count * kMlpIn * 4, hipMemcpyHostToDevice, stream), "features");
-    HTRY(launch_mlp_forward(m->dev_params, (const float*)dx.p, (float*)dy.p, count, stream), "forward");
+    HTRY(launch_mlp_forward(m->dev_params, m->members, (const float*)dx.p, (float*)dy.p, count, stream),
+         "forward");
     HTRY(hipMemcpyAsync(y, dy.p, (size_t)count * kMlpOut * 4, hipMemcpyDeviceToHost, stream), "predictions");
     HTRY(hipStreamSynchronize(stream), "prediction");
     return WEDGE_OK;
@@ -234,6 +260,7 @@ wedge_status wedge_model_predict(wedge_model_t m, const float* x, uint32_t count
 wedge_status wedge_model_grad(wedge_model_t m, const float* x, const float* t, const float* mask,
                               uint32_t count, float* grad, float* loss, hipStream_t stream) {
     if (!m || !x || !t || !mask || !grad || !count) return err(WEDGE_ERR_INVALID_ARG, "null argument");
+    if (m->members != 1) return err(WEDGE_ERR_UNSUPPORTED, "gradients are defined for one-member models");
     wedge_status st = model_to_device(m);
     if (st != WEDGE_OK) return st;
     DevBuf dx, dt, dm, dg, dl;
@@ -305,23 +332,32 @@ wedge_status wedge_model_train(wedge_model_t m, const wedge_trace_sample* s, uin
     HTRY(hipMemcpyAsync(dx.p, X.data(), X.size() * 4, hipMemcpyHostToDevice, stream), "upload");
     HTRY(hipMemcpyAsync(dt.p, T.data(), T.size() * 4, hipMemcpyHostToDevice, stream), "upload");
     HTRY(hipMemcpyAsync(dm.p, M.data(), M.size() * 4, hipMemcpyHostToDevice, stream), "upload");
-    HTRY(hipMemsetAsync(dg.p, 0, kMlpParams * 4, stream), "clear");
-    HTRY(hipMemsetAsync(d1.p, 0, kMlpParams * 4, stream), "clear");
-    HTRY(hipMemsetAsync(d2.p, 0, kMlpParams * 4, stream), "clear");
-    for (uint32_t e = 0; e < epochs; ++e) {
-        const bool last = e + 1 == epochs;
-        if (last) HTRY(hipMemsetAsync(dl.p, 0, 4, stream), "clear");
-        HTRY(launch_mlp_grad(m->dev_params, (const float*)dx.p, (const float*)dt.p, (const float*)dm.p,
-                             count, 1.0f / (float)count, (float*)dg.p, last ? (float*)dl.p : nullptr,
-                             stream), "gradient");
-        HTRY(launch_adam(m->dev_params, (float*)dg.p, (float*)d1.p, (float*)d2.p, lr, 0.9f, 0.999f, 1e-8f,
-                         e + 1, stream), "adam");
+    // each member is trained on its own from its own initial parameters (Adam
+    // state restarts per member); the reported loss is the members' mean
+    float lsum = 0.f;
+    for (uint32_t mb = 0; mb < m->members; ++mb) {
+        float* P = m->dev_params + (size_t)mb * kMlpParams;
+        HTRY(hipMemsetAsync(dg.p, 0, kMlpParams * 4, stream), "clear");
+        HTRY(hipMemsetAsync(d1.p, 0, kMlpParams * 4, stream), "clear");
+        HTRY(hipMemsetAsync(d2.p, 0, kMlpParams * 4, stream), "clear");
+        for (uint32_t e = 0; e < epochs; ++e) {
+            const bool last = e + 1 == epochs;
+            if (last) HTRY(hipMemsetAsync(dl.p, 0, 4, stream), "clear");
+            HTRY(launch_mlp_grad(P, (const float*)dx.p, (const float*)dt.p, (const float*)dm.p, count,
+                                 1.0f / (float)count, (float*)dg.p, last ? (float*)dl.p : nullptr,
+                                 stream), "gradient");
+            HTRY(launch_adam(P, (float*)dg.p, (float*)d1.p, (float*)d2.p, lr, 0.9f, 0.999f, 1e-8f, e + 1,
+                             stream), "adam");
+        }
+        float l = 0.f;
+        HTRY(hipMemcpyAsync(&l, dl.p, 4, hipMemcpyDeviceToHost, stream), "download");
+        HTRY(hipStreamSynchronize(stream), "training");
+        lsum += l;
     }
-    float l = 0.f;
-    HTRY(hipMemcpyAsync(m->params.data(), m->dev_params, kMlpParams * 4, hipMemcpyDeviceToHost, stream), "download");
-    HTRY(hipMemcpyAsync(&l, dl.p, 4, hipMemcpyDeviceToHost, stream), "download");
+    HTRY(hipMemcpyAsync(m->params.data(), m->dev_params, (size_t)m->members * kMlpParams * 4,
+                        hipMemcpyDeviceToHost, stream), "download");
     HTRY(hipStreamSynchronize(stream), "training");
-    if (final_loss) *final_loss = l;
+    if (final_loss) *final_loss = lsum / (float)m->members;
     return WEDGE_OK;
 }
 

@@ -109,7 +109,8 @@ inline uint64_t chunk_slots_count(uint64_t K, int lc) {
 // Learned-gate sizes: 8 features -> 32 -> 32 -> 4 predicted log-times.
 constexpr int kMlpIn = 8, kMlpHidden = 32, kMlpOut = 4;
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
-                           kMlpOut * kMlpHidden + kMlpOut;  // 1476
+                           kMlpOut * kMlpHidden + kMlpOut;
+constexpr uint32_t kMlpMaxMembers = 8;  // ensemble size limit  // 1476
 
 // Decision state of the device-side gate, carried across iterations.
 struct GateState {
@@ -229,7 +230,8 @@ struct Workspace {
 // Learned-gate model: FP32 parameters, the training envelope of each feature,
 // and their device copies (made on first use on a GPU).
 struct wedge_model_s {
-    std::vector<float> params;   // kMlpParams, layout W1 b1 W2 b2 W3 b3 (row-major out x in)
+    uint32_t members = 1;        // ensemble size (1 .. kMlpMaxMembers)
+    std::vector<float> params;   // members x kMlpParams, each W1 b1 W2 b2 W3 b3 (row-major out x in)
     std::vector<float> lo, hi;   // per-feature envelope
     float* dev_params = nullptr;
     float* dev_lo = nullptr;
@@ -329,16 +331,16 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStrea
 hipError_t launch_fill_u32_kernel(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
 hipError_t persistent_max_blocks(bool ms, int* blocks_per_cu);
 // Learned gate (mlp.hip)
-hipError_t launch_mlp_forward(const float* P, const float* X, float* Y, uint32_t count,
-                              hipStream_t s);
+hipError_t launch_mlp_forward(const float* P, uint32_t members, const float* X, float* Y,
+                              uint32_t count, hipStream_t s);
 hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const float* Mk,
                            uint32_t count, float scale, float* G, float* loss, hipStream_t s);
 hipError_t launch_adam(float* P, float* G, float* M1, float* M2, float lr, float b1, float b2,
                        float eps, uint32_t step, hipStream_t s);
 // P null: the threshold rule decides (no model)
-hipError_t launch_mlp_infer(const float* P, const float* lo, const float* hi, Ctl* ctl, double n,
-                            double m, uint64_t thr, uint32_t fallback_lc, double ticks_per_us,
-                            uint32_t app, hipStream_t s);
+hipError_t launch_mlp_infer(const float* P, uint32_t members, const float* lo, const float* hi,
+                            Ctl* ctl, double n, double m, uint64_t thr, uint32_t fallback_lc,
+                            double ticks_per_us, uint32_t app, hipStream_t s);
 hipError_t launch_gate_stamp(Ctl* ctl, hipStream_t s);
 // Host form of the gate features (same formula as the device).
 void mlp_features(float* x, double fcount, double active, double n, double m, double k,

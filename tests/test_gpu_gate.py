@@ -42,6 +42,18 @@ def test_forward_and_gradient_match_oracle():
     assert abs(loss - lref) <= 1e-5 * lref
 
 
+def test_ensemble_prediction_is_the_member_mean():
+    m = W.Model.create(seed=3, members=4)
+    rng = np.random.default_rng(2)
+    p = rng.normal(0, 0.3, 4 * 1476).astype(np.float32)
+    m.params(p)
+    x = rng.normal(0, 1, (500, 8)).astype(np.float32)
+    y = m.predict(x)
+    ref = np.mean([mlp.forward(p[e * 1476:(e + 1) * 1476].astype(np.float64), x.astype(np.float64))
+                   for e in range(4)], axis=0)
+    assert np.abs(y - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
 def synthetic_samples(n, seed):
     rng = np.random.default_rng(seed)
     S = (B.TraceSample * n)()
@@ -114,9 +126,9 @@ def test_learned_gate_keeps_results_exact(app):
     ro, col = gen.rmat(13, 16, seed=72)
     w = gen.edge_weights(ro, col, seed=5) if app == "sssp" else None
     s = int(gen.pick_sources(ro, 1, seed=6)[0])
-    m = W.Model.create(seed=9)
+    m = W.Model.create(seed=9, members=2)
     rng = np.random.default_rng(3)
-    m.params(rng.normal(0, 1.0, 1476))           # an arbitrary model: any decision is allowed
+    m.params(rng.normal(0, 1.0, 2 * 1476))       # an arbitrary ensemble: any decision is allowed
     if app == "cc":
         g = W.Graph.from_csr(ro, col, symmetrize=True)
         out, st, tr = W.cc(g, gate="learned", model=m.handle, trace_cap=256)

@@ -116,3 +116,52 @@ def test_model_file_roundtrip_and_corruption(tmp_path):
     q = np.linspace(-1, 1, 1476).astype(np.float32)
     np.testing.assert_array_equal(m.params(q), q)
     np.testing.assert_array_equal(m.params(), q)
+
+
+def fnv1a(data):
+    h = 1469598103934665603
+    for b in data:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_ensemble_create_roundtrip_and_errors(tmp_path):
+    single = W.Model.create(seed=5)
+    ens = W.Model.create(seed=5, members=3)
+    assert ens.members == 3 and single.members == 1
+    p = ens.params()
+    assert p.shape == (3 * 1476,)
+    # member 0 is the single model of the same seed; the others differ
+    np.testing.assert_array_equal(p[:1476], single.params())
+    assert np.any(p[1476:2952] != p[:1476]) and np.any(p[2952:] != p[1476:2952])
+    f = tmp_path / "ens.bin"
+    ens.save(str(f))
+    back = W.Model.load(str(f))
+    assert back.members == 3
+    np.testing.assert_array_equal(back.params(), p)
+    # a version-2 file (five-word header, one MLP) still loads as one member
+    q = np.linspace(-2, 2, 1476).astype(np.float32)
+    lo, hi = np.full(8, -1.0, np.float32), np.full(8, 1.0, np.float32)
+    body = (b"WEDGEMLP" + np.array([2, 1476, 8, 32, 4], np.uint32).tobytes() + lo.tobytes()
+            + hi.tobytes() + q.tobytes())
+    v2 = tmp_path / "v2.bin"
+    v2.write_bytes(body + np.array([fnv1a(body)], np.uint64).tobytes())
+    old = W.Model.load(str(v2))
+    assert old.members == 1
+    np.testing.assert_array_equal(old.params(), q)
+    np.testing.assert_array_equal(old.envelope()[1], hi)
+    # argument errors
+    for bad in (0, 9):
+        with pytest.raises(W.WedgeError) as e:
+            W.Model.create(seed=1, members=bad)
+        assert e.value.name == "WEDGE_ERR_INVALID_ARG"
+    buf = np.zeros(1476, np.float32)
+    assert B.lib().wedge_model_params(ens.handle, buf.ctypes.data, 1476, 0) != B.OK
+    # gradients are refused for ensembles before any device work
+    x = np.zeros((4, 8), np.float32)
+    t = np.zeros((4, 4), np.float32)
+    mk = np.ones((4, 4), np.float32)
+    g = np.zeros(1476, np.float32)
+    st = B.lib().wedge_model_grad(ens.handle, x.ctypes.data, t.ctypes.data, mk.ctypes.data, 4,
+                                  g.ctypes.data, None, None)
+    assert B.STATUS[st] == "WEDGE_ERR_UNSUPPORTED"
