@@ -109,7 +109,7 @@ __device__ __forceinline__ void ms_finalize_block(
     uint64_t vblock, uint64_t* bits, uint64_t words, uint32_t n, const uint32_t* row_off,
     uint32_t* list, uint32_t* degpre, Ctl* ctl, uint64_t* fcur, uint64_t* visited,
     uint64_t* retire, const uint64_t* nxt, uint32_t* lev, uint32_t K, uint32_t level) {
-    bitmap_compact_block_ex<true, true, kCompactWords>(
+    bitmap_compact_block_ex<kWavesPerBlock, true, true, kCompactWords>(
         vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
         [&](uint32_t v) -> uint64_t { return nxt[v]; },
         [&](uint32_t v, uint64_t nb) {
@@ -129,7 +129,7 @@ __device__ __forceinline__ void bfs_finalize_block(uint64_t vblock, uint64_t* bi
                                                    uint64_t words, uint32_t n,
                                                    const uint32_t* row_off, uint32_t* list,
                                                    uint32_t* degpre, Ctl* ctl, uint64_t* fcur) {
-    bitmap_compact_block_ex<true, true, kCompactWords>(
+    bitmap_compact_block_ex<kWavesPerBlock, true, true, kCompactWords>(
         vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
         [](uint32_t) -> uint64_t { return 0ull; }, [](uint32_t, uint64_t) {}, [](uint32_t) {});
 }

@@ -25,6 +25,14 @@ constexpr int kHotBlock = WEDGE_HOT_BLOCK;          // threads per block
 constexpr uint32_t kHotVerts = WEDGE_HOT_VERTS;     // values held in LDS (4 B each)
 constexpr int kHotBatch = WEDGE_HOT_BATCH;          // rows loaded at a time per wave
 constexpr uint32_t kHotMinVerts = 4096;
+// waves per block of the stand-alone compaction kernels: each block makes one
+// output-range reservation (an atomic on one shared counter), so fewer,
+// larger blocks contend less; 8 waves measured best at R-MAT scale 24
+// (2: 57.7, 4: 61.5, 8: 63.6, 16: 63.3 GTEPS for the whole bench step)
+#ifndef WEDGE_COMPACT_WAVES
+#define WEDGE_COMPACT_WAVES 8
+#endif
+constexpr int kCompactWaves = WEDGE_COMPACT_WAVES;
 // minimum resident waves per SIMD requested for the integer pulls (caps their
 // registers so that many rows' loads stay in flight per compute unit)
 #ifdef WEDGE_PULL_WAVES
@@ -183,21 +191,21 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
 // before it is overwritten (COPY only). A wave's loads are issued word-batch
 // by word-batch, never one word at a time: bitmap words (and the words being
 // replaced), then the out-degree bounds and load_set of every set bit.
-template <bool DEG, bool COPY, int G, class LoadSet, class OnSet, class OnOld>
+template <int WAVES, bool DEG, bool COPY, int G, class LoadSet, class OnSet, class OnOld>
 __device__ __forceinline__ void bitmap_compact_block_ex(
     uint64_t vblock, uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint64_t* __restrict__ copy_to, LoadSet load_set, OnSet on_set, OnOld on_old) {
-    __shared__ unsigned long long s_wave[kWavesPerBlock];
-    __shared__ unsigned long long s_all[kWavesPerBlock];
+    __shared__ unsigned long long s_wave[WAVES];
+    __shared__ unsigned long long s_all[WAVES];
     __shared__ unsigned long long s_base;
     // a block may run this for several virtual blocks in a row: wait until every
     // wave has read the previous call's shared values before they are rewritten
     __syncthreads();
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
-    const uint64_t w0 = (vblock * kWavesPerBlock + wid) * G;
+    const uint64_t w0 = (vblock * WAVES + wid) * G;
     uint64_t mk[G], lm[G], old[G], pre[G];
     uint32_t deg[G], r0[G], r1[G];
     uint64_t cnt = 0, all = 0, dsum = 0;
@@ -254,7 +262,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0, a = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) { t += s_wave[i]; a += s_all[i]; }
+        for (int i = 0; i < WAVES; ++i) { t += s_wave[i]; a += s_all[i]; }
         s_base = t ? atomicAdd(counter, t) : 0ull;
         if (total && a) atomicAdd(total, a);
     }
@@ -450,14 +458,14 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
     }
 }
 
-template <bool DEG, bool COMMIT, bool COPY, int G>
+template <bool DEG, bool COMMIT, bool COPY, int G, int WAVES = kWavesPerBlock>
 __device__ __forceinline__ void bitmap_compact_block(
     uint64_t vblock, uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
     uint64_t* __restrict__ copy_to) {
-    bitmap_compact_block_ex<DEG, COPY, G>(
+    bitmap_compact_block_ex<WAVES, DEG, COPY, G>(
         vblock, bits, words, limit, row_off, list, degpre, counter, total, copy_to,
         [&](uint32_t v) -> uint64_t { return COMMIT ? val[v] : 0u; },
         [&](uint32_t v, uint64_t x) { if (COMMIT) val_prev[v] = (uint32_t)x; }, [](uint32_t) {});

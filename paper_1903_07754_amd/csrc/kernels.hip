@@ -120,14 +120,15 @@ __global__ __launch_bounds__(kBlock) void k_translate(const uint32_t* __restrict
 //           the current one while it is cleared).
 // Counter layout: (count << 33) | out-degree sum.
 template <bool DEG, bool COMMIT, bool COPY, int G>
-__global__ __launch_bounds__(kBlock) void k_bitmap_compact(
+__global__ __launch_bounds__(kCompactWaves * 64) void k_bitmap_compact(
     uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
     uint64_t* __restrict__ copy_to) {
-    bitmap_compact_block<DEG, COMMIT, COPY, G>(blockIdx.x, bits, words, limit, row_off, list,
-                                               degpre, counter, total, val_prev, val, copy_to);
+    bitmap_compact_block<DEG, COMMIT, COPY, G, kCompactWaves>(blockIdx.x, bits, words, limit, row_off,
+                                                              list, degpre, counter, total, val_prev,
+                                                              val, copy_to);
 }
 
 // ------------------------------------------------------------- the pulls
@@ -523,8 +524,8 @@ hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list
                                  hipStream_t s) {
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
-    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_bitmap_compact<false, false, false, kCompactWords><<<blocks, kBlock, 0, s>>>(
+    const uint32_t blocks = (uint32_t)((waves + kCompactWaves - 1) / kCompactWaves);
+    k_bitmap_compact<false, false, false, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
         wbits, words, 0xFFFFFFFFu, nullptr, list, nullptr, &ctl->marked, nullptr, nullptr, nullptr,
         nullptr);
     return hipGetLastError();
@@ -536,17 +537,17 @@ hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
     const uint64_t words = ((uint64_t)n + 63) / 64;
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
-    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    const uint32_t blocks = (uint32_t)((waves + kCompactWaves - 1) / kCompactWaves);
     unsigned long long* c = &ctl->fnext;
     unsigned long long* t = &ctl->ftotal;
     if (val_prev && fcur)
-        k_bitmap_compact<true, true, true, kCompactWords><<<blocks, kBlock, 0, s>>>(
+        k_bitmap_compact<true, true, true, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
             fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur);
     else if (fcur)
-        k_bitmap_compact<true, false, true, kCompactWords><<<blocks, kBlock, 0, s>>>(
+        k_bitmap_compact<true, false, true, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
             fbits, words, n, row_off, flist, degpre, c, t, nullptr, nullptr, fcur);
     else
-        k_bitmap_compact<true, false, false, kCompactWords><<<blocks, kBlock, 0, s>>>(
+        k_bitmap_compact<true, false, false, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
             fbits, words, n, row_off, flist, degpre, c, t, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
