@@ -105,11 +105,12 @@ __device__ __forceinline__ void ms_pull_slots(const GraphArgs& g, uint64_t s0, u
 // vertices (with out-degree prefix), add the new masks to visited, write level
 // `level` for every newly set (vertex, source) bit into lev[v*K + s], clear
 // the masks of the frontier being retired, and move the bitmap to fcur.
+template <int WAVES = kWavesPerBlock>
 __device__ __forceinline__ void ms_finalize_block(
     uint64_t vblock, uint64_t* bits, uint64_t words, uint32_t n, const uint32_t* row_off,
     uint32_t* list, uint32_t* degpre, Ctl* ctl, uint64_t* fcur, uint64_t* visited,
     uint64_t* retire, const uint64_t* nxt, uint32_t* lev, uint32_t K, uint32_t level) {
-    bitmap_compact_block_ex<kWavesPerBlock, true, true, kCompactWords>(
+    bitmap_compact_block_ex<WAVES, true, true, kCompactWords>(
         vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
         [&](uint32_t v) -> uint64_t { return nxt[v]; },
         [&](uint32_t v, uint64_t nb) {
@@ -163,15 +164,15 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull_chunks(GraphArgs g, int lc,
         ms_pull_slots<kPullRows>(g, s0, slots, lc, list, K, all, visited, cur, nxt, fbits);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ms_finalize(uint64_t* bits, uint64_t words,
+__global__ __launch_bounds__(kCompactWaves * 64) void k_ms_finalize(uint64_t* bits, uint64_t words,
                                                         uint32_t n, const uint32_t* row_off,
                                                         uint32_t* list, uint32_t* degpre,
                                                         Ctl* ctl, uint64_t* fcur,
                                                         uint64_t* visited, uint64_t* retire,
                                                         const uint64_t* nxt, uint32_t* lev,
                                                         uint32_t K, uint32_t level) {
-    ms_finalize_block(blockIdx.x, bits, words, n, row_off, list, degpre, ctl, fcur, visited,
-                      retire, nxt, lev, K, level);
+    ms_finalize_block<kCompactWaves>(blockIdx.x, bits, words, n, row_off, list, degpre, ctl, fcur,
+                                     visited, retire, nxt, lev, K, level);
 }
 
 // Sources of a multi-source run: bit s of nxt[src[s]], and the vertex bit.
@@ -426,9 +427,9 @@ hipError_t launch_ms_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_o
     const uint64_t words = ((uint64_t)n + 63) / 64;
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
-    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_ms_finalize<<<blocks, kBlock, 0, s>>>(fbits, words, n, row_off, flist, degpre, ctl, fcur,
-                                            visited, retire, nxt, lev, K, level);
+    const uint32_t blocks = (uint32_t)((waves + kCompactWaves - 1) / kCompactWaves);
+    k_ms_finalize<<<blocks, kCompactWaves * 64, 0, s>>>(fbits, words, n, row_off, flist, degpre, ctl,
+                                                        fcur, visited, retire, nxt, lev, K, level);
     return hipGetLastError();
 }
 
