@@ -103,11 +103,79 @@ def cpu_baseline(ro, col, w, srcs, m):
     total = sum(t.values())
     log("oracle seconds: " + ", ".join(f"{k}={v:.2f}" for k, v in t.items()))
     return {"value": round(units / total / 1e9, 4), "unit": "GTEPS", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": ("same R-MAT s24 graph: BFS and SSSP from 1 source (sequential queue BFS, "
                        "Dial/Dijkstra), CC by union-find (sequential), PageRank 2 of 20 iterations "
                        "(FP64, OpenMP over destinations); units M+M+M+2M over the summed time"),
             "seconds": {k: round(v, 3) for k, v in t.items()}}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def pagerank_only(args):
+    """PageRank alone (20 iterations, d = 0.85) on R-MAT at --scale: the
+    full-pull roofline at sizes whose other applications would not be worth
+    the time (the 67M-vertex, 1.06B-edge scale-26 graph)."""
+    import torch
+
+    import gen
+    import paper_1903_07754_amd as W
+
+    log(f"generating R-MAT scale {args.scale}")
+    ro, col = gen.rmat(args.scale, 16, seed=1)
+    n, m = len(ro) - 1, len(col)
+    log(f"n={n} m={m}; building the layout")
+    g = W.Graph.from_csr(ro, col)
+    del ro, col
+    rank = torch.empty(n, dtype=torch.float32, device="cuda")
+    for i in range(args.warmup):
+        W.pagerank(g, 20, 0.85, out=rank)
+    torch.cuda.synchronize()
+    ms, pull_ms, launches = 0.0, 0.0, 0
+    for i in range(args.steps):
+        _, st = W.pagerank(g, 20, 0.85, out=rank, time_pull=True)
+        ms += st["ms"]
+        pull_ms += st["pull_ms"]
+        launches += st["pull_launches"]
+        log(f"step {i + 1}/{args.steps} done")
+    K = args.steps
+    avg_launch_s = pull_ms / 1e3 / launches
+    alg = pr_pull_bytes(g.info)
+    name = pr_kernel_name(g.info)
+    workload = f"rmat{args.scale}"
+    traffic = measured_traffic(name, workload)
+    roof = {"kernel": name, "bound": "hbm", "achieved": round(alg / avg_launch_s / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(alg / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": launches,
+            "algorithmic_bytes_per_launch": int(alg)}
+    if traffic:
+        roof["traffic_gbs"] = round(traffic / avg_launch_s / 1e9, 1)
+        roof["traffic_frac"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    out = {"metric": "PageRank GTEPS (20 iterations, full pull) R-MAT s%d" % args.scale,
+           "value": round(20 * m * K / (ms / 1e3) / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
+           "steps": K, "warmup": args.warmup, "ms_per_step": round(ms / K, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"R-MAT s{args.scale} ef16 PageRank x20", "n": n, "m": m},
+           "roofline": roof}
+    print(json.dumps(out), flush=True)
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {nbytes} bytes")
 
 
 def timed(fn, reps):
@@ -237,6 +305,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--pagerank-only", action="store_true",
+                    help="time only the PageRank leg (used for the scale-26 roofline)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB 3 times (a known-size "
                          "kernel for calibrating HBM byte counters)")
@@ -245,6 +315,9 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.pagerank_only:
+        pagerank_only(args)
+        return
 
     import numpy as np
     import torch

@@ -121,6 +121,14 @@ def choices(model, samples):
     return np.where(inside, y.argmin(1), thr), inside
 
 
+def fixed_modes(samples):
+    """Mode indices of the two fixed policies: every iteration full (0), and
+    every iteration Wedge at the application's default group size (32 edges
+    for BFS = mode 2, 16 for CC and SSSP = mode 1)."""
+    app = np.array([s.app for s in samples])
+    return np.zeros(len(app), int), np.where(app == 1, 2, 1)
+
+
 def regret(samples, pick):
     t = np.array([list(s.t_us) for s in samples], np.float64)
     best = t.min(1)
@@ -149,8 +157,13 @@ def eval_graphs(seeds=(2000, 2001, 2002, 2003), scale=24):
         yield kind, seed, ro, col
 
 
+GATES = ("threshold", "learned", "wedge", "full")
+
+
 def end_to_end(model, ro, col, seed, reps=3):
-    """Best-of-reps wall time (ms) per app under the threshold rule and the learned gate."""
+    """Best-of-reps wall time (ms) per app under the threshold rule, the learned
+    gate, and the two fixed policies (every iteration Wedge / every iteration
+    full); the learned runs include their inference cost."""
     import torch
     w = gen.edge_weights(ro, col, seed=4)
     src = int(gen.pick_sources(ro, 1, seed=seed)[0])
@@ -161,7 +174,7 @@ def end_to_end(model, ro, col, seed, reps=3):
     res = {}
     for app in APPS:
         times = {}
-        for gate in ("threshold", "learned"):
+        for gate in GATES:
             kw = {"gate": gate, "model": model.handle if gate == "learned" else None}
             best = 1e30
             for _ in range(reps):
@@ -194,6 +207,8 @@ def evaluate(model, seeds=(2000, 2001, 2002, 2003), scale=24, traces_out=None):
             "kind": kind, "seed": seed, "m": m, "iterations": len(samples),
             "model_decided": float(inside.mean()),
             "threshold": regret(samples, thr), "learned": regret(samples, pick),
+            "always_full": regret(samples, fixed_modes(samples)[0]),
+            "always_wedge": regret(samples, fixed_modes(samples)[1]),
             "end_to_end_ms": e2e,
             "end_to_end_gteps": {app: {k: round(m / v / 1e6, 3) for k, v in t.items()}
                                  for app, t in e2e.items()}})
@@ -203,7 +218,11 @@ def evaluate(model, seeds=(2000, 2001, 2002, 2003), scale=24, traces_out=None):
     pick, inside = choices(model, samples)
     thr = np.array([s.threshold_mode for s in samples])
     report["all"] = {"iterations": len(samples), "model_decided": float(inside.mean()),
-                     "threshold": regret(samples, thr), "learned": regret(samples, pick)}
+                     "threshold": regret(samples, thr), "learned": regret(samples, pick),
+                     "always_full": regret(samples, fixed_modes(samples)[0]),
+                     "always_wedge": regret(samples, fixed_modes(samples)[1])}
+    tot = {g: sum(t[g] for r in report["graphs"] for t in r["end_to_end_ms"].values()) for g in GATES}
+    report["all"]["end_to_end_total_ms"] = {g: round(v, 3) for g, v in tot.items()}
     return report
 
 
