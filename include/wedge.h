@@ -28,6 +28,15 @@
  *   - A graph handle is immutable after creation; one graph must not be used by
  *     two runs at the same time (its cached workspace is shared). A run on a
  *     busy graph returns WEDGE_ERR_BUSY.
+ *
+ * Environment (read by the library; all optional)
+ *   WEDGE_MAX_DEVICE_BYTES    cap on the device memory one graph may allocate
+ *                             (exceeding it gives WEDGE_ERR_OOM).
+ *   WEDGE_BARRIER_TIMEOUT_MS  deadline of every grid-barrier wait in persistent
+ *                             launches (default 10000); a wait past it makes
+ *                             every block exit and the run return WEDGE_ERR_HIP.
+ *   WEDGE_HOST_THREADS        threads of the host-side layout build (else
+ *                             OMP_NUM_THREADS, else the hardware count).
  */
 #ifndef WEDGE_H
 #define WEDGE_H

@@ -109,21 +109,10 @@ __device__ __forceinline__ uint32_t wave_last_le(const uint32_t* __restrict__ a,
     return L + (uint32_t)(63 - __clzll(__ballot(ok)));
 }
 
-__device__ __forceinline__ bool test_bit(const uint64_t* bits, uint32_t i) {
-    return (reinterpret_cast<const uint32_t*>(bits)[i >> 5] >> (i & 31)) & 1u;
-}
-
 __device__ __forceinline__ void set_bit(uint64_t* bits, uint32_t i) {
     atomicOr(reinterpret_cast<uint32_t*>(bits) + (i >> 5), 1u << (i & 31));
 }
 
-// Destination owning in-edge position p (valid p < m): the row mask marks
-// where destination segments start; rowseg is the segment at the row start.
-__device__ __forceinline__ uint32_t dst_of(const GraphArgs& g, uint32_t p) {
-    uint32_t r = p >> 6, b = p & 63;
-    uint64_t mk = g.rowmask[r];
-    return g.nzdst[g.rowseg[r] + (uint32_t)__popcll(mk & ~1ull & mask_le((int)b))];
-}
 
 
 // Frontier transformation work of one wave (see k_translate). The wave covers
