@@ -164,7 +164,10 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     d.short_spans = L.short_spans;
     g->perm_host = L.perm;
     if (g->host_only) { *out = g; return WEDGE_OK; }
-    HIP_TRY(hipGetDevice(&g->device), "hipGetDevice");
+    {
+        const hipError_t e = hipGetDevice(&g->device);
+        if (e != hipSuccess) { delete g; return hip_fail(e, "hipGetDevice"); }
+    }
     st = WEDGE_OK;
     if (st == WEDGE_OK) st = upload(g, &d.col_off, L.col_off, stream, "col_off");
     if (st == WEDGE_OK) st = upload(g, &d.in_src, L.in_src, stream, "in_src");
@@ -181,7 +184,12 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) st = hip_fail(e, "uploading graph");
     }
-    if (st != WEDGE_OK) { free_all(g); delete g; return st; }
+    if (st != WEDGE_OK) {
+        (void)hipStreamSynchronize(stream);  // no upload may still read host data or write freed memory
+        free_all(g);
+        delete g;
+        return st;
+    }
     g->host = HostLayout{};  // device graph: drop the host copy
     *out = g;
     return WEDGE_OK;
@@ -193,24 +201,30 @@ wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontie
     Workspace& w = g->ws;
     const DevGraph& d = g->dev;
     wedge_status st;
-    if (!w.ctl) {
-        if ((st = dev_alloc(g, (void**)&w.ctl, sizeof(Ctl), "counters")) != WEDGE_OK) return st;
-        HIP_TRY(hipHostMalloc((void**)&w.ctl_host, sizeof(Ctl), hipHostMallocDefault), "pinned counters");
-        for (auto& e : w.ev) HIP_TRY(hipEventCreate(&e), "event");
-    }
-    if (need_frontier && !w.fbits) {
+    // every buffer is allocated on its own when missing, so a run after a
+    // failed (partial) allocation completes the workspace instead of using it
+    auto need = [&](void** p, size_t bytes, const char* what) -> wedge_status {
+        return *p ? WEDGE_OK : dev_alloc(g, p, bytes, what);
+    };
+    if ((st = need((void**)&w.ctl, sizeof(Ctl), "counters")) != WEDGE_OK) return st;
+    if (!w.ctl_host) HIP_TRY(hipHostMalloc((void**)&w.ctl_host, sizeof(Ctl), hipHostMallocDefault), "pinned counters");
+    for (auto& e : w.ev)
+        if (!e) HIP_TRY(hipEventCreate(&e), "event");
+    if (need_frontier) {
         w.n = d.n;
         w.m = d.m;
         const uint64_t fw = ((uint64_t)d.n + 63) / 64;
-        if ((st = dev_alloc(g, (void**)&w.fbits, fw * 8, "frontier bitmap")) != WEDGE_OK) return st;
-        HIP_TRY(hipMemset(w.fbits, 0, fw ? fw * 8 : 8), "clearing frontier bitmap");
-        if ((st = dev_alloc(g, (void**)&w.fcur, fw * 8, "current frontier bitmap")) != WEDGE_OK) return st;
-        if (d.inv && (st = dev_alloc(g, (void**)&w.val, (size_t)d.n * 4, "values")) != WEDGE_OK) return st;
-        for (int i = 0; i < 2; ++i) {
-            if ((st = dev_alloc(g, (void**)&w.flist[i], (size_t)d.n * 4, "frontier list")) != WEDGE_OK) return st;
-            if ((st = dev_alloc(g, (void**)&w.degpre[i], (size_t)d.n * 4, "degree prefix")) != WEDGE_OK) return st;
+        if (!w.fbits) {
+            if ((st = dev_alloc(g, (void**)&w.fbits, fw * 8, "frontier bitmap")) != WEDGE_OK) return st;
+            HIP_TRY(hipMemset(w.fbits, 0, fw ? fw * 8 : 8), "clearing frontier bitmap");
         }
-        if ((st = dev_alloc(g, (void**)&w.val_prev, (size_t)d.n * 4, "committed values")) != WEDGE_OK) return st;
+        if ((st = need((void**)&w.fcur, fw * 8, "current frontier bitmap")) != WEDGE_OK) return st;
+        if (d.inv && (st = need((void**)&w.val, (size_t)d.n * 4, "values")) != WEDGE_OK) return st;
+        for (int i = 0; i < 2; ++i) {
+            if ((st = need((void**)&w.flist[i], (size_t)d.n * 4, "frontier list")) != WEDGE_OK) return st;
+            if ((st = need((void**)&w.degpre[i], (size_t)d.n * 4, "degree prefix")) != WEDGE_OK) return st;
+        }
+        if ((st = need((void**)&w.val_prev, (size_t)d.n * 4, "committed values")) != WEDGE_OK) return st;
     }
     if (need_chunks) {
         const uint64_t chunks = (d.m + (1ull << log_chunk) - 1) >> log_chunk;
@@ -505,32 +519,43 @@ wedge_status ensure_batch(wedge_graph_t g, uint32_t nroots, uint32_t K) {
     Workspace& w = g->ws;
     const DevGraph& d = g->dev;
     wedge_status st;
+    // as in ensure_workspace, each buffer is (re)allocated on its own, and a
+    // capacity is only raised once its buffers exist
+    auto need = [&](void** p, size_t bytes, const char* what) -> wedge_status {
+        return *p ? WEDGE_OK : dev_alloc(g, p, bytes, what);
+    };
     if (nroots > w.roots_cap) {
         if (w.roots) { (void)hipFree(w.roots); g->device_bytes -= (uint64_t)w.roots_cap * 4; w.roots = nullptr; }
         if (w.roots_host) { (void)hipHostFree(w.roots_host); w.roots_host = nullptr; }
+        w.roots_cap = 0;
         if ((st = dev_alloc(g, (void**)&w.roots, (size_t)nroots * 4, "sources")) != WEDGE_OK) return st;
         HIP_TRY(hipHostMalloc((void**)&w.roots_host, (size_t)nroots * 4, hipHostMallocDefault), "pinned sources");
         w.roots_cap = nroots;
         w.generation++;
     }
-    if (K && !w.visited) {
-        if ((st = dev_alloc(g, (void**)&w.visited, (size_t)d.n * 8, "visited masks")) != WEDGE_OK) return st;
+    if (K && !(w.visited && w.masks[0] && w.masks[1])) {
+        if ((st = need((void**)&w.visited, (size_t)d.n * 8, "visited masks")) != WEDGE_OK) return st;
         for (int i = 0; i < 2; ++i)
-            if ((st = dev_alloc(g, (void**)&w.masks[i], (size_t)d.n * 8, "frontier masks")) != WEDGE_OK) return st;
+            if ((st = need((void**)&w.masks[i], (size_t)d.n * 8, "frontier masks")) != WEDGE_OK) return st;
         w.generation++;
     }
     if (K > w.lev_k) {
         if (w.lev) { (void)hipFree(w.lev); g->device_bytes -= (uint64_t)d.n * w.lev_k * 4; w.lev = nullptr; }
+        w.lev_k = 0;
         if ((st = dev_alloc(g, (void**)&w.lev, (size_t)d.n * K * 4, "multi-source levels")) != WEDGE_OK) return st;
         w.lev_k = K;
         w.generation++;
     }
-    if (!w.ps) {
-        if ((st = dev_alloc(g, (void**)&w.ps, sizeof(PersistState), "persistent state")) != WEDGE_OK) return st;
-        HIP_TRY(hipHostMalloc((void**)&w.ps_host, sizeof(PersistState), hipHostMallocDefault), "pinned state");
+    if (!(w.ps && w.ps_host && w.trace && w.trace_host)) {
+        if ((st = need((void**)&w.ps, sizeof(PersistState), "persistent state")) != WEDGE_OK) return st;
+        if (!w.ps_host)
+            HIP_TRY(hipHostMalloc((void**)&w.ps_host, sizeof(PersistState), hipHostMallocDefault), "pinned state");
         w.trace_cap = 4096;
-        if ((st = dev_alloc(g, (void**)&w.trace, (size_t)w.trace_cap * sizeof(wedge_iter_record), "trace")) != WEDGE_OK) return st;
-        HIP_TRY(hipHostMalloc((void**)&w.trace_host, (size_t)w.trace_cap * sizeof(wedge_iter_record), hipHostMallocDefault), "pinned trace");
+        if ((st = need((void**)&w.trace, (size_t)w.trace_cap * sizeof(wedge_iter_record), "trace")) != WEDGE_OK)
+            return st;
+        if (!w.trace_host)
+            HIP_TRY(hipHostMalloc((void**)&w.trace_host, (size_t)w.trace_cap * sizeof(wedge_iter_record),
+                                  hipHostMallocDefault), "pinned trace");
         w.generation++;
     }
     return WEDGE_OK;

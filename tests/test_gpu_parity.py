@@ -322,3 +322,53 @@ def test_repeated_runs_reuse_workspace():
                                           oracle.bfs(ro, col, int(s)))
             np.testing.assert_array_equal(W.u32(W.sssp(g, int(s), chunk=chunk)[0]),
                                           oracle.sssp(ro, col, w, int(s)))
+
+
+def device_bytes(g):
+    info = W._binding.GraphInfo()
+    W._binding.check(W._binding.lib().wedge_graph_get_info(g.handle, W._binding.C.byref(info)))
+    return info.device_bytes
+
+
+def test_device_memory_cap_fails_cleanly_and_recovers(monkeypatch):
+    """The per-graph device cap refuses creation, and a run whose workspace
+    stops part-way; once lifted, the same graph completes its workspace and
+    every result still equals the oracle."""
+    ro, col = gen.rmat(12, 16, seed=61)
+    w = gen.edge_weights(ro, col, seed=2)
+    n = len(ro) - 1
+    probe = W.Graph.from_csr(ro, col, w)
+    layout = device_bytes(probe)
+    probe.close()
+    print(f"  [cap: layout {layout} bytes, n={n}]", flush=True)
+    monkeypatch.setenv("WEDGE_MAX_DEVICE_BYTES", str(layout // 2))
+    with pytest.raises(W.WedgeError) as e:
+        W.Graph.from_csr(ro, col, w)
+    assert e.value.name == "WEDGE_ERR_OOM"
+    # room for the layout and the first few workspace buffers only
+    monkeypatch.setenv("WEDGE_MAX_DEVICE_BYTES", str(layout + 4 * n + 4096))
+    g = W.Graph.from_csr(ro, col, w)
+    assert device_bytes(g) == layout
+    for run in (lambda: W.bfs(g, 0, chunk=16), lambda: W.sssp(g, 0, chunk=16)):
+        with pytest.raises(W.WedgeError) as e:
+            run()
+        assert e.value.name == "WEDGE_ERR_OOM"
+    partial = device_bytes(g)
+    assert layout < partial <= layout + 4 * n + 4096
+    monkeypatch.delenv("WEDGE_MAX_DEVICE_BYTES")
+    np.testing.assert_array_equal(W.u32(W.bfs(g, 0, chunk=16)[0]), oracle.bfs(ro, col, 0))
+    np.testing.assert_array_equal(W.u32(W.sssp(g, 0, chunk=16)[0]), oracle.sssp(ro, col, w, 0))
+    # the multi-source buffers: the visited masks fit, the second frontier mask does not
+    full = device_bytes(g)
+    srcs = gen.pick_sources(ro, 8, seed=5)
+    monkeypatch.setenv("WEDGE_MAX_DEVICE_BYTES", str(full + 2 * 8 * n + 256))
+    with pytest.raises(W.WedgeError) as e:
+        W.bfs_multisource(g, srcs, chunk=16)
+    assert e.value.name == "WEDGE_ERR_OOM"
+    assert device_bytes(g) > full
+    monkeypatch.delenv("WEDGE_MAX_DEVICE_BYTES")
+    lv, _, _ = W.bfs_multisource(g, srcs, chunk=16)
+    lv = W.u32(lv).reshape(len(srcs), n)
+    for i, s in enumerate(srcs):
+        np.testing.assert_array_equal(lv[i], oracle.bfs(ro, col, int(s)))
+    g.close()
