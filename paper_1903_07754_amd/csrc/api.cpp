@@ -643,7 +643,6 @@ wedge_status run_persistent(wedge_graph_t g, bool ms, uint32_t count, uint32_t* 
         P.wwords = c.wwords;
         P.chunks = w.chunks;
         P.lc = c.lc;
-        P.ctl = w.ctl;
         P.ps = w.ps;
         P.trace = w.trace;
         P.trace_cap = w.trace_cap;
@@ -658,7 +657,6 @@ wedge_status run_persistent(wedge_graph_t g, bool ms, uint32_t count, uint32_t* 
         if (e == hipSuccess) e = launch_fill_u64(w.fbits, fwords, 0, cs);
         if (e == hipSuccess) e = launch_fill_u64(w.fcur, fwords, 0, cs);
         if (e == hipSuccess && c.gate != WEDGE_GATE_ALWAYS_FULL) e = launch_fill_u64(w.wbits, c.wwords, 0, cs);
-        if (e == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t*>(w.ctl), sizeof(Ctl) / 8, 0, cs);
         if (e == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t*>(w.ps), sizeof(PersistState) / 8, 0, cs);
         if (ms) {
             if (e == hipSuccess) e = launch_fill_u64(w.visited, d.n, 0, cs);

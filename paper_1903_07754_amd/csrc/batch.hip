@@ -218,32 +218,62 @@ __global__ void k_fill_u32b(uint32_t* __restrict__ p, uint64_t count, uint32_t v
 // ------------------------------------------------------- persistent kernel
 //
 // One launch runs every iteration: the blocks stride over each phase's work,
-// separated by grid-wide barriers, and block 0 evaluates the fullness gate
-// between iterations from the device counters, so no host round trip is
-// needed. The grid is sized from the occupancy API so that every block is
-// resident; each barrier wait is additionally bounded by a wall-clock
-// deadline, after which the kernel records an error and every block exits.
+// separated by grid-wide barriers. Every block takes the fullness-gate
+// decision itself from the same device counters, so the decision needs no
+// barrier of its own. The grid is sized from the occupancy API so that every
+// block is resident; each barrier wait is additionally bounded by a
+// wall-clock deadline, after which the kernel records an error and every
+// block exits.
 
-__device__ __forceinline__ unsigned ld_acq(unsigned* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned ld_rlx(unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ unsigned long long ld_counter(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_counter(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Two-level barrier: a block arrives on its group's counter (block b is in
+// group b mod G), the last block of a group arrives on the top counter, and
+// the last group advances the generation that the other blocks wait on.
+//
+// One release and one acquire per block and barrier, no more: on this part an
+// agent-scope release writes back the XCD's L2 and an acquire invalidates it,
+// so the wait polls with relaxed loads (an acquire load per poll would
+// invalidate the L2 under the blocks still at work). The generation read
+// cannot be stale (coherence of one location: this thread has seen the
+// current value, and it cannot advance before this block arrives), and the
+// release fence keeps it ahead of the arrival.
 __device__ bool grid_sync(PersistState* ps, uint64_t timeout_ticks) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        __threadfence();
-        const unsigned gen = ld_acq(&ps->bar_gen);
-        const unsigned arrived = atomicAdd(&ps->bar_count, 1u);
-        if (arrived == gridDim.x - 1) {
-            atomicExch(&ps->bar_count, 0u);
+        const unsigned gen = ld_rlx(&ps->bar_gen);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned nb = gridDim.x;
+        const unsigned groups = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
+        const unsigned grp = blockIdx.x % groups;
+        const unsigned members = (nb - grp + groups - 1) / groups;  // blocks b < nb with b % groups == grp
+        bool released = false;
+        if (atomicAdd(&ps->bar_grp[grp][0], 1u) == members - 1) {
+            atomicExch(&ps->bar_grp[grp][0], 0u);
             __threadfence();
-            atomicAdd(&ps->bar_gen, 1u);
-        } else {
+            if (atomicAdd(&ps->bar_top[0], 1u) == groups - 1) {
+                atomicExch(&ps->bar_top[0], 0u);
+                __threadfence();
+                atomicAdd(&ps->bar_gen, 1u);
+                released = true;
+            }
+        }
+        if (!released) {
             const uint64_t deadline = wall_clock64() + timeout_ticks;
-            while (ld_acq(&ps->bar_gen) == gen) {
-                if (ld_acq(&ps->error)) { ok = 0; break; }
+            while (ld_rlx(&ps->bar_gen) == gen) {
+                if (ld_rlx(&ps->error)) { ok = 0; break; }
                 if (wall_clock64() > deadline) {
                     atomicExch(&ps->error, 1u);
                     ok = 0;
@@ -252,8 +282,8 @@ __device__ bool grid_sync(PersistState* ps, uint64_t timeout_ticks) {
                 __builtin_amdgcn_s_sleep(2);
             }
         }
-        __threadfence();
-        if (ld_acq(&ps->error)) ok = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (ld_rlx(&ps->error)) ok = 0;
         s_ok = ok;
     }
     __syncthreads();
@@ -268,69 +298,68 @@ __global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
     const uint64_t gwave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     PersistState* ps = P.ps;
-    Ctl* ctl = P.ctl;
     uint64_t* ma = P.masks[0];
     uint64_t* mb = P.masks[1];
+    __shared__ unsigned long long s_a, s_b;
 
     // the seeds were written as the output of "iteration -1": list them
     for (uint64_t vb = blockIdx.x; vb < fblocks; vb += gridDim.x) {
-        if (MS) ms_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0], ctl,
-                                  P.fcur, P.visited, mb, ma, P.lev, P.K, 0u);
-        else bfs_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0], ctl,
-                                P.fcur);
+        if (MS) ms_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0],
+                                  &ps->cnt[0].c, P.fcur, P.visited, mb, ma, P.lev, P.K, 0u);
+        else bfs_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0],
+                                &ps->cnt[0].c, P.fcur);
     }
     if (!grid_sync(ps, P.timeout_ticks)) return;
 
+    unsigned prev_mode = 0;
     for (uint32_t k = 0;; ++k) {
         const int cur = k & 1;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            // close the previous iteration's record, then decide this one
-            if (k > 0 && k - 1 < P.trace_cap && ps->mode)
-                P.trace[k - 1].marked_chunks = ctl->marked >> kDegBits;
-            const unsigned long long fcount = ctl->ftotal;
-            const unsigned long long flisted = ctl->fnext >> kDegBits;
-            const unsigned long long active = ctl->fnext & kDegMask;
-            unsigned done = 0, mode = 0;
-            if (fcount == 0) {
-                done = 1;
-            } else if (k >= P.max_iters) {
-                done = 1;
-                ps->not_converged = 1;
-            } else {
-                mode = P.gate == WEDGE_GATE_ALWAYS_WEDGE ? 1u
-                     : P.gate == WEDGE_GATE_ALWAYS_FULL ? 0u
-                     : (active < P.thr ? 1u : 0u);
-                if (k < P.trace_cap) {
-                    wedge_iter_record r;
-                    r.iter = k;
-                    r.mode = mode;
-                    r.chunk_edges = mode ? (1u << P.lc) : 0u;
-                    r.reserved = 0;
-                    r.frontier = fcount;
-                    r.active_edges = active;
-                    r.marked_chunks = 0;
-                    r.ms = 0.f;
-                    r.reserved2 = 0.f;
-                    P.trace[k] = r;
-                }
-            }
-            ps->iters = k;
-            ps->done = done;
-            ps->mode = mode;
-            ps->flisted = flisted;
-            ps->active = active;
-            ctl->fnext = 0;
-            ctl->ftotal = 0;
-            ctl->marked = 0;
-            __threadfence();
+        Ctl* C = &ps->cnt[cur].c;       // counters of F_k (and this iteration's chunk count)
+        Ctl* N = &ps->cnt[cur ^ 1].c;   // counters being built for F_{k+1}
+        if (threadIdx.x == 0) {
+            s_a = ld_counter(&C->ftotal);
+            s_b = ld_counter(&C->fnext);
         }
-        if (!grid_sync(ps, P.timeout_ticks)) return;
-        if (__hip_atomic_load(&ps->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        const unsigned mode = __hip_atomic_load(&ps->mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const unsigned long long fcount = s_a;
+        const unsigned long long flisted = s_b >> kDegBits;
+        const unsigned long long active = s_b & kDegMask;
+        const bool done = fcount == 0 || k >= P.max_iters;
+        const unsigned mode = done ? 0u
+                            : P.gate == WEDGE_GATE_ALWAYS_WEDGE ? 1u
+                            : P.gate == WEDGE_GATE_ALWAYS_FULL ? 0u
+                            : (active < P.thr ? 1u : 0u);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            // N was last used by iteration k-1, which every block has finished
+            // (its reads of N came before the barriers that closed k-1): close
+            // k-1's record, then clear N for this iteration's commit, which
+            // starts only after at least one more barrier
+            if (k > 0 && k - 1 < P.trace_cap && prev_mode)
+                P.trace[k - 1].marked_chunks = ld_counter(&N->marked) >> kDegBits;
+            if (!done && k < P.trace_cap) {
+                wedge_iter_record r;
+                r.iter = k;
+                r.mode = mode;
+                r.chunk_edges = mode ? (1u << P.lc) : 0u;
+                r.reserved = 0;
+                r.frontier = fcount;
+                r.active_edges = active;
+                r.marked_chunks = 0;
+                r.ms = 0.f;
+                r.reserved2 = 0.f;
+                P.trace[k] = r;
+            }
+            if (fcount != 0 && k >= P.max_iters) ps->not_converged = 1;
+            ps->iters = k;
+            st_counter(&N->fnext, 0ull);
+            st_counter(&N->ftotal, 0ull);
+            st_counter(&N->marked, 0ull);
+        }
+        prev_mode = mode;
+        if (done) break;
         uint64_t* mcur = cur ? mb : ma;   // masks of F_k (multi-source)
         uint64_t* mnxt = cur ? ma : mb;   // masks being built for F_{k+1}
         if (mode) {
-            const unsigned long long flisted = ps->flisted, active = ps->active;
             const uint64_t twaves = (active + 64ull * kTranslateEpt - 1) / (64ull * kTranslateEpt);
             for (uint64_t w = gwave; w < twaves; w += nwaves)
                 translate_wave<kTranslateEpt>(w, P.flist[cur], P.degpre[cur], (uint32_t)flisted,
@@ -340,10 +369,12 @@ __global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
             const uint64_t cblocks = (P.wwords + kCompactWords * kWavesPerBlock - 1) / (kCompactWords * kWavesPerBlock);
             for (uint64_t vb = blockIdx.x; vb < cblocks; vb += gridDim.x)
                 bitmap_compact_block<false, false, false, kCompactWords>(
-                    vb, P.wbits, P.wwords, 0xFFFFFFFFu, nullptr, P.chunks, nullptr, &ctl->marked,
+                    vb, P.wbits, P.wwords, 0xFFFFFFFFu, nullptr, P.chunks, nullptr, &C->marked,
                     nullptr, nullptr, nullptr, nullptr);
             if (!grid_sync(ps, P.timeout_ticks)) return;
-            const uint64_t K = __hip_atomic_load(&ctl->marked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> kDegBits;
+            if (threadIdx.x == 0) s_a = ld_counter(&C->marked) >> kDegBits;
+            __syncthreads();
+            const uint64_t K = s_a;
             const uint64_t slots = chunk_slots(K, P.lc);
             for (uint64_t s0 = gwave * kPullRows; s0 < slots; s0 += nwaves * kPullRows) {
                 if (MS) {
@@ -378,10 +409,10 @@ __global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
         if (!grid_sync(ps, P.timeout_ticks)) return;
         for (uint64_t vb = blockIdx.x; vb < fblocks; vb += gridDim.x) {
             if (MS) ms_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[cur ^ 1],
-                                      P.degpre[cur ^ 1], ctl, P.fcur, P.visited, mcur, mnxt, P.lev,
+                                      P.degpre[cur ^ 1], N, P.fcur, P.visited, mcur, mnxt, P.lev,
                                       P.K, k + 1);
             else bfs_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[cur ^ 1],
-                                    P.degpre[cur ^ 1], ctl, P.fcur);
+                                    P.degpre[cur ^ 1], N, P.fcur);
         }
         if (!grid_sync(ps, P.timeout_ticks)) return;
     }

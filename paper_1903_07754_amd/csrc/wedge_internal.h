@@ -136,19 +136,30 @@ static_assert(sizeof(Ctl) == 64, "counter block layout");
 constexpr int kDegBits = 33;
 constexpr unsigned long long kDegMask = (1ull << kDegBits) - 1;
 
-// Control block of the persistent traversal kernel (device memory).
+// Control block of the persistent traversal kernel (device memory). The
+// barrier's words sit on cache lines of their own: the generation (polled by
+// every waiting block), the top-level arrival counter, and one arrival counter
+// per block group, so that arrivals of different groups do not serialise on
+// one address. Words written by plain stores (the iteration count, the
+// counter blocks) have lines of their own too. Iteration k reads its frontier
+// counters from cnt[k & 1]; its commit writes cnt[(k + 1) & 1].
+constexpr int kBarGroups = 16;
+constexpr int kLineWords = 32;  // 128-byte lines of 4-byte words
+struct alignas(128) CtlLine {
+    Ctl c;
+};
 struct PersistState {
-    unsigned bar_count;      // grid barrier arrivals
     unsigned bar_gen;        // grid barrier generation
     unsigned error;          // set when a barrier wait passed its deadline
-    unsigned done;           // traversal finished
-    unsigned mode;           // current iteration: 1 Wedge Frontier, 0 full pull
+    unsigned pad0[kLineWords - 2];
+    unsigned bar_top[kLineWords];                // [0]: groups arrived
+    unsigned bar_grp[kBarGroups][kLineWords];    // [g][0]: blocks of group g arrived
     unsigned iters;          // iterations run
     unsigned not_converged;  // stopped by max_iters with a non-empty frontier
-    unsigned pad;
-    unsigned long long flisted;  // listed frontier vertices (with out-edges)
-    unsigned long long active;   // A of the current frontier
+    unsigned pad1[kLineWords - 2];
+    CtlLine cnt[2];
 };
+static_assert(sizeof(CtlLine) == 128 && sizeof(PersistState) % 128 == 0, "persistent state layout");
 
 struct PersistParams {
     GraphArgs g;
@@ -169,7 +180,6 @@ struct PersistParams {
     uint64_t wwords;
     uint32_t* chunks;
     int lc;
-    Ctl* ctl;
     PersistState* ps;
     wedge_iter_record* trace;
     uint32_t trace_cap;
