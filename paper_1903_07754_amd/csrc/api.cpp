@@ -932,26 +932,31 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
     Workspace& w = g->ws;
     if ((st = ensure_workspace(g, 6, false, false)) != WEDGE_OK) return st;
-    if (!w.pr_sum) {
-        w.pr_tiles = (d.rows + kPrTileRows - 1) / kPrTileRows;
-        w.pr_parts = pr_epilogue_blocks(d.n);
-        if ((st = dev_alloc(g, (void**)&w.pr_sum, (size_t)d.n * 4, "PageRank sums")) != WEDGE_OK) return st;
-        if ((st = dev_alloc(g, (void**)&w.pr_contrib, (size_t)d.n * 4, "PageRank contributions")) != WEDGE_OK) return st;
-        if ((st = dev_alloc(g, (void**)&w.pr_head, w.pr_tiles * 4, "PageRank tile heads")) != WEDGE_OK) return st;
-        if ((st = dev_alloc(g, (void**)&w.pr_tail, w.pr_tiles * 4, "PageRank tile tails")) != WEDGE_OK) return st;
-        if ((st = dev_alloc(g, (void**)&w.pr_part, (size_t)w.pr_parts * 8, "PageRank partials")) != WEDGE_OK) return st;
-        if ((st = dev_alloc(g, (void**)&w.pr_d, 16, "dangling mass")) != WEDGE_OK) return st;
-        if (d.inv && (st = dev_alloc(g, (void**)&w.pr_rank, (size_t)d.n * 4, "ranks")) != WEDGE_OK) return st;
-    }
+    // each buffer is allocated on its own when missing (see ensure_workspace)
+    w.pr_tiles = (d.rows + kPrTileRows - 1) / kPrTileRows;
+    w.pr_parts = pr_epilogue_blocks(d.n);
+    auto need = [&](void** p, size_t bytes, const char* what) -> wedge_status {
+        return *p ? WEDGE_OK : dev_alloc(g, p, bytes, what);
+    };
+    if ((st = need((void**)&w.pr_sum, (size_t)d.n * 4, "PageRank sums")) != WEDGE_OK) return st;
+    if ((st = need((void**)&w.pr_contrib, (size_t)d.n * 4, "PageRank contributions")) != WEDGE_OK) return st;
+    if ((st = need((void**)&w.pr_head, w.pr_tiles * 4, "PageRank tile heads")) != WEDGE_OK) return st;
+    if ((st = need((void**)&w.pr_tail, w.pr_tiles * 4, "PageRank tile tails")) != WEDGE_OK) return st;
+    if ((st = need((void**)&w.pr_part, (size_t)w.pr_parts * 8, "PageRank partials")) != WEDGE_OK) return st;
+    if ((st = need((void**)&w.pr_d, 16, "dangling mass")) != WEDGE_OK) return st;
+    if (d.inv && (st = need((void**)&w.pr_rank, (size_t)d.n * 4, "ranks")) != WEDGE_OK) return st;
     float* rank = d.inv ? w.pr_rank : rank_dev;
     const bool time_pull = o.flags & WEDGE_RUN_TIME_PULL;
     const int cus = device_cus(g->device);
     std::vector<hipEvent_t> evs;
+    auto cleanup = [&] { for (auto ev : evs) if (ev) (void)hipEventDestroy(ev); };
     if (time_pull) {
-        evs.resize(2 * (size_t)iters);
-        for (auto& e : evs) HIP_TRY(hipEventCreate(&e), "event");
+        evs.assign(2 * (size_t)iters, nullptr);
+        for (auto& ev : evs) {
+            const hipError_t ce = hipEventCreate(&ev);
+            if (ce != hipSuccess) { ev = nullptr; cleanup(); return hip_fail(ce, "event"); }
+        }
     }
-    auto cleanup = [&] { for (auto e : evs) if (e) (void)hipEventDestroy(e); };
     // D_0 comes from the host; D_k (k >= 1) is reduced from the previous
     // epilogue's partials by the fix-up launch of iteration k
     hipError_t e = launch_pr_init(d.n, d.row_off, rank, w.pr_contrib, w.pr_sum, s);
@@ -1038,9 +1043,11 @@ wedge_status wedge_frontier_translate(wedge_graph_t g, const uint32_t* frontier_
     // compact a copy so the caller keeps the bitmap
     uint64_t* tmp = nullptr;
     HIP_TRY(hipMallocAsync((void**)&tmp, words ? words * 8 : 8, s), "scratch bitmap");
-    HIP_TRY(hipMemcpyAsync(tmp, wbits_dev, words * 8, hipMemcpyDeviceToDevice, s), "copying bitmap");
-    HIP_TRY(launch_compact_chunks(tmp, words, chunk_list_dev, w.ctl, s), "chunk compaction");
-    HIP_TRY(hipFreeAsync(tmp, s), "scratch bitmap");
+    hipError_t e = hipMemcpyAsync(tmp, wbits_dev, words * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_compact_chunks(tmp, words, chunk_list_dev, w.ctl, s);
+    const hipError_t fe = hipFreeAsync(tmp, s);
+    if (e != hipSuccess) return hip_fail(e, "chunk compaction");
+    HIP_TRY(fe, "scratch bitmap");
     HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
     HIP_TRY(hipStreamSynchronize(s), "frontier translation");
     *marked = w.ctl_host->marked >> kDegBits;

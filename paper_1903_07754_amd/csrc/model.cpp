@@ -72,12 +72,16 @@ wedge_status model_to_device(wedge_model_s* m) {
     HTRY(hipGetDevice(&dev), "hipGetDevice");
     if (m->dev_params && m->device != dev) free_device(m);
     const size_t np = (size_t)m->members * kMlpParams;
-    if (!m->dev_params) {
-        HTRY(hipMalloc((void**)&m->dev_params, np * sizeof(float)), "model parameters");
-        HTRY(hipMalloc((void**)&m->dev_lo, kMlpIn * sizeof(float)), "model envelope");
-        HTRY(hipMalloc((void**)&m->dev_hi, kMlpIn * sizeof(float)), "model envelope");
-        m->device = dev;
+    // each buffer is allocated when missing, so a failed upload is completed
+    // by the next one rather than leaving null buffers behind
+    if (!m->dev_params || !m->dev_lo || !m->dev_hi) {
         m->dirty = true;
+        if (!m->dev_params) {
+            HTRY(hipMalloc((void**)&m->dev_params, np * sizeof(float)), "model parameters");
+            m->device = dev;
+        }
+        if (!m->dev_lo) HTRY(hipMalloc((void**)&m->dev_lo, kMlpIn * sizeof(float)), "model envelope");
+        if (!m->dev_hi) HTRY(hipMalloc((void**)&m->dev_hi, kMlpIn * sizeof(float)), "model envelope");
     }
     if (m->dirty) {
         HTRY(hipMemcpy(m->dev_params, m->params.data(), np * sizeof(float), hipMemcpyHostToDevice), "model upload");

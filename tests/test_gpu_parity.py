@@ -371,4 +371,14 @@ def test_device_memory_cap_fails_cleanly_and_recovers(monkeypatch):
     lv = W.u32(lv).reshape(len(srcs), n)
     for i, s in enumerate(srcs):
         np.testing.assert_array_equal(lv[i], oracle.bfs(ro, col, int(s)))
+    # PageRank's buffers: the sums fit, the contributions do not
+    full = device_bytes(g)
+    monkeypatch.setenv("WEDGE_MAX_DEVICE_BYTES", str(full + 4 * n + 256))
+    with pytest.raises(W.WedgeError) as e:
+        W.pagerank(g, iters=5)
+    assert e.value.name == "WEDGE_ERR_OOM"
+    assert device_bytes(g) > full
+    monkeypatch.delenv("WEDGE_MAX_DEVICE_BYTES")
+    r, _ = W.pagerank(g, iters=5)
+    assert rel_l1(r.cpu().numpy(), oracle.pagerank(ro, col, 5, 0.85)) <= 1e-5
     g.close()
