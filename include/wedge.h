@@ -197,9 +197,10 @@ typedef struct {
     uint32_t trace_cap;      /* entries available at trace */
     wedge_iter_record* trace;/* host array, nullable */
     const void* model;       /* wedge_model_t for WEDGE_GATE_LEARNED, nullable */
-    uint32_t blocks_per_cu;  /* WEDGE_RUN_PERSISTENT: resident blocks of 256 threads per compute
-                                unit; 0 = as many as the kernel's occupancy allows (the value is
-                                clamped to that maximum so every block is co-resident) */
+    uint32_t blocks_per_cu;  /* WEDGE_RUN_PERSISTENT: resident blocks per compute unit (blocks
+                                of 512 threads for multi-source BFS, 768 otherwise); 0 = as many
+                                as the kernel's occupancy allows (the value is clamped to that
+                                maximum so every block is co-resident) */
     uint32_t reserved;
 } wedge_opts;
 
@@ -393,8 +394,8 @@ wedge_status wedge_bfs_batch(wedge_graph_t g, const uint32_t* srcs, uint32_t* le
 /*
  * Autotuner: times the BFS kind on this graph and these sources for every
  * combination of edges per Wedge bit {16, 32, 64}, host-driven or persistent
- * launch, and persistent blocks per compute unit {1, 2, 4, occupancy max}
- * (best of two runs each), and writes the fastest options to *best (its gate
+ * launch, and persistent blocks per compute unit (1, 2 and 4 where below the
+ * occupancy maximum, and that maximum; best of two runs each), and writes the fastest options to *best (its gate
  * and threshold are taken from *best on entry). Results do not depend on the
  * choice. out_dev is scratch output of the kind's size. The winner is also
  * kept in a process-wide table keyed by (kind, source count, ceil(log2 m)),

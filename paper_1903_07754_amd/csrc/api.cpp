@@ -1262,10 +1262,15 @@ wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs
     if (kind > WEDGE_TUNE_BATCH) return fail(WEDGE_ERR_INVALID_ARG, "unknown kind");
     const wedge_opts base = *best;
     struct Cand { uint32_t chunk, persistent, bpc; };
+    // per-CU block counts below the occupancy maximum, and the maximum (0)
+    int bpc_max = 0;
+    if (persistent_max_blocks(kind == WEDGE_TUNE_MULTISOURCE, &bpc_max) != hipSuccess) bpc_max = 0;
     std::vector<Cand> cands;
     for (uint32_t c : {16u, 32u, 64u}) {
         cands.push_back({c, 0, 0});
-        for (uint32_t b : {1u, 2u, 4u, 0u}) cands.push_back({c, 1, b});
+        for (uint32_t b : {1u, 2u, 4u})
+            if ((int)b < bpc_max) cands.push_back({c, 1, b});
+        cands.push_back({c, 1, 0});
     }
     double best_t = 1e300;
     wedge_opts win = base;

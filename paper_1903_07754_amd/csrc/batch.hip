@@ -126,11 +126,12 @@ __device__ __forceinline__ void ms_finalize_block(
         [&](uint32_t v) { retire[v] = 0ull; });
 }
 
+template <int WAVES = kWavesPerBlock>
 __device__ __forceinline__ void bfs_finalize_block(uint64_t vblock, uint64_t* bits,
                                                    uint64_t words, uint32_t n,
                                                    const uint32_t* row_off, uint32_t* list,
                                                    uint32_t* degpre, Ctl* ctl, uint64_t* fcur) {
-    bitmap_compact_block_ex<kWavesPerBlock, true, true, kCompactWords>(
+    bitmap_compact_block_ex<WAVES, true, true, kCompactWords>(
         vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
         [](uint32_t) -> uint64_t { return 0ull; }, [](uint32_t, uint64_t) {}, [](uint32_t) {});
 }
@@ -225,6 +226,13 @@ __global__ void k_fill_u32b(uint32_t* __restrict__ p, uint64_t count, uint32_t v
 // wall-clock deadline, after which the kernel records an error and every
 // block exits.
 
+// One block per CU holding all the waves the kernel's registers allow (2 per
+// SIMD with the multi-source masks, 3 single-source): the same resident waves
+// as several smaller blocks, but fewer blocks pay the per-block release at
+// every barrier.
+constexpr int kPersistWavesMs = 8;
+constexpr int kPersistWavesBfs = 12;
+
 __device__ __forceinline__ unsigned ld_rlx(unsigned* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -290,11 +298,11 @@ __device__ bool grid_sync(PersistState* ps, uint64_t timeout_ticks) {
     return s_ok != 0;
 }
 
-template <bool MS>
-__global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
+template <bool MS, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_bfs_persistent(PersistParams P) {
     const GraphArgs g = P.g;
     const uint64_t fwords = ((uint64_t)P.n + 63) / 64;
-    const uint64_t fblocks = (fwords + kCompactWords * kWavesPerBlock - 1) / (kCompactWords * kWavesPerBlock);
+    const uint64_t fblocks = (fwords + kCompactWords * WAVES - 1) / (kCompactWords * WAVES);
     const uint64_t gwave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     PersistState* ps = P.ps;
@@ -304,9 +312,9 @@ __global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
 
     // the seeds were written as the output of "iteration -1": list them
     for (uint64_t vb = blockIdx.x; vb < fblocks; vb += gridDim.x) {
-        if (MS) ms_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0],
+        if (MS) ms_finalize_block<WAVES>(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0],
                                   &ps->cnt[0].c, P.fcur, P.visited, mb, ma, P.lev, P.K, 0u);
-        else bfs_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0],
+        else bfs_finalize_block<WAVES>(vb, P.fbits, fwords, P.n, P.row_off, P.flist[0], P.degpre[0],
                                 &ps->cnt[0].c, P.fcur);
     }
     if (!grid_sync(ps, P.timeout_ticks)) return;
@@ -366,9 +374,9 @@ __global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
                                               (uint32_t)active, P.row_off, P.pos, P.lc,
                                               reinterpret_cast<uint32_t*>(P.wbits));
             if (!grid_sync(ps, P.timeout_ticks)) return;
-            const uint64_t cblocks = (P.wwords + kCompactWords * kWavesPerBlock - 1) / (kCompactWords * kWavesPerBlock);
+            const uint64_t cblocks = (P.wwords + kCompactWords * WAVES - 1) / (kCompactWords * WAVES);
             for (uint64_t vb = blockIdx.x; vb < cblocks; vb += gridDim.x)
-                bitmap_compact_block<false, false, false, kCompactWords>(
+                bitmap_compact_block<false, false, false, kCompactWords, WAVES>(
                     vb, P.wbits, P.wwords, 0xFFFFFFFFu, nullptr, P.chunks, nullptr, &C->marked,
                     nullptr, nullptr, nullptr, nullptr);
             if (!grid_sync(ps, P.timeout_ticks)) return;
@@ -408,10 +416,10 @@ __global__ __launch_bounds__(kBlock) void k_bfs_persistent(PersistParams P) {
         }
         if (!grid_sync(ps, P.timeout_ticks)) return;
         for (uint64_t vb = blockIdx.x; vb < fblocks; vb += gridDim.x) {
-            if (MS) ms_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[cur ^ 1],
+            if (MS) ms_finalize_block<WAVES>(vb, P.fbits, fwords, P.n, P.row_off, P.flist[cur ^ 1],
                                       P.degpre[cur ^ 1], N, P.fcur, P.visited, mcur, mnxt, P.lev,
                                       P.K, k + 1);
-            else bfs_finalize_block(vb, P.fbits, fwords, P.n, P.row_off, P.flist[cur ^ 1],
+            else bfs_finalize_block<WAVES>(vb, P.fbits, fwords, P.n, P.row_off, P.flist[cur ^ 1],
                                     P.degpre[cur ^ 1], N, P.fcur);
         }
         if (!grid_sync(ps, P.timeout_ticks)) return;
@@ -497,13 +505,15 @@ hipError_t launch_fill_u32_kernel(uint32_t* p, uint64_t count, uint32_t value, h
 }
 
 hipError_t persistent_max_blocks(bool ms, int* blocks_per_cu) {
-    return ms ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bfs_persistent<true>, kBlock, 0)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bfs_persistent<false>, kBlock, 0);
+    return ms ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bfs_persistent<true, kPersistWavesMs>,
+                                                             kPersistWavesMs * 64, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bfs_persistent<false, kPersistWavesBfs>,
+                                                             kPersistWavesBfs * 64, 0);
 }
 
 hipError_t launch_bfs_persistent(bool ms, const PersistParams& P, uint32_t blocks, hipStream_t s) {
-    if (ms) k_bfs_persistent<true><<<blocks, kBlock, 0, s>>>(P);
-    else k_bfs_persistent<false><<<blocks, kBlock, 0, s>>>(P);
+    if (ms) k_bfs_persistent<true, kPersistWavesMs><<<blocks, kPersistWavesMs * 64, 0, s>>>(P);
+    else k_bfs_persistent<false, kPersistWavesBfs><<<blocks, kPersistWavesBfs * 64, 0, s>>>(P);
     return hipGetLastError();
 }
 
