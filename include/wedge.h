@@ -27,7 +27,12 @@
  *     thread-local message for the last failure.
  *   - A graph handle is immutable after creation; one graph must not be used by
  *     two runs at the same time (its cached workspace is shared). A run on a
- *     busy graph returns WEDGE_ERR_BUSY.
+ *     busy graph returns WEDGE_ERR_BUSY. Different graphs may run concurrently
+ *     from different threads. Persistent runs (WEDGE_RUN_PERSISTENT) need
+ *     their whole grid resident, so the library runs them one at a time per
+ *     device within a process; a persistent run that shares the device with
+ *     another process's persistent kernels may stall until the barrier
+ *     deadline and fail.
  *
  * Environment (read by the library; all optional)
  *   WEDGE_MAX_DEVICE_BYTES    cap on the device memory one graph may allocate

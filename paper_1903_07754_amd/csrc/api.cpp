@@ -681,9 +681,18 @@ wedge_status run_persistent(wedge_graph_t g, bool ms, uint32_t count, uint32_t* 
         HIP_TRY(hipGraphInstantiate(&w.graph_exec, w.graph, nullptr, nullptr, 0), "graph instantiation");
         w.graph_key = key;
     }
-    HIP_TRY(hipGraphLaunch(w.graph_exec, s), "graph launch");
-    HIP_TRY(hipMemcpyAsync(w.ps_host, w.ps, sizeof(PersistState), hipMemcpyDeviceToHost, s), "reading state");
-    HIP_TRY(hipStreamSynchronize(s), "persistent traversal");
+    {
+        // The kernel's grid barriers need every block resident. Two persistent
+        // grids on one device could each hold part of the CUs and wait for
+        // blocks the other keeps out, so this process runs them one at a time
+        // per device.
+        static std::mutex device_mu[64];
+        std::unique_lock<std::mutex> one_at_a_time;
+        if (g->device >= 0 && g->device < 64) one_at_a_time = std::unique_lock<std::mutex>(device_mu[g->device]);
+        HIP_TRY(hipGraphLaunch(w.graph_exec, s), "graph launch");
+        HIP_TRY(hipMemcpyAsync(w.ps_host, w.ps, sizeof(PersistState), hipMemcpyDeviceToHost, s), "reading state");
+        HIP_TRY(hipStreamSynchronize(s), "persistent traversal");
+    }
     if (w.ps_host->error)
         return fail(WEDGE_ERR_HIP, "persistent traversal: a grid barrier passed its deadline "
                                    "(blocks not co-resident or WEDGE_BARRIER_TIMEOUT_MS too small)");

@@ -4,7 +4,7 @@ R-MAT scale 16 (BFS, 8 sources) and the scale-24 R-MAT and Erdos-Renyi graphs
 (BFS, SSSP, CC, PageRank) are checked against the CPU oracle computed in full:
 bit-exact for integers, per-iteration frontier size, out-degree sum and gate
 decision for one BFS and one SSSP run, and <= 1e-5 relative L1 for PageRank.
-The scale-26 PageRank case is opt-in (WEDGE_FULLSCALE=1).
+The scale-26 PageRank case (1.06B edges) runs too, printing its progress.
 """
 import time
 
