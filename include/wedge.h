@@ -206,7 +206,9 @@ typedef struct {
                                 of 512 threads for multi-source BFS, 768 otherwise); 0 = as many
                                 as the kernel's occupancy allows (the value is clamped to that
                                 maximum so every block is co-resident) */
-    uint32_t reserved;
+    uint32_t rows_per_wave;  /* host-driven BFS, multi-source and batch runs: 64-edge rows a
+                                wave pulls per step, 4, 8 or 16 (0 = 8); results do not
+                                depend on it. Other runs take 0 or 8 */
 } wedge_opts;
 
 typedef struct {
@@ -398,9 +400,10 @@ wedge_status wedge_bfs_batch(wedge_graph_t g, const uint32_t* srcs, uint32_t* le
 
 /*
  * Autotuner: times the BFS kind on this graph and these sources for every
- * combination of edges per Wedge bit {16, 32, 64}, host-driven or persistent
- * launch, and persistent blocks per compute unit (1, 2 and 4 where below the
- * occupancy maximum, and that maximum; best of two runs each), and writes the fastest options to *best (its gate
+ * combination of edges per Wedge bit {16, 32, 64} with, for the host-driven
+ * loop, rows per wave {4, 8, 16} and, for the persistent launch, blocks per
+ * compute unit (1, 2 and 4 where below the occupancy maximum, and that
+ * maximum); best of two runs each. It writes the fastest options to *best (its gate
  * and threshold are taken from *best on entry). Results do not depend on the
  * choice. out_dev is scratch output of the kind's size. The winner is also
  * kept in a process-wide table keyed by (kind, source count, ceil(log2 m)),
@@ -411,8 +414,9 @@ wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs
                             double* best_ms);
 
 /* Tuned options for (kind, count, edge count m), if wedge_tune_bfs has
- * recorded them in this process: copies chunk_edges, flags' persistent bit and
- * blocks_per_cu into *opts and returns WEDGE_OK; else WEDGE_ERR_UNSUPPORTED. */
+ * recorded them in this process: copies chunk_edges, flags' persistent bit,
+ * blocks_per_cu and rows_per_wave into *opts and returns WEDGE_OK; else
+ * WEDGE_ERR_UNSUPPORTED. */
 wedge_status wedge_tune_lookup(uint32_t kind, uint32_t count, uint64_t m, wedge_opts* opts);
 
 /* ------------------------------------------------------- single steps */

@@ -66,7 +66,7 @@ class Opts(C.Structure):
     _fields_ = [("gate", C.c_uint32), ("threshold_ppm", C.c_uint32), ("chunk_edges", C.c_uint32),
                 ("max_iters", C.c_uint32), ("flags", C.c_uint32), ("trace_cap", C.c_uint32),
                 ("trace", C.POINTER(IterRecord)), ("model", C.c_void_p),
-                ("blocks_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
+                ("blocks_per_cu", C.c_uint32), ("rows_per_wave", C.c_uint32)]
 
 
 class Stats(C.Structure):
@@ -256,13 +256,15 @@ class Graph:
 
 
 def make_opts(gate="threshold", theta_ppm=0, chunk=0, max_iters=0, time_pull=False,
-              time_iters=False, trace_cap=0, model=None, persistent=False, blocks_per_cu=0):
+              time_iters=False, trace_cap=0, model=None, persistent=False, blocks_per_cu=0,
+              rows_per_wave=0):
     o = Opts()
     o.gate = GATE[gate] if isinstance(gate, str) else int(gate)
     o.threshold_ppm, o.chunk_edges, o.max_iters = theta_ppm, chunk, max_iters
     o.flags = ((RUN_TIME_PULL if time_pull else 0) | (RUN_TIME_ITERS if time_iters else 0)
                | (RUN_PERSISTENT if persistent else 0))
     o.blocks_per_cu = blocks_per_cu
+    o.rows_per_wave = rows_per_wave
     trace = (IterRecord * trace_cap)() if trace_cap else None
     o.trace_cap = trace_cap
     o.trace = C.cast(trace, C.POINTER(IterRecord)) if trace is not None else None
@@ -305,9 +307,9 @@ def sssp(g, src, out=None, stream=None, trace_cap=0, **kw):
     return _run_int(lib().wedge_sssp, g, (src,), out, stream, trace_cap, **kw)
 
 
-def pagerank(g, iters=20, damping=0.85, out=None, stream=None, time_pull=False):
+def pagerank(g, iters=20, damping=0.85, out=None, stream=None, time_pull=False, rows_per_wave=0):
     import torch
-    o, _ = make_opts(time_pull=time_pull)
+    o, _ = make_opts(time_pull=time_pull, rows_per_wave=rows_per_wave)
     if out is None:
         out = torch.empty(max(g.n, 1), dtype=torch.float32, device="cuda")
     st = Stats()
@@ -349,7 +351,8 @@ def tune_bfs(g, kind, srcs, out, stream=None, gate="threshold", theta_ppm=0):
     check(lib().wedge_tune_bfs(g.handle, TUNE[kind], srcs.ctypes.data, len(srcs), _ptr(out),
                                _stream_handle(stream), C.byref(o), C.byref(ms)))
     best = {"chunk": o.chunk_edges, "persistent": bool(o.flags & RUN_PERSISTENT),
-            "blocks_per_cu": o.blocks_per_cu, "gate": o.gate, "theta_ppm": o.threshold_ppm}
+            "blocks_per_cu": o.blocks_per_cu, "rows_per_wave": o.rows_per_wave, "gate": o.gate,
+            "theta_ppm": o.threshold_ppm}
     return best, ms.value
 
 
@@ -359,7 +362,7 @@ def tune_lookup(kind, count, m):
     if st != OK:
         return None
     return {"chunk": o.chunk_edges, "persistent": bool(o.flags & RUN_PERSISTENT),
-            "blocks_per_cu": o.blocks_per_cu}
+            "blocks_per_cu": o.blocks_per_cu, "rows_per_wave": o.rows_per_wave}
 
 
 def frontier_translate(g, frontier, chunk, stream=None):

@@ -267,6 +267,16 @@ wedge_status check_run(wedge_graph_t g, const void* out, const wedge_opts* o) {
     if (o->trace_cap && !o->trace) return fail(WEDGE_ERR_INVALID_ARG, "trace_cap set but trace is null");
     if (o->flags & ~(WEDGE_RUN_TIME_PULL | WEDGE_RUN_TIME_ITERS | WEDGE_RUN_PERSISTENT))
         return fail(WEDGE_ERR_INVALID_ARG, "unknown run flag bits");
+    if (o->rows_per_wave && o->rows_per_wave != 4 && o->rows_per_wave != 8 && o->rows_per_wave != 16)
+        return fail(WEDGE_ERR_INVALID_ARG, "rows_per_wave must be 0, 4, 8 or 16");
+    return WEDGE_OK;
+}
+
+// Pull shapes other than the default exist for the host-driven BFS kinds only.
+wedge_status check_rows(const wedge_opts& o, bool shaped) {
+    if (o.rows_per_wave && o.rows_per_wave != (uint32_t)kPullRows && !shaped)
+        return fail(WEDGE_ERR_UNSUPPORTED,
+                    "rows_per_wave other than 8 applies to host-driven BFS, multi-source and batch runs");
     return WEDGE_OK;
 }
 
@@ -295,6 +305,7 @@ struct LoopCfg {
     double ticks_per_us = 100.0;
     uint64_t m = 0;
     uint32_t app = kBfs;       // application (a gate feature)
+    int rows = kPullRows;      // pull shape: 64-edge rows per wave step
     // the smallest chunk exponent this run may use (bitmap and list sizes)
     int min_lc() const { return learned ? std::min(lc, 4) : lc; }
     uint64_t chunks_of(int l) const { return (m + (1ull << l) - 1) >> l; }
@@ -397,6 +408,7 @@ LoopCfg loop_cfg(const wedge_opts& o, const DevGraph& d, App app, uint32_t theta
     c.thr = ((uint64_t)theta * d.m) / 1000000ull;
     c.gate = o.gate;
     c.max_iters = o.max_iters ? o.max_iters : d.n + 1;
+    c.rows = o.rows_per_wave ? (int)o.rows_per_wave : kPullRows;
     c.time_pull = o.flags & WEDGE_RUN_TIME_PULL;
     c.time_iter = o.flags & WEDGE_RUN_TIME_ITERS;
     c.nchunks = (d.m + chunk - 1) >> c.lc;
@@ -466,6 +478,7 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         return fail(WEDGE_ERR_UNSUPPORTED, "CC runs on the undirected view: create the graph with WEDGE_SYMMETRIZE");
     if (app == kBfs && (o.flags & WEDGE_RUN_PERSISTENT))
         return run_bfs_roots(g, &src, 1, val, opts_in, s, stats);
+    if ((st = check_rows(o, app == kBfs)) != WEDGE_OK) return st;
     RunGuard guard(g->busy);
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
     wedge_stats local{};
@@ -496,8 +509,8 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         g, o, c, s, local, t0, stats,
         [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
             return wedge_mode ? launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev,
-                                                   w.fcur, w.fbits, s)
-                              : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s);
+                                                   w.fcur, w.fbits, s, c.rows)
+                              : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s, c.rows);
         },
         [&](uint32_t, int cur) {
             return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
@@ -724,6 +737,7 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
     if (count && !roots) return fail(WEDGE_ERR_INVALID_ARG, "sources pointer is null");
     for (uint32_t i = 0; i < count; ++i)
         if (roots[i] >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
+    if ((st = check_rows(o, !(o.flags & WEDGE_RUN_PERSISTENT))) != WEDGE_OK) return st;
     RunGuard guard(g->busy);
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
     wedge_stats local{};
@@ -751,8 +765,8 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
             g, o, c, s, local, t0, stats,
             [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
                 return wedge_mode ? launch_pull_chunks(kBfs, d, k, lc, w.chunks, w.ctl, maxk, val,
-                                                       nullptr, w.fcur, w.fbits, s)
-                                  : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, s);
+                                                       nullptr, w.fcur, w.fbits, s, c.rows)
+                                  : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, s, c.rows);
             },
             [&](uint32_t, int cur) {
                 return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1],
@@ -779,6 +793,7 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
     if (!srcs) return fail(WEDGE_ERR_INVALID_ARG, "sources pointer is null");
     for (uint32_t i = 0; i < count; ++i)
         if (srcs[i] >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
+    if ((st = check_rows(o, !(o.flags & WEDGE_RUN_PERSISTENT))) != WEDGE_OK) return st;
     RunGuard guard(g->busy);
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
     wedge_stats local{};
@@ -811,8 +826,8 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
                 const uint64_t* mc = w.masks[k & 1];
                 uint64_t* mn = w.masks[(k & 1) ^ 1];
                 return wedge_mode ? launch_ms_pull_chunks(d, lc, w.chunks, w.ctl, maxk, all, w.visited,
-                                                          mc, mn, w.fbits, s)
-                                  : launch_ms_pull_full(d, all, w.visited, mc, mn, w.fbits, s);
+                                                          mc, mn, w.fbits, s, c.rows)
+                                  : launch_ms_pull_full(d, all, w.visited, mc, mn, w.fbits, s, c.rows);
             },
             [&](uint32_t k, int cur) {
                 return launch_ms_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1],
@@ -933,6 +948,7 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
     wedge_status st = check_run(g, rank_dev, &o);
     if (st != WEDGE_OK) return st;
     if (!(damping > 0.0f && damping < 1.0f)) return fail(WEDGE_ERR_INVALID_ARG, "damping must be in (0, 1)");
+    if ((st = check_rows(o, false)) != WEDGE_OK) return st;
     RunGuard guard(g->busy);
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
     wedge_stats local{};
@@ -1149,6 +1165,10 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
     *count = 0;
     const wedge_opts& o0 = opts_in ? *opts_in : kDefaultOpts;
     if (app < WEDGE_APP_BFS || app > WEDGE_APP_SSSP) return fail(WEDGE_ERR_INVALID_ARG, "unknown app");
+    {
+        const wedge_status rs = check_rows(o0, false);
+        if (rs != WEDGE_OK) return rs;
+    }
     wedge_opts o = o0;
     o.gate = WEDGE_GATE_THRESHOLD;
     o.flags = 0;
@@ -1270,16 +1290,22 @@ wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs
     if (!g || !srcs || !out_dev || !best) return fail(WEDGE_ERR_INVALID_ARG, "null argument");
     if (kind > WEDGE_TUNE_BATCH) return fail(WEDGE_ERR_INVALID_ARG, "unknown kind");
     const wedge_opts base = *best;
-    struct Cand { uint32_t chunk, persistent, bpc; };
-    // per-CU block counts below the occupancy maximum, and the maximum (0)
+    struct Cand { uint32_t chunk, persistent, bpc, rows; };
+    // host-driven: every pull shape; persistent: per-CU block counts below the
+    // occupancy maximum, and the maximum (0). The learned gate runs host-driven.
     int bpc_max = 0;
-    if (persistent_max_blocks(kind == WEDGE_TUNE_MULTISOURCE, &bpc_max) != hipSuccess) bpc_max = 0;
+    if (persistent_max_blocks(kind == WEDGE_TUNE_MULTISOURCE, &bpc_max) != hipSuccess) {
+        (void)hipGetLastError();
+        bpc_max = 0;
+    }
+    const bool persistent_ok = base.gate != WEDGE_GATE_LEARNED;
     std::vector<Cand> cands;
     for (uint32_t c : {16u, 32u, 64u}) {
-        cands.push_back({c, 0, 0});
+        for (uint32_t r : {4u, 8u, 16u}) cands.push_back({c, 0, 0, r});
+        if (!persistent_ok) continue;
         for (uint32_t b : {1u, 2u, 4u})
-            if ((int)b < bpc_max) cands.push_back({c, 1, b});
-        cands.push_back({c, 1, 0});
+            if ((int)b < bpc_max) cands.push_back({c, 1, b, 0});
+        cands.push_back({c, 1, 0, 0});
     }
     double best_t = 1e300;
     wedge_opts win = base;
@@ -1289,6 +1315,7 @@ wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs
         o.flags = (base.flags & ~(WEDGE_RUN_PERSISTENT | WEDGE_RUN_TIME_ITERS | WEDGE_RUN_TIME_PULL)) |
                   (cd.persistent ? WEDGE_RUN_PERSISTENT : 0u);
         o.blocks_per_cu = cd.bpc;
+        o.rows_per_wave = cd.rows;
         o.trace = nullptr;
         o.trace_cap = 0;
         double t = 1e300;
@@ -1318,6 +1345,7 @@ wedge_status wedge_tune_lookup(uint32_t kind, uint32_t count, uint64_t m, wedge_
     opts->chunk_edges = it->second.chunk_edges;
     opts->flags = (opts->flags & ~WEDGE_RUN_PERSISTENT) | (it->second.flags & WEDGE_RUN_PERSISTENT);
     opts->blocks_per_cu = it->second.blocks_per_cu;
+    opts->rows_per_wave = it->second.rows_per_wave;
     return WEDGE_OK;
 }
 

@@ -138,17 +138,19 @@ __device__ __forceinline__ void bfs_finalize_block(uint64_t vblock, uint64_t* bi
 
 // --------------------------------------------------- per-iteration kernels
 
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_ms_pull_full(GraphArgs g, uint64_t all,
                                                          const uint64_t* __restrict__ visited,
                                                          const uint64_t* __restrict__ cur,
                                                          uint64_t* __restrict__ nxt,
                                                          uint64_t* __restrict__ fbits) {
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t r0 = wave * kPullRows;
+    const uint64_t r0 = wave * R;
     if (r0 >= g.rows) return;
-    ms_pull_rows<kPullRows>(g, r0, all, visited, cur, nxt, fbits);
+    ms_pull_rows<R>(g, r0, all, visited, cur, nxt, fbits);
 }
 
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_ms_pull_chunks(GraphArgs g, int lc,
                                                            const uint32_t* __restrict__ list,
                                                            const unsigned long long* marked,
@@ -160,9 +162,9 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull_chunks(GraphArgs g, int lc,
     const uint64_t K = *marked >> kDegBits;
     const uint64_t slots = chunk_slots(K, lc);
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t s0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kPullRows;
-         s0 < slots; s0 += nwaves * kPullRows)
-        ms_pull_slots<kPullRows>(g, s0, slots, lc, list, K, all, visited, cur, nxt, fbits);
+    for (uint64_t s0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * R;
+         s0 < slots; s0 += nwaves * R)
+        ms_pull_slots<R>(g, s0, slots, lc, list, K, all, visited, cur, nxt, fbits);
 }
 
 __global__ __launch_bounds__(kCompactWaves * 64) void k_ms_finalize(uint64_t* bits, uint64_t words,
@@ -436,26 +438,49 @@ uint32_t grid_for(uint64_t threads, uint32_t cap) {
 
 // ------------------------------------------------------------- launchers
 
+template <int R>
+void ms_pull_full_rows(const DevGraph& g, uint64_t all, const uint64_t* visited, const uint64_t* cur,
+                       uint64_t* nxt, uint64_t* fbits, hipStream_t s) {
+    const uint64_t waves = (g.rows + R - 1) / R;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    k_ms_pull_full<R><<<blocks, kBlock, 0, s>>>(args_of(g), all, visited, cur, nxt, fbits);
+}
+
 hipError_t launch_ms_pull_full(const DevGraph& g, uint64_t all, const uint64_t* visited,
                                const uint64_t* cur, uint64_t* nxt, uint64_t* fbits,
-                               hipStream_t s) {
+                               hipStream_t s, int rows) {
     if (!g.rows) return hipSuccess;
-    const uint64_t waves = (g.rows + kPullRows - 1) / kPullRows;
-    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_ms_pull_full<<<blocks, kBlock, 0, s>>>(args_of(g), all, visited, cur, nxt, fbits);
+    switch (rows) {
+        case 4: ms_pull_full_rows<4>(g, all, visited, cur, nxt, fbits, s); break;
+        case kPullRows: ms_pull_full_rows<kPullRows>(g, all, visited, cur, nxt, fbits, s); break;
+        case 16: ms_pull_full_rows<16>(g, all, visited, cur, nxt, fbits, s); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
+}
+
+template <int R>
+void ms_pull_chunks_rows(const DevGraph& g, int lc, const uint32_t* list, const Ctl* ctl,
+                         uint64_t max_chunks, uint64_t all, const uint64_t* visited,
+                         const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s) {
+    uint64_t waves = (chunk_slots_count(max_chunks, lc) + R - 1) / R;
+    if (waves > 256ull * 32) waves = 256ull * 32;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    k_ms_pull_chunks<R><<<blocks, kBlock, 0, s>>>(args_of(g), lc, list, &ctl->marked, all, visited,
+                                                  cur, nxt, fbits);
 }
 
 hipError_t launch_ms_pull_chunks(const DevGraph& g, int lc, const uint32_t* list, const Ctl* ctl,
                                  uint64_t max_chunks, uint64_t all, const uint64_t* visited,
                                  const uint64_t* cur, uint64_t* nxt, uint64_t* fbits,
-                                 hipStream_t s) {
+                                 hipStream_t s, int rows) {
     if (!max_chunks) return hipSuccess;
-    uint64_t waves = (chunk_slots_count(max_chunks, lc) + kPullRows - 1) / kPullRows;
-    if (waves > 256ull * 32) waves = 256ull * 32;
-    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_ms_pull_chunks<<<blocks, kBlock, 0, s>>>(args_of(g), lc, list, &ctl->marked, all, visited,
-                                               cur, nxt, fbits);
+    switch (rows) {
+        case 4: ms_pull_chunks_rows<4>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, s); break;
+        case kPullRows: ms_pull_chunks_rows<kPullRows>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, s); break;
+        case 16: ms_pull_chunks_rows<16>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, s); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -10,7 +10,6 @@ namespace dev {
 
 constexpr int kBlock = 256;           // 4 waves
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kPullRows = 8;          // rows (64 positions each) per wave in the integer pulls
 // LDS copy of the highest-out-degree vertices' values in the full pulls
 #ifndef WEDGE_HOT_BLOCK
 #define WEDGE_HOT_BLOCK 768

@@ -552,51 +552,80 @@ hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
     return hipGetLastError();
 }
 
+// BFS pulls come in three shapes (rows per wave step); CC and SSSP in one.
+template <int R>
+uint32_t full_blocks(const DevGraph& g) {
+    const uint64_t waves = (g.rows + R - 1) / R;
+    return (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
 hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
                             const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
-                            hipStream_t s) {
+                            hipStream_t s, int rows) {
     if (!g.rows) return hipSuccess;
-    const uint64_t waves = (g.rows + kPullRows - 1) / kPullRows;
-    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (app != kBfs && rows != kPullRows) return hipErrorInvalidValue;
     GraphArgs a = args_of(g);
-    switch (app) {
-        case kBfs: k_pull_full<kBfs, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
-        case kCc: k_pull_full<kCc, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
-        default: k_pull_full<kSssp, kPullRows><<<blocks, kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
+    if (app == kBfs) {
+        switch (rows) {
+            case 4: k_pull_full<kBfs, 4><<<full_blocks<4>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
+            case 16: k_pull_full<kBfs, 16><<<full_blocks<16>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
+            case kPullRows: k_pull_full<kBfs, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (app == kCc) {
+        k_pull_full<kCc, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits);
+    } else {
+        k_pull_full<kSssp, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits);
     }
     return hipGetLastError();
 }
 
-template <int FORM>
-void launch_chunks_form(int app, uint32_t blocks, const GraphArgs& a, uint32_t iter, int lc,
+template <int APP, int R, int FORM>
+void launch_chunks_form(uint32_t blocks, const GraphArgs& a, uint32_t iter, int lc,
                         const uint32_t* list, const unsigned long long* mk, uint32_t* val,
                         const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
                         hipStream_t s) {
-    switch (app) {
-        case kBfs: k_pull_chunks<kBfs, kPullRows, FORM><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits); break;
-        case kCc: k_pull_chunks<kCc, kPullRows, FORM><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits); break;
-        default: k_pull_chunks<kSssp, kPullRows, FORM><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits); break;
-    }
+    k_pull_chunks<APP, R, FORM><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits);
+}
+
+template <int APP, int R>
+void launch_chunks_rows(uint64_t slots, const GraphArgs& a, uint32_t iter, int lc,
+                        const uint32_t* list, const unsigned long long* mk, uint32_t* val,
+                        const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
+                        hipStream_t s) {
+    uint64_t waves = (slots + R - 1) / R;
+    const uint64_t cap = 256ull * 32;  // resident waves on 256 CUs at 8 waves/SIMD
+    if (waves > cap) waves = cap;
+    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    const int form = slot_form<R>(lc);
+    if (form == kSlotsShared) launch_chunks_form<APP, R, kSlotsShared>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, s);
+    else if (form == kSlotsLong) launch_chunks_form<APP, R, kSlotsLong>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, s);
+    else launch_chunks_form<APP, R, kSlotsEach>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, s);
 }
 
 hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
                               const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
                               uint32_t* val, const uint32_t* val_prev, const uint64_t* fcur,
-                              uint64_t* fbits, hipStream_t s) {
+                              uint64_t* fbits, hipStream_t s, int rows) {
     if (!max_chunks) return hipSuccess;
+    if (app != kBfs && rows != kPullRows) return hipErrorInvalidValue;
     const uint64_t slots = log_chunk <= 6
                                ? (max_chunks + (64u >> log_chunk) - 1) / (64u >> log_chunk)
                                : max_chunks << (log_chunk - 6);
-    uint64_t waves = (slots + kPullRows - 1) / kPullRows;
-    const uint64_t cap = 256ull * 32;  // resident waves on 256 CUs at 8 waves/SIMD
-    if (waves > cap) waves = cap;
-    const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     GraphArgs a = args_of(g);
     const unsigned long long* mk = &ctl->marked;
-    const int form = slot_form<kPullRows>(log_chunk);
-    if (form == kSlotsShared) launch_chunks_form<kSlotsShared>(app, blocks, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
-    else if (form == kSlotsLong) launch_chunks_form<kSlotsLong>(app, blocks, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
-    else launch_chunks_form<kSlotsEach>(app, blocks, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
+    if (app == kBfs) {
+        switch (rows) {
+            case 4: launch_chunks_rows<kBfs, 4>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s); break;
+            case 16: launch_chunks_rows<kBfs, 16>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s); break;
+            case kPullRows: launch_chunks_rows<kBfs, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (app == kCc) {
+        launch_chunks_rows<kCc, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
+    } else {
+        launch_chunks_rows<kSssp, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
+    }
     return hipGetLastError();
 }
 
@@ -614,14 +643,17 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
     const uint32_t hot = std::min<uint32_t>(g.n, kHotVerts);
     if (cus > 0 && hot >= kHotMinVerts) {
         // resident blocks per CU at the full LDS size (the same for every graph)
-        static int per_cu = -1;
-        if (per_cu < 0) {
+        // (a function-local static: initialised once, safely across threads; a
+        // failed query leaves 0, which selects the plain kernel)
+        static const int per_cu = [] {
             int b = 0;
-            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &b, k_pr_pull_hot<kPrTileRows>, kHotBlock, (kHotVerts + 8) * sizeof(float));
-            if (e != hipSuccess) return e;
-            per_cu = b;
-        }
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_pr_pull_hot<kPrTileRows>, kHotBlock,
+                                                             (kHotVerts + 8) * sizeof(float)) != hipSuccess) {
+                (void)hipGetLastError();
+                return 0;
+            }
+            return b;
+        }();
         const uint64_t blocks = (uint64_t)cus * (uint64_t)per_cu;
         // the LDS copy pays off once every wave has several tiles to stride over
         if (per_cu > 0 && tiles >= 4 * blocks * (kHotBlock / 64)) {

@@ -17,6 +17,7 @@ namespace wedge {
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kWave = 64;
+constexpr int kPullRows = 8;         // default rows (64 positions each) per wave in the integer pulls
 constexpr uint32_t kPrTileRows = 8;  // PageRank pull tile: 8 rows of 64 in-edge positions
 constexpr uint32_t kPrShortSpan = 8; // spans over at most this many extra tiles are fixed up per lane
 
@@ -109,8 +110,8 @@ inline uint64_t chunk_slots_count(uint64_t K, int lc) {
 // Learned-gate sizes: 8 features -> 32 -> 32 -> 4 predicted log-times.
 constexpr int kMlpIn = 8, kMlpHidden = 32, kMlpOut = 4;
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
-                           kMlpOut * kMlpHidden + kMlpOut;
-constexpr uint32_t kMlpMaxMembers = 8;  // ensemble size limit  // 1476
+                           kMlpOut * kMlpHidden + kMlpOut;  // 1476
+constexpr uint32_t kMlpMaxMembers = 8;  // ensemble size limit
 
 // Decision state of the device-side gate, carried across iterations.
 struct GateState {
@@ -293,13 +294,15 @@ hipError_t launch_translate(const uint32_t* flist, const uint32_t* degpre, uint3
                             int log_chunk, uint64_t* wbits, hipStream_t s);
 hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list, Ctl* ctl,
                                  hipStream_t s);
+// rows: 64-edge rows per wave step, 4, 8 or 16 for BFS, 8 for CC and SSSP
+// (anything else returns hipErrorInvalidValue before any launch).
 hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
                             const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
-                            hipStream_t s);
+                            hipStream_t s, int rows = kPullRows);
 hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
                               const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
                               uint32_t* val, const uint32_t* val_prev, const uint64_t* fcur,
-                              uint64_t* fbits, hipStream_t s);
+                              uint64_t* fbits, hipStream_t s, int rows = kPullRows);
 // Lists the next-frontier bitmap (with out-degree prefix), commits val to
 // val_prev for listed vertices (when val_prev is set), moves the bitmap into
 // fcur (when set) and clears it.
@@ -321,10 +324,12 @@ hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* 
 uint32_t pr_epilogue_blocks(uint32_t n);
 // Batched BFS (batch.hip)
 hipError_t launch_ms_pull_full(const DevGraph& g, uint64_t all, const uint64_t* visited,
-                               const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s);
+                               const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s,
+                               int rows = kPullRows);
 hipError_t launch_ms_pull_chunks(const DevGraph& g, int lc, const uint32_t* list, const Ctl* ctl,
                                  uint64_t max_chunks, uint64_t all, const uint64_t* visited,
-                                 const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s);
+                                 const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s,
+                                 int rows = kPullRows);
 // Commit of a multi-source iteration (see ms_finalize_block); `retire` holds
 // the masks of the frontier being replaced, `nxt` those just built.
 hipError_t launch_ms_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,

@@ -97,6 +97,51 @@ def test_batch_equals_per_part_bfs(persistent, keep_ids):
     assert [r["frontier"] for r in tr] == F
 
 
+@pytest.mark.parametrize("rows", [4, 16])
+def test_pull_shapes_give_identical_results(rows):
+    """Every pull shape (rows per wave step) gives the oracle's levels and the
+    default shape's per-iteration records, for each BFS kind, over chunk sizes
+    whose chunk-list reads take each of the three slot forms."""
+    ro, col = gen.rmat(13, 16, seed=67)
+    g = W.Graph.from_csr(ro, col)
+    srcs = gen.pick_sources(ro, 9, seed=14)
+    want = np.stack([oracle.bfs(ro, col, int(s)) for s in srcs])
+    keys = ("frontier", "active_edges", "mode", "marked_chunks", "chunk_edges")
+    print(f"  [pull shape rows={rows}]", flush=True)
+    for chunk in (1, 16, 128):
+        for gate in ("threshold", "wedge", "full"):
+            a, _, ta = W.bfs(g, int(srcs[0]), trace_cap=64, gate=gate, chunk=chunk)
+            b, _, tb = W.bfs(g, int(srcs[0]), trace_cap=64, gate=gate, chunk=chunk, rows_per_wave=rows)
+            np.testing.assert_array_equal(W.u32(b), want[0])
+            assert [[r[k] for k in keys] for r in ta] == [[r[k] for k in keys] for r in tb]
+            lv, _, _ = W.bfs_multisource(g, srcs, gate=gate, chunk=chunk, rows_per_wave=rows)
+            np.testing.assert_array_equal(lv.cpu().numpy().view(np.uint32), want)
+    parts, bsrcs = make_parts(20, 9)
+    gb = W.Graph.from_batch_csr(parts)
+    first = gb.parts()
+    got = W.u32(W.bfs_batch(gb, bsrcs, rows_per_wave=rows)[0])
+    for i, (r, c) in enumerate(parts):
+        np.testing.assert_array_equal(got[first[i]:first[i + 1]], oracle.bfs(r, c, int(bsrcs[i])))
+
+
+def test_pull_shape_errors():
+    ro, col = gen.rmat(10, 16, seed=68)
+    w = gen.edge_weights(ro, col, seed=3)
+    g = W.Graph.from_csr(ro, col, w)
+    gs = W.Graph.from_csr(ro, col, symmetrize=True)
+    cases = [(lambda: W.bfs(g, 0, rows_per_wave=5), "WEDGE_ERR_INVALID_ARG"),
+             (lambda: W.bfs(g, 0, rows_per_wave=16, persistent=True), "WEDGE_ERR_UNSUPPORTED"),
+             (lambda: W.sssp(g, 0, rows_per_wave=4), "WEDGE_ERR_UNSUPPORTED"),
+             (lambda: W.cc(gs, rows_per_wave=16), "WEDGE_ERR_UNSUPPORTED"),
+             (lambda: W.pagerank(g, iters=2, rows_per_wave=4), "WEDGE_ERR_UNSUPPORTED")]
+    for run, name in cases:
+        with pytest.raises(W.WedgeError) as e:
+            run()
+        assert e.value.name == name
+    # the default shape, spelled out, is accepted everywhere
+    np.testing.assert_array_equal(W.u32(W.sssp(g, 0, rows_per_wave=8)[0]), oracle.sssp(ro, col, w, 0))
+
+
 def test_persistent_bfs_matches_host_driven_records():
     ro, col = gen.rmat(14, 16, seed=63)
     g = W.Graph.from_csr(ro, col)
@@ -157,10 +202,12 @@ def test_autotuner_picks_a_candidate_and_results_hold():
     out = torch.empty(64 * g.n, dtype=torch.int32, device="cuda")
     best, ms = W.tune_bfs(g, "multisource", srcs, out)
     assert best["chunk"] in (16, 32, 64) and best["blocks_per_cu"] in (0, 1, 2, 4)
+    assert best["rows_per_wave"] in ((0,) if best["persistent"] else (4, 8, 16))
     assert ms > 0
-    assert W.tune_lookup("multisource", 64, g.m) == {k: best[k] for k in ("chunk", "persistent", "blocks_per_cu")}
+    keys = ("chunk", "persistent", "blocks_per_cu", "rows_per_wave")
+    assert W.tune_lookup("multisource", 64, g.m) == {k: best[k] for k in keys}
     lv, _, _ = W.bfs_multisource(g, srcs, chunk=best["chunk"], persistent=best["persistent"],
-                                 blocks_per_cu=best["blocks_per_cu"])
+                                 blocks_per_cu=best["blocks_per_cu"], rows_per_wave=best["rows_per_wave"])
     want = np.stack([oracle.bfs(ro, col, int(s)) for s in srcs])
     np.testing.assert_array_equal(lv.cpu().numpy().view(np.uint32), want)
 
