@@ -400,12 +400,34 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
         // destination is committed at most once per wave (a hub spanning many
         // rows would otherwise send one atomic per row to the same address).
         uint32_t x[R], cur[R];
+        if (!ROWS) {
+            // Pull over marked chunks: most sources of a marked chunk are
+            // inactive, so test the source's frontier bit (a 1-bit gather from
+            // an L2-resident bitmap) and gather the value of active sources
+            // only; inactive ones read one shared address. Any superset of the
+            // active edges gives the same result (reading 1). The full pull
+            // gathers without the test: there most sources are active and the
+            // bit only adds a dependent load.
+            uint32_t fw[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) x[i] = val_prev[u[i]];
+            for (int i = 0; i < R; ++i) fw[i] = reinterpret_cast<const uint32_t*>(fcur)[u[i] >> 5];
 #pragma unroll
-        for (int i = 0; i < R; ++i) cur[i] = val[valid[i] ? dst[i] : 0u];
+            for (int i = 0; i < R; ++i) cur[i] = val[valid[i] ? dst[i] : 0u];
+            bool act[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) x[i] = valid[i] ? x[i] : kInf;
+            for (int i = 0; i < R; ++i) act[i] = valid[i] & (((fw[i] >> (u[i] & 31)) & 1u) != 0u);
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[i] = val_prev[act[i] ? u[i] : 0u];
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[i] = act[i] ? x[i] : kInf;
+        } else {
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[i] = val_prev[u[i]];
+#pragma unroll
+            for (int i = 0; i < R; ++i) cur[i] = val[valid[i] ? dst[i] : 0u];
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[i] = valid[i] ? x[i] : kInf;
+        }
         uint32_t carry = kInf;
         bool first_shared = true, last_shared = true, lane0_first = true;
         if (ROWS) {
