@@ -309,16 +309,24 @@ wedge_status wedge_model_create_ensemble(uint64_t seed, uint32_t members, wedge_
 /* Number of ensemble members of m. */
 wedge_status wedge_model_members(wedge_model_t m, uint32_t* members);
 wedge_status wedge_model_free(wedge_model_t m);
-/* Versioned binary file: magic "WEDGEMLP", version, shape, envelope, 1476
- * parameters per member, FNV-1a-64 checksum (version 3: member count in the
- * header; version 2 files, one MLP, still load). Load returns WEDGE_ERR_MODEL for a missing,
- * truncated, corrupt or mismatched file. */
+/* Versioned binary file: magic "WEDGEMLP", version, shape, member count,
+ * decision margin, envelope, 1476 parameters per member, FNV-1a-64 checksum
+ * (version 4; version 3 files without the margin and version 2 files with
+ * one MLP still load, with margin 0). Load returns WEDGE_ERR_MODEL for a
+ * missing, truncated, corrupt or mismatched file. */
 wedge_status wedge_model_load(const char* path, wedge_model_t* out);
 wedge_status wedge_model_save(wedge_model_t m, const char* path);
 /* Copy the 1476 x members parameters (per member W1[32x8] b1 W2[32x32] b2
  * W3[4x32] b3, row-major; members one after another) out (set = 0) or in
  * (set = 1); count must equal 1476 x members. */
 wedge_status wedge_model_params(wedge_model_t m, float* params, uint32_t count, int set);
+/* Decision margin (>= 0, default 0), read (set = 0) or written (set = 1).
+ * Inside the envelope the learned gate takes the model's choice (the argmin
+ * of the members' mean predicted log-times) only when its predicted time is
+ * below that of the threshold rule's choice by more than the margin;
+ * otherwise it keeps the threshold rule's decision. 0 = the plain argmin.
+ * WEDGE_ERR_INVALID_ARG for a negative or non-finite margin. */
+wedge_status wedge_model_margin(wedge_model_t m, float* margin, int set);
 /* Copy the per-feature envelope lo[8], hi[8] out (set = 0) or in (set = 1). */
 wedge_status wedge_model_envelope(wedge_model_t m, float* lo, float* hi, int set);
 /* Features of samples (host): x[count*8]. */

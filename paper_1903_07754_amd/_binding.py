@@ -120,6 +120,7 @@ def lib():
     L.wedge_model_save.argtypes = [vp, C.c_char_p]
     L.wedge_model_params.argtypes = [vp, vp, u32, C.c_int]
     L.wedge_model_envelope.argtypes = [vp, vp, vp, C.c_int]
+    L.wedge_model_margin.argtypes = [vp, C.POINTER(C.c_float), C.c_int]
     L.wedge_model_features.argtypes = [vp, u32, vp]
     L.wedge_model_predict.argtypes = [vp, vp, u32, vp, vp]
     L.wedge_model_grad.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp]
@@ -137,7 +138,7 @@ def lib():
                  "wedge_bfs_batch", "wedge_tune_bfs", "wedge_tune_lookup", "wedge_model_create",
                  "wedge_model_create_ensemble", "wedge_model_members",
                  "wedge_model_free", "wedge_model_load", "wedge_model_save", "wedge_model_params",
-                 "wedge_model_envelope", "wedge_model_features", "wedge_model_predict",
+                 "wedge_model_envelope", "wedge_model_margin", "wedge_model_features", "wedge_model_predict",
                  "wedge_model_grad", "wedge_model_train", "wedge_trace_counterfactual"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -435,6 +436,12 @@ class Model:
         else:
             check(lib().wedge_model_envelope(self._h, a.ctypes.data, b.ctypes.data, 0))
         return a, b
+
+    def margin(self, value=None):
+        """The decision margin over the threshold rule (set it when value is given)."""
+        v = C.c_float(0.0 if value is None else value)
+        check(lib().wedge_model_margin(self._h, C.byref(v), 0 if value is None else 1))
+        return v.value
 
     def predict(self, x, stream=None):
         x = np.ascontiguousarray(x, np.float32)

@@ -302,6 +302,7 @@ struct LoopCfg {
     uint32_t members = 1;
     const float* lo = nullptr;
     const float* hi = nullptr;
+    float margin = 0.f;
     double ticks_per_us = 100.0;
     uint64_t m = 0;
     uint32_t app = kBfs;       // application (a gate feature)
@@ -317,7 +318,7 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
     Workspace& w = g->ws;
     const DevGraph& d = g->dev;
     if (c.learned)
-        HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr, (uint32_t)c.lc,
+        HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, c.margin, w.ctl, (double)d.n, (double)d.m, c.thr, (uint32_t)c.lc,
                                  c.ticks_per_us, c.app, s), "gate inference");
     HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
     HIP_TRY(hipStreamSynchronize(s), "initialising run");
@@ -361,7 +362,7 @@ wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hip
         HIP_TRY(fin(k, cur), "frontier finalisation");
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
         if (c.learned)
-            HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, w.ctl, (double)d.n, (double)d.m, c.thr,
+            HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, c.margin, w.ctl, (double)d.n, (double)d.m, c.thr,
                                      (uint32_t)c.lc, c.ticks_per_us, c.app, s), "gate inference");
         HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
         HIP_TRY(hipStreamSynchronize(s), "iteration");
@@ -422,6 +423,7 @@ LoopCfg loop_cfg(const wedge_opts& o, const DevGraph& d, App app, uint32_t theta
             c.members = md->members;
             c.lo = md->dev_lo;
             c.hi = md->dev_hi;
+            c.margin = md->margin;
         }
     }
     return c;
@@ -446,6 +448,7 @@ wedge_status prepare_gate(wedge_graph_t g, const wedge_opts& o, LoopCfg* c) {
         c->members = md->members;
         c->lo = md->dev_lo;
         c->hi = md->dev_hi;
+        c->margin = md->margin;
     }
     return WEDGE_OK;
 }

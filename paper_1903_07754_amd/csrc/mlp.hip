@@ -190,19 +190,24 @@ __global__ void k_gate_stamp(Ctl* ctl) {
     }
 }
 
-__global__ void k_mlp_infer(const float* __restrict__ P, uint32_t members,
-                            const float* __restrict__ env_lo,
-                            const float* __restrict__ env_hi, Ctl* ctl,
-                            double n, double m, uint64_t thr, uint32_t fallback_lc,
-                            double ticks_per_us, uint32_t app) {
+// One wave per ensemble member (block of 64 x members threads), so the
+// members' three dependent layers run side by side rather than one after
+// another; the outputs are summed in member order, as before.
+__global__ __launch_bounds__(64 * kMlpMaxMembers) void k_mlp_infer(
+    const float* __restrict__ P, uint32_t members, const float* __restrict__ env_lo,
+    const float* __restrict__ env_hi, float margin, Ctl* ctl, double n, double m, uint64_t thr,
+    uint32_t fallback_lc, double ticks_per_us, uint32_t app) {
     GateState* gs = &ctl->gate;
-    __shared__ float h1[kMlpHidden], h2[kMlpHidden], xs[kMlpIn];
+    __shared__ float h1[kMlpMaxMembers][kMlpHidden], h2[kMlpMaxMembers][kMlpHidden];
+    __shared__ float out[kMlpMaxMembers][kMlpOut];
+    __shared__ float xs[kMlpIn];
     __shared__ int s_in;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const uint32_t e = threadIdx.x >> 6;
     const uint64_t now = wall_clock64();
     const double fcount = (double)ctl->ftotal;
     const unsigned long long active = ctl->fnext & kDegMask;
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         const double prev_us = gs->stamp ? (double)(now - gs->stamp) / ticks_per_us : 0.0;
         float x[kMlpIn];
         make_features(x, fcount, (double)active, n, m, (double)gs->k, prev_us, (double)gs->prev_mode,
@@ -215,39 +220,49 @@ __global__ void k_mlp_infer(const float* __restrict__ P, uint32_t members,
         s_in = in;
     }
     __syncthreads();
-    // the ensemble's summed outputs (argmin of the sum = argmin of the mean)
-    float acc[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
-    if (s_in) {
-        for (uint32_t e = 0; e < members; ++e) {
-            const float* Q = P + (size_t)e * kMlpParams;
-            if (lane < kMlpHidden) {
-                float a = Q[kB1 + lane];
-                for (int i = 0; i < kMlpIn; ++i) a += Q[kW1 + lane * kMlpIn + i] * xs[i];
-                h1[lane] = a > 0.f ? a : 0.f;
-            }
-            __syncthreads();
-            if (lane < kMlpHidden) {
-                float a = Q[kB2 + lane];
-                for (int i = 0; i < kMlpHidden; ++i) a += Q[kW2 + lane * kMlpHidden + i] * h1[i];
-                h2[lane] = a > 0.f ? a : 0.f;
-            }
-            __syncthreads();
-            if (lane == 0)
-                for (int j = 0; j < kMlpOut; ++j) {
-                    float a = Q[kB3 + j];
-                    for (int i = 0; i < kMlpHidden; ++i) a += Q[kW3 + j * kMlpHidden + i] * h2[i];
-                    acc[j] += a;
-                }
-            __syncthreads();
-        }
+    const bool run = s_in && e < members;
+    const float* Q = P + (size_t)(run ? e : 0) * kMlpParams;
+    if (run && lane < kMlpHidden) {
+        float a = Q[kB1 + lane];
+        for (int i = 0; i < kMlpIn; ++i) a += Q[kW1 + lane * kMlpIn + i] * xs[i];
+        h1[e][lane] = a > 0.f ? a : 0.f;
     }
-    if (lane == 0) {
+    __syncthreads();
+    if (run && lane < kMlpHidden) {
+        float a = Q[kB2 + lane];
+        for (int i = 0; i < kMlpHidden; ++i) a += Q[kW2 + lane * kMlpHidden + i] * h1[e][i];
+        h2[e][lane] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    if (run && lane < kMlpOut) {
+        float a = Q[kB3 + lane];
+        for (int i = 0; i < kMlpHidden; ++i) a += Q[kW3 + lane * kMlpHidden + i] * h2[e][i];
+        out[e][lane] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // the ensemble's summed outputs (argmin of the sum = argmin of the mean)
+        float acc[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
+        if (s_in)
+            for (uint32_t k = 0; k < members; ++k)
+                for (int j = 0; j < kMlpOut; ++j) acc[j] += out[k][j];
         uint32_t mode = 0, lc = fallback_lc;
         if (s_in) {
-            float best = 0.f;
-            for (int j = 0; j < kMlpOut; ++j)
-                if (j == 0 || acc[j] < best) { best = acc[j]; mode = j; }
-            lc = mode ? 3 + mode : fallback_lc;  // modes 1, 2, 3 = 16, 32, 64 edges per bit
+            // the model's choice (argmin, ties to the lower index) replaces the
+            // threshold rule's only when its predicted mean log-time is lower
+            // than that of the rule's choice by more than the margin
+            uint32_t jb = 0;
+            for (int j = 1; j < kMlpOut; ++j)
+                if (acc[j] < acc[jb]) jb = j;
+            const bool thr_wedge = active < thr;
+            const uint32_t jt = thr_wedge ? mode_of_lc(fallback_lc) : 0u;
+            if (jb != jt && acc[jt] - acc[jb] > margin * (float)members) {
+                mode = jb;
+                lc = mode ? 3 + mode : fallback_lc;  // modes 1, 2, 3 = 16, 32, 64 edges per bit
+            } else {
+                mode = jt;
+                lc = fallback_lc;
+            }
             gs->learned++;
         } else {
             mode = active < thr ? 1u : 0u;         // the threshold rule
@@ -284,9 +299,10 @@ hipError_t launch_adam(float* P, float* G, float* M1, float* M2, float lr, float
 }
 
 hipError_t launch_mlp_infer(const float* P, uint32_t members, const float* lo, const float* hi,
-                            Ctl* ctl, double n, double m, uint64_t thr, uint32_t fallback_lc,
-                            double ticks_per_us, uint32_t app, hipStream_t s) {
-    k_mlp_infer<<<1, 64, 0, s>>>(P, members, lo, hi, ctl, n, m, thr, fallback_lc, ticks_per_us, app);
+                            float margin, Ctl* ctl, double n, double m, uint64_t thr,
+                            uint32_t fallback_lc, double ticks_per_us, uint32_t app, hipStream_t s) {
+    const uint32_t waves = P ? (members < 1 ? 1u : members > kMlpMaxMembers ? kMlpMaxMembers : members) : 1u;
+    k_mlp_infer<<<1, 64 * waves, 0, s>>>(P, waves, lo, hi, margin, ctl, n, m, thr, fallback_lc, ticks_per_us, app);
     return hipGetLastError();
 }
 

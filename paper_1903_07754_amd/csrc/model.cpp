@@ -15,7 +15,7 @@ using namespace wedge;
 namespace {
 
 constexpr char kMagic[8] = {'W', 'E', 'D', 'G', 'E', 'M', 'L', 'P'};
-constexpr uint32_t kVersion = 3;  // 3: ensemble (member count in the header); 2: one MLP
+constexpr uint32_t kVersion = 4;  // 4: + decision margin; 3: ensemble (member count); 2: one MLP
 
 wedge_status err(wedge_status st, const std::string& m) { return set_error(st, m); }
 
@@ -134,6 +134,17 @@ wedge_status wedge_model_create(uint64_t seed, wedge_model_t* out) {
     return wedge_model_create_ensemble(seed, 1, out);
 }
 
+wedge_status wedge_model_margin(wedge_model_t m, float* margin, int set) {
+    if (!m || !margin) return err(WEDGE_ERR_INVALID_ARG, "null argument");
+    if (set) {
+        if (!std::isfinite(*margin) || *margin < 0.f) return err(WEDGE_ERR_INVALID_ARG, "margin must be finite and >= 0");
+        m->margin = *margin;
+    } else {
+        *margin = m->margin;
+    }
+    return WEDGE_OK;
+}
+
 wedge_status wedge_model_members(wedge_model_t m, uint32_t* members) {
     if (!m || !members) return err(WEDGE_ERR_INVALID_ARG, "null argument");
     *members = m->members;
@@ -176,8 +187,10 @@ wedge_status wedge_model_save(wedge_model_t m, const char* path) {
         const unsigned char* c = static_cast<const unsigned char*>(p);
         buf.insert(buf.end(), c, c + n);
     };
-    const uint32_t hdr[6] = {kVersion, (uint32_t)kMlpParams, (uint32_t)kMlpIn, (uint32_t)kMlpHidden,
-                             (uint32_t)kMlpOut, m->members};
+    uint32_t margin_bits;
+    std::memcpy(&margin_bits, &m->margin, 4);
+    const uint32_t hdr[7] = {kVersion, (uint32_t)kMlpParams, (uint32_t)kMlpIn, (uint32_t)kMlpHidden,
+                             (uint32_t)kMlpOut, m->members, margin_bits};
     put(kMagic, 8);
     put(hdr, sizeof hdr);
     put(m->lo.data(), kMlpIn * sizeof(float));
@@ -205,15 +218,19 @@ wedge_status wedge_model_load(const char* path, wedge_model_t* out) {
     std::fclose(f);
     if (buf.size() < 8 + 5 * 4 || std::memcmp(buf.data(), kMagic, 8) != 0)
         return err(WEDGE_ERR_MODEL, "not a model file");
-    uint32_t hdr[6] = {0, 0, 0, 0, 0, 1};
+    uint32_t hdr[7] = {0, 0, 0, 0, 0, 1, 0};
     std::memcpy(hdr, buf.data() + 8, 5 * 4);
-    // version 2 files hold one MLP and a five-word header
-    const size_t hwords = hdr[0] == 2 ? 5 : 6;
-    if (hdr[0] == kVersion && buf.size() >= 8 + 6 * 4) std::memcpy(hdr, buf.data() + 8, 6 * 4);
-    if ((hdr[0] != kVersion && hdr[0] != 2) || hdr[1] != (uint32_t)kMlpParams ||
+    // header words by version: 2 = five (one MLP), 3 = six (+ members),
+    // 4 = seven (+ decision margin); older files load with margin 0
+    const size_t hwords = hdr[0] == 2 ? 5 : hdr[0] == 3 ? 6 : 7;
+    if ((hdr[0] == 3 || hdr[0] == 4) && buf.size() >= 8 + hwords * 4) std::memcpy(hdr, buf.data() + 8, hwords * 4);
+    if (hdr[0] < 2 || hdr[0] > kVersion || hdr[1] != (uint32_t)kMlpParams ||
         hdr[2] != (uint32_t)kMlpIn || hdr[3] != (uint32_t)kMlpHidden || hdr[4] != (uint32_t)kMlpOut ||
         hdr[5] < 1 || hdr[5] > kMlpMaxMembers)
         return err(WEDGE_ERR_MODEL, "model version or shape mismatch");
+    float margin = 0.f;
+    std::memcpy(&margin, &hdr[6], 4);
+    if (!std::isfinite(margin) || margin < 0.f) return err(WEDGE_ERR_MODEL, "model has an invalid margin");
     const size_t np = (size_t)hdr[5] * kMlpParams;
     const size_t want = 8 + hwords * 4 + 2 * kMlpIn * 4 + np * 4 + 8;
     if (buf.size() != want) return err(WEDGE_ERR_MODEL, "model file has the wrong size");
@@ -223,6 +240,7 @@ wedge_status wedge_model_load(const char* path, wedge_model_t* out) {
     auto* m = new wedge_model_s();
     const unsigned char* p = buf.data() + 8 + hwords * 4;
     m->members = hdr[5];
+    m->margin = margin;
     m->lo.resize(kMlpIn);
     m->hi.resize(kMlpIn);
     m->params.resize(np);

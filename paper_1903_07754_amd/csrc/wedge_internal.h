@@ -244,6 +244,7 @@ struct wedge_model_s {
     uint32_t members = 1;        // ensemble size (1 .. kMlpMaxMembers)
     std::vector<float> params;   // members x kMlpParams, each W1 b1 W2 b2 W3 b3 (row-major out x in)
     std::vector<float> lo, hi;   // per-feature envelope
+    float margin = 0.f;          // decision margin over the threshold rule (mean log-time units)
     float* dev_params = nullptr;
     float* dev_lo = nullptr;
     float* dev_hi = nullptr;
@@ -354,8 +355,8 @@ hipError_t launch_adam(float* P, float* G, float* M1, float* M2, float lr, float
                        float eps, uint32_t step, hipStream_t s);
 // P null: the threshold rule decides (no model)
 hipError_t launch_mlp_infer(const float* P, uint32_t members, const float* lo, const float* hi,
-                            Ctl* ctl, double n, double m, uint64_t thr, uint32_t fallback_lc,
-                            double ticks_per_us, uint32_t app, hipStream_t s);
+                            float margin, Ctl* ctl, double n, double m, uint64_t thr,
+                            uint32_t fallback_lc, double ticks_per_us, uint32_t app, hipStream_t s);
 hipError_t launch_gate_stamp(Ctl* ctl, hipStream_t s);
 // Host form of the gate features (same formula as the device).
 void mlp_features(float* x, double fcount, double active, double n, double m, double k,

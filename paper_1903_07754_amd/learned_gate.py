@@ -6,7 +6,10 @@ Fullness Threshold): for every iteration of BFS, CC and SSSP on a corpus of
 seeded R-MAT and Erdos-Renyi graphs of scales 18-22, the library times the
 iteration in all four modes (full pull; Wedge Frontier at 16, 32, 64 edges per
 bit) from the same state. Training and inference run in the library's HIP
-kernels; this module only drives them. Evaluation uses held-out scale-24
+kernels; this module only drives them. The gate departs from the threshold
+rule only where the model predicts a gain above a decision margin, chosen by
+training on the corpus scales up to 20 and measuring regret at scale 22 (the
+same two-scale gap as from the corpus to the evaluation graphs). Evaluation uses held-out scale-24
 graphs: regret against the per-iteration best mode, and end-to-end GTEPS of
 real runs under the learned gate and under the threshold rule.
 
@@ -111,14 +114,21 @@ def collect(count=200, first_seed=1000, apps=APPS):
     return concat(chunks)
 
 
-def choices(model, samples):
-    """Mode index the learned gate picks per sample (threshold rule outside the envelope)."""
+def choices(model, samples, margin=None):
+    """Mode index the learned gate picks per sample, as the device does: the
+    threshold rule's choice outside the envelope, and inside it unless the
+    model's argmin is predicted faster than that choice by more than the
+    margin (the model's own unless given)."""
     x = B.features(samples)
     y = model.predict(x)
     lo, hi = model.envelope()
     inside = np.all((x >= lo) & (x <= hi), axis=1)
     thr = np.array([s.threshold_mode for s in samples])
-    return np.where(inside, y.argmin(1), thr), inside
+    margin = model.margin() if margin is None else margin
+    jb = y.argmin(1)
+    rows = np.arange(len(thr))
+    deviate = inside & (jb != thr) & (y[rows, thr] - y[rows, jb] > margin)
+    return np.where(deviate, jb, thr), inside
 
 
 def fixed_modes(samples):
@@ -145,6 +155,36 @@ def train(samples, epochs=3000, lr=3e-3, seed=7, members=6):
     m = B.Model.create(seed=seed, members=members)
     loss = m.train(samples, epochs=epochs, lr=lr)
     return m, loss
+
+
+MARGINS = (0.0, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.8, 1.0)
+
+
+def subset(samples, idx):
+    return (B.TraceSample * len(idx))(*[samples[int(i)] for i in idx])
+
+
+def select_margin(samples, epochs=3000, lr=3e-3, seed=7, members=6):
+    """Decision margin for extrapolating two scales beyond the corpus: train on
+    the corpus scales up to the largest minus two, and take the margin with the
+    lowest regret on the largest scale (the gate then serves graphs two scales
+    beyond its training scales, the gap from scale 22 to the scale-24 graphs)."""
+    scale = np.round(np.log2([s.n for s in samples])).astype(int)
+    top = int(scale.max())
+    fit, val = np.where(scale <= top - 2)[0], np.where(scale == top)[0]
+    if len(fit) == 0 or len(val) == 0:
+        return 0.0, {}
+    m, _ = train(subset(samples, fit), epochs, lr, seed, members)
+    vs = subset(samples, val)
+    thr = np.array([s.threshold_mode for s in vs])
+    table = {"threshold": regret(vs, thr)["regret_us"]}
+    for mg in MARGINS:
+        table[mg] = regret(vs, choices(m, vs, mg)[0])["regret_us"]
+    best = min(MARGINS, key=lambda mg: (table[mg], mg))
+    log(f"margin selection (fit on scales <= {top - 2}, regret on scale {top}): "
+        + ", ".join(f"{k}: {v / 1e3:.1f} ms" for k, v in table.items()) + f" -> {best}")
+    m.close()
+    return best, table
 
 
 def eval_graphs(seeds=(2000, 2001, 2002, 2003), scale=24):
@@ -193,7 +233,7 @@ def end_to_end(model, ro, col, seed, reps=3):
 
 
 def evaluate(model, seeds=(2000, 2001, 2002, 2003), scale=24, traces_out=None):
-    report = {"graphs": []}
+    report = {"margin": model.margin(), "graphs": []}
     all_samples = []
     for kind, seed, ro, col in eval_graphs(seeds, scale):
         log(f"evaluating on {kind} s{scale} seed {seed}")
@@ -240,6 +280,8 @@ def main(argv=None):
     t.add_argument("--lr", type=float, default=3e-3)
     t.add_argument("--seed", type=int, default=7)
     t.add_argument("--members", type=int, default=6)
+    t.add_argument("--margin", type=float, default=None,
+                   help="decision margin (default: selected by the extrapolation protocol)")
     e = sub.add_parser("evaluate")
     e.add_argument("--model", default=DEFAULT_MODEL)
     e.add_argument("--out", required=True)
@@ -252,13 +294,17 @@ def main(argv=None):
         log(f"{len(samples)} samples -> {a.out}")
     elif a.cmd == "train":
         samples = from_arrays(dict(np.load(a.traces)))
+        margin = a.margin
+        if margin is None:
+            margin, _ = select_margin(samples, a.epochs, a.lr, a.seed, a.members)
         m, loss = train(samples, a.epochs, a.lr, a.seed, a.members)
+        m.margin(margin)
         m.save(a.out)
         pick, inside = choices(m, samples)
         thr = np.array([s.threshold_mode for s in samples])
         log(f"trained on {len(samples)} samples: final loss {loss:.4f}; training-set regret "
             f"threshold {regret(samples, thr)['regret_us']:.0f} us, "
-            f"learned {regret(samples, pick)['regret_us']:.0f} us -> {a.out}")
+            f"learned {regret(samples, pick)['regret_us']:.0f} us (margin {margin}) -> {a.out}")
     else:
         model = B.Model.load(a.model)
         rep = evaluate(model, scale=a.scale, traces_out=a.traces_out)

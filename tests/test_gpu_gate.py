@@ -163,6 +163,28 @@ def test_learned_gate_without_model_or_outside_envelope_is_the_threshold_rule():
                [(r["mode"], r["chunk_edges"], r["marked_chunks"]) for r in base]
 
 
+def test_learned_gate_margin_keeps_the_threshold_rule_unless_confident():
+    """With a margin no prediction gap can exceed, the learned gate takes every
+    threshold decision; with margin 0 the same model decides by its argmin."""
+    ro, col = gen.rmat(13, 16, seed=74)
+    w = gen.edge_weights(ro, col, seed=9)
+    s = int(gen.pick_sources(ro, 1, seed=10)[0])
+    g = W.Graph.from_csr(ro, col, w)
+    _, _, base = W.sssp(g, s, trace_cap=256)
+    m = W.Model.create(seed=4, members=2)
+    rng = np.random.default_rng(5)
+    m.params(rng.normal(0, 1.0, 2 * 1476))
+    m.margin(1e30)
+    out, _, held = W.sssp(g, s, gate="learned", model=m.handle, trace_cap=256)
+    np.testing.assert_array_equal(W.u32(out), oracle.sssp(ro, col, w, s))
+    assert [(r["mode"], r["chunk_edges"], r["marked_chunks"]) for r in held] == \
+           [(r["mode"], r["chunk_edges"], r["marked_chunks"]) for r in base]
+    m.margin(0.0)
+    out, _, free = W.sssp(g, s, gate="learned", model=m.handle, trace_cap=256)
+    np.testing.assert_array_equal(W.u32(out), oracle.sssp(ro, col, w, s))
+    assert all(r["mode"] == 0 or r["chunk_edges"] in (16, 32, 64) for r in free)
+
+
 def test_learned_gate_refuses_persistent_launch():
     ro, col = gen.random_graph(200, 1000, 1)
     g = W.Graph.from_csr(ro, col)

@@ -165,3 +165,37 @@ def test_ensemble_create_roundtrip_and_errors(tmp_path):
     st = B.lib().wedge_model_grad(ens.handle, x.ctypes.data, t.ctypes.data, mk.ctypes.data, 4,
                                   g.ctypes.data, None, None)
     assert B.STATUS[st] == "WEDGE_ERR_UNSUPPORTED"
+
+
+def test_model_margin_roundtrip_versions_and_errors(tmp_path):
+    m = W.Model.create(seed=11, members=2)
+    assert m.margin() == 0.0
+    assert m.margin(0.375) == pytest.approx(0.375)
+    f = tmp_path / "m.bin"
+    m.save(str(f))
+    back = W.Model.load(str(f))
+    assert back.margin() == pytest.approx(0.375) and back.members == 2
+    np.testing.assert_array_equal(back.params(), m.params())
+    for bad in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(W.WedgeError) as e:
+            m.margin(bad)
+        assert e.value.name == "WEDGE_ERR_INVALID_ARG"
+    # a version-3 file (six-word header: no margin) loads with margin 0
+    q = np.linspace(-1, 1, 2 * 1476).astype(np.float32)
+    lo, hi = np.full(8, -2.0, np.float32), np.full(8, 2.0, np.float32)
+    body = (b"WEDGEMLP" + np.array([3, 1476, 8, 32, 4, 2], np.uint32).tobytes() + lo.tobytes()
+            + hi.tobytes() + q.tobytes())
+    v3 = tmp_path / "v3.bin"
+    v3.write_bytes(body + np.array([fnv1a(body)], np.uint64).tobytes())
+    old = W.Model.load(str(v3))
+    assert old.margin() == 0.0 and old.members == 2
+    np.testing.assert_array_equal(old.params(), q)
+    # a version-4 file whose margin is negative is refused
+    neg = np.array([-1.0], np.float32).view(np.uint32)[0]
+    body = (b"WEDGEMLP" + np.array([4, 1476, 8, 32, 4, 2, neg], np.uint32).tobytes() + lo.tobytes()
+            + hi.tobytes() + q.tobytes())
+    v4 = tmp_path / "neg.bin"
+    v4.write_bytes(body + np.array([fnv1a(body)], np.uint64).tobytes())
+    with pytest.raises(W.WedgeError) as e:
+        W.Model.load(str(v4))
+    assert e.value.name == "WEDGE_ERR_MODEL"
