@@ -197,12 +197,30 @@ __global__ void k_roots_seed(const uint32_t* __restrict__ roots, uint32_t count,
     }
 }
 
-// Caller layout of multi-source levels: out[s*n + v] = lev[perm[v]*K + s].
-__global__ void k_ms_output(uint32_t n, uint32_t K, const uint32_t* __restrict__ perm,
-                            const uint32_t* __restrict__ lev, uint32_t* __restrict__ out) {
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const uint32_t* row = lev + (uint64_t)(perm ? perm[v] : v) * K;
-        for (uint32_t s = 0; s < K; ++s) out[(uint64_t)s * n + v] = row[s];
+// Caller layout of multi-source levels: out[s*n + v] = lev[perm[v]*K + s], a
+// transpose staged through LDS in tiles of 64 vertices x K sources: a wave
+// reads one vertex's row of K levels (one coalesced load), and writes one
+// source's 64 consecutive vertices (one coalesced store).
+constexpr int kOutTile = 64;
+__global__ __launch_bounds__(kBlock) void k_ms_output(uint32_t n, uint32_t K,
+                                                      const uint32_t* __restrict__ perm,
+                                                      const uint32_t* __restrict__ lev,
+                                                      uint32_t* __restrict__ out) {
+    __shared__ uint32_t tile[kOutTile][kOutTile + 1];
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * kOutTile; v0 < n; v0 += (uint64_t)gridDim.x * kOutTile) {
+        for (int r = wave; r < kOutTile; r += kWavesPerBlock) {
+            const uint64_t v = v0 + r;
+            if (v < n && (uint32_t)lane < K)
+                tile[r][lane] = lev[(uint64_t)(perm ? perm[v] : (uint32_t)v) * K + lane];
+        }
+        __syncthreads();
+        for (uint32_t s = wave; s < K; s += kWavesPerBlock) {
+            const uint64_t v = v0 + lane;
+            if (v < n) out[(uint64_t)s * n + v] = tile[lane][s];
+        }
+        __syncthreads();
     }
 }
 
@@ -513,7 +531,9 @@ hipError_t launch_roots_seed(const uint32_t* roots, uint32_t count, uint32_t* le
 hipError_t launch_ms_output(uint32_t n, uint32_t K, const uint32_t* perm, const uint32_t* lev,
                             uint32_t* out, hipStream_t s) {
     if (!n) return hipSuccess;
-    k_ms_output<<<grid_for(n, 16384), kBlock, 0, s>>>(n, K, perm, lev, out);
+    if (K > kOutTile) return hipErrorInvalidValue;
+    const uint64_t tiles = ((uint64_t)n + kOutTile - 1) / kOutTile;
+    k_ms_output<<<(uint32_t)std::min<uint64_t>(tiles, 65536), kBlock, 0, s>>>(n, K, perm, lev, out);
     return hipGetLastError();
 }
 
