@@ -199,3 +199,49 @@ def test_model_margin_roundtrip_versions_and_errors(tmp_path):
     with pytest.raises(W.WedgeError) as e:
         W.Model.load(str(v4))
     assert e.value.name == "WEDGE_ERR_MODEL"
+
+
+class _StubModel:
+    """Fixed predictions, an envelope and a margin: the decision rule alone."""
+
+    def __init__(self, y, margin, lo=None, hi=None):
+        self.y, self.m = np.asarray(y, np.float32), margin
+        self.lo = np.full(8, -np.inf, np.float32) if lo is None else lo
+        self.hi = np.full(8, np.inf, np.float32) if hi is None else hi
+
+    def predict(self, x):
+        return self.y
+
+    def envelope(self):
+        return self.lo, self.hi
+
+    def margin(self):
+        return self.m
+
+
+def test_host_decision_rule_matches_the_device_rule():
+    """learned_gate.choices: the model's argmin replaces the threshold rule's
+    mode only when its predicted log-time is lower by more than the margin
+    (ties to the lower index), and outside the envelope the rule decides."""
+    from paper_1903_07754_amd import learned_gate as LG
+    rows = [  # (predictions for modes 0..3, threshold mode, expected pick at margin 0.4)
+        ([0.0, -1.0, 0.5, 0.5], 0, 1),     # gain 1.0 > 0.4: departs
+        ([0.0, -0.3, 0.5, 0.5], 0, 0),     # gain 0.3: keeps the rule
+        ([0.0, -0.4, 0.5, 0.5], 0, 0),     # gain exactly the margin: keeps the rule
+        ([0.2, -0.5, -0.5, 0.1], 0, 1),    # tie between 1 and 2: the lower index
+        ([0.0, 0.1, -0.2, 0.3], 2, 2),     # the rule's mode is the argmin
+        ([-0.6, 0.0, 0.1, 0.2], 1, 0),     # to the full pull
+    ]
+    S = (B.TraceSample * len(rows))()
+    for s, (_, thr, _) in zip(S, rows):
+        s.frontier, s.active, s.n, s.m, s.iter, s.app, s.threshold_mode = 10, 100, 1 << 12, 1 << 16, 1, 1, thr
+    y = [r[0] for r in rows]
+    pick, inside = LG.choices(_StubModel(y, 0.4), S)
+    assert inside.all()
+    assert list(pick) == [r[2] for r in rows]
+    pick0, _ = LG.choices(_StubModel(y, 0.0), S)
+    assert list(pick0) == [1, 1, 1, 1, 2, 0]
+    # outside the envelope every decision is the rule's
+    lo = np.full(8, 5.0, np.float32)
+    pick_out, inside = LG.choices(_StubModel(y, 0.0, lo=lo, hi=lo + 1), S)
+    assert not inside.any() and list(pick_out) == [r[1] for r in rows]
