@@ -110,20 +110,36 @@ __device__ __forceinline__ void ms_finalize_block(
     uint64_t vblock, uint64_t* bits, uint64_t words, uint32_t n, const uint32_t* row_off,
     uint32_t* list, uint32_t* degpre, Ctl* ctl, uint64_t* fcur, uint64_t* visited,
     uint64_t* retire, const uint64_t* nxt, uint32_t* lev, uint32_t K, uint32_t level) {
+    // the new masks of the wave's vertices, one slot per (word, lane), for the
+    // level writes below (each lane only touches its own slots)
+    __shared__ uint64_t s_nb[WAVES][kCompactWords][64];
+    const int lane = lane_id();
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int g = 0; g < kCompactWords; ++g) s_nb[wid][g][lane] = 0ull;
     bitmap_compact_block_ex<WAVES, true, true, kCompactWords>(
         vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
         [&](uint32_t v) -> uint64_t { return nxt[v]; },
         [&](uint32_t v, uint64_t nb) {
             atomicOr(reinterpret_cast<unsigned long long*>(visited + v), (unsigned long long)nb);
-            uint64_t b = nb;
-            uint32_t* row = lev + (uint64_t)v * K;
-            while (b) {
-                const int s = __builtin_ctzll(b);
-                row[s] = level;
-                b &= b - 1;
-            }
+            s_nb[wid][(v >> 6) % kCompactWords][lane] = nb;
         },
         [&](uint32_t v) { retire[v] = 0ull; });
+    // levels: one coalesced store of a vertex's row (lane s writes source s)
+    // per newly reached vertex, instead of one scattered store per new bit
+    const uint64_t w0 = (vblock * WAVES + wid) * kCompactWords;
+#pragma unroll
+    for (int g = 0; g < kCompactWords; ++g) {
+        const uint64_t nbv = s_nb[wid][g][lane];
+        uint64_t todo = __ballot(nbv != 0ull);
+        while (todo) {
+            const int j = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint64_t nb = __shfl(nbv, j, 64);
+            const uint64_t v = (w0 + g) * 64 + (uint64_t)j;
+            if ((uint32_t)lane < K && ((nb >> lane) & 1ull)) lev[v * K + lane] = level;
+        }
+    }
 }
 
 template <int WAVES = kWavesPerBlock>
