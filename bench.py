@@ -227,7 +227,7 @@ def batched_section(reps=3):
     and 256 R-MAT graphs of scales drawn from 10..16 as one disjoint union.
     Both batched forms are timed host-driven, as one persistent launch
     replayed from a captured hipGraph, and in the autotuned configuration
-    (chunk size, host-driven or persistent launch, blocks per CU)."""
+    (chunk size, host-driven or persistent launch, blocks per CU, rows per wave)."""
     import numpy as np
     import torch
 
@@ -247,7 +247,8 @@ def batched_section(reps=3):
     best, _ = W.tune_bfs(g, "multisource", srcs, outk)
     t_tuned = timed(lambda: W.bfs_multisource(g, srcs, out=outk, chunk=best["chunk"],
                                               persistent=best["persistent"],
-                                              blocks_per_cu=best["blocks_per_cu"]), reps)
+                                              blocks_per_cu=best["blocks_per_cu"],
+                                              rows_per_wave=best["rows_per_wave"]), reps)
     t_pers = timed(lambda: W.bfs_multisource(g, srcs, out=outk, persistent=True), reps)
     lv = outk.view(64, n)
     for i in (0, 31, 63):
@@ -279,7 +280,8 @@ def batched_section(reps=3):
     best, _ = W.tune_bfs(gb, "batch", bsrcs, outb)
     t_tuned = timed(lambda: W.bfs_batch(gb, bsrcs, out=outb, chunk=best["chunk"],
                                         persistent=best["persistent"],
-                                        blocks_per_cu=best["blocks_per_cu"]), reps)
+                                        blocks_per_cu=best["blocks_per_cu"],
+                                        rows_per_wave=best["rows_per_wave"]), reps)
     first = gb.parts()
     for i in (0, 100, 255):
         assert torch.equal(outb[int(first[i]):int(first[i + 1])], outs[i]), "batch part differs"

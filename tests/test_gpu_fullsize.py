@@ -156,6 +156,23 @@ def test_rmat24_pagerank():
 
 
 @pytest.mark.timeout(900)
+def test_config4_learned_gate_rmat24_exact():
+    """The shipped learned gate at scale 24: every result bit-exact (its
+    decisions may differ from the threshold rule's, the values may not)."""
+    b = big("rmat")
+    from paper_1903_07754_amd import learned_gate as LG
+    model = W.Model.load(LG.DEFAULT_MODEL)
+    s = b.srcs[2]
+    out, st, _ = W.bfs(b.g, s, gate="learned", model=model.handle)
+    np.testing.assert_array_equal(W.u32(out), oracle.bfs(b.ro, b.col, s))
+    out, st, _ = W.sssp(b.g, s, gate="learned", model=model.handle)
+    np.testing.assert_array_equal(W.u32(out), oracle.sssp(b.ro, b.col, b.w, s))
+    out, st, _ = W.cc(b.gs, gate="learned", model=model.handle)
+    np.testing.assert_array_equal(W.u32(out), oracle.cc(b.ro, b.col))
+    say(f"rmat learned gate bfs/sssp/cc ok (margin {model.margin():.2f})")
+
+
+@pytest.mark.timeout(900)
 def test_config2_er24_bfs_sssp():
     check_bfs_sssp("er")
 
@@ -187,3 +204,39 @@ def test_config3_pagerank_rmat26():
     say(f"pagerank s26 rel L1 {e:.3e}")
     assert e <= 1e-5
     assert abs(got.astype(np.float64).sum() - 1.0) < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_config5_multisource_rmat22_64_sources():
+    """The bench's 64-source workload (R-MAT scale 22, seeds 5 and 6): every
+    one of the 64 rows equals the oracle's BFS, host-driven and persistent."""
+    ro, col = gen.rmat(22, 16, seed=5)
+    srcs = gen.pick_sources(ro, 64, seed=6)
+    g = W.Graph.from_csr(ro, col)
+    n = len(ro) - 1
+    want = np.stack([oracle.bfs(ro, col, int(s)) for s in srcs])
+    say(f"rmat22 oracle for 64 sources done (n={n} m={len(col)})")
+    for persistent in (False, True):
+        lv, st, _ = W.bfs_multisource(g, srcs, persistent=persistent)
+        np.testing.assert_array_equal(lv.cpu().numpy().view(np.uint32), want)
+        say(f"rmat22 64-source persistent={persistent} ok ({st['iterations']} iters, {st['ms']:.2f} ms)")
+    g.close()
+
+
+@pytest.mark.timeout(900)
+def test_config5_batch_of_256_graphs():
+    """The bench's 256-graph batch (scales 10..16, seeds 7, 3000+i, 4000+i):
+    every part equals the oracle's BFS of its own graph."""
+    scales = gen.batch_scales(256, 10, 16, seed=7)
+    parts = [gen.rmat(int(s), 16, seed=3000 + i) for i, s in enumerate(scales)]
+    srcs = np.array([int(gen.pick_sources(r, 1, seed=4000 + i)[0]) for i, (r, _) in enumerate(parts)],
+                    np.uint32)
+    gb = W.Graph.from_batch_csr(parts)
+    first = gb.parts()
+    want = [oracle.bfs(r, c, int(srcs[i])) for i, (r, c) in enumerate(parts)]
+    for persistent in (False, True):
+        got = W.u32(W.bfs_batch(gb, srcs, persistent=persistent)[0])
+        for i in range(len(parts)):
+            np.testing.assert_array_equal(got[first[i]:first[i + 1]], want[i])
+        say(f"256-graph batch persistent={persistent} ok (n={gb.n})")
+    gb.close()
