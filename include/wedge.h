@@ -265,13 +265,16 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
  * A small learned cost model for the fullness decision: an FP32 MLP
  * 8 -> 32 -> 32 -> 4 (ReLU) predicting, for each mode, log(1 + microseconds)
  * of the next iteration minus that of the full pull (mode 0 = full pull,
- * modes 1, 2, 3 = Wedge Frontier at 16, 32, 64 edges per bit). With WEDGE_GATE_LEARNED the decision
- * is the mode of smallest prediction (ties to the lower index), computed on
- * the device between iterations. The paper's threshold rule (Frontier
- * Transformation, Frontier Fullness Threshold) decides instead when no model
- * is given or a feature lies outside the model's training envelope. The
- * choice never changes results (any mode visits a superset of the active
- * edges).
+ * modes 1, 2, 3 = Wedge Frontier at 16, 32, 64 edges per bit); a model is an
+ * ensemble of such MLPs and predicts their mean. With WEDGE_GATE_LEARNED the
+ * decision is computed on the device between iterations: the mode of
+ * smallest prediction (ties to the lower index) when it is predicted faster
+ * than the threshold rule's mode by more than the model's decision margin
+ * (wedge_model_margin), else the threshold rule's mode. The paper's
+ * threshold rule (Frontier Transformation, Frontier Fullness Threshold) also
+ * decides when no model is given or a feature lies outside the model's
+ * training envelope. The choice never changes results (any mode visits a
+ * superset of the active edges).
  *
  * Features of the frontier F_k about to be consumed (float, in this order):
  * |F_k|/n, A_k/m, 1 - exp(-A_k/ceil(m/16)), WEDGE_APP_* / 3, log2(m)/32,
