@@ -202,9 +202,14 @@ wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontie
     const DevGraph& d = g->dev;
     wedge_status st;
     // every buffer is allocated on its own when missing, so a run after a
-    // failed (partial) allocation completes the workspace instead of using it
+    // failed (partial) allocation completes the workspace instead of using it.
+    // Any buffer that is (re)allocated here moves, so the generation is bumped:
+    // a captured persistent traversal holds the old addresses and must be
+    // recorded again.
     auto need = [&](void** p, size_t bytes, const char* what) -> wedge_status {
-        return *p ? WEDGE_OK : dev_alloc(g, p, bytes, what);
+        if (*p) return WEDGE_OK;
+        w.generation++;
+        return dev_alloc(g, p, bytes, what);
     };
     if ((st = need((void**)&w.ctl, sizeof(Ctl), "counters")) != WEDGE_OK) return st;
     if (!w.ctl_host) HIP_TRY(hipHostMalloc((void**)&w.ctl_host, sizeof(Ctl), hipHostMallocDefault), "pinned counters");
@@ -215,6 +220,7 @@ wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontie
         w.m = d.m;
         const uint64_t fw = ((uint64_t)d.n + 63) / 64;
         if (!w.fbits) {
+            w.generation++;
             if ((st = dev_alloc(g, (void**)&w.fbits, fw * 8, "frontier bitmap")) != WEDGE_OK) return st;
             HIP_TRY(hipMemset(w.fbits, 0, fw ? fw * 8 : 8), "clearing frontier bitmap");
         }
@@ -230,12 +236,14 @@ wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontie
         const uint64_t chunks = (d.m + (1ull << log_chunk) - 1) >> log_chunk;
         const uint64_t words = (chunks + 63) / 64;
         if (words > w.wbits_words || !w.wbits) {
+            w.generation++;
             if (w.wbits) { (void)hipFree(w.wbits); g->device_bytes -= w.wbits_words * 8; w.wbits = nullptr; }
             if ((st = dev_alloc(g, (void**)&w.wbits, words * 8, "Wedge Frontier bitmap")) != WEDGE_OK) return st;
             w.wbits_words = words ? words : 1;
             HIP_TRY(hipMemset(w.wbits, 0, w.wbits_words * 8), "clearing Wedge bitmap");
         }
         if (chunks > w.chunks_cap || !w.chunks) {
+            w.generation++;
             if (w.chunks) { (void)hipFree(w.chunks); g->device_bytes -= w.chunks_cap * 4; w.chunks = nullptr; }
             if ((st = dev_alloc(g, (void**)&w.chunks, chunks * 4, "chunk list")) != WEDGE_OK) return st;
             w.chunks_cap = chunks ? chunks : 2;

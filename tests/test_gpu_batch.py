@@ -157,6 +157,31 @@ def test_persistent_bfs_matches_host_driven_records():
                 assert ra[key] == rb[key], (key, ra, rb)
 
 
+def test_persistent_replay_after_workspace_grows():
+    """A captured persistent traversal holds the workspace addresses it was
+    recorded with. A run that needs a larger Wedge bitmap or chunk list (SSSP
+    at 16 edges per bit, after a persistent BFS at 32) reallocates them; the
+    next persistent BFS into the same output must be recorded again, not
+    replayed against the freed buffers."""
+    ro, col = gen.rmat(14, 16, seed=67)
+    w = gen.edge_weights(ro, col, seed=4)
+    g = W.Graph.from_csr(ro, col, w)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    srcs = [int(s) for s in gen.pick_sources(ro, 3, seed=13)]
+    print(f"  [persistent replay after growth: n={g.n} m={g.m}]", flush=True)
+    W.bfs(g, srcs[0], out=out, chunk=32, persistent=True)
+    np.testing.assert_array_equal(W.u32(out), oracle.bfs(ro, col, srcs[0]))
+    W.sssp(g, srcs[1], out=dist, chunk=16)
+    np.testing.assert_array_equal(W.u32(dist), oracle.sssp(ro, col, w, srcs[1]))
+    W.bfs(g, srcs[2], out=out, chunk=32, persistent=True)
+    np.testing.assert_array_equal(W.u32(out), oracle.bfs(ro, col, srcs[2]))
+    W.sssp(g, srcs[0], out=dist, chunk=1)
+    np.testing.assert_array_equal(W.u32(dist), oracle.sssp(ro, col, w, srcs[0]))
+    W.bfs(g, srcs[1], out=out, chunk=32, persistent=True)
+    np.testing.assert_array_equal(W.u32(out), oracle.bfs(ro, col, srcs[1]))
+
+
 def test_graph_replays_with_eager_work_between():
     """The captured traversal is replayed many times (new sources each time, same
     graph), with the program's own device work and synchronisations between

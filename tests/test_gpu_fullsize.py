@@ -3,7 +3,8 @@
 R-MAT scale 16 (BFS, 8 sources) and the scale-24 R-MAT and Erdos-Renyi graphs
 (BFS, SSSP, CC, PageRank) are checked against the CPU oracle computed in full:
 bit-exact for integers, per-iteration frontier size, out-degree sum and gate
-decision for one BFS and one SSSP run, and <= 1e-5 relative L1 for PageRank.
+decision for every BFS and SSSP source the benchmark times, and <= 1e-5
+relative L1 for PageRank.
 The scale-26 PageRank case (1.06B edges) runs too, printing its progress.
 """
 import time
@@ -85,25 +86,45 @@ def big(kind):
     return _cache[kind]
 
 
+def level_trace(levels, outdeg, thr):
+    """Per-iteration |F_k|, A_k and gate decision of a synchronous BFS, read off
+    its final levels: the frontier consumed by iteration k is exactly the set
+    of vertices at level k."""
+    lv = np.asarray(levels)
+    reached = lv[lv != oracle.INF]
+    depth = int(reached.max()) + 1 if reached.size else 0
+    F = np.bincount(reached, minlength=depth).astype(np.int64)
+    A = np.bincount(reached, weights=outdeg[lv != oracle.INF], minlength=depth).astype(np.int64)
+    return list(F), list(A), [1 if a < thr else 0 for a in A]
+
+
 def check_bfs_sssp(kind):
+    """Every source the benchmark times (4 per graph), each with its
+    per-iteration records: BFS against the level sets of the oracle's BFS (and,
+    for the first source, against the oracle's pull engine as well), SSSP
+    against the oracle's pull engine."""
     b = big(kind)
-    for i, s in enumerate(b.srcs[:2]):
+    m = len(b.col)
+    outdeg = np.diff(b.ro.astype(np.int64))
+    for i, s in enumerate(b.srcs):
         out, st, tr = W.bfs(b.g, s, trace_cap=256)
         want = oracle.bfs(b.ro, b.col, s)
         np.testing.assert_array_equal(W.u32(out), want)
-        say(f"{kind} bfs src={s} ok ({st['iterations']} iters, {st['ms']:.2f} ms)")
+        F, A, mode = level_trace(want, outdeg, oracle.threshold_edges(10_000, m))
+        assert [r["frontier"] for r in tr] == F
+        assert [r["active_edges"] for r in tr] == A
+        assert [r["mode"] for r in tr] == mode
+        if i == 0:
+            ref = oracle.pull_engine("bfs", b.ro, b.col, None, s, theta_ppm=10_000, chunk=0)
+            assert (list(ref.F), list(ref.A), list(ref.mode)) == (F, A, mode)
+        say(f"{kind} bfs src={s} ok with its trace ({st['iterations']} iters, {st['ms']:.2f} ms)")
         d, st, trs = W.sssp(b.g, s, trace_cap=4096)
         np.testing.assert_array_equal(W.u32(d), oracle.sssp(b.ro, b.col, b.w, s))
-        say(f"{kind} sssp src={s} ok ({st['iterations']} iters, {st['ms']:.2f} ms)")
-        if i == 0:
-            for app, t in (("bfs", tr), ("sssp", trs)):
-                theta = 10_000 if app == "bfs" else 200_000
-                ref = oracle.pull_engine(app, b.ro, b.col, b.w if app == "sssp" else None, s,
-                                         theta_ppm=theta, chunk=0)
-                assert [r["frontier"] for r in t] == list(ref.F)
-                assert [r["active_edges"] for r in t] == list(ref.A)
-                assert [r["mode"] for r in t] == list(ref.mode)
-                say(f"{kind} {app} per-iteration trace matches ({ref.iters} iters)")
+        ref = oracle.pull_engine("sssp", b.ro, b.col, b.w, s, theta_ppm=200_000, chunk=0)
+        assert [r["frontier"] for r in trs] == list(ref.F)
+        assert [r["active_edges"] for r in trs] == list(ref.A)
+        assert [r["mode"] for r in trs] == list(ref.mode)
+        say(f"{kind} sssp src={s} ok with its trace ({st['iterations']} iters, {st['ms']:.2f} ms)")
 
 
 def check_cc(kind):
@@ -113,7 +134,7 @@ def check_cc(kind):
     say(f"{kind} cc ok ({st['iterations']} iters, {st['ms']:.2f} ms)")
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1200)
 def test_config2_rmat24_bfs_sssp():
     check_bfs_sssp("rmat")
 
@@ -172,7 +193,7 @@ def test_config4_learned_gate_rmat24_exact():
     say(f"rmat learned gate bfs/sssp/cc ok (margin {model.margin():.2f})")
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1200)
 def test_config2_er24_bfs_sssp():
     check_bfs_sssp("er")
 

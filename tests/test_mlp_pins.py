@@ -73,6 +73,37 @@ def test_adam_matches_torch():
     np.testing.assert_allclose(q, tp.detach().numpy(), rtol=1e-10, atol=1e-12)
 
 
+def test_oracle_features_against_hand_values():
+    """The gate's features pinned to values worked out by hand from their
+    definitions in the library header (|F|/n, A/m, 1 - exp(-A/ceil(m/16)),
+    app/3, log2(m)/32, min(k, 255)/64, log(1 + us)/16, mode/3), on inputs
+    chosen so that a plausible misreading changes a value: m = 1000 makes
+    ceil(m/16) = 63 differ from m/16 = 62.5; k = 300 tests the clamp at 255;
+    prev_us = e - 1 makes log(1 + us) exactly 1 (log(us) would give 0.5413);
+    A = 0 and A = m are the ends of the active-edge range."""
+    e = 2.718281828459045
+    cases = [
+        # (frontier, active, n, m, k, prev_us, prev_mode, app) -> expected 8 features
+        ((8, 0, 64, 1024, 0, 0.0, 0, 1),
+         [0.125, 0.0, 0.0, 1 / 3, 0.3125, 0.0, 0.0, 0.0]),
+        # A = 63 = ceil(1000/16): 1 - e^-1
+        ((100, 63, 400, 1000, 255, e - 1.0, 1, 2),
+         [0.25, 0.063, 0.6321205588285577, 2 / 3, 0.31143075889569023, 3.984375, 0.0625,
+          1 / 3]),
+        # k beyond the clamp, A = m (A/ceil(m/16) = 1000/63 = 15.873...)
+        ((400, 1000, 400, 1000, 300, 0.0, 3, 3),
+         [1.0, 1.0, 0.9999998722276757, 1.0, 0.31143075889569023, 3.984375, 0.0, 1.0]),
+        # m = 2^20 (log2 m / 32 = 0.625; A/ceil(m/16) = 2^-16, so 1 - exp(-x) =
+        # x - x^2/2 + ... = 1.52587890625e-05 - 1.164e-10), prev_us = e^2 - 1 -> 2/16
+        ((1, 1, 2, 1 << 20, 64, 6.38905609893065, 2, 1),
+         [0.5, 9.5367431640625e-07, 1.5258672647733285e-05, 1 / 3, 0.625, 1.0, 0.125,
+          2 / 3]),
+    ]
+    for args, want in cases:
+        got = mlp.features(*args)
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-15, err_msg=str(args))
+
+
 def test_library_features_equal_oracle():
     rows = [(1, 1, 2**10, 2**14, 0, 0.0, 0, 1), (500, 123456, 2**20, 2**24, 7, 350.5, 2, 2),
             (2**18, 2**22, 2**18, 2**22, 300, 1e5, 3, 3)]
