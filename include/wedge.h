@@ -232,6 +232,32 @@ wedge_status wedge_bfs(wedge_graph_t g, uint32_t src, uint32_t* level_dev, const
                        hipStream_t stream, wedge_stats* stats);
 
 /*
+ * BFS that allocates nothing: for callers that cannot allocate device or
+ * pinned memory during the run (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same arguments, results and
+ * per-iteration trace as wedge_bfs, from the same kernels; the graph (made
+ * beforehand) and level_dev (the caller's) are the only other memory used.
+ * The workspace lives in a fixed device array of 32 MiB that the library
+ * holds on each GPU it runs on until the process ends (looked up once per
+ * device, on its first call there). It needs, in bytes, rounded up to 256
+ * each: 64 (counters) + 2 * ceil(n/64) * 8 (frontier bitmaps) + 8n (frontier
+ * list and out-degree prefix) + 4n (values, unless created with
+ * WEDGE_KEEP_IDS) + ceil(ceil(m/C)/64) * 8 + ceil(m/C) * 4 (Wedge bitmap and
+ * marked-group list), C = chunk_edges (default 32); a graph needing more is
+ * refused with WEDGE_ERR_INVALID_ARG before any device work (about n = 2.4M
+ * at 16 edges per vertex). The graph's device must be current
+ * (WEDGE_ERR_INVALID_ARG otherwise). Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (each call clears what must
+ * start at zero): calls that overlapped on one GPU would race, so the library
+ * runs them one at a time per device within a process. Refused with
+ * WEDGE_ERR_UNSUPPORTED: WEDGE_GATE_LEARNED (its model buffers are
+ * allocated on first use) and any wedge_opts.flags bit (timing events,
+ * persistent launch buffers).
+ */
+wedge_status wedge_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* level_dev,
+                               const wedge_opts* opts, hipStream_t stream, wedge_stats* stats);
+
+/*
  * Connected components by label propagation (HCC; Evaluation, Applications)
  * on an undirected graph (created with WEDGE_SYMMETRIZE): label_dev[n]
  * receives the smallest vertex id of each component.

@@ -102,6 +102,7 @@ def lib():
     L.wedge_graph_get_info.argtypes = [vp, C.POINTER(GraphInfo)]
     L.wedge_graph_layout.argtypes = [vp, C.c_int, vp, u64]
     L.wedge_bfs.argtypes = [vp, u32, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
+    L.wedge_bfs_noalloc.argtypes = [vp, u32, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
     L.wedge_cc.argtypes = [vp, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
     L.wedge_sssp.argtypes = [vp, u32, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
     L.wedge_pagerank.argtypes = [vp, u32, C.c_float, vp, C.POINTER(Opts), vp, C.POINTER(Stats)]
@@ -132,7 +133,7 @@ def lib():
     L.wedge_last_error.restype = C.c_char_p
     L.wedge_version.restype = C.c_char_p
     for name in ("wedge_graph_create_csr", "wedge_graph_create_csc", "wedge_graph_destroy",
-                 "wedge_graph_get_info", "wedge_graph_layout", "wedge_bfs", "wedge_cc",
+                 "wedge_graph_get_info", "wedge_graph_layout", "wedge_bfs", "wedge_bfs_noalloc", "wedge_cc",
                  "wedge_sssp", "wedge_pagerank", "wedge_frontier_translate",
                  "wedge_bfs_multisource", "wedge_graph_create_batch_csr", "wedge_graph_batch_parts",
                  "wedge_bfs_batch", "wedge_tune_bfs", "wedge_tune_lookup", "wedge_model_create",
@@ -298,6 +299,12 @@ def _run_int(fn, g, args, out, stream, trace_cap, **kw):
 def bfs(g, src, out=None, stream=None, trace_cap=0, **kw):
     """Levels (int32 tensor viewed as uint32; 0xFFFFFFFF = unreachable), stats, trace."""
     return _run_int(lib().wedge_bfs, g, (src,), out, stream, trace_cap, **kw)
+
+
+def bfs_noalloc(g, src, out=None, stream=None, trace_cap=0, **kw):
+    """BFS with the library's fixed device scratch as its workspace (no allocation in
+    the library; pass `out` to keep the call itself allocation-free)."""
+    return _run_int(lib().wedge_bfs_noalloc, g, (src,), out, stream, trace_cap, **kw)
 
 
 def cc(g, out=None, stream=None, trace_cap=0, **kw):

@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
         o = os.path.join(obj_dir, src + ".o")
         _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)
-    for src in ("kernels.hip", "batch.hip", "mlp.hip"):
+    for src in ("kernels.hip", "batch.hip", "mlp.hip", "noalloc.hip"):
         o = os.path.join(obj_dir, src + ".o")
         _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

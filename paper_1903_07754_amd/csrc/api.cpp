@@ -321,9 +321,9 @@ struct LoopCfg {
 };
 
 template <class Pull, class Fin>
-wedge_status iterate(wedge_graph_t g, const wedge_opts& o, const LoopCfg& c, hipStream_t s,
-                     wedge_stats& local, double t0, wedge_stats* stats, Pull pull, Fin fin) {
-    Workspace& w = g->ws;
+wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const LoopCfg& c,
+                     hipStream_t s, wedge_stats& local, double t0, wedge_stats* stats, Pull pull,
+                     Fin fin) {
     const DevGraph& d = g->dev;
     if (c.learned)
         HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, c.margin, w.ctl, (double)d.n, (double)d.m, c.thr, (uint32_t)c.lc,
@@ -463,7 +463,7 @@ wedge_status prepare_gate(wedge_graph_t g, const wedge_opts& o, LoopCfg* c) {
 
 // Clears both frontier bitmaps (and the Wedge bitmap when it may be used).
 wedge_status clear_bitmaps(wedge_graph_t g, const LoopCfg& c, hipStream_t s) {
-    Workspace& w = g->ws;
+    const Workspace& w = g->ws;
     const uint64_t fwords = ((uint64_t)g->dev.n + 63) / 64;
     HIP_TRY(hipMemsetAsync(w.fbits, 0, fwords * 8, s), "clearing frontier bitmap");
     HIP_TRY(hipMemsetAsync(w.fcur, 0, fwords * 8, s), "clearing frontier bitmap");
@@ -517,7 +517,7 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
                                    w.ctl, s), "seeding source");
     }
     st = iterate(
-        g, o, c, s, local, t0, stats,
+        g, w, o, c, s, local, t0, stats,
         [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
             return wedge_mode ? launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev,
                                                    w.fcur, w.fbits, s, c.rows)
@@ -532,6 +532,117 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         HIP_TRY(launch_unpermute_u32(d.n, d.perm, val, out, s), "writing results");
         HIP_TRY(hipStreamSynchronize(s), "writing results");
     }
+    local.ms = now_ms() - t0;
+    if (stats) *stats = local;
+    return WEDGE_OK;
+}
+
+// BFS with its whole workspace carved out of the library's fixed device
+// scratch (noalloc.hip) instead of the graph's allocated workspace. The loop
+// and the kernels are those of run_frontier_app; what differs is that no
+// call here allocates or frees memory: buffers are cleared by fill kernels,
+// the counters are read back into a host variable, and the options that need
+// an allocation (the learned gate's device model, timing events, the
+// persistent launch's buffers) are refused. One frontier list and prefix
+// serve both iterations' roles: the translation reads them before the pull,
+// and the finalisation rewrites them after it, in stream order.
+struct NoAllocPlan {
+    uint64_t fwords, wwords, nchunks;
+    size_t off_fbits, off_fcur, off_flist, off_degpre, off_val, off_wbits, off_chunks, off_ctl, total;
+};
+
+NoAllocPlan noalloc_plan(const DevGraph& d, const LoopCfg& c) {
+    NoAllocPlan p{};
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    p.fwords = ((uint64_t)d.n + 63) / 64;
+    p.nchunks = c.chunks_of(c.lc);
+    p.wwords = (p.nchunks + 63) / 64;
+    size_t at = 0;
+    p.off_ctl = at;    at += up(sizeof(Ctl));
+    p.off_fbits = at;  at += up(p.fwords * 8);
+    p.off_fcur = at;   at += up(p.fwords * 8);
+    p.off_flist = at;  at += up((size_t)d.n * 4);
+    p.off_degpre = at; at += up((size_t)d.n * 4);
+    p.off_val = at;    at += d.inv ? up((size_t)d.n * 4) : 0;
+    p.off_wbits = at;  at += up((p.wwords ? p.wwords : 1) * 8);
+    p.off_chunks = at; at += up((p.nchunks ? p.nchunks : 1) * 4);
+    p.total = at;
+    return p;
+}
+
+wedge_status run_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* out, const wedge_opts* opts_in,
+                             hipStream_t s, wedge_stats* stats) {
+    const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
+    wedge_status st = check_run(g, out, &o);
+    if (st != WEDGE_OK) return st;
+    const DevGraph& d = g->dev;
+    if (src >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
+    if (o.gate == WEDGE_GATE_LEARNED)
+        return fail(WEDGE_ERR_UNSUPPORTED, "the learned gate needs device model buffers: use wedge_bfs");
+    if (o.flags)
+        return fail(WEDGE_ERR_UNSUPPORTED,
+                    "timing and persistent runs need events or graph buffers: use wedge_bfs");
+    if ((st = check_rows(o, true)) != WEDGE_OK) return st;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != g->device) return fail(WEDGE_ERR_INVALID_ARG, "the graph's device must be the current device");
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(WEDGE_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    const LoopCfg c = loop_cfg(o, d, kBfs, 10000u, 32u);
+    const NoAllocPlan p = noalloc_plan(d, c);
+    if (p.total > kNoAllocScratchBytes)
+        return fail(WEDGE_ERR_INVALID_ARG,
+                    "graph needs " + std::to_string(p.total) + " bytes of BFS workspace; the fixed scratch holds " +
+                        std::to_string(kNoAllocScratchBytes) + " (use wedge_bfs)");
+    RunGuard guard(g->busy);
+    if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
+    std::lock_guard<std::mutex> one_at_a_time(noalloc_run_lock(dev));
+    void* base = nullptr;
+    HIP_TRY(noalloc_scratch(dev, &base), "looking up the device scratch");
+    unsigned char* b = static_cast<unsigned char*>(base);
+    Workspace w{};
+    Ctl host_ctl{};
+    w.n = d.n;
+    w.m = d.m;
+    w.ctl = reinterpret_cast<Ctl*>(b + p.off_ctl);
+    w.ctl_host = &host_ctl;
+    w.fbits = reinterpret_cast<uint64_t*>(b + p.off_fbits);
+    w.fcur = reinterpret_cast<uint64_t*>(b + p.off_fcur);
+    w.flist[0] = w.flist[1] = reinterpret_cast<uint32_t*>(b + p.off_flist);
+    w.degpre[0] = w.degpre[1] = reinterpret_cast<uint32_t*>(b + p.off_degpre);
+    w.val = d.inv ? reinterpret_cast<uint32_t*>(b + p.off_val) : nullptr;
+    w.wbits = reinterpret_cast<uint64_t*>(b + p.off_wbits);
+    w.wbits_words = p.wwords;
+    w.chunks = reinterpret_cast<uint32_t*>(b + p.off_chunks);
+    w.chunks_cap = p.nchunks;
+    wedge_stats local{};
+    const double t0 = now_ms();
+    // the scratch keeps the previous call's contents: clear what must start at zero
+    HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.ctl), sizeof(Ctl) / 8, 0, s), "clearing counters");
+    HIP_TRY(launch_fill_u64(w.fbits, p.fwords, 0, s), "clearing frontier bitmap");
+    HIP_TRY(launch_fill_u64(w.fcur, p.fwords, 0, s), "clearing frontier bitmap");
+    if (c.gate != WEDGE_GATE_ALWAYS_FULL) HIP_TRY(launch_fill_u64(w.wbits, p.wwords, 0, s), "clearing Wedge bitmap");
+    uint32_t* val = d.inv ? w.val : out;
+    const uint32_t isrc = g->perm_host.empty() ? src : g->perm_host[src];
+    HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
+    HIP_TRY(launch_seed_source(isrc, d.row_off, val, nullptr, w.flist[0], w.degpre[0], w.fcur, w.ctl, s),
+            "seeding source");
+    st = iterate(
+        g, w, o, c, s, local, t0, stats,
+        [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
+            return wedge_mode ? launch_pull_chunks(kBfs, d, k, lc, w.chunks, w.ctl, maxk, val, nullptr,
+                                                   w.fcur, w.fbits, s, c.rows)
+                              : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, s, c.rows);
+        },
+        [&](uint32_t, int cur) {
+            return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
+                                   nullptr, val, w.fcur, s);
+        });
+    if (st != WEDGE_OK) {
+        (void)hipStreamSynchronize(s);  // the next user of the scratch must not meet this run's kernels
+        return st;
+    }
+    if (d.inv) HIP_TRY(launch_unpermute_u32(d.n, d.perm, val, out, s), "writing results");
+    HIP_TRY(hipStreamSynchronize(s), "writing results");
     local.ms = now_ms() - t0;
     if (stats) *stats = local;
     return WEDGE_OK;
@@ -773,7 +884,7 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
         HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr,
                                 w.fcur, s), "listing roots");
         st = iterate(
-            g, o, c, s, local, t0, stats,
+            g, w, o, c, s, local, t0, stats,
             [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
                 return wedge_mode ? launch_pull_chunks(kBfs, d, k, lc, w.chunks, w.ctl, maxk, val,
                                                        nullptr, w.fcur, w.fbits, s, c.rows)
@@ -832,7 +943,7 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
         HIP_TRY(launch_ms_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, w.fcur,
                                    w.visited, w.masks[1], w.masks[0], w.lev, count, 0, s), "listing sources");
         st = iterate(
-            g, o, c, s, local, t0, stats,
+            g, w, o, c, s, local, t0, stats,
             [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
                 const uint64_t* mc = w.masks[k & 1];
                 uint64_t* mn = w.masks[(k & 1) ^ 1];
@@ -941,6 +1052,11 @@ wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void*
 wedge_status wedge_bfs(wedge_graph_t g, uint32_t src, uint32_t* level_dev, const wedge_opts* opts,
                        hipStream_t stream, wedge_stats* stats) {
     return run_frontier_app(kBfs, g, src, level_dev, opts, stream, stats);
+}
+
+wedge_status wedge_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* level_dev,
+                               const wedge_opts* opts, hipStream_t stream, wedge_stats* stats) {
+    return run_bfs_noalloc(g, src, level_dev, opts, stream, stats);
 }
 
 wedge_status wedge_cc(wedge_graph_t g, uint32_t* label_dev, const wedge_opts* opts,

@@ -363,4 +363,12 @@ void mlp_features(float* x, double fcount, double active, double n, double m, do
                   double prev_us, double prev_mode, double app);
 hipError_t launch_bfs_persistent(bool ms, const PersistParams& P, uint32_t blocks, hipStream_t s);
 
+// Allocation-free BFS (noalloc.hip): the fixed device scratch of each GPU,
+// looked up once per device (dev must be the current device), and the lock
+// that runs its users one at a time per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_scratch(int dev, void** ptr);
+std::mutex& noalloc_run_lock(int dev);  // dev in [0, kNoAllocMaxDevices)
+
 }  // namespace wedge
