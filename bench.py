@@ -92,22 +92,52 @@ def minpull_bytes(info, weighted):
 
 
 def cpu_baseline(ro, col, w, srcs, m):
+    """The CPU oracle on a bounded sample of the bench workload, on this host.
+
+    value: the oracle's synchronous full-scan pull engine (the method's own
+    iteration semantics, OpenMP over destinations on every host thread; its
+    CSC build and per-iteration frontier scan are serial) for BFS from the
+    first bench source, plus 2 of the 20 PageRank iterations (FP64, OpenMP),
+    on the same R-MAT s24 graph; units M + 2M over the summed time.
+    engines: per the measurement plan, the textbook push engine on 1 core
+    (BFS at s24) and the pull engine on 1 core and on every thread at s22
+    (BFS), each with the threads it used."""
+    import gen
     import oracle
     log("timing the CPU oracle on a sample of the workload")
+    nthr = oracle.threads()
     t = {}
-    t0 = time.perf_counter(); oracle.bfs(ro, col, int(srcs[0])); t["bfs"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.cc(ro, col); t["cc"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.sssp(ro, col, w, int(srcs[0])); t["sssp"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.pagerank(ro, col, 2, 0.85); t["pr"] = time.perf_counter() - t0
-    units = m + m + m + 2 * m
+    t0 = time.perf_counter()
+    oracle.pull_engine("bfs", ro, col, None, int(srcs[0]), chunk=0)
+    t["bfs_pull_engine"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.pagerank(ro, col, 2, 0.85)
+    t["pagerank_2_iters"] = time.perf_counter() - t0
     total = sum(t.values())
     log("oracle seconds: " + ", ".join(f"{k}={v:.2f}" for k, v in t.items()))
-    return {"value": round(units / total / 1e9, 4), "unit": "GTEPS", "cores": oracle.threads(),
+    engines = {}
+    t0 = time.perf_counter()
+    oracle.push_engine("bfs", ro, col, None, int(srcs[0]))
+    dt = time.perf_counter() - t0
+    engines["push_engine_bfs_rmat24_1core"] = {"s": round(dt, 3), "gteps": round(m / dt / 1e9, 4),
+                                               "threads": 1}
+    r22, c22 = gen.rmat(22, 16, seed=1)
+    s22 = int(gen.pick_sources(r22, 1, seed=3)[0])
+    m22 = len(c22)
+    for thr in (1, nthr):
+        t0 = time.perf_counter()
+        oracle.pull_engine("bfs", r22, c22, None, s22, chunk=0, threads=thr)
+        dt = time.perf_counter() - t0
+        engines[f"pull_engine_bfs_rmat22_{thr}threads"] = {"s": round(dt, 3),
+                                                          "gteps": round(m22 / dt / 1e9, 4),
+                                                          "threads": thr}
+    log("oracle engines: " + ", ".join(f"{k}={v['s']}s" for k, v in engines.items()))
+    return {"value": round(3 * m / total / 1e9, 4), "unit": "GTEPS", "cores": nthr,
             "kind": "oracle", "cpu": cpu_model(),
-            "sample": ("same R-MAT s24 graph: BFS and SSSP from 1 source (sequential queue BFS, "
-                       "Dial/Dijkstra), CC by union-find (sequential), PageRank 2 of 20 iterations "
-                       "(FP64, OpenMP over destinations); units M+M+M+2M over the summed time"),
-            "seconds": {k: round(v, 3) for k, v in t.items()}}
+            "sample": ("same R-MAT s24 graph: BFS from 1 source by the oracle's synchronous "
+                       "full-scan pull engine and 2 of the 20 PageRank iterations (FP64), both "
+                       f"OpenMP on {nthr} threads; units M + 2M over the summed time"),
+            "seconds": {k: round(v, 3) for k, v in t.items()}, "engines": engines}
 
 
 def cpu_model():
@@ -221,6 +251,185 @@ def learned_section(W, g, gs, srcs, m, outs, reps=2):
     return res
 
 
+def engines_section(W, g, gs, src, m, outs, reps=2):
+    """The paper's comparison on this GPU (Fig. 8 and Fig. 9 analogues): BFS and
+    SSSP from the first bench source and CC, end to end under the Wedge
+    threshold gate, the hybrid baseline (push below 5% of the edges, a pull over
+    every in-edge above), the push engine alone and the pull over every in-edge
+    alone (best of `reps` runs each); and per-iteration device times of the
+    push engine, the full pull and the Wedge pull (translation included) from
+    the same frontiers."""
+    lev, dist, lab = outs
+    res = {"unit": "ms per run (GTEPS = M/t)", "source": int(src)}
+    for app in ("bfs", "sssp", "cc"):
+        row = {}
+        for gate in ("threshold", "hybrid", "push", "full"):
+            if app == "bfs":
+                fn = lambda: W.bfs(g, src, out=lev, gate=gate)
+            elif app == "sssp":
+                fn = lambda: W.sssp(g, src, out=dist, gate=gate)
+            else:
+                fn = lambda: W.cc(gs, out=lab, gate=gate)
+            t = timed(fn, reps)
+            row[gate] = {"ms": round(t * 1e3, 3), "gteps": round(m / t / 1e9, 3)}
+        per_iter = {}
+        for gate in ("push", "full", "wedge"):
+            if app == "bfs":
+                _, st, tr = W.bfs(g, src, out=lev, gate=gate, time_iters=True, trace_cap=4096)
+            elif app == "sssp":
+                _, st, tr = W.sssp(g, src, out=dist, gate=gate, time_iters=True, trace_cap=4096)
+            else:
+                _, st, tr = W.cc(gs, out=lab, gate=gate, time_iters=True, trace_cap=4096)
+            per_iter[gate] = [round(r["ms"], 4) for r in tr]
+            if gate == "push":
+                per_iter["active_edges_pct"] = [round(100.0 * r["active_edges"] / (gs.m if app == "cc" else m), 4)
+                                                for r in tr]
+        wins = sum(1 for a, b in zip(per_iter["wedge"], per_iter["push"]) if a < b)
+        row["per_iteration_ms"] = per_iter
+        row["iterations_wedge_beats_push"] = f"{wins}/{len(per_iter['push'])}"
+        row["threshold_over_hybrid"] = round(row["hybrid"]["ms"] / row["threshold"]["ms"], 3)
+        res[app] = row
+    return res
+
+
+def inplace_section(W, g, gs, src, outs, reps=2, grid_side=4096):
+    """Synchronous (Jacobi) against in-place (asynchronous) pulls for SSSP and CC
+    (threshold gate; and the in-place pull over every in-edge in every
+    iteration): on the bench graph, and on a grid_side^2 2-D mesh
+    in row-major vertex order (a high-diameter stand-in for a road network,
+    the graph class on which the paper saw drops travel several hops per
+    iteration). Iterations and best-of-`reps` wall time per run."""
+    import torch
+
+    import gen
+    lev, dist, lab = outs
+    res = {"unit": "ms per run; iterations"}
+
+    def both(name, sssp_g, cc_g, s, dout, lout):
+        row = {}
+        for app in ("sssp", "cc"):
+            r = {}
+            for mode, kw in (("jacobi", {}), ("inplace", {"inplace": True}),
+                             ("inplace_full_pull", {"inplace": True, "gate": "full"})):
+                if app == "sssp":
+                    fn = lambda: W.sssp(sssp_g, s, out=dout, **kw)
+                else:
+                    fn = lambda: W.cc(cc_g, out=lout, **kw)
+                _, st, _ = fn()
+                r[mode] = {"iterations": st["iterations"], "ms": round(timed(fn, reps) * 1e3, 3)}
+            r["speedup"] = round(r["jacobi"]["ms"] / min(r["inplace"]["ms"], r["inplace_full_pull"]["ms"]), 3)
+            row[app] = r
+        res[name] = row
+
+    both("rmat24", g, gs, src, dist, lab)
+    log(f"in-place: {grid_side}x{grid_side} grid")
+    ro, col = gen.grid2d(grid_side, grid_side)
+    w = gen.edge_weights(ro, col, seed=4)
+    n = len(ro) - 1
+    gg = W.Graph.from_csr(ro, col, w, keep_ids=True)
+    ggs = W.Graph.from_csr(ro, col, symmetrize=True, keep_ids=True)
+    d2 = torch.empty(n, dtype=torch.int32, device="cuda")
+    l2 = torch.empty(n, dtype=torch.int32, device="cuda")
+    both(f"grid{grid_side}x{grid_side}", gg, ggs, 0, d2, l2)
+    res[f"grid{grid_side}x{grid_side}"]["n"] = n
+    res[f"grid{grid_side}x{grid_side}"]["m"] = int(len(col))
+    gg.close()
+    ggs.close()
+    return res
+
+
+def configs_section(m_rmat24, steps=10):
+    """The other configurations of the measurement plan, outside the headline:
+    config 1 (R-MAT s16, BFS from 8 sources: median of `steps` runs after 2
+    warm-ups per source), config 2's Erdos-Renyi graph (G(2^24, M of the R-MAT
+    s24 graph), BFS and SSSP from 4 sources, CC; best of 2), and config 3
+    (PageRank, 20 iterations, on R-MAT s26, with the pull's roofline)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1903_07754_amd as W
+    res = {}
+    log("configs: R-MAT s16 BFS from 8 sources")
+    ro, col = gen.rmat(16, 16, seed=1)
+    srcs = [int(x) for x in gen.pick_sources(ro, 8, seed=2)]
+    g = W.Graph.from_csr(ro, col)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    meds = []
+    for sv in srcs:
+        for _ in range(2):
+            W.bfs(g, sv, out=out)
+        ts = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            W.bfs(g, sv, out=out)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        meds.append(float(np.median(ts)))
+    res["config1_rmat16_bfs"] = {
+        "n": g.n, "m": g.m, "sources": srcs, "median_ms_per_source": [round(x * 1e3, 4) for x in meds],
+        "gteps": round(g.m * len(meds) / sum(meds) / 1e9, 3)}
+    g.close()
+    del ro, col
+
+    log("configs: Erdos-Renyi G(2^24, m) BFS/SSSP x4, CC")
+    ro, col = gen.erdos_renyi(1 << 24, m_rmat24, seed=2)
+    w = gen.edge_weights(ro, col, seed=4)
+    srcs = [int(x) for x in gen.pick_sources(ro, 4, seed=3)]
+    n, m = len(ro) - 1, len(col)
+    g = W.Graph.from_csr(ro, col, w)
+    gs = W.Graph.from_csr(ro, col, symmetrize=True)
+    del ro, col, w
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    row = {"n": n, "m": m, "m_undirected": gs.m, "unit": "ms per run; GTEPS = M/t"}
+    for app in ("bfs", "sssp", "cc"):
+        if app == "bfs":
+            fn = lambda: [W.bfs(g, sv, out=out) for sv in srcs]
+        elif app == "sssp":
+            fn = lambda: [W.sssp(g, sv, out=out) for sv in srcs]
+        else:
+            fn = lambda: W.cc(gs, out=out)
+        fn()
+        runs = 1 if app == "cc" else len(srcs)
+        t = timed(fn, 2) / runs
+        row[app] = {"ms": round(t * 1e3, 3), "gteps": round(m / t / 1e9, 3)}
+    res["config2_er24"] = row
+    g.close()
+    gs.close()
+
+    log("configs: PageRank on R-MAT s26")
+    ro, col = gen.rmat(26, 16, seed=1)
+    n, m = len(ro) - 1, len(col)
+    g = W.Graph.from_csr(ro, col)
+    del ro, col
+    rank = torch.empty(n, dtype=torch.float32, device="cuda")
+    W.pagerank(g, 20, 0.85, out=rank)
+    ms, pull_ms, launches = 0.0, 0.0, 0
+    for _ in range(2):
+        _, st = W.pagerank(g, 20, 0.85, out=rank, time_pull=True)
+        ms += st["ms"]
+        pull_ms += st["pull_ms"]
+        launches += st["pull_launches"]
+    info = g.info
+    alg = pr_pull_bytes(info)
+    avg = pull_ms / 1e3 / launches
+    name = pr_kernel_name(info)
+    traffic = measured_traffic(name, "rmat26")
+    roof = {"kernel": name, "bound": "hbm", "achieved": round(alg / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(alg / avg / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "avg_launch_us": round(avg * 1e6, 2), "launches": launches,
+            "algorithmic_bytes_per_launch": int(alg)}
+    if traffic:
+        roof["traffic_gbs"] = round(traffic / avg / 1e9, 1)
+        roof["traffic_frac"] = round(traffic / avg / 1e9 / HBM_PEAK_GBS, 4)
+    res["config3_pagerank_rmat26"] = {"n": n, "m": m, "ms_per_run": round(ms / 2, 3),
+                                      "gteps": round(20 * m * 2 / (ms / 1e3) / 1e9, 3),
+                                      "roofline": roof}
+    g.close()
+    return res
+
+
 def batched_section(reps=3):
     """Batched BFS against the plain threshold-gated single-query path on the
     same GPU: 64 sources on R-MAT scale 22 as 64-bit masks in one traversal,
@@ -307,6 +516,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-engines", action="store_true")
+    ap.add_argument("--no-inplace", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip config 1 (s16), the ER s24 graph and PageRank on R-MAT s26")
     ap.add_argument("--pagerank-only", action="store_true",
                     help="time only the PageRank leg (used for the scale-26 roofline)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -435,14 +648,23 @@ def main():
         "roofline": roof,
         "roofline_others": roofs[1:],
     }
+    if not args.no_engines:
+        log("engines: Wedge pull vs hybrid vs push vs full pull")
+        out["engines"] = engines_section(W, g, gs, srcs[0], m, (lev, dist, lab))
+    if not args.no_inplace:
+        log("in-place vs synchronous pulls")
+        out["inplace"] = inplace_section(W, g, gs, srcs[0], (lev, dist, lab))
     if not args.no_learned:
         log("learned gate vs threshold rule on the bench graph")
         out["learned_gate"] = learned_section(W, g, gs, srcs, m, (lev, dist, lab))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ro, col, w, srcs, m)
-    if not args.no_batched:
+    if not args.no_batched or not args.no_configs:
         del g, gs, lev, lab, dist, rank
+    if not args.no_batched:
         out["batched"] = batched_section()
+    if not args.no_configs:
+        out["configs"] = configs_section(m)
     print(json.dumps(out), flush=True)
     if args.copy_probe_mib:
         nbytes = args.copy_probe_mib << 20

@@ -17,20 +17,26 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libwedgegen.so")
+# WEDGE_GEN_LIB selects another build (the address/undefined-behaviour sanitizer
+# build, libwedgegen_asan.so, in the host sanitizer test)
+_SO = os.environ.get("WEDGE_GEN_LIB") or os.path.join(_HERE, "libwedgegen.so")
+_SO_ASAN = os.path.join(_HERE, "libwedgegen_asan.so")
 _lib = None
 
 RMAT_ABCD = (0.57, 0.19, 0.19, 0.05)
 
 
-def build() -> str:
-    """Compile gen.c into libwedgegen.so (gcc, OpenMP)."""
+def build(sanitize: bool = False) -> str:
+    """Compile gen.c into libwedgegen.so (gcc, OpenMP); with sanitize, into
+    libwedgegen_asan.so under AddressSanitizer and UBSan."""
     src = os.path.join(_HERE, "gen.c")
-    tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-fPIC", "-shared",
-                           "-o", tmp, src])
-    os.replace(tmp, _SO)
-    return _SO
+    out = _SO_ASAN if sanitize else os.path.join(_HERE, "libwedgegen.so")
+    tmp = out + ".tmp"
+    flags = (["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+              "-fno-sanitize-recover=undefined"] if sanitize else ["-O3", "-march=x86-64-v2"])
+    subprocess.check_call(["gcc", *flags, "-fopenmp", "-fPIC", "-shared", "-o", tmp, src])
+    os.replace(tmp, out)
+    return out
 
 
 def _load():

@@ -42,6 +42,9 @@
  *                             every block exit and the run return WEDGE_ERR_HIP.
  *   WEDGE_HOST_THREADS        threads of the host-side layout build (else
  *                             OMP_NUM_THREADS, else the hardware count).
+ *   WEDGE_TUNE_CACHE          path of a text file that keeps the autotuner's
+ *                             table across processes (read on first use,
+ *                             rewritten after every wedge_tune_bfs).
  */
 #ifndef WEDGE_H
 #define WEDGE_H
@@ -166,14 +169,21 @@ typedef enum {
     WEDGE_GATE_THRESHOLD = 0,    /* Wedge Frontier iff A_k < floor(theta * m) (the paper's rule) */
     WEDGE_GATE_ALWAYS_WEDGE = 1, /* build the Wedge Frontier every iteration */
     WEDGE_GATE_ALWAYS_FULL = 2,  /* never build it: pull over all in-edges every iteration */
-    WEDGE_GATE_LEARNED = 3       /* learned cost model (see wedge_model_*); falls back to the
+    WEDGE_GATE_LEARNED = 3,      /* learned cost model (see wedge_model_*); falls back to the
                                     threshold rule when no valid model is given */
+    WEDGE_GATE_ALWAYS_PUSH = 4,  /* baseline: the push engine every iteration (Background, Push
+                                    vs. Pull): each frontier vertex sends its value along its
+                                    out-edges, destinations updated by atomics */
+    WEDGE_GATE_HYBRID = 5        /* baseline: the hybrid engine the paper compares against
+                                    (Background, Hybrid Graph Processing): push iff
+                                    A_k < floor(theta * m), else a pull over every in-edge; theta
+                                    defaults to 5% (threshold_ppm 0 = 50000) for every application */
 } wedge_gate;
 
 /* per-iteration record written to wedge_opts.trace */
 typedef struct {
     uint32_t iter;          /* k */
-    uint32_t mode;          /* 0 = full pull, 1 = Wedge Frontier */
+    uint32_t mode;          /* 0 = full pull, 1 = Wedge Frontier, 2 = push */
     uint32_t chunk_edges;   /* group size used (mode 1) */
     uint32_t reserved;
     uint64_t frontier;      /* |F_k| */
@@ -190,11 +200,22 @@ typedef struct {
                                      kernel (grid barriers between steps, the fullness gate
                                      evaluated on the device), captured once in a hipGraph and
                                      replayed; per-iteration times are not available */
+#define WEDGE_RUN_INPLACE    0x8u /* CC and SSSP pull gates only: the pull reads sources' values
+                                     as this iteration lowers them (asynchronous, Gauss-Seidel
+                                     style) instead of the values committed at the end of the
+                                     previous iteration, so a drop can travel several hops in one
+                                     iteration (the multi-hop propagation the paper observes
+                                     with coarse groups; Evaluation, Frontier Precision). The
+                                     result is the same fixed point, bit for bit, in at most as
+                                     many iterations; the per-iteration frontiers then depend on
+                                     the schedule. WEDGE_ERR_UNSUPPORTED for BFS kinds, PageRank
+                                     and the push and hybrid gates */
 
 typedef struct {
     uint32_t gate;           /* wedge_gate */
     uint32_t threshold_ppm;  /* theta in parts per million of the traversed edge count; 0 = the
-                                application default (BFS 10000 = 1%, CC/SSSP 200000 = 20%) */
+                                application default (BFS 10000 = 1%, CC/SSSP 200000 = 20%;
+                                the hybrid gate: 50000 = 5%) */
     uint32_t chunk_edges;    /* edges per Wedge Frontier bit: a power of two in [1, 4096];
                                 0 = application default (BFS 32, CC/SSSP 16) */
     uint32_t max_iters;      /* 0 = unlimited (n + 1 bounds every application) */
@@ -221,12 +242,21 @@ typedef struct {
     double pull_ms;          /* sum of event-timed pull kernel durations */
     double full_pull_ms;     /* of which the pulls over every in-edge */
     uint32_t full_pull_launches; /* timed pulls over every in-edge */
-    uint32_t reserved;
+    uint32_t push_iters;     /* iterations run by the push engine (push and hybrid gates) */
 } wedge_stats;
 
 /*
  * BFS (Evaluation, Applications): level_dev[n] receives the hop level of every
  * vertex from src, 0xFFFFFFFF when unreachable. opts and stats are nullable.
+ *
+ * BFS, CC and SSSP share one iteration semantics whatever engine runs an
+ * iteration (the Wedge pull, the pull over every in-edge, or the push
+ * engine of the baseline gates): iteration k uses the values committed at
+ * the end of iteration k-1, and a vertex joins the next frontier exactly when
+ * its value drops. Results and per-iteration frontiers are therefore the same
+ * under every gate. The push engine needs the graph's out-edges in CSR order;
+ * the first push or hybrid run on a graph builds them on the device (4 bytes
+ * per edge, 8 with weights) and keeps them with the graph.
  */
 wedge_status wedge_bfs(wedge_graph_t g, uint32_t src, uint32_t* level_dev, const wedge_opts* opts,
                        hipStream_t stream, wedge_stats* stats);
@@ -251,7 +281,8 @@ wedge_status wedge_bfs(wedge_graph_t g, uint32_t src, uint32_t* level_dev, const
  * start at zero): calls that overlapped on one GPU would race, so the library
  * runs them one at a time per device within a process. Refused with
  * WEDGE_ERR_UNSUPPORTED: WEDGE_GATE_LEARNED (its model buffers are
- * allocated on first use) and any wedge_opts.flags bit (timing events,
+ * allocated on first use), the push and hybrid gates (their out-edge arrays
+ * are built on first use) and any wedge_opts.flags bit (timing events,
  * persistent launch buffers).
  */
 wedge_status wedge_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* level_dev,
@@ -443,17 +474,18 @@ wedge_status wedge_bfs_batch(wedge_graph_t g, const uint32_t* srcs, uint32_t* le
  * maximum); best of two runs each. It writes the fastest options to *best (its gate
  * and threshold are taken from *best on entry). Results do not depend on the
  * choice. out_dev is scratch output of the kind's size. The winner is also
- * kept in a process-wide table keyed by (kind, source count, ceil(log2 m)),
- * which wedge_tune_lookup reads.
+ * kept in a process-wide table keyed by (kind, source count, ceil(log2 m),
+ * the device's compute unit count), which wedge_tune_lookup reads, and, when
+ * WEDGE_TUNE_CACHE names a file, in that file, so later processes find it.
  */
 wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs, uint32_t count,
                             uint32_t* out_dev, hipStream_t stream, wedge_opts* best,
                             double* best_ms);
 
-/* Tuned options for (kind, count, edge count m), if wedge_tune_bfs has
- * recorded them in this process: copies chunk_edges, flags' persistent bit,
- * blocks_per_cu and rows_per_wave into *opts and returns WEDGE_OK; else
- * WEDGE_ERR_UNSUPPORTED. */
+/* Tuned options for (kind, count, edge count m) on the current device, if
+ * wedge_tune_bfs has recorded them in this process or in the WEDGE_TUNE_CACHE
+ * file: copies chunk_edges, flags' persistent bit, blocks_per_cu and
+ * rows_per_wave into *opts and returns WEDGE_OK; else WEDGE_ERR_UNSUPPORTED. */
 wedge_status wedge_tune_lookup(uint32_t kind, uint32_t count, uint64_t m, wedge_opts* opts);
 
 /* ------------------------------------------------------- single steps */

@@ -21,20 +21,30 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# WEDGE_ORACLE_LIB selects another build (the address/undefined-behaviour sanitizer
+# build, liboracle_asan.so, in the host sanitizer test)
+_SO = os.environ.get("WEDGE_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_SO_ASAN = os.path.join(_HERE, "liboracle_asan.so")
 _lib = None
 
 INF = 0xFFFFFFFF
 APP = {"bfs": 1, "cc": 2, "sssp": 3}
 
 
-def build() -> str:
-    """Compile oracle.c into liboracle.so (gcc -O2, OpenMP)."""
+SANITIZE = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+            "-fno-sanitize-recover=undefined"]
+
+
+def build(sanitize: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc -O2, OpenMP); with sanitize, into
+    liboracle_asan.so under AddressSanitizer and UBSan (host code only)."""
     src = os.path.join(_HERE, "oracle.c")
-    tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
-    os.replace(tmp, _SO)
-    return _SO
+    out = _SO_ASAN if sanitize else os.path.join(_HERE, "liboracle.so")
+    tmp = out + ".tmp"
+    flags = SANITIZE if sanitize else ["-O2"]
+    subprocess.check_call(["gcc", *flags, "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
 
 
 def _load():

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libwedge.so")
+# WEDGE_LIB selects another build of the library (e.g. libwedge_debug.so, with
+# device checks compiled in)
+LIB_PATH = os.environ.get("WEDGE_LIB") or os.path.join(HERE, "libwedge.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "wedge.h")
 
 OK = 0
@@ -23,8 +25,8 @@ STATUS = {0: "WEDGE_OK", -1: "WEDGE_ERR_INVALID_ARG", -2: "WEDGE_ERR_BAD_GRAPH",
           -9: "WEDGE_ERR_BUSY"}
 
 INPUT_DEVICE, SYMMETRIZE, HOST_ONLY, KEEP_IDS = 0x1, 0x2, 0x4, 0x8
-GATE = {"threshold": 0, "wedge": 1, "full": 2, "learned": 3}
-RUN_TIME_PULL, RUN_TIME_ITERS, RUN_PERSISTENT = 0x1, 0x2, 0x4
+GATE = {"threshold": 0, "wedge": 1, "full": 2, "learned": 3, "push": 4, "hybrid": 5}
+RUN_TIME_PULL, RUN_TIME_ITERS, RUN_PERSISTENT, RUN_INPLACE = 0x1, 0x2, 0x4, 0x8
 TUNE = {"single": 0, "multisource": 1, "batch": 2}
 LAYOUT = {"col_off": 0, "in_src": 1, "in_w": 2, "row_off": 3, "pos": 4, "rowmask": 5,
           "rowseg": 6, "nzdst": 7, "pr_spans": 8, "perm": 9}
@@ -74,7 +76,7 @@ class Stats(C.Structure):
                 ("full_iters", C.c_uint32), ("pull_launches", C.c_uint32),
                 ("edges_scanned", C.c_uint64), ("ms", C.c_double), ("pull_ms", C.c_double),
                 ("full_pull_ms", C.c_double), ("full_pull_launches", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("push_iters", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -173,10 +175,15 @@ class Graph:
     def __init__(self, handle, keep=None):
         self._h = C.c_void_p(handle)
         self._keep = keep
+        info = self.info
+        self.n, self.m = info["n"], info["m"]
+
+    @property
+    def info(self):
+        """wedge_graph_info, read afresh (device_bytes grows as workspaces are made)."""
         info = GraphInfo()
         check(lib().wedge_graph_get_info(self._h, C.byref(info)))
-        self.info = {k: getattr(info, k) for k, _ in GraphInfo._fields_}
-        self.n, self.m = info.n, info.m
+        return {k: getattr(info, k) for k, _ in GraphInfo._fields_}
 
     @staticmethod
     def _make(fn, n, off, ids, w, symmetrize, host_only, stream, keep_ids=False):
@@ -259,12 +266,12 @@ class Graph:
 
 def make_opts(gate="threshold", theta_ppm=0, chunk=0, max_iters=0, time_pull=False,
               time_iters=False, trace_cap=0, model=None, persistent=False, blocks_per_cu=0,
-              rows_per_wave=0):
+              rows_per_wave=0, inplace=False):
     o = Opts()
     o.gate = GATE[gate] if isinstance(gate, str) else int(gate)
     o.threshold_ppm, o.chunk_edges, o.max_iters = theta_ppm, chunk, max_iters
     o.flags = ((RUN_TIME_PULL if time_pull else 0) | (RUN_TIME_ITERS if time_iters else 0)
-               | (RUN_PERSISTENT if persistent else 0))
+               | (RUN_PERSISTENT if persistent else 0) | (RUN_INPLACE if inplace else 0))
     o.blocks_per_cu = blocks_per_cu
     o.rows_per_wave = rows_per_wave
     trace = (IterRecord * trace_cap)() if trace_cap else None
@@ -315,9 +322,10 @@ def sssp(g, src, out=None, stream=None, trace_cap=0, **kw):
     return _run_int(lib().wedge_sssp, g, (src,), out, stream, trace_cap, **kw)
 
 
-def pagerank(g, iters=20, damping=0.85, out=None, stream=None, time_pull=False, rows_per_wave=0):
+def pagerank(g, iters=20, damping=0.85, out=None, stream=None, time_pull=False, rows_per_wave=0,
+             **kw):
     import torch
-    o, _ = make_opts(time_pull=time_pull, rows_per_wave=rows_per_wave)
+    o, _ = make_opts(time_pull=time_pull, rows_per_wave=rows_per_wave, **kw)
     if out is None:
         out = torch.empty(max(g.n, 1), dtype=torch.float32, device="cuda")
     st = Stats()

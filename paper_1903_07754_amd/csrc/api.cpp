@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "wedge_internal.h"
 
 namespace wedge {
@@ -23,6 +25,16 @@ using namespace wedge;
 namespace {
 
 thread_local std::string g_err;
+
+// roctx range over a scope: runs and iterations show up as named phases in a
+// marker trace (rocprofv3 --marker-trace); without a tool attached the calls
+// do nothing.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 wedge_status fail(wedge_status st, const std::string& msg) {
     g_err = msg;
@@ -84,13 +96,13 @@ wedge_status upload(wedge_graph_s* g, T** dst, const std::vector<T>& src, hipStr
 void free_all(wedge_graph_s* g) {
     DevGraph& d = g->dev;
     void* ptrs[] = {d.col_off, d.in_src, d.in_w, d.row_off, d.pos, d.rowmask, d.rowseg, d.nzdst, d.spans,
-                    d.perm, d.inv};
+                    d.perm, d.inv, d.out_dst, d.out_w};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     Workspace& w = g->ws;
     void* wp[] = {w.fbits, w.fcur, w.flist[0], w.flist[1], w.degpre[0], w.degpre[1], w.val_prev,
                   w.val, w.wbits, w.chunks, w.ctl, w.pr_sum, w.pr_contrib, w.pr_rank, w.pr_head,
-                  w.pr_tail, w.pr_part, w.pr_d};
+                  w.pr_tail, w.pr_part, w.pr_d, w.fsum, w.csum, w.wsum};
     for (void* p : wp)
         if (p) (void)hipFree(p);
     if (w.ctl_host) (void)hipHostFree(w.ctl_host);
@@ -225,6 +237,12 @@ wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontie
             HIP_TRY(hipMemset(w.fbits, 0, fw ? fw * 8 : 8), "clearing frontier bitmap");
         }
         if ((st = need((void**)&w.fcur, fw * 8, "current frontier bitmap")) != WEDGE_OK) return st;
+        if (!w.fsum) {
+            w.generation++;
+            if ((st = dev_alloc(g, (void**)&w.fsum, sum_flags(d.n) * 4, "frontier summary")) != WEDGE_OK) return st;
+            HIP_TRY(hipMemset(w.fsum, 0, sum_flags(d.n) * 4), "clearing frontier summary");
+        }
+        if ((st = need((void**)&w.csum, sum_flags(d.n) * 4, "current frontier summary")) != WEDGE_OK) return st;
         if (d.inv && (st = need((void**)&w.val, (size_t)d.n * 4, "values")) != WEDGE_OK) return st;
         for (int i = 0; i < 2; ++i) {
             if ((st = need((void**)&w.flist[i], (size_t)d.n * 4, "frontier list")) != WEDGE_OK) return st;
@@ -235,12 +253,18 @@ wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontie
     if (need_chunks) {
         const uint64_t chunks = (d.m + (1ull << log_chunk) - 1) >> log_chunk;
         const uint64_t words = (chunks + 63) / 64;
-        if (words > w.wbits_words || !w.wbits) {
+        if (words > w.wbits_words || !w.wbits || !w.wsum) {
             w.generation++;
             if (w.wbits) { (void)hipFree(w.wbits); g->device_bytes -= w.wbits_words * 8; w.wbits = nullptr; }
-            if ((st = dev_alloc(g, (void**)&w.wbits, words * 8, "Wedge Frontier bitmap")) != WEDGE_OK) return st;
-            w.wbits_words = words ? words : 1;
+            if (w.wsum) { (void)hipFree(w.wsum); g->device_bytes -= sum_flags(w.wbits_words * 64) * 4; w.wsum = nullptr; }
+            w.wbits_words = 0;
+            const uint64_t alloc_words = words ? words : 1;
+            if ((st = dev_alloc(g, (void**)&w.wbits, alloc_words * 8, "Wedge Frontier bitmap")) != WEDGE_OK) return st;
+            w.wbits_words = alloc_words;
             HIP_TRY(hipMemset(w.wbits, 0, w.wbits_words * 8), "clearing Wedge bitmap");
+            const uint64_t flags = sum_flags(w.wbits_words * 64);
+            if ((st = dev_alloc(g, (void**)&w.wsum, flags * 4, "Wedge Frontier summary")) != WEDGE_OK) return st;
+            HIP_TRY(hipMemset(w.wsum, 0, flags * 4), "clearing Wedge summary");
         }
         if (chunks > w.chunks_cap || !w.chunks) {
             w.generation++;
@@ -269,11 +293,11 @@ wedge_status check_run(wedge_graph_t g, const void* out, const wedge_opts* o) {
     if (!g) return fail(WEDGE_ERR_INVALID_ARG, "graph is null");
     if (g->host_only) return fail(WEDGE_ERR_UNSUPPORTED, "graph was created with WEDGE_HOST_ONLY");
     if (!out && g->dev.n) return fail(WEDGE_ERR_INVALID_ARG, "output pointer is null");
-    if (o->gate > WEDGE_GATE_LEARNED) return fail(WEDGE_ERR_INVALID_ARG, "unknown gate");
+    if (o->gate > WEDGE_GATE_HYBRID) return fail(WEDGE_ERR_INVALID_ARG, "unknown gate");
     if (o->chunk_edges && (!is_pow2(o->chunk_edges) || o->chunk_edges > 4096))
         return fail(WEDGE_ERR_INVALID_ARG, "chunk_edges must be a power of two in [1, 4096]");
     if (o->trace_cap && !o->trace) return fail(WEDGE_ERR_INVALID_ARG, "trace_cap set but trace is null");
-    if (o->flags & ~(WEDGE_RUN_TIME_PULL | WEDGE_RUN_TIME_ITERS | WEDGE_RUN_PERSISTENT))
+    if (o->flags & ~(WEDGE_RUN_TIME_PULL | WEDGE_RUN_TIME_ITERS | WEDGE_RUN_PERSISTENT | WEDGE_RUN_INPLACE))
         return fail(WEDGE_ERR_INVALID_ARG, "unknown run flag bits");
     if (o->rows_per_wave && o->rows_per_wave != 4 && o->rows_per_wave != 8 && o->rows_per_wave != 16)
         return fail(WEDGE_ERR_INVALID_ARG, "rows_per_wave must be 0, 4, 8 or 16");
@@ -291,12 +315,38 @@ wedge_status check_rows(const wedge_opts& o, bool shaped) {
 wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t count, uint32_t* out,
                            const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats);
 
+bool push_gate(uint32_t gate) { return gate == WEDGE_GATE_ALWAYS_PUSH || gate == WEDGE_GATE_HYBRID; }
+
+// Gates that may build the Wedge Frontier (and so need its bitmap and list).
+bool wedge_gate_used(uint32_t gate) { return gate != WEDGE_GATE_ALWAYS_FULL && !push_gate(gate); }
+
+// The push engine's out-edge arrays, built once per graph on the device from
+// the edge index and the row layout.
+wedge_status ensure_push(wedge_graph_s* g, hipStream_t s) {
+    DevGraph& d = g->dev;
+    if (d.out_built) return WEDGE_OK;
+    wedge_status st;
+    if (!d.out_dst && (st = dev_alloc(g, (void**)&d.out_dst, (size_t)d.m * 4, "push out-edges")) != WEDGE_OK)
+        return st;
+    if (d.in_w && !d.out_w && (st = dev_alloc(g, (void**)&d.out_w, (size_t)d.m * 4, "push weights")) != WEDGE_OK)
+        return st;
+    HIP_TRY(launch_out_edges(d, d.pos, d.out_dst, d.out_w, s), "building push out-edges");
+    HIP_TRY(hipStreamSynchronize(s), "building push out-edges");
+    d.out_built = true;
+    return WEDGE_OK;
+}
+
 // ------------------------------------------------------------ the loop
 //
 // The control loop of one traversal (Wedge Overview, Fig. 5): with the
 // frontier's size, listed count and A read back from the device, choose the
 // mode, build the Wedge Frontier when chosen, pull, finalise, repeat until the
 // frontier is empty. The app supplies the pull and finalise launches.
+// Engine of one iteration (the mode recorded in wedge_iter_record).
+constexpr int kModeFull = 0, kModeWedge = 1, kModePush = 2;
+// Default threshold of the hybrid baseline: 5% of the edges.
+constexpr uint32_t kHybridThetaPpm = 50000;
+
 struct LoopCfg {
     int lc = 5;
     uint64_t thr = 0;
@@ -315,6 +365,9 @@ struct LoopCfg {
     uint64_t m = 0;
     uint32_t app = kBfs;       // application (a gate feature)
     int rows = kPullRows;      // pull shape: 64-edge rows per wave step
+    // values the push engine updates and reads (push and hybrid gates)
+    uint32_t* val = nullptr;
+    const uint32_t* val_prev = nullptr;
     // the smallest chunk exponent this run may use (bitmap and list sizes)
     int min_lc() const { return learned ? std::min(lc, 4) : lc; }
     uint64_t chunks_of(int l) const { return (m + (1ull << l) - 1) >> l; }
@@ -341,18 +394,24 @@ wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const L
             if (stats) { local.ms = now_ms() - t0; *stats = local; }
             return fail(WEDGE_ERR_NOT_CONVERGED, "max_iters reached with a non-empty frontier");
         }
-        bool wedge_mode;
+        int mode;  // kModeFull, kModeWedge or kModePush
         int lc = c.lc;
         if (c.learned) {
-            wedge_mode = w.ctl_host->gate.mode != 0;
+            mode = w.ctl_host->gate.mode != 0 ? kModeWedge : kModeFull;
             lc = (int)w.ctl_host->gate.lc;
         } else {
             switch (c.gate) {
-                case WEDGE_GATE_ALWAYS_WEDGE: wedge_mode = true; break;
-                case WEDGE_GATE_ALWAYS_FULL: wedge_mode = false; break;
-                default: wedge_mode = active < c.thr; break;  // the fullness threshold (strict <)
+                case WEDGE_GATE_ALWAYS_WEDGE: mode = kModeWedge; break;
+                case WEDGE_GATE_ALWAYS_FULL: mode = kModeFull; break;
+                case WEDGE_GATE_ALWAYS_PUSH: mode = kModePush; break;
+                // the hybrid engine: push below the threshold, else the full pull
+                case WEDGE_GATE_HYBRID: mode = active < c.thr ? kModePush : kModeFull; break;
+                default: mode = active < c.thr ? kModeWedge : kModeFull; break;  // strict <
             }
         }
+        const bool wedge_mode = mode == kModeWedge;
+        Range iter_range(mode == kModeWedge ? "wedge iteration"
+                         : mode == kModePush ? "push iteration" : "full-pull iteration");
         if (c.learned) HIP_TRY(launch_gate_stamp(w.ctl, s), "clearing counters");
         else HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[2], s), "event");
@@ -360,12 +419,16 @@ wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const L
         if (wedge_mode) {
             const uint64_t nch = c.chunks_of(lc);
             HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)flisted, active, d.row_off,
-                                     d.pos, lc, w.wbits, s), "frontier translation");
-            HIP_TRY(launch_compact_chunks(w.wbits, (nch + 63) / 64, w.chunks, w.ctl, s), "chunk compaction");
+                                     d.pos, lc, w.wbits, w.wsum, s), "frontier translation");
+            HIP_TRY(launch_compact_chunks(w.wbits, (nch + 63) / 64, w.chunks, w.ctl, w.wsum, s), "chunk compaction");
             maxk = active < nch ? active : nch;
         }
         if (c.time_pull) HIP_TRY(hipEventRecord(w.ev[0], s), "event");
-        HIP_TRY(pull(k, wedge_mode, maxk, cur, lc), wedge_mode ? "chunk pull" : "full pull");
+        if (mode == kModePush)
+            HIP_TRY(launch_push(c.app, w.flist[cur], w.degpre[cur], (uint32_t)flisted, active, d.row_off,
+                                d.out_dst, d.out_w, k, c.val, c.val_prev, w.fbits, w.fsum, s), "push");
+        else
+            HIP_TRY(pull(k, wedge_mode, maxk, cur, lc), wedge_mode ? "chunk pull" : "full pull");
         if (c.time_pull) HIP_TRY(hipEventRecord(w.ev[1], s), "event");
         HIP_TRY(fin(k, cur), "frontier finalisation");
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[3], s), "event");
@@ -379,7 +442,7 @@ wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const L
         if (c.time_iter) HIP_TRY(hipEventElapsedTime(&ims, w.ev[2], w.ev[3]), "event time");
         local.pull_ms += pms;
         local.pull_launches++;
-        if (!wedge_mode) {
+        if (mode == kModeFull) {
             local.full_pull_ms += pms;
             local.full_pull_launches++;
         }
@@ -387,7 +450,7 @@ wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const L
         if (o.trace && k < o.trace_cap) {
             wedge_iter_record& r = o.trace[k];
             r.iter = k;
-            r.mode = wedge_mode ? 1u : 0u;
+            r.mode = (uint32_t)mode;
             r.chunk_edges = wedge_mode ? (1u << lc) : 0u;
             r.reserved = 0;
             r.frontier = fcount;
@@ -396,7 +459,8 @@ wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const L
             r.ms = ims;
             r.reserved2 = 0.f;
         }
-        if (wedge_mode) { local.wedge_iters++; local.edges_scanned += marked << lc; }
+        if (mode == kModeWedge) { local.wedge_iters++; local.edges_scanned += marked << lc; }
+        else if (mode == kModePush) { local.push_iters++; local.edges_scanned += active; }
         else { local.full_iters++; local.edges_scanned += d.m; }
         fcount = w.ctl_host->ftotal;
         flisted = w.ctl_host->fnext >> kDegBits;
@@ -411,7 +475,8 @@ LoopCfg loop_cfg(const wedge_opts& o, const DevGraph& d, App app, uint32_t theta
                  uint32_t chunk_default) {
     LoopCfg c;
     c.app = (uint32_t)app;
-    const uint32_t theta = o.threshold_ppm ? o.threshold_ppm : theta_default;
+    const uint32_t theta = o.threshold_ppm ? o.threshold_ppm
+                                           : (o.gate == WEDGE_GATE_HYBRID ? kHybridThetaPpm : theta_default);
     const uint32_t chunk = o.chunk_edges ? o.chunk_edges : chunk_default;
     c.lc = log2u(chunk);
     c.thr = ((uint64_t)theta * d.m) / 1000000ull;
@@ -467,14 +532,20 @@ wedge_status clear_bitmaps(wedge_graph_t g, const LoopCfg& c, hipStream_t s) {
     const uint64_t fwords = ((uint64_t)g->dev.n + 63) / 64;
     HIP_TRY(hipMemsetAsync(w.fbits, 0, fwords * 8, s), "clearing frontier bitmap");
     HIP_TRY(hipMemsetAsync(w.fcur, 0, fwords * 8, s), "clearing frontier bitmap");
-    if (c.gate != WEDGE_GATE_ALWAYS_FULL)
-        HIP_TRY(hipMemsetAsync(w.wbits, 0, (c.chunks_of(c.min_lc()) + 63) / 64 * 8, s), "clearing Wedge bitmap");
+    HIP_TRY(hipMemsetAsync(w.fsum, 0, sum_flags(g->dev.n) * 4, s), "clearing frontier summary");
+    HIP_TRY(hipMemsetAsync(w.csum, 0, sum_flags(g->dev.n) * 4, s), "clearing frontier summary");
+    if (wedge_gate_used(c.gate)) {
+        const uint64_t words = (c.chunks_of(c.min_lc()) + 63) / 64;
+        HIP_TRY(hipMemsetAsync(w.wbits, 0, words * 8, s), "clearing Wedge bitmap");
+        HIP_TRY(hipMemsetAsync(w.wsum, 0, sum_flags(words * 64) * 4, s), "clearing Wedge summary");
+    }
     return WEDGE_OK;
 }
 
 // BFS, CC and SSSP from one source (or all vertices for CC).
 wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* val,
                               const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
+    Range run_range(app == kBfs ? "wedge_bfs" : app == kCc ? "wedge_cc" : "wedge_sssp");
     const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
     wedge_status st = check_run(g, val, &o);
     if (st != WEDGE_OK) return st;
@@ -487,8 +558,12 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     }
     if (app == kCc && !(g->flags & WEDGE_SYMMETRIZE))
         return fail(WEDGE_ERR_UNSUPPORTED, "CC runs on the undirected view: create the graph with WEDGE_SYMMETRIZE");
+    const bool inplace = o.flags & WEDGE_RUN_INPLACE;
+    if (inplace && (app == kBfs || push_gate(o.gate)))
+        return fail(WEDGE_ERR_UNSUPPORTED, "the in-place pull applies to CC and SSSP with pull gates");
     if (app == kBfs && (o.flags & WEDGE_RUN_PERSISTENT))
         return run_bfs_roots(g, &src, 1, val, opts_in, s, stats);
+    if ((o.flags & WEDGE_RUN_PERSISTENT)) return fail(WEDGE_ERR_UNSUPPORTED, "persistent runs are BFS kinds only");
     if ((st = check_rows(o, app == kBfs)) != WEDGE_OK) return st;
     RunGuard guard(g->busy);
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
@@ -497,7 +572,8 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
     LoopCfg c = loop_cfg(o, d, (App)app, app == kBfs ? 10000u : 200000u, app == kBfs ? 32u : 16u);
     if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
-    if ((st = ensure_workspace(g, c.min_lc(), true, c.gate != WEDGE_GATE_ALWAYS_FULL)) != WEDGE_OK) return st;
+    if ((st = ensure_workspace(g, c.min_lc(), true, wedge_gate_used(c.gate))) != WEDGE_OK) return st;
+    if (push_gate(c.gate) && (st = ensure_push(g, s)) != WEDGE_OK) return st;
     Workspace& w = g->ws;
     if ((st = clear_bitmaps(g, c, s)) != WEDGE_OK) return st;
     // values are computed in internal vertex order; a relabelled graph works in
@@ -506,26 +582,29 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     if (d.inv) val = w.val;
     const uint32_t isrc = (app != kCc && !g->perm_host.empty()) ? g->perm_host[src] : src;
     uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
+    c.val = val;
+    c.val_prev = vprev;
     HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
     if (app == kCc) {
         HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, d.inv, val, w.val_prev, w.flist[0], w.degpre[0],
-                                w.fcur, w.ctl, s), "seeding CC");
+                                w.fcur, w.csum, w.ctl, s), "seeding CC");
     } else {
         HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
         if (vprev) HIP_TRY(launch_fill_u32(vprev, d.n, kInf, s), "initialising values");
         HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur,
-                                   w.ctl, s), "seeding source");
+                                   w.csum, w.ctl, s), "seeding source");
     }
     st = iterate(
         g, w, o, c, s, local, t0, stats,
         [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
             return wedge_mode ? launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev,
-                                                   w.fcur, w.fbits, s, c.rows)
-                              : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s, c.rows);
+                                                   w.fcur, w.fbits, w.fsum, s, c.rows, inplace)
+                              : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, w.fsum, s, c.rows, inplace);
         },
         [&](uint32_t, int cur) {
+            // the in-place pull reads no committed copy, so nothing is committed
             return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                   vprev, val, w.fcur, s);
+                                   inplace ? nullptr : vprev, val, w.fcur, w.fsum, w.csum, s);
         });
     if (st != WEDGE_OK) return st;
     if (d.inv) {
@@ -547,8 +626,9 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
 // serve both iterations' roles: the translation reads them before the pull,
 // and the finalisation rewrites them after it, in stream order.
 struct NoAllocPlan {
-    uint64_t fwords, wwords, nchunks;
-    size_t off_fbits, off_fcur, off_flist, off_degpre, off_val, off_wbits, off_chunks, off_ctl, total;
+    uint64_t fwords, wwords, nchunks, fflags, wflags;
+    size_t off_fbits, off_fcur, off_flist, off_degpre, off_val, off_wbits, off_chunks, off_ctl;
+    size_t off_fsum, off_csum, off_wsum, total;
 };
 
 NoAllocPlan noalloc_plan(const DevGraph& d, const LoopCfg& c) {
@@ -566,6 +646,11 @@ NoAllocPlan noalloc_plan(const DevGraph& d, const LoopCfg& c) {
     p.off_val = at;    at += d.inv ? up((size_t)d.n * 4) : 0;
     p.off_wbits = at;  at += up((p.wwords ? p.wwords : 1) * 8);
     p.off_chunks = at; at += up((p.nchunks ? p.nchunks : 1) * 4);
+    p.fflags = sum_flags(d.n);
+    p.wflags = sum_flags((p.wwords ? p.wwords : 1) * 64);
+    p.off_fsum = at;   at += up(p.fflags * 4);
+    p.off_csum = at;   at += up(p.fflags * 4);
+    p.off_wsum = at;   at += up(p.wflags * 4);
     p.total = at;
     return p;
 }
@@ -579,6 +664,8 @@ wedge_status run_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* out, const
     if (src >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
     if (o.gate == WEDGE_GATE_LEARNED)
         return fail(WEDGE_ERR_UNSUPPORTED, "the learned gate needs device model buffers: use wedge_bfs");
+    if (push_gate(o.gate))
+        return fail(WEDGE_ERR_UNSUPPORTED, "the push engine builds out-edge arrays on first use: use wedge_bfs");
     if (o.flags)
         return fail(WEDGE_ERR_UNSUPPORTED,
                     "timing and persistent runs need events or graph buffers: use wedge_bfs");
@@ -614,28 +701,36 @@ wedge_status run_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* out, const
     w.wbits_words = p.wwords;
     w.chunks = reinterpret_cast<uint32_t*>(b + p.off_chunks);
     w.chunks_cap = p.nchunks;
+    w.fsum = reinterpret_cast<uint32_t*>(b + p.off_fsum);
+    w.csum = reinterpret_cast<uint32_t*>(b + p.off_csum);
+    w.wsum = reinterpret_cast<uint32_t*>(b + p.off_wsum);
     wedge_stats local{};
     const double t0 = now_ms();
     // the scratch keeps the previous call's contents: clear what must start at zero
     HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(w.ctl), sizeof(Ctl) / 8, 0, s), "clearing counters");
     HIP_TRY(launch_fill_u64(w.fbits, p.fwords, 0, s), "clearing frontier bitmap");
     HIP_TRY(launch_fill_u64(w.fcur, p.fwords, 0, s), "clearing frontier bitmap");
-    if (c.gate != WEDGE_GATE_ALWAYS_FULL) HIP_TRY(launch_fill_u64(w.wbits, p.wwords, 0, s), "clearing Wedge bitmap");
+    HIP_TRY(launch_fill_u32_kernel(w.fsum, p.fflags, 0, s), "clearing frontier summary");
+    HIP_TRY(launch_fill_u32_kernel(w.csum, p.fflags, 0, s), "clearing frontier summary");
+    if (c.gate != WEDGE_GATE_ALWAYS_FULL) {
+        HIP_TRY(launch_fill_u64(w.wbits, p.wwords, 0, s), "clearing Wedge bitmap");
+        HIP_TRY(launch_fill_u32_kernel(w.wsum, p.wflags, 0, s), "clearing Wedge summary");
+    }
     uint32_t* val = d.inv ? w.val : out;
     const uint32_t isrc = g->perm_host.empty() ? src : g->perm_host[src];
     HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
-    HIP_TRY(launch_seed_source(isrc, d.row_off, val, nullptr, w.flist[0], w.degpre[0], w.fcur, w.ctl, s),
+    HIP_TRY(launch_seed_source(isrc, d.row_off, val, nullptr, w.flist[0], w.degpre[0], w.fcur, w.csum, w.ctl, s),
             "seeding source");
     st = iterate(
         g, w, o, c, s, local, t0, stats,
         [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
             return wedge_mode ? launch_pull_chunks(kBfs, d, k, lc, w.chunks, w.ctl, maxk, val, nullptr,
-                                                   w.fcur, w.fbits, s, c.rows)
-                              : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, s, c.rows);
+                                                   w.fcur, w.fbits, w.fsum, s, c.rows)
+                              : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, w.fsum, s, c.rows);
         },
         [&](uint32_t, int cur) {
             return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                   nullptr, val, w.fcur, s);
+                                   nullptr, val, w.fcur, w.fsum, w.csum, s);
         });
     if (st != WEDGE_OK) {
         (void)hipStreamSynchronize(s);  // the next user of the scratch must not meet this run's kernels
@@ -798,10 +893,10 @@ wedge_status run_persistent(wedge_graph_t g, bool ms, uint32_t count, uint32_t* 
             if (e == hipSuccess) e = launch_fill_u64(w.masks[0], d.n, 0, cs);
             if (e == hipSuccess) e = launch_fill_u64(w.masks[1], d.n, 0, cs);
             if (e == hipSuccess) e = launch_fill_u32_kernel(w.lev, (uint64_t)d.n * count, kInf, cs);
-            if (e == hipSuccess) e = launch_ms_seed(w.roots, count, w.masks[0], w.fbits, cs);
+            if (e == hipSuccess) e = launch_ms_seed(w.roots, count, w.masks[0], w.fbits, nullptr, cs);
         } else {
             if (e == hipSuccess) e = launch_fill_u32_kernel(level, d.n, kInf, cs);
-            if (e == hipSuccess) e = launch_roots_seed(w.roots, count, level, w.fbits, cs);
+            if (e == hipSuccess) e = launch_roots_seed(w.roots, count, level, w.fbits, nullptr, cs);
         }
         if (e == hipSuccess) e = launch_bfs_persistent(ms, P, blocks, cs);
         if (e == hipSuccess) {
@@ -852,11 +947,13 @@ wedge_status run_persistent(wedge_graph_t g, bool ms, uint32_t count, uint32_t* 
 // of each vertex is the one from its own part's root).
 wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t count, uint32_t* out,
                            const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
+    Range run_range("wedge_bfs roots");
     const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
     wedge_status st = check_run(g, out, &o);
     if (st != WEDGE_OK) return st;
     const DevGraph& d = g->dev;
     if (count && !roots) return fail(WEDGE_ERR_INVALID_ARG, "sources pointer is null");
+    if (o.flags & WEDGE_RUN_INPLACE) return fail(WEDGE_ERR_UNSUPPORTED, "the in-place pull applies to CC and SSSP");
     for (uint32_t i = 0; i < count; ++i)
         if (roots[i] >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
     if ((st = check_rows(o, !(o.flags & WEDGE_RUN_PERSISTENT))) != WEDGE_OK) return st;
@@ -869,8 +966,11 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
     if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
     if ((o.flags & WEDGE_RUN_PERSISTENT) && c.learned)
         return fail(WEDGE_ERR_UNSUPPORTED, "the learned gate runs with the host-driven loop");
+    if ((o.flags & WEDGE_RUN_PERSISTENT) && push_gate(c.gate))
+        return fail(WEDGE_ERR_UNSUPPORTED, "the push engine runs with the host-driven loop");
     if ((st = ensure_workspace(g, c.min_lc(), true, true)) != WEDGE_OK) return st;
     if ((st = ensure_batch(g, count ? count : 1, 0)) != WEDGE_OK) return st;
+    if (push_gate(c.gate) && (st = ensure_push(g, s)) != WEDGE_OK) return st;
     Workspace& w = g->ws;
     if ((st = upload_roots(g, roots, count, s)) != WEDGE_OK) return st;
     if (o.flags & WEDGE_RUN_PERSISTENT) {
@@ -878,21 +978,22 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
     } else {
         if ((st = clear_bitmaps(g, c, s)) != WEDGE_OK) return st;
         uint32_t* val = d.inv ? w.val : out;
+        c.val = val;
         HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
         HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
-        HIP_TRY(launch_roots_seed(w.roots, count, val, w.fbits, s), "seeding roots");
+        HIP_TRY(launch_roots_seed(w.roots, count, val, w.fbits, w.fsum, s), "seeding roots");
         HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr,
-                                w.fcur, s), "listing roots");
+                                w.fcur, w.fsum, w.csum, s), "listing roots");
         st = iterate(
             g, w, o, c, s, local, t0, stats,
             [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
                 return wedge_mode ? launch_pull_chunks(kBfs, d, k, lc, w.chunks, w.ctl, maxk, val,
-                                                       nullptr, w.fcur, w.fbits, s, c.rows)
-                                  : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, s, c.rows);
+                                                       nullptr, w.fcur, w.fbits, w.fsum, s, c.rows)
+                                  : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, w.fsum, s, c.rows);
             },
             [&](uint32_t, int cur) {
                 return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1],
-                                       w.ctl, nullptr, val, w.fcur, s);
+                                       w.ctl, nullptr, val, w.fcur, w.fsum, w.csum, s);
             });
         if (st == WEDGE_OK && d.inv) {
             HIP_TRY(launch_unpermute_u32(d.n, d.perm, val, out, s), "writing results");
@@ -907,15 +1008,19 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
 // Multi-source BFS with 64-bit masks.
 wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t count, uint32_t* out,
                              const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
+    Range run_range("wedge_bfs_multisource");
     const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
     wedge_status st = check_run(g, out, &o);
     if (st != WEDGE_OK) return st;
     const DevGraph& d = g->dev;
     if (count < 1 || count > 64) return fail(WEDGE_ERR_INVALID_ARG, "count must be in [1, 64]");
+    if (o.flags & WEDGE_RUN_INPLACE) return fail(WEDGE_ERR_UNSUPPORTED, "the in-place pull applies to CC and SSSP");
     if (!srcs) return fail(WEDGE_ERR_INVALID_ARG, "sources pointer is null");
     for (uint32_t i = 0; i < count; ++i)
         if (srcs[i] >= d.n) return fail(WEDGE_ERR_INVALID_ARG, "source vertex out of range");
     if ((st = check_rows(o, !(o.flags & WEDGE_RUN_PERSISTENT))) != WEDGE_OK) return st;
+    if (push_gate(o.gate))
+        return fail(WEDGE_ERR_UNSUPPORTED, "multi-source BFS has no push engine (use the threshold gate)");
     RunGuard guard(g->busy);
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
     wedge_stats local{};
@@ -939,22 +1044,22 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
         HIP_TRY(hipMemsetAsync(w.masks[0], 0, (size_t)d.n * 8, s), "clearing masks");
         HIP_TRY(hipMemsetAsync(w.masks[1], 0, (size_t)d.n * 8, s), "clearing masks");
         HIP_TRY(launch_fill_u32_kernel(w.lev, (uint64_t)d.n * count, kInf, s), "initialising levels");
-        HIP_TRY(launch_ms_seed(w.roots, count, w.masks[0], w.fbits, s), "seeding sources");
+        HIP_TRY(launch_ms_seed(w.roots, count, w.masks[0], w.fbits, w.fsum, s), "seeding sources");
         HIP_TRY(launch_ms_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, w.fcur,
-                                   w.visited, w.masks[1], w.masks[0], w.lev, count, 0, s), "listing sources");
+                                   w.visited, w.masks[1], w.masks[0], w.lev, count, 0, w.fsum, w.csum, s), "listing sources");
         st = iterate(
             g, w, o, c, s, local, t0, stats,
             [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
                 const uint64_t* mc = w.masks[k & 1];
                 uint64_t* mn = w.masks[(k & 1) ^ 1];
                 return wedge_mode ? launch_ms_pull_chunks(d, lc, w.chunks, w.ctl, maxk, all, w.visited,
-                                                          mc, mn, w.fbits, s, c.rows)
-                                  : launch_ms_pull_full(d, all, w.visited, mc, mn, w.fbits, s, c.rows);
+                                                          mc, mn, w.fbits, w.fsum, s, c.rows)
+                                  : launch_ms_pull_full(d, all, w.visited, mc, mn, w.fbits, w.fsum, s, c.rows);
             },
             [&](uint32_t k, int cur) {
                 return launch_ms_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1],
                                           w.ctl, w.fcur, w.visited, w.masks[k & 1],
-                                          w.masks[(k & 1) ^ 1], w.lev, count, k + 1, s);
+                                          w.masks[(k & 1) ^ 1], w.lev, count, k + 1, w.fsum, w.csum, s);
             });
         if (st == WEDGE_OK) {
             HIP_TRY(launch_ms_output(d.n, count, d.perm, w.lev, out, s), "writing results");
@@ -963,6 +1068,23 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
     }
     local.ms = now_ms() - t0;
     if (stats) *stats = local;
+    return st;
+}
+
+// Debug builds: a run whose kernels failed a device check reports it (release
+// builds read nothing).
+wedge_status debug_verdict(wedge_status st) {
+#ifdef WEDGE_DEBUG_CHECKS
+    unsigned a = 0, b = 0, c = 0;
+    if (debug_take_kernels(&a) != hipSuccess || debug_take_batch(&b) != hipSuccess ||
+        debug_take_push(&c) != hipSuccess)
+        return fail(WEDGE_ERR_HIP, "reading the device check words");
+    if (a | b | c) {
+        char msg[128];
+        std::snprintf(msg, sizeof msg, "device check failed: codes 0x%x 0x%x 0x%x", a, b, c);
+        return fail(WEDGE_ERR_HIP, msg);
+    }
+#endif
     return st;
 }
 
@@ -1051,30 +1173,33 @@ wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void*
 
 wedge_status wedge_bfs(wedge_graph_t g, uint32_t src, uint32_t* level_dev, const wedge_opts* opts,
                        hipStream_t stream, wedge_stats* stats) {
-    return run_frontier_app(kBfs, g, src, level_dev, opts, stream, stats);
+    return debug_verdict(run_frontier_app(kBfs, g, src, level_dev, opts, stream, stats));
 }
 
 wedge_status wedge_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* level_dev,
                                const wedge_opts* opts, hipStream_t stream, wedge_stats* stats) {
-    return run_bfs_noalloc(g, src, level_dev, opts, stream, stats);
+    return debug_verdict(run_bfs_noalloc(g, src, level_dev, opts, stream, stats));
 }
 
 wedge_status wedge_cc(wedge_graph_t g, uint32_t* label_dev, const wedge_opts* opts,
                       hipStream_t stream, wedge_stats* stats) {
-    return run_frontier_app(kCc, g, 0, label_dev, opts, stream, stats);
+    return debug_verdict(run_frontier_app(kCc, g, 0, label_dev, opts, stream, stats));
 }
 
 wedge_status wedge_sssp(wedge_graph_t g, uint32_t src, uint32_t* dist_dev, const wedge_opts* opts,
                         hipStream_t stream, wedge_stats* stats) {
-    return run_frontier_app(kSssp, g, src, dist_dev, opts, stream, stats);
+    return debug_verdict(run_frontier_app(kSssp, g, src, dist_dev, opts, stream, stats));
 }
 
 wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, float* rank_dev,
                             const wedge_opts* opts_in, hipStream_t s, wedge_stats* stats) {
+    Range run_range("wedge_pagerank");
     const wedge_opts& o = opts_in ? *opts_in : kDefaultOpts;
     wedge_status st = check_run(g, rank_dev, &o);
     if (st != WEDGE_OK) return st;
     if (!(damping > 0.0f && damping < 1.0f)) return fail(WEDGE_ERR_INVALID_ARG, "damping must be in (0, 1)");
+    if (o.flags & (WEDGE_RUN_INPLACE | WEDGE_RUN_PERSISTENT))
+        return fail(WEDGE_ERR_UNSUPPORTED, "PageRank runs the synchronous host-driven pull");
     if ((st = check_rows(o, false)) != WEDGE_OK) return st;
     RunGuard guard(g->busy);
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
@@ -1182,21 +1307,22 @@ wedge_status wedge_frontier_translate(wedge_graph_t g, const uint32_t* frontier_
             fb[v >> 6] |= 1ull << (v & 63);
         }
         HIP_TRY(hipMemcpyAsync(w.fbits, fb.data(), fb.size() * 8, hipMemcpyHostToDevice, s), "uploading frontier");
+        HIP_TRY(launch_fill_u32_kernel(w.fsum, sum_flags(d.n), 1u, s), "marking frontier summary");
         HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr,
-                                nullptr, s), "frontier list");
+                                nullptr, w.fsum, nullptr, s), "frontier list");
         HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
         HIP_TRY(hipStreamSynchronize(s), "frontier list");
         const uint64_t flisted = w.ctl_host->fnext >> kDegBits;
         const uint64_t active = w.ctl_host->fnext & kDegMask;
         HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
         HIP_TRY(launch_translate(w.flist[0], w.degpre[0], (uint32_t)flisted, active, d.row_off, d.pos,
-                                 lc, wbits_dev, s), "frontier translation");
+                                 lc, wbits_dev, nullptr, s), "frontier translation");
     }
     // compact a copy so the caller keeps the bitmap
     uint64_t* tmp = nullptr;
     HIP_TRY(hipMallocAsync((void**)&tmp, words ? words * 8 : 8, s), "scratch bitmap");
     hipError_t e = hipMemcpyAsync(tmp, wbits_dev, words * 8, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = launch_compact_chunks(tmp, words, chunk_list_dev, w.ctl, s);
+    if (e == hipSuccess) e = launch_compact_chunks(tmp, words, chunk_list_dev, w.ctl, nullptr, s);
     const hipError_t fe = hipFreeAsync(tmp, s);
     if (e != hipSuccess) return hip_fail(e, "chunk compaction");
     HIP_TRY(fe, "scratch bitmap");
@@ -1209,7 +1335,7 @@ wedge_status wedge_frontier_translate(wedge_graph_t g, const uint32_t* frontier_
 wedge_status wedge_bfs_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t count,
                                    uint32_t* levels_dev, const wedge_opts* opts,
                                    hipStream_t stream, wedge_stats* stats) {
-    return run_multisource(g, srcs, count, levels_dev, opts, stream, stats);
+    return debug_verdict(run_multisource(g, srcs, count, levels_dev, opts, stream, stats));
 }
 
 wedge_status wedge_graph_create_batch_csr(uint32_t count, const uint32_t* n_each,
@@ -1282,7 +1408,7 @@ wedge_status wedge_bfs_batch(wedge_graph_t g, const uint32_t* srcs, uint32_t* le
             return fail(WEDGE_ERR_INVALID_ARG, "source out of range in part " + std::to_string(i));
         roots[i] = (uint32_t)(g->parts[i] + srcs[i]);
     }
-    return run_bfs_roots(g, roots.data(), count, levels_dev, opts, stream, stats);
+    return debug_verdict(run_bfs_roots(g, roots.data(), count, levels_dev, opts, stream, stats));
 }
 
 wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t src,
@@ -1319,22 +1445,23 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
     c16.lc = 4;
     if ((st = clear_bitmaps(g, c16, s)) != WEDGE_OK) return st;
     const uint64_t fwords = ((uint64_t)d.n + 63) / 64;
-    struct Tmp { void* p = nullptr; ~Tmp() { if (p) (void)hipFree(p); } } tval, sv, sp, sf;
+    struct Tmp { void* p = nullptr; ~Tmp() { if (p) (void)hipFree(p); } } tval, sv, sp, sf, sc;
     uint32_t* val = d.inv ? w.val : nullptr;
     if (!val) { HIP_TRY(hipMalloc(&tval.p, (size_t)d.n * 4), "trace values"); val = (uint32_t*)tval.p; }
     HIP_TRY(hipMalloc(&sv.p, (size_t)d.n * 4), "snapshot");
     HIP_TRY(hipMalloc(&sp.p, (size_t)d.n * 4), "snapshot");
     HIP_TRY(hipMalloc(&sf.p, fwords * 8), "snapshot");
+    HIP_TRY(hipMalloc(&sc.p, sum_flags(d.n) * 4), "snapshot");
     uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
     const uint32_t isrc = (app != kCc && !g->perm_host.empty()) ? g->perm_host[src] : src;
     HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
     if (app == kCc) {
         HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, d.inv, val, w.val_prev, w.flist[0], w.degpre[0],
-                                w.fcur, w.ctl, s), "seeding CC");
+                                w.fcur, w.csum, w.ctl, s), "seeding CC");
     } else {
         HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
         if (vprev) HIP_TRY(launch_fill_u32(vprev, d.n, kInf, s), "initialising values");
-        HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur, w.ctl, s),
+        HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur, w.csum, w.ctl, s),
                 "seeding source");
     }
     HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
@@ -1351,28 +1478,30 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
         HIP_TRY(hipMemcpyAsync(sv.p, val, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s), "snapshot");
         if (vprev) HIP_TRY(hipMemcpyAsync(sp.p, vprev, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s), "snapshot");
         HIP_TRY(hipMemcpyAsync(sf.p, w.fcur, fwords * 8, hipMemcpyDeviceToDevice, s), "snapshot");
+        HIP_TRY(hipMemcpyAsync(sc.p, w.csum, sum_flags(d.n) * 4, hipMemcpyDeviceToDevice, s), "snapshot");
         float t[4] = {0, 0, 0, 0};
         for (uint32_t mi = 0; mi < 4; ++mi) {
             if (mi) {
                 HIP_TRY(hipMemcpyAsync(val, sv.p, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s), "restore");
                 if (vprev) HIP_TRY(hipMemcpyAsync(vprev, sp.p, (size_t)d.n * 4, hipMemcpyDeviceToDevice, s), "restore");
                 HIP_TRY(hipMemcpyAsync(w.fcur, sf.p, fwords * 8, hipMemcpyDeviceToDevice, s), "restore");
+                HIP_TRY(hipMemcpyAsync(w.csum, sc.p, sum_flags(d.n) * 4, hipMemcpyDeviceToDevice, s), "restore");
             }
             HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
             HIP_TRY(hipEventRecord(w.ev[0], s), "event");
             if (mi == 0) {
-                HIP_TRY(launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, s), "full pull");
+                HIP_TRY(launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, w.fsum, s), "full pull");
             } else {
                 const int lc = 3 + (int)mi;
                 const uint64_t nch = c.chunks_of(lc);
                 HIP_TRY(launch_translate(w.flist[cur], w.degpre[cur], (uint32_t)flisted, active, d.row_off,
-                                         d.pos, lc, w.wbits, s), "frontier translation");
-                HIP_TRY(launch_compact_chunks(w.wbits, (nch + 63) / 64, w.chunks, w.ctl, s), "chunk compaction");
+                                         d.pos, lc, w.wbits, w.wsum, s), "frontier translation");
+                HIP_TRY(launch_compact_chunks(w.wbits, (nch + 63) / 64, w.chunks, w.ctl, w.wsum, s), "chunk compaction");
                 HIP_TRY(launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, active < nch ? active : nch, val,
-                                           vprev, w.fcur, w.fbits, s), "chunk pull");
+                                           vprev, w.fcur, w.fbits, w.fsum, s), "chunk pull");
             }
             HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                    vprev, val, w.fcur, s), "frontier finalisation");
+                                    vprev, val, w.fcur, w.fsum, w.csum, s), "frontier finalisation");
             HIP_TRY(hipEventRecord(w.ev[1], s), "event");
             HIP_TRY(hipEventSynchronize(w.ev[1]), "trace iteration");
             HIP_TRY(hipEventElapsedTime(&t[mi], w.ev[0], w.ev[1]), "event time");
@@ -1405,10 +1534,72 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
 }
 
 namespace {
+// The tuner's table: (kind, source count, ceil(log2 m), compute units) -> the
+// winning options. With WEDGE_TUNE_CACHE set, the table also lives in that
+// text file: it is read once per process on first use, and rewritten (to a
+// temporary file, then renamed) after every tuning run, so tuned choices
+// survive the process. Lines: "kind count bucket cus chunk persistent bpc rows"
+// after a "wedge-tune-v1" header; malformed lines are ignored.
+using TuneKey = std::tuple<uint32_t, uint32_t, int, int>;
 std::mutex g_tune_mu;
-std::map<std::tuple<uint32_t, uint32_t, int>, wedge_opts> g_tune;
+std::map<TuneKey, wedge_opts> g_tune;
+bool g_tune_loaded = false;
 
 int size_bucket(uint64_t m) { int b = 0; while ((1ull << b) < m) ++b; return b; }
+
+int current_cus() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return 0; }
+    return device_cus(dev);
+}
+
+void tune_cache_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("WEDGE_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    if (!std::fgets(line, sizeof line, f) || std::strncmp(line, "wedge-tune-v1", 13) != 0) {
+        std::fclose(f);
+        return;
+    }
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned kind, count, chunk, pers, bpc, rows;
+        int bucket, cus;
+        if (std::sscanf(line, "%u %u %d %d %u %u %u %u", &kind, &count, &bucket, &cus, &chunk, &pers,
+                        &bpc, &rows) != 8)
+            continue;
+        if (kind > WEDGE_TUNE_BATCH || !is_pow2(chunk) || chunk > 4096 || pers > 1 ||
+            (rows && rows != 4 && rows != 8 && rows != 16))
+            continue;
+        wedge_opts o = kDefaultOpts;
+        o.chunk_edges = chunk;
+        o.flags = pers ? WEDGE_RUN_PERSISTENT : 0u;
+        o.blocks_per_cu = bpc;
+        o.rows_per_wave = rows;
+        g_tune[TuneKey(kind, count, bucket, cus)] = o;
+    }
+    std::fclose(f);
+}
+
+void tune_cache_save_locked() {
+    const char* path = std::getenv("WEDGE_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "wedge-tune-v1\n");
+    for (const auto& kv : g_tune)
+        std::fprintf(f, "%u %u %d %d %u %u %u %u\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                     std::get<2>(kv.first), std::get<3>(kv.first), kv.second.chunk_edges,
+                     (kv.second.flags & WEDGE_RUN_PERSISTENT) ? 1u : 0u, kv.second.blocks_per_cu,
+                     kv.second.rows_per_wave);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), path);
+    else std::remove(tmp.c_str());
+}
 }  // namespace
 
 wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs, uint32_t count,
@@ -1460,14 +1651,18 @@ wedge_status wedge_tune_bfs(wedge_graph_t g, uint32_t kind, const uint32_t* srcs
     *best = win;
     if (best_ms) *best_ms = best_t;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(kind, count, size_bucket(g->dev.m))] = win;
+    tune_cache_load_locked();
+    g_tune[TuneKey(kind, count, size_bucket(g->dev.m), device_cus(g->device))] = win;
+    tune_cache_save_locked();
     return WEDGE_OK;
 }
 
 wedge_status wedge_tune_lookup(uint32_t kind, uint32_t count, uint64_t m, wedge_opts* opts) {
     if (!opts) return fail(WEDGE_ERR_INVALID_ARG, "null argument");
+    const int cus = current_cus();
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(std::make_tuple(kind, count, size_bucket(m)));
+    tune_cache_load_locked();
+    auto it = g_tune.find(TuneKey(kind, count, size_bucket(m), cus));
     if (it == g_tune.end()) return fail(WEDGE_ERR_UNSUPPORTED, "no tuned entry for this kind and size");
     opts->chunk_edges = it->second.chunk_edges;
     opts->flags = (opts->flags & ~WEDGE_RUN_PERSISTENT) | (it->second.flags & WEDGE_RUN_PERSISTENT);

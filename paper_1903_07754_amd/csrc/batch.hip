@@ -22,7 +22,8 @@ __device__ __forceinline__ void ms_pull_lanes(const GraphArgs& g, const uint32_t
                                               const uint64_t* __restrict__ visited,
                                               const uint64_t* __restrict__ cur,
                                               uint64_t* __restrict__ nxt,
-                                              uint64_t* __restrict__ fbits) {
+                                              uint64_t* __restrict__ fbits,
+                                              uint32_t* __restrict__ fsum) {
     const int lane = lane_id();
     // branch-free loads (see pull_lanes): lanes without an edge read position
     // 0, lanes that need no edge point at one shared address, and loaded
@@ -66,7 +67,7 @@ __device__ __forceinline__ void ms_pull_lanes(const GraphArgs& g, const uint32_t
             if (nb) {
                 atomicOr(reinterpret_cast<unsigned long long*>(nxt + dst[i]),
                          (unsigned long long)nb);
-                set_bit(fbits, dst[i]);
+                set_bit_sum(fbits, fsum, dst[i]);
             }
         }
     }
@@ -75,7 +76,7 @@ __device__ __forceinline__ void ms_pull_lanes(const GraphArgs& g, const uint32_t
 template <int R>
 __device__ __forceinline__ void ms_pull_rows(const GraphArgs& g, uint64_t r0, uint64_t all,
                                              const uint64_t* visited, const uint64_t* cur,
-                                             uint64_t* nxt, uint64_t* fbits) {
+                                             uint64_t* nxt, uint64_t* fbits, uint32_t* fsum) {
     const int lane = lane_id();
     uint32_t p[R];
     bool valid[R];
@@ -85,7 +86,7 @@ __device__ __forceinline__ void ms_pull_rows(const GraphArgs& g, uint64_t r0, ui
         valid[i] = pp < g.m;
         p[i] = (uint32_t)pp;
     }
-    ms_pull_lanes<R>(g, p, valid, all, visited, cur, nxt, fbits);
+    ms_pull_lanes<R>(g, p, valid, all, visited, cur, nxt, fbits, fsum);
 }
 
 template <int R>
@@ -93,12 +94,12 @@ __device__ __forceinline__ void ms_pull_slots(const GraphArgs& g, uint64_t s0, u
                                               int lc, const uint32_t* list, uint64_t K,
                                               uint64_t all, const uint64_t* visited,
                                               const uint64_t* cur, uint64_t* nxt,
-                                              uint64_t* fbits) {
+                                              uint64_t* fbits, uint32_t* fsum) {
     const int lane = lane_id();
     uint32_t p[R];
     bool valid[R];
     chunk_slot_rows_any<R>(s0, slots, lane, lc, list, K, g.m, p, valid);
-    ms_pull_lanes<R>(g, p, valid, all, visited, cur, nxt, fbits);
+    ms_pull_lanes<R>(g, p, valid, all, visited, cur, nxt, fbits, fsum);
 }
 
 // Commit of one multi-source iteration, over the next-frontier bitmap: list the
@@ -109,7 +110,8 @@ template <int WAVES = kWavesPerBlock>
 __device__ __forceinline__ void ms_finalize_block(
     uint64_t vblock, uint64_t* bits, uint64_t words, uint32_t n, const uint32_t* row_off,
     uint32_t* list, uint32_t* degpre, Ctl* ctl, uint64_t* fcur, uint64_t* visited,
-    uint64_t* retire, const uint64_t* nxt, uint32_t* lev, uint32_t K, uint32_t level) {
+    uint64_t* retire, const uint64_t* nxt, uint32_t* lev, uint32_t K, uint32_t level,
+    uint32_t* fsum = nullptr, uint32_t* csum = nullptr) {
     // the new masks of the wave's vertices, one slot per (word, lane), for the
     // level writes below (each lane only touches its own slots)
     __shared__ uint64_t s_nb[WAVES][kCompactWords][64];
@@ -118,7 +120,7 @@ __device__ __forceinline__ void ms_finalize_block(
 #pragma unroll
     for (int g = 0; g < kCompactWords; ++g) s_nb[wid][g][lane] = 0ull;
     bitmap_compact_block_ex<WAVES, true, true, kCompactWords>(
-        vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
+        vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur, fsum, csum,
         [&](uint32_t v) -> uint64_t { return nxt[v]; },
         [&](uint32_t v, uint64_t nb) {
             atomicOr(reinterpret_cast<unsigned long long*>(visited + v), (unsigned long long)nb);
@@ -148,7 +150,7 @@ __device__ __forceinline__ void bfs_finalize_block(uint64_t vblock, uint64_t* bi
                                                    const uint32_t* row_off, uint32_t* list,
                                                    uint32_t* degpre, Ctl* ctl, uint64_t* fcur) {
     bitmap_compact_block_ex<WAVES, true, true, kCompactWords>(
-        vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur,
+        vblock, bits, words, n, row_off, list, degpre, &ctl->fnext, &ctl->ftotal, fcur, nullptr, nullptr,
         [](uint32_t) -> uint64_t { return 0ull; }, [](uint32_t, uint64_t) {}, [](uint32_t) {});
 }
 
@@ -159,11 +161,12 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull_full(GraphArgs g, uint64_t a
                                                          const uint64_t* __restrict__ visited,
                                                          const uint64_t* __restrict__ cur,
                                                          uint64_t* __restrict__ nxt,
-                                                         uint64_t* __restrict__ fbits) {
+                                                         uint64_t* __restrict__ fbits,
+                                                         uint32_t* __restrict__ fsum) {
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t r0 = wave * R;
     if (r0 >= g.rows) return;
-    ms_pull_rows<R>(g, r0, all, visited, cur, nxt, fbits);
+    ms_pull_rows<R>(g, r0, all, visited, cur, nxt, fbits, fsum);
 }
 
 template <int R>
@@ -174,13 +177,14 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull_chunks(GraphArgs g, int lc,
                                                            const uint64_t* __restrict__ visited,
                                                            const uint64_t* __restrict__ cur,
                                                            uint64_t* __restrict__ nxt,
-                                                           uint64_t* __restrict__ fbits) {
+                                                           uint64_t* __restrict__ fbits,
+                                                           uint32_t* __restrict__ fsum) {
     const uint64_t K = *marked >> kDegBits;
     const uint64_t slots = chunk_slots(K, lc);
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     for (uint64_t s0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * R;
          s0 < slots; s0 += nwaves * R)
-        ms_pull_slots<R>(g, s0, slots, lc, list, K, all, visited, cur, nxt, fbits);
+        ms_pull_slots<R>(g, s0, slots, lc, list, K, all, visited, cur, nxt, fbits, fsum);
 }
 
 __global__ __launch_bounds__(kCompactWaves * 64) void k_ms_finalize(uint64_t* bits, uint64_t words,
@@ -189,27 +193,28 @@ __global__ __launch_bounds__(kCompactWaves * 64) void k_ms_finalize(uint64_t* bi
                                                         Ctl* ctl, uint64_t* fcur,
                                                         uint64_t* visited, uint64_t* retire,
                                                         const uint64_t* nxt, uint32_t* lev,
-                                                        uint32_t K, uint32_t level) {
+                                                        uint32_t K, uint32_t level, uint32_t* fsum,
+                                                        uint32_t* csum) {
     ms_finalize_block<kCompactWaves>(blockIdx.x, bits, words, n, row_off, list, degpre, ctl, fcur,
-                                     visited, retire, nxt, lev, K, level);
+                                     visited, retire, nxt, lev, K, level, fsum, csum);
 }
 
 // Sources of a multi-source run: bit s of nxt[src[s]], and the vertex bit.
 __global__ void k_ms_seed(const uint32_t* __restrict__ srcs, uint32_t K, uint64_t* nxt,
-                          uint64_t* fbits) {
+                          uint64_t* fbits, uint32_t* fsum) {
     const uint32_t s = threadIdx.x;
     if (blockIdx.x == 0 && s < K) {
         atomicOr(reinterpret_cast<unsigned long long*>(nxt + srcs[s]), 1ull << s);
-        set_bit(fbits, srcs[s]);
+        set_bit_sum(fbits, fsum, srcs[s]);
     }
 }
 
 // Roots of a multi-root BFS: level 0 and the vertex bit.
 __global__ void k_roots_seed(const uint32_t* __restrict__ roots, uint32_t count,
-                             uint32_t* __restrict__ level, uint64_t* fbits) {
+                             uint32_t* __restrict__ level, uint64_t* fbits, uint32_t* fsum) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
         level[roots[i]] = 0;
-        set_bit(fbits, roots[i]);
+        set_bit_sum(fbits, fsum, roots[i]);
     }
 }
 
@@ -408,7 +413,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_bfs_persistent(PersistParams P) 
             for (uint64_t w = gwave; w < twaves; w += nwaves)
                 translate_wave<kTranslateEpt>(w, P.flist[cur], P.degpre[cur], (uint32_t)flisted,
                                               (uint32_t)active, P.row_off, P.pos, P.lc,
-                                              reinterpret_cast<uint32_t*>(P.wbits));
+                                              reinterpret_cast<uint32_t*>(P.wbits), nullptr);
             if (!grid_sync(ps, P.timeout_ticks)) return;
             const uint64_t cblocks = (P.wwords + kCompactWords * WAVES - 1) / (kCompactWords * WAVES);
             for (uint64_t vb = blockIdx.x; vb < cblocks; vb += gridDim.x)
@@ -423,19 +428,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_bfs_persistent(PersistParams P) 
             for (uint64_t s0 = gwave * kPullRows; s0 < slots; s0 += nwaves * kPullRows) {
                 if (MS) {
                     ms_pull_slots<kPullRows>(g, s0, slots, P.lc, P.chunks, K, P.all, P.visited, mcur,
-                                             mnxt, P.fbits);
+                                             mnxt, P.fbits, nullptr);
                 } else {
                     const int lane = lane_id();
                     uint32_t p[kPullRows];
                     bool valid[kPullRows];
                     chunk_slot_rows_any<kPullRows>(s0, slots, lane, P.lc, P.chunks, K, g.m, p, valid);
-                    pull_lanes<kBfs, kPullRows>(g, p, valid, k, P.level, nullptr, P.fcur, P.fbits);
+                    pull_lanes<kBfs, kPullRows>(g, p, valid, k, P.level, nullptr, P.fcur, P.fbits, nullptr);
                 }
             }
         } else {
             for (uint64_t r0 = gwave * kPullRows; r0 < g.rows; r0 += nwaves * kPullRows) {
                 if (MS) {
-                    ms_pull_rows<kPullRows>(g, r0, P.all, P.visited, mcur, mnxt, P.fbits);
+                    ms_pull_rows<kPullRows>(g, r0, P.all, P.visited, mcur, mnxt, P.fbits, nullptr);
                 } else {
                     const int lane = lane_id();
                     uint32_t p[kPullRows];
@@ -446,7 +451,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_bfs_persistent(PersistParams P) 
                         valid[i] = pp < g.m;
                         p[i] = (uint32_t)pp;
                     }
-                    pull_lanes<kBfs, kPullRows>(g, p, valid, k, P.level, nullptr, P.fcur, P.fbits);
+                    pull_lanes<kBfs, kPullRows>(g, p, valid, k, P.level, nullptr, P.fcur, P.fbits, nullptr);
                 }
             }
         }
@@ -474,20 +479,20 @@ uint32_t grid_for(uint64_t threads, uint32_t cap) {
 
 template <int R>
 void ms_pull_full_rows(const DevGraph& g, uint64_t all, const uint64_t* visited, const uint64_t* cur,
-                       uint64_t* nxt, uint64_t* fbits, hipStream_t s) {
+                       uint64_t* nxt, uint64_t* fbits, uint32_t* fsum, hipStream_t s) {
     const uint64_t waves = (g.rows + R - 1) / R;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_ms_pull_full<R><<<blocks, kBlock, 0, s>>>(args_of(g), all, visited, cur, nxt, fbits);
+    k_ms_pull_full<R><<<blocks, kBlock, 0, s>>>(args_of(g), all, visited, cur, nxt, fbits, fsum);
 }
 
 hipError_t launch_ms_pull_full(const DevGraph& g, uint64_t all, const uint64_t* visited,
-                               const uint64_t* cur, uint64_t* nxt, uint64_t* fbits,
+                               const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, uint32_t* fsum,
                                hipStream_t s, int rows) {
     if (!g.rows) return hipSuccess;
     switch (rows) {
-        case 4: ms_pull_full_rows<4>(g, all, visited, cur, nxt, fbits, s); break;
-        case kPullRows: ms_pull_full_rows<kPullRows>(g, all, visited, cur, nxt, fbits, s); break;
-        case 16: ms_pull_full_rows<16>(g, all, visited, cur, nxt, fbits, s); break;
+        case 4: ms_pull_full_rows<4>(g, all, visited, cur, nxt, fbits, fsum, s); break;
+        case kPullRows: ms_pull_full_rows<kPullRows>(g, all, visited, cur, nxt, fbits, fsum, s); break;
+        case 16: ms_pull_full_rows<16>(g, all, visited, cur, nxt, fbits, fsum, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -496,23 +501,24 @@ hipError_t launch_ms_pull_full(const DevGraph& g, uint64_t all, const uint64_t* 
 template <int R>
 void ms_pull_chunks_rows(const DevGraph& g, int lc, const uint32_t* list, const Ctl* ctl,
                          uint64_t max_chunks, uint64_t all, const uint64_t* visited,
-                         const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s) {
+                         const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, uint32_t* fsum,
+                         hipStream_t s) {
     uint64_t waves = (chunk_slots_count(max_chunks, lc) + R - 1) / R;
     if (waves > 256ull * 32) waves = 256ull * 32;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     k_ms_pull_chunks<R><<<blocks, kBlock, 0, s>>>(args_of(g), lc, list, &ctl->marked, all, visited,
-                                                  cur, nxt, fbits);
+                                                  cur, nxt, fbits, fsum);
 }
 
 hipError_t launch_ms_pull_chunks(const DevGraph& g, int lc, const uint32_t* list, const Ctl* ctl,
                                  uint64_t max_chunks, uint64_t all, const uint64_t* visited,
-                                 const uint64_t* cur, uint64_t* nxt, uint64_t* fbits,
+                                 const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, uint32_t* fsum,
                                  hipStream_t s, int rows) {
     if (!max_chunks) return hipSuccess;
     switch (rows) {
-        case 4: ms_pull_chunks_rows<4>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, s); break;
-        case kPullRows: ms_pull_chunks_rows<kPullRows>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, s); break;
-        case 16: ms_pull_chunks_rows<16>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, s); break;
+        case 4: ms_pull_chunks_rows<4>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, fsum, s); break;
+        case kPullRows: ms_pull_chunks_rows<kPullRows>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, fsum, s); break;
+        case 16: ms_pull_chunks_rows<16>(g, lc, list, ctl, max_chunks, all, visited, cur, nxt, fbits, fsum, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -521,26 +527,28 @@ hipError_t launch_ms_pull_chunks(const DevGraph& g, int lc, const uint32_t* list
 hipError_t launch_ms_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
                               uint32_t* flist, uint32_t* degpre, Ctl* ctl, uint64_t* fcur,
                               uint64_t* visited, uint64_t* retire, const uint64_t* nxt,
-                              uint32_t* lev, uint32_t K, uint32_t level, hipStream_t s) {
+                              uint32_t* lev, uint32_t K, uint32_t level, uint32_t* fsum,
+                              uint32_t* csum, hipStream_t s) {
     const uint64_t words = ((uint64_t)n + 63) / 64;
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
     const uint32_t blocks = (uint32_t)((waves + kCompactWaves - 1) / kCompactWaves);
     k_ms_finalize<<<blocks, kCompactWaves * 64, 0, s>>>(fbits, words, n, row_off, flist, degpre, ctl,
-                                                        fcur, visited, retire, nxt, lev, K, level);
+                                                        fcur, visited, retire, nxt, lev, K, level,
+                                                        fsum, csum);
     return hipGetLastError();
 }
 
 hipError_t launch_ms_seed(const uint32_t* srcs, uint32_t K, uint64_t* nxt, uint64_t* fbits,
-                          hipStream_t s) {
-    k_ms_seed<<<1, 64, 0, s>>>(srcs, K, nxt, fbits);
+                          uint32_t* fsum, hipStream_t s) {
+    k_ms_seed<<<1, 64, 0, s>>>(srcs, K, nxt, fbits, fsum);
     return hipGetLastError();
 }
 
 hipError_t launch_roots_seed(const uint32_t* roots, uint32_t count, uint32_t* level,
-                             uint64_t* fbits, hipStream_t s) {
+                             uint64_t* fbits, uint32_t* fsum, hipStream_t s) {
     if (!count) return hipSuccess;
-    k_roots_seed<<<grid_for(count, 1024), kBlock, 0, s>>>(roots, count, level, fbits);
+    k_roots_seed<<<grid_for(count, 1024), kBlock, 0, s>>>(roots, count, level, fbits, fsum);
     return hipGetLastError();
 }
 
@@ -577,5 +585,7 @@ hipError_t launch_bfs_persistent(bool ms, const PersistParams& P, uint32_t block
     else k_bfs_persistent<false, kPersistWavesBfs><<<blocks, kPersistWavesBfs * 64, 0, s>>>(P);
     return hipGetLastError();
 }
+
+WEDGE_DEBUG_ACCESSOR(debug_take_batch)
 
 }  // namespace wedge

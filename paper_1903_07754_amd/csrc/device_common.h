@@ -48,6 +48,30 @@ constexpr int kTranslateEpt = 4;      // frontier out-edges per lane in the tran
 constexpr int kCompactWords = 8;      // 64-bit bitmap words per wave in the compaction
 constexpr uint32_t kPrEpilogueVerts = 8192;  // vertices per PageRank epilogue block
 
+// Device checks of debug builds (WEDGE_DEBUG_CHECKS): a failed check ORs its
+// code into the translation unit's error word, which the host reads after
+// every run (WEDGE_DEBUG_ACCESSOR defines the reader). Release builds compile
+// them away.
+#ifdef WEDGE_DEBUG_CHECKS
+static __device__ unsigned wedge_debug_word;
+#define WEDGE_DCHECK(cond, code) \
+    do { if (!(cond)) atomicOr(&::wedge::dev::wedge_debug_word, (unsigned)(code)); } while (0)
+#define WEDGE_DEBUG_ACCESSOR(name)                                                   \
+    hipError_t name(unsigned* word) {                                                \
+        *word = 0;                                                                   \
+        hipError_t e = hipMemcpyFromSymbol(word, HIP_SYMBOL(dev::wedge_debug_word),  \
+                                           sizeof(unsigned), 0, hipMemcpyDeviceToHost); \
+        if (e != hipSuccess || !*word) return e;                                     \
+        const unsigned zero = 0;                                                     \
+        return hipMemcpyToSymbol(HIP_SYMBOL(dev::wedge_debug_word), &zero, sizeof(unsigned), 0, \
+                                 hipMemcpyHostToDevice);                             \
+    }
+#else
+#define WEDGE_DCHECK(cond, code) do { } while (0)
+#define WEDGE_DEBUG_ACCESSOR(name) \
+    hipError_t name(unsigned* word) { *word = 0; return hipSuccess; }
+#endif
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 __device__ __forceinline__ uint64_t mask_le(int l) { return l == 63 ? ~0ull : ((2ull << l) - 1ull); }
 __device__ __forceinline__ uint64_t mask_lt(int l) { return (1ull << l) - 1ull; }
@@ -112,6 +136,26 @@ __device__ __forceinline__ void set_bit(uint64_t* bits, uint32_t i) {
     atomicOr(reinterpret_cast<uint32_t*>(bits) + (i >> 5), 1u << (i & 31));
 }
 
+// Hierarchical bitmaps. A bitmap that a compaction lists (the next frontier,
+// the Wedge Frontier) has a summary of one 32-bit flag per 4096 bits, the
+// range one compaction block covers. Every writer of a bit also stores 1 into
+// the flag of its range (a plain store: concurrent writers store the same
+// value), so the compaction reads a flag and skips a range nobody touched,
+// and its cost follows the touched ranges rather than the bitmap's length. A
+// null summary means "scan everything".
+constexpr int kSumShift = 12;  // log2 of the bits per summary flag
+static_assert(kCompactWaves * kCompactWords * 64 == (1 << kSumShift),
+              "one summary flag per compaction block");
+
+__device__ __forceinline__ void mark_sum(uint32_t* sum, uint32_t bit) {
+    if (sum) sum[bit >> kSumShift] = 1u;
+}
+
+__device__ __forceinline__ void set_bit_sum(uint64_t* bits, uint32_t* sum, uint32_t i) {
+    set_bit(bits, i);
+    mark_sum(sum, i);
+}
+
 
 
 // Frontier transformation work of one wave (see k_translate). The wave covers
@@ -127,7 +171,8 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
                                                uint32_t fcount, uint32_t active,
                                                const uint32_t* __restrict__ row_off,
                                                const uint32_t* __restrict__ pos, int lc,
-                                               uint32_t* __restrict__ wbits32) {
+                                               uint32_t* __restrict__ wbits32,
+                                               uint32_t* __restrict__ wsum) {
     const int lane = lane_id();
     const uint64_t base = wave * 64ull * EPT;
     if (base >= active) return;
@@ -152,6 +197,13 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
         uint32_t key = kInf, bit = 0;
         const uint32_t dt = __shfl(dw, t, 64);
         const uint32_t rt = __shfl(rw, t, 64);
+#ifdef WEDGE_DEBUG_CHECKS
+        {
+            // the owner found for edge a holds it: prefix[t] <= a < prefix[t+1]
+            const uint32_t dn = __shfl(dw, (t + 1) & 63, 64);
+            if (valid) WEDGE_DCHECK(dt <= a && (t == 63 || a < (uint64_t)dn), kDbgTranslate);
+        }
+#endif
         if (valid) {
             const uint32_t q = rt + (uint32_t)(a - dt);
             const uint32_t c = pos[q] >> lc;
@@ -168,7 +220,10 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
         const bool head = lane == 0 || prev != key;
         const uint64_t heads = __ballot(head);
         bit = seg_reduce(bit, seg_span(heads, lane), [](uint32_t x, uint32_t y) { return x | y; });
-        if (head && valid) atomicOr(wbits32 + key, bit);
+        if (head && valid) {
+            atomicOr(wbits32 + key, bit);
+            if (wsum) wsum[key >> (kSumShift - 5)] = 1u;
+        }
     }
 }
 
@@ -179,18 +234,32 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
 // before it is overwritten (COPY only). A wave's loads are issued word-batch
 // by word-batch, never one word at a time: bitmap words (and the words being
 // replaced), then the out-degree bounds and load_set of every set bit.
+//
+// sum_bits / sum_copy (nullable; used only when a block covers exactly one
+// summary flag's range) are the summaries of bits and copy_to: a block whose
+// flags are both clear returns at once (nothing set, nothing to clear); a
+// processed block clears its bits flag and hands it to copy_to's.
 template <int WAVES, bool DEG, bool COPY, int G, class LoadSet, class OnSet, class OnOld>
 __device__ __forceinline__ void bitmap_compact_block_ex(
     uint64_t vblock, uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
-    uint64_t* __restrict__ copy_to, LoadSet load_set, OnSet on_set, OnOld on_old) {
+    uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits,
+    uint32_t* __restrict__ sum_copy, LoadSet load_set, OnSet on_set, OnOld on_old) {
     __shared__ unsigned long long s_wave[WAVES];
     __shared__ unsigned long long s_all[WAVES];
     __shared__ unsigned long long s_base;
     // a block may run this for several virtual blocks in a row: wait until every
     // wave has read the previous call's shared values before they are rewritten
     __syncthreads();
+    constexpr bool kSummed = WAVES * G * 64 == (1 << kSumShift);
+    uint32_t fb = 1u;
+    if (kSummed && sum_bits) {
+        // block-uniform: every thread reads the same flags and leaves together
+        fb = sum_bits[vblock];
+        const uint32_t fc = (COPY && sum_copy) ? sum_copy[vblock] : 0u;
+        if (!fb && !fc) return;
+    }
     const int lane = lane_id();
     const int wid = threadIdx.x >> 6;
     const uint64_t w0 = (vblock * WAVES + wid) * G;
@@ -286,6 +355,10 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
         cb += (uint32_t)__popcll(lm[g]);
         db += dtot;
     }
+    if (kSummed && threadIdx.x == 0) {
+        if (sum_bits) sum_bits[vblock] = 0u;
+        if (COPY && sum_copy) sum_copy[vblock] = fb;  // copy_to now holds what bits held
+    }
 }
 
 // Destinations of R positions per lane, every load issued before any is
@@ -312,8 +385,8 @@ __device__ __forceinline__ void dst_of_rows(const GraphArgs& g, const uint32_t (
 // has `commit` set gets its bit, with one atomicOr per distinct bitmap word
 // (consecutive destinations share words, so a row of 64 positions needs one
 // or two atomics instead of one per destination). All lanes must call it.
-__device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint32_t dst, bool commit,
-                                             uint64_t heads, int lane) {
+__device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint32_t* __restrict__ fsum,
+                                             uint32_t dst, bool commit, uint64_t heads, int lane) {
     if (!__ballot(commit)) return;  // most rows of a late iteration change nothing
     const int hl = 63 - __clzll(heads & mask_le(lane));  // head lane of this lane's segment
     const bool c = __shfl((int)commit, hl, 64) != 0;
@@ -323,7 +396,10 @@ __device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint3
     const bool head = lane == 0 || prev != key;
     const uint64_t wheads = __ballot(head);
     const uint32_t orv = seg_reduce(bit, seg_span(wheads, lane), [](uint32_t a, uint32_t b) { return a | b; });
-    if (head && key != kInf) atomicOr(reinterpret_cast<uint32_t*>(fbits) + key, orv);
+    if (head && key != kInf) {
+        atomicOr(reinterpret_cast<uint32_t*>(fbits) + key, orv);
+        if (fsum) fsum[key >> (kSumShift - 5)] = 1u;
+    }
 }
 
 // ROWS: the R positions of each lane are the lanes of R consecutive rows
@@ -331,13 +407,20 @@ __device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint3
 // whose in-edges all lie in the wave is written by this wave only, and takes
 // a plain store instead of a min-atomic; only the wave's first and last
 // segments can be shared with the neighbouring waves.
-template <int APP, int R, bool ROWS = false>
+// INPLACE (CC and SSSP): sources' values are gathered from val, the array
+// this iteration lowers, instead of the committed copy val_prev (an
+// asynchronous, Gauss-Seidel style pull: a value lowered earlier in the same
+// iteration travels on at once). Every value read is still the length of a
+// real path (or a real label), and values only fall, so the fixed point, and
+// the final result, are those of the synchronous pull.
+template <int APP, int R, bool ROWS = false, bool INPLACE = false>
 __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&p)[R],
                                            const bool (&valid)[R], uint32_t iter,
                                            uint32_t* __restrict__ val,
                                            const uint32_t* __restrict__ val_prev,
                                            const uint64_t* __restrict__ fcur,
-                                           uint64_t* __restrict__ fbits) {
+                                           uint64_t* __restrict__ fbits,
+                                           uint32_t* __restrict__ fsum) {
     const int lane = lane_id();
     // loads are branch-free: a lane without an edge reads position 0 (its
     // results are masked), so all rows' loads of one step are in flight at once
@@ -354,6 +437,15 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
     dst_of_rows<R>(g, pc, dst);
 #pragma unroll
     for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst[i] : kInf;
+#ifdef WEDGE_DEBUG_CHECKS
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        if (!valid[i]) continue;
+        WEDGE_DCHECK(pc[i] < g.m, kDbgPullPos);
+        WEDGE_DCHECK(dst[i] < g.n, kDbgPullDst);
+        if (dst[i] < g.n) WEDGE_DCHECK(g.col_off[dst[i]] <= pc[i] && pc[i] < g.col_off[dst[i] + 1], kDbgPullEdge);
+    }
+#endif
 
     if (APP == kBfs) {
         // only unvisited destinations read their in-edges: the others point
@@ -388,7 +480,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                 commit = ((fm >> lane) & seg) != 0;
                 if (commit) val[dst[i]] = iter + 1;
             }
-            set_bits_row(fbits, dst[i], commit, heads, lane);
+            set_bits_row(fbits, fsum, dst[i], commit, heads, lane);
         }
     } else {
         // All loads of the R rows are issued before any result is used, and
@@ -417,12 +509,12 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
 #pragma unroll
             for (int i = 0; i < R; ++i) act[i] = valid[i] & (((fw[i] >> (u[i] & 31)) & 1u) != 0u);
 #pragma unroll
-            for (int i = 0; i < R; ++i) x[i] = val_prev[act[i] ? u[i] : 0u];
+            for (int i = 0; i < R; ++i) x[i] = (INPLACE ? val : val_prev)[act[i] ? u[i] : 0u];
 #pragma unroll
             for (int i = 0; i < R; ++i) x[i] = act[i] ? x[i] : kInf;
         } else {
 #pragma unroll
-            for (int i = 0; i < R; ++i) x[i] = val_prev[u[i]];
+            for (int i = 0; i < R; ++i) x[i] = (INPLACE ? val : val_prev)[u[i]];
 #pragma unroll
             for (int i = 0; i < R; ++i) cur[i] = val[valid[i] ? dst[i] : 0u];
 #pragma unroll
@@ -462,7 +554,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                 if (shared) atomicMin(val + dst[i], best);
                 else val[dst[i]] = best;
             }
-            set_bits_row(fbits, dst[i], commit, heads, lane);
+            set_bits_row(fbits, fsum, dst[i], commit, heads, lane);
             lane0_first = lane0_first && defer == 0;
         }
     }
@@ -474,9 +566,10 @@ __device__ __forceinline__ void bitmap_compact_block(
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
-    uint64_t* __restrict__ copy_to) {
+    uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits = nullptr,
+    uint32_t* __restrict__ sum_copy = nullptr) {
     bitmap_compact_block_ex<WAVES, DEG, COPY, G>(
-        vblock, bits, words, limit, row_off, list, degpre, counter, total, copy_to,
+        vblock, bits, words, limit, row_off, list, degpre, counter, total, copy_to, sum_bits, sum_copy,
         [&](uint32_t v) -> uint64_t { return COMMIT ? val[v] : 0u; },
         [&](uint32_t v, uint64_t x) { if (COMMIT) val_prev[v] = (uint32_t)x; }, [](uint32_t) {});
 }
@@ -515,6 +608,8 @@ __device__ __forceinline__ void chunk_slot_rows(uint64_t s0w, uint64_t slotsw, i
             const uint32_t idx = (uint32_t)i * per + sub;
             const uint32_t c = __shfl(mine, (int)idx, 64);
             const uint64_t pp = ((uint64_t)c << lc) + off;
+            // a listed chunk starts inside the in-edge array
+            WEDGE_DCHECK(!((s0 + i < slots) & (first + idx < K)) || ((uint64_t)c << lc) < m, kDbgChunk);
             valid[i] = (s0 + i < slots) & (first + idx < K) & (pp < m);
             p[i] = valid[i] ? (uint32_t)pp : 0u;
         }
@@ -529,6 +624,7 @@ __device__ __forceinline__ void chunk_slot_rows(uint64_t s0w, uint64_t slotsw, i
             const uint32_t idx = (s >> hi) - first;
             const uint32_t c = __shfl(mine, (int)idx, 64);
             const uint64_t pp = ((uint64_t)c << lc) + ((uint64_t)(s & ((1u << hi) - 1u)) << 6) + ul;
+            WEDGE_DCHECK(!((s < slots) & (first + idx < K)) || ((uint64_t)c << lc) < m, kDbgChunk);
             valid[i] = (s < slots) & (first + idx < K) & (pp < m);
             p[i] = valid[i] ? (uint32_t)pp : 0u;
         }
@@ -539,7 +635,10 @@ __device__ __forceinline__ void chunk_slot_rows(uint64_t s0w, uint64_t slotsw, i
             if (s0 + i < slots) {
                 const uint32_t ci = (s0 + (uint32_t)i) * (64u >> lc) + (ul >> lc);
                 const uint32_t off = ul & ((1u << lc) - 1u);
-                if (ci < K) pp = ((uint64_t)list[ci] << lc) + off;
+                if (ci < K) {
+                    pp = ((uint64_t)list[ci] << lc) + off;
+                    WEDGE_DCHECK(((uint64_t)list[ci] << lc) < m, kDbgChunk);
+                }
             }
             valid[i] = pp < m;
             p[i] = valid[i] ? (uint32_t)pp : 0u;

@@ -36,13 +36,13 @@ __global__ void k_iota_u32(uint32_t* __restrict__ p, uint32_t count) {
 // source's bit in the current-frontier bitmap.
 __global__ void k_seed_source(uint32_t src, const uint32_t* __restrict__ row_off,
                               uint32_t* val_a, uint32_t* val_b, uint32_t* flist, uint32_t* degpre,
-                              uint64_t* fcur, Ctl* ctl) {
+                              uint64_t* fcur, uint32_t* csum, Ctl* ctl) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         val_a[src] = 0;
         if (val_b) val_b[src] = 0;
         flist[0] = src;
         degpre[0] = 0;
-        set_bit(fcur, src);
+        set_bit_sum(fcur, csum, src);
         const unsigned long long d = row_off[src + 1] - row_off[src];
         ctl->fnext = ((d ? 1ull : 0ull) << kDegBits) | d;
         ctl->ftotal = 1;
@@ -55,7 +55,8 @@ __global__ void k_seed_source(uint32_t src, const uint32_t* __restrict__ row_off
 __global__ void k_seed_all(uint32_t n, uint32_t m, const uint32_t* __restrict__ row_off,
                            const uint32_t* __restrict__ inv, uint32_t* __restrict__ label,
                            uint32_t* __restrict__ val_prev, uint32_t* __restrict__ flist,
-                           uint32_t* __restrict__ degpre, uint64_t* __restrict__ fcur, Ctl* ctl) {
+                           uint32_t* __restrict__ degpre, uint64_t* __restrict__ fcur,
+                           uint32_t* __restrict__ csum, Ctl* ctl) {
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const uint32_t id = inv ? inv[v] : v;
         label[v] = id;
@@ -67,6 +68,7 @@ __global__ void k_seed_all(uint32_t n, uint32_t m, const uint32_t* __restrict__ 
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) {
         const uint32_t left = n - i * 64;
         fcur[i] = left >= 64 ? ~0ull : ((1ull << left) - 1ull);
+        if (csum && (i & 63) == 0) csum[i >> 6] = 1u;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->fnext = ((unsigned long long)n << kDegBits) | (unsigned long long)m;
@@ -100,9 +102,10 @@ __global__ __launch_bounds__(kBlock) void k_translate(const uint32_t* __restrict
                                                       uint32_t fcount, uint32_t active,
                                                       const uint32_t* __restrict__ row_off,
                                                       const uint32_t* __restrict__ pos, int lc,
-                                                      uint32_t* __restrict__ wbits32) {
+                                                      uint32_t* __restrict__ wbits32,
+                                                      uint32_t* __restrict__ wsum) {
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    translate_wave<EPT>(wave, flist, degpre, fcount, active, row_off, pos, lc, wbits32);
+    translate_wave<EPT>(wave, flist, degpre, fcount, active, row_off, pos, lc, wbits32, wsum);
 }
 
 // ------------------------------------------------------- bitmap compaction
@@ -125,10 +128,10 @@ __global__ __launch_bounds__(kCompactWaves * 64) void k_bitmap_compact(
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
-    uint64_t* __restrict__ copy_to) {
+    uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits, uint32_t* __restrict__ sum_copy) {
     bitmap_compact_block<DEG, COMMIT, COPY, G, kCompactWaves>(blockIdx.x, bits, words, limit, row_off,
                                                               list, degpre, counter, total, val_prev,
-                                                              val, copy_to);
+                                                              val, copy_to, sum_bits, sum_copy);
 }
 
 // ------------------------------------------------------------- the pulls
@@ -157,12 +160,13 @@ __global__ __launch_bounds__(kCompactWaves * 64) void k_bitmap_compact(
 // which is why any chunk granularity, or none, gives the same result
 // (Frontier Transformation, "Frontier Precision").
 // Full pull: wave w covers rows [w*R, w*R + R), i.e. every in-edge once.
-template <int APP, int R>
+template <int APP, int R, bool INPLACE = false>
 __global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_full(GraphArgs g, uint32_t iter,
                                                       uint32_t* __restrict__ val,
                                                       const uint32_t* __restrict__ val_prev,
                                                       const uint64_t* __restrict__ fcur,
-                                                      uint64_t* __restrict__ fbits) {
+                                                      uint64_t* __restrict__ fbits,
+                                                      uint32_t* __restrict__ fsum) {
     const int lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t r0 = wave * R;
@@ -175,21 +179,22 @@ __global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_full(Graph
         valid[i] = pp < g.m;
         p[i] = (uint32_t)pp;
     }
-    pull_lanes<APP, R, true>(g, p, valid, iter, val, val_prev, fcur, fbits);
+    pull_lanes<APP, R, true, INPLACE>(g, p, valid, iter, val, val_prev, fcur, fbits, fsum);
 }
 
 // Pull over the marked chunks: the chunk list holds K = *marked chunk ids of
 // 2^lc positions each. A 64-lane slot covers 64 >> lc chunks (lc <= 6) or one
 // 64-position part of a chunk (lc > 6). Waves stride over the slots, R slots at
 // a time; K is read on the device, so the launch needs no host round trip.
-template <int APP, int R, int FORM>
+template <int APP, int R, int FORM, bool INPLACE = false>
 __global__ __launch_bounds__(kBlock) WEDGE_CHUNK_OCCUPANCY void k_pull_chunks(GraphArgs g, uint32_t iter, int lc,
                                                         const uint32_t* __restrict__ list,
                                                         const unsigned long long* marked,
                                                         uint32_t* __restrict__ val,
                                                         const uint32_t* __restrict__ val_prev,
                                                         const uint64_t* __restrict__ fcur,
-                                                        uint64_t* __restrict__ fbits) {
+                                                        uint64_t* __restrict__ fbits,
+                                                        uint32_t* __restrict__ fsum) {
     const int lane = lane_id();
     const uint64_t K = *marked >> kDegBits;
     const uint64_t slots = chunk_slots(K, lc);
@@ -199,7 +204,7 @@ __global__ __launch_bounds__(kBlock) WEDGE_CHUNK_OCCUPANCY void k_pull_chunks(Gr
         uint32_t p[R];
         bool valid[R];
         chunk_slot_rows<R, FORM>(s0, slots, lane, lc, list, K, g.m, p, valid);
-        pull_lanes<APP, R>(g, p, valid, iter, val, val_prev, fcur, fbits);
+        pull_lanes<APP, R, false, INPLACE>(g, p, valid, iter, val, val_prev, fcur, fbits, fsum);
     }
 }
 
@@ -481,16 +486,16 @@ hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s) {
 
 hipError_t launch_seed_source(uint32_t src, const uint32_t* row_off, uint32_t* val_a,
                               uint32_t* val_b, uint32_t* flist, uint32_t* degpre, uint64_t* fcur,
-                              Ctl* ctl, hipStream_t s) {
-    k_seed_source<<<1, 64, 0, s>>>(src, row_off, val_a, val_b, flist, degpre, fcur, ctl);
+                              uint32_t* csum, Ctl* ctl, hipStream_t s) {
+    k_seed_source<<<1, 64, 0, s>>>(src, row_off, val_a, val_b, flist, degpre, fcur, csum, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_seed_all(uint32_t n, uint64_t m, const uint32_t* row_off, const uint32_t* inv,
                            uint32_t* label, uint32_t* val_prev, uint32_t* flist, uint32_t* degpre,
-                           uint64_t* fcur, Ctl* ctl, hipStream_t s) {
+                           uint64_t* fcur, uint32_t* csum, Ctl* ctl, hipStream_t s) {
     k_seed_all<<<grid_for(n, 8192), kBlock, 0, s>>>(n, (uint32_t)m, row_off, inv, label, val_prev,
-                                                    flist, degpre, fcur, ctl);
+                                                    flist, degpre, fcur, csum, ctl);
     return hipGetLastError();
 }
 
@@ -510,30 +515,30 @@ hipError_t launch_unpermute_f32(uint32_t n, const uint32_t* perm, const float* v
 
 hipError_t launch_translate(const uint32_t* flist, const uint32_t* degpre, uint32_t fcount,
                             uint64_t active, const uint32_t* row_off, const uint32_t* pos,
-                            int log_chunk, uint64_t* wbits, hipStream_t s) {
+                            int log_chunk, uint64_t* wbits, uint32_t* wsum, hipStream_t s) {
     if (!fcount || !active) return hipSuccess;
     const uint64_t waves = (active + 64ull * kTranslateEpt - 1) / (64ull * kTranslateEpt);
     const uint64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
     k_translate<kTranslateEpt><<<(uint32_t)blocks, kBlock, 0, s>>>(
         flist, degpre, fcount, (uint32_t)active, row_off, pos, log_chunk,
-        reinterpret_cast<uint32_t*>(wbits));
+        reinterpret_cast<uint32_t*>(wbits), wsum);
     return hipGetLastError();
 }
 
 hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list, Ctl* ctl,
-                                 hipStream_t s) {
+                                 uint32_t* wsum, hipStream_t s) {
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
     const uint32_t blocks = (uint32_t)((waves + kCompactWaves - 1) / kCompactWaves);
     k_bitmap_compact<false, false, false, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
         wbits, words, 0xFFFFFFFFu, nullptr, list, nullptr, &ctl->marked, nullptr, nullptr, nullptr,
-        nullptr);
+        nullptr, wsum, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
                            uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
-                           uint64_t* fcur, hipStream_t s) {
+                           uint64_t* fcur, uint32_t* fsum, uint32_t* csum, hipStream_t s) {
     const uint64_t words = ((uint64_t)n + 63) / 64;
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
@@ -542,13 +547,13 @@ hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
     unsigned long long* t = &ctl->ftotal;
     if (val_prev && fcur)
         k_bitmap_compact<true, true, true, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
-            fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur);
+            fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur, fsum, csum);
     else if (fcur)
         k_bitmap_compact<true, false, true, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
-            fbits, words, n, row_off, flist, degpre, c, t, nullptr, nullptr, fcur);
+            fbits, words, n, row_off, flist, degpre, c, t, nullptr, nullptr, fcur, fsum, csum);
     else
         k_bitmap_compact<true, false, false, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
-            fbits, words, n, row_off, flist, degpre, c, t, nullptr, nullptr, nullptr);
+            fbits, words, n, row_off, flist, degpre, c, t, nullptr, nullptr, nullptr, fsum, nullptr);
     return hipGetLastError();
 }
 
@@ -561,54 +566,58 @@ uint32_t full_blocks(const DevGraph& g) {
 
 hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
                             const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
-                            hipStream_t s, int rows) {
+                            uint32_t* fsum, hipStream_t s, int rows, bool inplace) {
     if (!g.rows) return hipSuccess;
     if (app != kBfs && rows != kPullRows) return hipErrorInvalidValue;
+    if (inplace && app == kBfs) return hipErrorInvalidValue;
     GraphArgs a = args_of(g);
     if (app == kBfs) {
         switch (rows) {
-            case 4: k_pull_full<kBfs, 4><<<full_blocks<4>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
-            case 16: k_pull_full<kBfs, 16><<<full_blocks<16>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
-            case kPullRows: k_pull_full<kBfs, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits); break;
+            case 4: k_pull_full<kBfs, 4><<<full_blocks<4>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum); break;
+            case 16: k_pull_full<kBfs, 16><<<full_blocks<16>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum); break;
+            case kPullRows: k_pull_full<kBfs, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum); break;
             default: return hipErrorInvalidValue;
         }
     } else if (app == kCc) {
-        k_pull_full<kCc, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits);
+        if (inplace) k_pull_full<kCc, kPullRows, true><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum);
+        else k_pull_full<kCc, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum);
     } else {
-        k_pull_full<kSssp, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits);
+        if (inplace) k_pull_full<kSssp, kPullRows, true><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum);
+        else k_pull_full<kSssp, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum);
     }
     return hipGetLastError();
 }
 
-template <int APP, int R, int FORM>
+template <int APP, int R, int FORM, bool INPLACE>
 void launch_chunks_form(uint32_t blocks, const GraphArgs& a, uint32_t iter, int lc,
                         const uint32_t* list, const unsigned long long* mk, uint32_t* val,
                         const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
-                        hipStream_t s) {
-    k_pull_chunks<APP, R, FORM><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits);
+                        uint32_t* fsum, hipStream_t s) {
+    k_pull_chunks<APP, R, FORM, INPLACE><<<blocks, kBlock, 0, s>>>(a, iter, lc, list, mk, val, val_prev, fcur, fbits, fsum);
 }
 
-template <int APP, int R>
+template <int APP, int R, bool INPLACE = false>
 void launch_chunks_rows(uint64_t slots, const GraphArgs& a, uint32_t iter, int lc,
                         const uint32_t* list, const unsigned long long* mk, uint32_t* val,
                         const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
-                        hipStream_t s) {
+                        uint32_t* fsum, hipStream_t s) {
     uint64_t waves = (slots + R - 1) / R;
     const uint64_t cap = 256ull * 32;  // resident waves on 256 CUs at 8 waves/SIMD
     if (waves > cap) waves = cap;
     const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     const int form = slot_form<R>(lc);
-    if (form == kSlotsShared) launch_chunks_form<APP, R, kSlotsShared>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, s);
-    else if (form == kSlotsLong) launch_chunks_form<APP, R, kSlotsLong>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, s);
-    else launch_chunks_form<APP, R, kSlotsEach>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, s);
+    if (form == kSlotsShared) launch_chunks_form<APP, R, kSlotsShared, INPLACE>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, fsum, s);
+    else if (form == kSlotsLong) launch_chunks_form<APP, R, kSlotsLong, INPLACE>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, fsum, s);
+    else launch_chunks_form<APP, R, kSlotsEach, INPLACE>(blocks, a, iter, lc, list, mk, val, val_prev, fcur, fbits, fsum, s);
 }
 
 hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
                               const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
                               uint32_t* val, const uint32_t* val_prev, const uint64_t* fcur,
-                              uint64_t* fbits, hipStream_t s, int rows) {
+                              uint64_t* fbits, uint32_t* fsum, hipStream_t s, int rows, bool inplace) {
     if (!max_chunks) return hipSuccess;
     if (app != kBfs && rows != kPullRows) return hipErrorInvalidValue;
+    if (inplace && app == kBfs) return hipErrorInvalidValue;
     const uint64_t slots = log_chunk <= 6
                                ? (max_chunks + (64u >> log_chunk) - 1) / (64u >> log_chunk)
                                : max_chunks << (log_chunk - 6);
@@ -616,15 +625,17 @@ hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log
     const unsigned long long* mk = &ctl->marked;
     if (app == kBfs) {
         switch (rows) {
-            case 4: launch_chunks_rows<kBfs, 4>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s); break;
-            case 16: launch_chunks_rows<kBfs, 16>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s); break;
-            case kPullRows: launch_chunks_rows<kBfs, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s); break;
+            case 4: launch_chunks_rows<kBfs, 4>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, fsum, s); break;
+            case 16: launch_chunks_rows<kBfs, 16>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, fsum, s); break;
+            case kPullRows: launch_chunks_rows<kBfs, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, fsum, s); break;
             default: return hipErrorInvalidValue;
         }
     } else if (app == kCc) {
-        launch_chunks_rows<kCc, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
+        if (inplace) launch_chunks_rows<kCc, kPullRows, true>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, fsum, s);
+        else launch_chunks_rows<kCc, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, fsum, s);
     } else {
-        launch_chunks_rows<kSssp, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, s);
+        if (inplace) launch_chunks_rows<kSssp, kPullRows, true>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, fsum, s);
+        else launch_chunks_rows<kSssp, kPullRows>(slots, a, iter, log_chunk, list, mk, val, val_prev, fcur, fbits, fsum, s);
     }
     return hipGetLastError();
 }
@@ -699,5 +710,7 @@ hipError_t launch_set_f64(double* p, double v, hipStream_t s) {
     k_set_f64<<<1, 64, 0, s>>>(p, v);
     return hipGetLastError();
 }
+
+WEDGE_DEBUG_ACCESSOR(debug_take_kernels)
 
 }  // namespace wedge

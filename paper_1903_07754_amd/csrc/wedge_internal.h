@@ -72,6 +72,10 @@ struct DevGraph {
     uint32_t* spans = nullptr;
     uint32_t* perm = nullptr;  // original -> internal (null: identity)
     uint32_t* inv = nullptr;   // internal -> original (null: identity)
+    // push engine (built on first use): out-edge destinations and weights in CSR order
+    uint32_t* out_dst = nullptr;
+    uint32_t* out_w = nullptr;
+    bool out_built = false;
 };
 
 // Kernel view of a device graph.
@@ -84,6 +88,9 @@ struct GraphArgs {
     const uint64_t* __restrict__ rowmask;
     const uint32_t* __restrict__ rowseg;
     const uint32_t* __restrict__ nzdst;
+#ifdef WEDGE_DEBUG_CHECKS
+    const uint32_t* __restrict__ col_off;  // checks that a lane's (position, destination) is an in-edge
+#endif
 };
 
 inline GraphArgs args_of(const DevGraph& g) {
@@ -96,6 +103,9 @@ inline GraphArgs args_of(const DevGraph& g) {
     a.rowmask = g.rowmask;
     a.rowseg = g.rowseg;
     a.nzdst = g.nzdst;
+#ifdef WEDGE_DEBUG_CHECKS
+    a.col_off = g.col_off;
+#endif
     return a;
 }
 
@@ -201,6 +211,9 @@ struct Workspace {
     uint32_t* val_prev = nullptr;  // n
     uint64_t* wbits = nullptr;     // ceil(ceil(m/chunk)/64) words for the smallest chunk so far
     uint64_t wbits_words = 0;
+    uint32_t* fsum = nullptr;      // summary flags of fbits (kept all-zero between uses)
+    uint32_t* csum = nullptr;      // summary flags of fcur
+    uint32_t* wsum = nullptr;      // summary flags of wbits (sized with it)
     uint32_t* chunks = nullptr;    // chunk list
     uint64_t chunks_cap = 0;
     Ctl* ctl = nullptr;            // device counters
@@ -279,12 +292,18 @@ wedge_status model_to_device(wedge_model_s* m);
 // (kernels.hip). Every launcher enqueues on `s` and returns the launch status.
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
+// Summaries (fsum of the next-frontier bitmap, csum of the current one, wsum of
+// the Wedge bitmap): one 32-bit flag per 4096 bits, set by every writer of a
+// bit in that range and cleared by the compaction that lists it; nullable
+// (null: the compaction scans every word and no flag is kept).
+constexpr uint32_t kSumBits = 4096;
+inline uint64_t sum_flags(uint64_t bits) { return (bits + kSumBits - 1) / kSumBits; }
 hipError_t launch_seed_source(uint32_t src, const uint32_t* row_off, uint32_t* val_a,
                               uint32_t* val_b, uint32_t* flist, uint32_t* degpre, uint64_t* fcur,
-                              Ctl* ctl, hipStream_t s);
+                              uint32_t* csum, Ctl* ctl, hipStream_t s);
 hipError_t launch_seed_all(uint32_t n, uint64_t m, const uint32_t* row_off, const uint32_t* inv,
                            uint32_t* label, uint32_t* val_prev, uint32_t* flist, uint32_t* degpre,
-                           uint64_t* fcur, Ctl* ctl, hipStream_t s);
+                           uint64_t* fcur, uint32_t* csum, Ctl* ctl, hipStream_t s);
 hipError_t launch_unpermute_u32(uint32_t n, const uint32_t* perm, const uint32_t* val,
                                 uint32_t* out, hipStream_t s);
 hipError_t launch_unpermute_f32(uint32_t n, const uint32_t* perm, const float* val, float* out,
@@ -292,24 +311,26 @@ hipError_t launch_unpermute_f32(uint32_t n, const uint32_t* perm, const float* v
 hipError_t launch_set_f64(double* p, double v, hipStream_t s);
 hipError_t launch_translate(const uint32_t* flist, const uint32_t* degpre, uint32_t fcount,
                             uint64_t active, const uint32_t* row_off, const uint32_t* pos,
-                            int log_chunk, uint64_t* wbits, hipStream_t s);
+                            int log_chunk, uint64_t* wbits, uint32_t* wsum, hipStream_t s);
 hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list, Ctl* ctl,
-                                 hipStream_t s);
+                                 uint32_t* wsum, hipStream_t s);
 // rows: 64-edge rows per wave step, 4, 8 or 16 for BFS, 8 for CC and SSSP
 // (anything else returns hipErrorInvalidValue before any launch).
+// inplace (CC and SSSP): gather sources' values from val instead of val_prev.
 hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
                             const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
-                            hipStream_t s, int rows = kPullRows);
+                            uint32_t* fsum, hipStream_t s, int rows = kPullRows, bool inplace = false);
 hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log_chunk,
                               const uint32_t* list, const Ctl* ctl, uint64_t max_chunks,
                               uint32_t* val, const uint32_t* val_prev, const uint64_t* fcur,
-                              uint64_t* fbits, hipStream_t s, int rows = kPullRows);
+                              uint64_t* fbits, uint32_t* fsum, hipStream_t s, int rows = kPullRows,
+                              bool inplace = false);
 // Lists the next-frontier bitmap (with out-degree prefix), commits val to
 // val_prev for listed vertices (when val_prev is set), moves the bitmap into
 // fcur (when set) and clears it.
 hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
                            uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
-                           uint64_t* fcur, hipStream_t s);
+                           uint64_t* fcur, uint32_t* fsum, uint32_t* csum, hipStream_t s);
 // PageRank
 hipError_t launch_pr_init(uint32_t n, const uint32_t* row_off, float* rank, float* contrib,
                           float* sum, hipStream_t s);
@@ -325,22 +346,23 @@ hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* 
 uint32_t pr_epilogue_blocks(uint32_t n);
 // Batched BFS (batch.hip)
 hipError_t launch_ms_pull_full(const DevGraph& g, uint64_t all, const uint64_t* visited,
-                               const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s,
-                               int rows = kPullRows);
+                               const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, uint32_t* fsum,
+                               hipStream_t s, int rows = kPullRows);
 hipError_t launch_ms_pull_chunks(const DevGraph& g, int lc, const uint32_t* list, const Ctl* ctl,
                                  uint64_t max_chunks, uint64_t all, const uint64_t* visited,
-                                 const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, hipStream_t s,
-                                 int rows = kPullRows);
+                                 const uint64_t* cur, uint64_t* nxt, uint64_t* fbits, uint32_t* fsum,
+                                 hipStream_t s, int rows = kPullRows);
 // Commit of a multi-source iteration (see ms_finalize_block); `retire` holds
 // the masks of the frontier being replaced, `nxt` those just built.
 hipError_t launch_ms_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
                               uint32_t* flist, uint32_t* degpre, Ctl* ctl, uint64_t* fcur,
                               uint64_t* visited, uint64_t* retire, const uint64_t* nxt,
-                              uint32_t* lev, uint32_t K, uint32_t level, hipStream_t s);
+                              uint32_t* lev, uint32_t K, uint32_t level, uint32_t* fsum,
+                              uint32_t* csum, hipStream_t s);
 hipError_t launch_ms_seed(const uint32_t* srcs, uint32_t K, uint64_t* nxt, uint64_t* fbits,
-                          hipStream_t s);
+                          uint32_t* fsum, hipStream_t s);
 hipError_t launch_roots_seed(const uint32_t* roots, uint32_t count, uint32_t* level,
-                             uint64_t* fbits, hipStream_t s);
+                             uint64_t* fbits, uint32_t* fsum, hipStream_t s);
 hipError_t launch_ms_output(uint32_t n, uint32_t K, const uint32_t* perm, const uint32_t* lev,
                             uint32_t* out, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);
@@ -362,6 +384,25 @@ hipError_t launch_gate_stamp(Ctl* ctl, hipStream_t s);
 void mlp_features(float* x, double fcount, double active, double n, double m, double k,
                   double prev_us, double prev_mode, double app);
 hipError_t launch_bfs_persistent(bool ms, const PersistParams& P, uint32_t blocks, hipStream_t s);
+
+// Push engine (push.hip): the out-edge arrays from the edge index, and one
+// push iteration over the listed frontier (val_prev: committed values, CC and
+// SSSP; out_w: SSSP).
+hipError_t launch_out_edges(const DevGraph& g, const uint32_t* pos, uint32_t* out_dst, uint32_t* out_w,
+                            hipStream_t s);
+hipError_t launch_push(int app, const uint32_t* flist, const uint32_t* degpre, uint32_t fcount,
+                       uint64_t active, const uint32_t* row_off, const uint32_t* out_dst,
+                       const uint32_t* out_w, uint32_t iter, uint32_t* val, const uint32_t* val_prev,
+                       uint64_t* fbits, uint32_t* fsum, hipStream_t s);
+
+// Debug builds (WEDGE_DEBUG_CHECKS): each kernel source keeps an error word
+// that failed device checks OR their codes into; these read and clear them
+// (0 in other builds).
+hipError_t debug_take_kernels(unsigned* word);
+hipError_t debug_take_batch(unsigned* word);
+hipError_t debug_take_push(unsigned* word);
+constexpr unsigned kDbgPullPos = 1u, kDbgPullDst = 2u, kDbgPullEdge = 4u, kDbgTranslate = 8u,
+                   kDbgChunk = 16u;
 
 // Allocation-free BFS (noalloc.hip): the fixed device scratch of each GPU,
 // looked up once per device (dev must be the current device), and the lock

@@ -22,6 +22,8 @@ if not torch.cuda.is_available():
 
 import paper_1903_07754_amd as W  # noqa: E402
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 INF = oracle.INF
 
 
@@ -247,3 +249,29 @@ def test_multisource_errors():
     with pytest.raises(W.WedgeError) as e:
         W.bfs_batch(g, np.array([0], np.uint32))
     assert e.value.name == "WEDGE_ERR_UNSUPPORTED"
+
+
+def test_autotuner_cache_file_survives_the_process(tmp_path, monkeypatch):
+    # with WEDGE_TUNE_CACHE set, a tuning run writes its table to the file and a
+    # new process finds the winner there without tuning again
+    import json
+    import subprocess
+    import sys
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("WEDGE_TUNE_CACHE", str(path))
+    ro, col = gen.rmat(11, 8, seed=67)
+    g = W.Graph.from_csr(ro, col)
+    srcs = gen.pick_sources(ro, 1, seed=14)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    best, _ = W.tune_bfs(g, "single", srcs, out)
+    lines = path.read_text().splitlines()
+    assert lines[0] == "wedge-tune-v1" and len(lines) >= 2
+    keys = ("chunk", "persistent", "blocks_per_cu", "rows_per_wave")
+    code = ("import json, sys; sys.path.insert(0, %r); import paper_1903_07754_amd as W; "
+            "print(json.dumps(W.tune_lookup('single', 1, %d)))" % (str(ROOT), g.m))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                       env={**os.environ, "WEDGE_TUNE_CACHE": str(path)})
+    assert r.returncode == 0, r.stderr
+    got = json.loads(r.stdout.strip().splitlines()[-1])
+    assert got == {k: best[k] for k in keys}
+    g.close()
