@@ -25,6 +25,10 @@
  *   - Errors are status codes; nothing throws across the ABI. All argument
  *     checks happen before any device work. wedge_last_error() gives a
  *     thread-local message for the last failure.
+ *   - The library's own calls that are not stream ordered (device allocation
+ *     and free, synchronous clears, pinned allocation, event creation) never
+ *     overlap its own stream captures in another thread (one process-wide
+ *     lock), so concurrent runs cannot invalidate a persistent run's capture.
  *   - A graph handle is immutable after creation; one graph must not be used by
  *     two runs at the same time (its cached workspace is shared). A run on a
  *     busy graph returns WEDGE_ERR_BUSY. Different graphs may run concurrently
@@ -42,6 +46,9 @@
  *                             every block exit and the run return WEDGE_ERR_HIP.
  *   WEDGE_HOST_THREADS        threads of the host-side layout build (else
  *                             OMP_NUM_THREADS, else the hardware count).
+ *   WEDGE_SLICED_PULL         "1": build the source-sliced in-edge copy for every
+ *                             graph, "0": for none; unset: for graphs of at
+ *                             least 2^22 edges (read at graph create).
  *   WEDGE_TUNE_CACHE          path of a text file that keeps the autotuner's
  *                             table across processes (read on first use,
  *                             rewritten after every wedge_tune_bfs).
@@ -107,7 +114,13 @@ typedef struct wedge_graph_s* wedge_graph_t;
  *     where a destination's in-edge list begins, the index of the destination
  *     segment covering the row's first position, and the list of destinations
  *     with at least one in-edge. These name each position's destination
- *     without the vertex index (the role the paper gives Vector-Sparse).
+ *     without the vertex index (the role the paper gives Vector-Sparse);
+ *   - for large graphs (see WEDGE_SLICED_PULL), a second copy of the in-edges
+ *     split into 8 slices by source (groups of 1024 consecutive internal
+ *     ids dealt to the slices in turn), each grouped by destination with its
+ *     own row layout. The CC and SSSP pulls over every in-edge run slice j on
+ *     the 8th of the GPU's workgroups that the hardware places on XCD j, so
+ *     each XCD's L2 caches only its slice's source values.
  * The stream orders the uploads; the call returns after they finish.
  * Returns WEDGE_ERR_BAD_GRAPH for malformed input, WEDGE_ERR_OOM on allocation
  * failure. *out is set only on success.
@@ -138,6 +151,8 @@ typedef struct {
     uint64_t device_bytes; /* device memory held by the graph (layout + cached workspace) */
     uint64_t pr_short_spans; /* of pr_spans, those over at most 9 tiles (listed first) */
     uint32_t relabeled;    /* 1 when the internal vertex order differs from the caller's */
+    uint64_t xs_rows;      /* rows of the source-sliced in-edge copy (0: not built) */
+    uint64_t xs_segments;  /* its destination segments */
 } wedge_graph_info;
 
 wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info);
@@ -153,7 +168,15 @@ typedef enum {
     WEDGE_LAYOUT_ROWSEG = 6,  /* uint32[rows] segment index covering the row's first position */
     WEDGE_LAYOUT_NZDST = 7,   /* uint32[nonempty] destination of each segment */
     WEDGE_LAYOUT_PR_SPANS = 8,/* uint32[3*pr_spans] (vertex, first tile, last tile) */
-    WEDGE_LAYOUT_PERM = 9     /* uint32[n] internal id of each caller id (relabelled graphs) */
+    WEDGE_LAYOUT_PERM = 9,    /* uint32[n] internal id of each caller id (relabelled graphs) */
+    /* the source-sliced copy of the in-edges (graphs with xs_rows > 0): */
+    WEDGE_LAYOUT_XS_SRC = 10,     /* uint32[64*xs_rows] sources; padding positions hold 0 */
+    WEDGE_LAYOUT_XS_W = 11,       /* uint32[64*xs_rows] weights (weighted graphs) */
+    WEDGE_LAYOUT_XS_ROWMASK = 12, /* uint64[xs_rows] */
+    WEDGE_LAYOUT_XS_ROWSEG = 13,  /* uint32[xs_rows] */
+    WEDGE_LAYOUT_XS_NZDST = 14,   /* uint32[xs_segments] */
+    WEDGE_LAYOUT_XS_BOUNDS = 15   /* uint32[17]: first row of slices 0..8, then the end
+                                     position of slices 0..7 */
 } wedge_layout_array;
 
 /* Layout arrays are indexed and valued by internal vertex ids. */

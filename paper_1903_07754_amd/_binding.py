@@ -29,7 +29,8 @@ GATE = {"threshold": 0, "wedge": 1, "full": 2, "learned": 3, "push": 4, "hybrid"
 RUN_TIME_PULL, RUN_TIME_ITERS, RUN_PERSISTENT, RUN_INPLACE = 0x1, 0x2, 0x4, 0x8
 TUNE = {"single": 0, "multisource": 1, "batch": 2}
 LAYOUT = {"col_off": 0, "in_src": 1, "in_w": 2, "row_off": 3, "pos": 4, "rowmask": 5,
-          "rowseg": 6, "nzdst": 7, "pr_spans": 8, "perm": 9}
+          "rowseg": 6, "nzdst": 7, "pr_spans": 8, "perm": 9, "xs_src": 10, "xs_w": 11,
+          "xs_rowmask": 12, "xs_rowseg": 13, "xs_nzdst": 14, "xs_bounds": 15}
 
 
 class WedgeError(RuntimeError):
@@ -44,7 +45,8 @@ class GraphInfo(C.Structure):
                 ("rows", C.c_uint64), ("flags", C.c_uint32), ("weighted", C.c_uint32),
                 ("dangling", C.c_uint32), ("pr_tile_edges", C.c_uint32),
                 ("pr_spans", C.c_uint64), ("device_bytes", C.c_uint64),
-                ("pr_short_spans", C.c_uint64), ("relabeled", C.c_uint32)]
+                ("pr_short_spans", C.c_uint64), ("relabeled", C.c_uint32),
+                ("xs_rows", C.c_uint64), ("xs_segments", C.c_uint64)]
 
 
 class IterRecord(C.Structure):
@@ -238,11 +240,14 @@ class Graph:
         return first
 
     def layout(self, name):
-        dt = np.uint64 if name == "rowmask" else np.uint32
+        dt = np.uint64 if name in ("rowmask", "xs_rowmask") else np.uint32
+        info = self.info
         sizes = {"col_off": self.n + 1, "in_src": self.m, "in_w": self.m, "row_off": self.n + 1,
-                 "pos": self.m, "rowmask": self.info["rows"], "rowseg": self.info["rows"],
-                 "nzdst": self.info["nonempty"], "pr_spans": 3 * self.info["pr_spans"],
-                 "perm": self.n}
+                 "pos": self.m, "rowmask": info["rows"], "rowseg": info["rows"],
+                 "nzdst": info["nonempty"], "pr_spans": 3 * info["pr_spans"],
+                 "perm": self.n, "xs_src": 64 * info["xs_rows"], "xs_w": 64 * info["xs_rows"],
+                 "xs_rowmask": info["xs_rows"], "xs_rowseg": info["xs_rows"],
+                 "xs_nzdst": info["xs_segments"], "xs_bounds": 17}
         out = np.zeros(max(int(sizes[name]), 1), dt)
         nbytes = int(sizes[name]) * out.itemsize
         check(lib().wedge_graph_layout(self._h, LAYOUT[name], out.ctypes.data, nbytes))

@@ -45,6 +45,10 @@ wedge_status fail(wedge_status st, const std::string& msg) {
 
 namespace wedge {
 wedge_status set_error(wedge_status st, const std::string& msg) { return fail(st, msg); }
+std::recursive_mutex& setup_mutex() {
+    static std::recursive_mutex mu;
+    return mu;
+}
 }  // namespace wedge
 
 namespace {
@@ -67,6 +71,7 @@ uint64_t device_cap() {
 
 // Device allocation accounted against the graph (and the optional cap).
 wedge_status dev_alloc(wedge_graph_s* g, void** p, size_t bytes, const char* what) {
+    SetupLock lock;
     *p = nullptr;
     if (bytes == 0) bytes = 8;
     uint64_t cap = device_cap();
@@ -94,9 +99,11 @@ wedge_status upload(wedge_graph_s* g, T** dst, const std::vector<T>& src, hipStr
 }
 
 void free_all(wedge_graph_s* g) {
+    SetupLock lock;
     DevGraph& d = g->dev;
     void* ptrs[] = {d.col_off, d.in_src, d.in_w, d.row_off, d.pos, d.rowmask, d.rowseg, d.nzdst, d.spans,
-                    d.perm, d.inv, d.out_dst, d.out_w};
+                    d.perm, d.inv, d.out_dst, d.out_w, d.xs_src, d.xs_w, d.xs_rowmask, d.xs_rowseg,
+                    d.xs_nzdst};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     Workspace& w = g->ws;
@@ -134,6 +141,13 @@ wedge_status copy_input(const T* p, uint64_t count, bool on_device, std::vector<
     return WEDGE_OK;
 }
 
+// Whether a graph gets the source-sliced in-edge copy (WEDGE_SLICED_PULL).
+bool sliced_pull_wanted(uint64_t m) {
+    const char* e = std::getenv("WEDGE_SLICED_PULL");
+    if (e && *e) return e[0] == '1';
+    return m >= (1ull << 22);
+}
+
 wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, const uint32_t* ids,
                     const uint32_t* w, uint32_t flags, hipStream_t stream, wedge_graph_t* out) {
     if (!out) return fail(WEDGE_ERR_INVALID_ARG, "out is null");
@@ -164,6 +178,7 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     st = from_csr ? build_layout_from_csr(n, m, hoff, hids, hw, sym, relabel, &L, &g_err)
                   : build_layout_from_csc(n, m, hoff, hids, hw, sym, relabel, &L, &g_err);
     if (st != WEDGE_OK) { delete g; return st; }
+    if (sliced_pull_wanted(L.m)) build_xcd_slices(&L);
     g->weighted = !L.in_w.empty() || (w != nullptr);
     g->dangling = L.dangling;
     g->max_w = L.max_w;
@@ -174,6 +189,13 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     d.nonempty = (uint32_t)L.nzdst.size();
     d.nspans = L.spans.size() / 3;
     d.short_spans = L.short_spans;
+    if (!L.xs_rowmask.empty() && L.xs_row_begin[kXcdSlices]) {
+        d.xs_rows = L.xs_row_begin[kXcdSlices];
+        d.xs_positions = d.xs_rows * 64;
+        d.xs_segments = L.xs_nzdst.size();
+        std::memcpy(d.xs_row_begin, L.xs_row_begin, sizeof d.xs_row_begin);
+        std::memcpy(d.xs_edge_end, L.xs_edge_end, sizeof d.xs_edge_end);
+    }
     g->perm_host = L.perm;
     if (g->host_only) { *out = g; return WEDGE_OK; }
     {
@@ -181,6 +203,7 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
         if (e != hipSuccess) { delete g; return hip_fail(e, "hipGetDevice"); }
     }
     st = WEDGE_OK;
+    SetupLock upload_lock;
     if (st == WEDGE_OK) st = upload(g, &d.col_off, L.col_off, stream, "col_off");
     if (st == WEDGE_OK) st = upload(g, &d.in_src, L.in_src, stream, "in_src");
     if (st == WEDGE_OK && g->weighted) st = upload(g, &d.in_w, L.in_w, stream, "in_w");
@@ -192,6 +215,11 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     if (st == WEDGE_OK) st = upload(g, &d.spans, L.spans, stream, "spans");
     if (st == WEDGE_OK && !L.perm.empty()) st = upload(g, &d.perm, L.perm, stream, "perm");
     if (st == WEDGE_OK && !L.inv.empty()) st = upload(g, &d.inv, L.inv, stream, "inv");
+    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_src, L.xs_src, stream, "sliced in-edges");
+    if (st == WEDGE_OK && d.xs_rows && !L.xs_w.empty()) st = upload(g, &d.xs_w, L.xs_w, stream, "sliced weights");
+    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowmask, L.xs_rowmask, stream, "sliced row masks");
+    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowseg, L.xs_rowseg, stream, "sliced row segments");
+    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_nzdst, L.xs_nzdst, stream, "sliced segment destinations");
     if (st == WEDGE_OK) {
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) st = hip_fail(e, "uploading graph");
@@ -210,6 +238,7 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
 // ----------------------------------------------------------- workspace
 
 wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontier, bool need_chunks) {
+    SetupLock lock;
     Workspace& w = g->ws;
     const DevGraph& d = g->dev;
     wedge_status st;
@@ -323,6 +352,7 @@ bool wedge_gate_used(uint32_t gate) { return gate != WEDGE_GATE_ALWAYS_FULL && !
 // The push engine's out-edge arrays, built once per graph on the device from
 // the edge index and the row layout.
 wedge_status ensure_push(wedge_graph_s* g, hipStream_t s) {
+    SetupLock lock;
     DevGraph& d = g->dev;
     if (d.out_built) return WEDGE_OK;
     wedge_status st;
@@ -746,6 +776,7 @@ wedge_status run_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* out, const
 // ---------------------------------------------------------------- batching
 
 wedge_status ensure_batch(wedge_graph_t g, uint32_t nroots, uint32_t K) {
+    SetupLock lock;
     Workspace& w = g->ws;
     const DevGraph& d = g->dev;
     wedge_status st;
@@ -846,6 +877,7 @@ wedge_status run_persistent(wedge_graph_t g, bool ms, uint32_t count, uint32_t* 
                   (unsigned long long)w.generation, (unsigned long long)timeout);
     const std::string key(keybuf);
     if (key != w.graph_key || !w.graph_exec) {
+        SetupLock capture_lock;
         if (w.graph_exec) { (void)hipGraphExecDestroy(w.graph_exec); w.graph_exec = nullptr; }
         if (w.graph) { (void)hipGraphDestroy(w.graph); w.graph = nullptr; }
         w.graph_key.clear();
@@ -1133,6 +1165,9 @@ wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info) {
     info->device_bytes = g->device_bytes;
     info->pr_short_spans = g->dev.short_spans;
     info->relabeled = g->perm_host.empty() ? 0u : 1u;
+    info->xs_rows = g->host_only ? (g->host.xs_rowmask.empty() ? 0 : g->host.xs_row_begin[kXcdSlices])
+                                 : g->dev.xs_rows;
+    info->xs_segments = g->host_only ? g->host.xs_nzdst.size() : g->dev.xs_segments;
     return WEDGE_OK;
 }
 
@@ -1156,6 +1191,31 @@ wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void*
         case WEDGE_LAYOUT_ROWSEG: size = d.rows * 4; hsrc = L.rowseg.data(); dsrc = d.rowseg; break;
         case WEDGE_LAYOUT_NZDST: size = (uint64_t)d.nonempty * 4; hsrc = L.nzdst.data(); dsrc = d.nzdst; break;
         case WEDGE_LAYOUT_PR_SPANS: size = d.nspans * 12; hsrc = L.spans.data(); dsrc = d.spans; break;
+        case WEDGE_LAYOUT_XS_SRC:
+        case WEDGE_LAYOUT_XS_W:
+        case WEDGE_LAYOUT_XS_ROWMASK:
+        case WEDGE_LAYOUT_XS_ROWSEG:
+        case WEDGE_LAYOUT_XS_NZDST:
+        case WEDGE_LAYOUT_XS_BOUNDS: {
+            const uint64_t xr = g->host_only ? (L.xs_rowmask.empty() ? 0 : L.xs_row_begin[kXcdSlices]) : d.xs_rows;
+            const uint64_t xseg = g->host_only ? L.xs_nzdst.size() : d.xs_segments;
+            if (!xr) return fail(WEDGE_ERR_UNSUPPORTED, "graph has no source-sliced in-edge copy");
+            if (which == WEDGE_LAYOUT_XS_BOUNDS) {
+                uint32_t b[2 * kXcdSlices + 1];
+                for (int j = 0; j <= kXcdSlices; ++j) b[j] = g->host_only ? L.xs_row_begin[j] : d.xs_row_begin[j];
+                for (int j = 0; j < kXcdSlices; ++j) b[kXcdSlices + 1 + j] = g->host_only ? L.xs_edge_end[j] : d.xs_edge_end[j];
+                if (bytes != sizeof b) return fail(WEDGE_ERR_INVALID_ARG, "bytes does not match the array size");
+                std::memcpy(dst, b, sizeof b);
+                return WEDGE_OK;
+            }
+            if (which == WEDGE_LAYOUT_XS_W && !g->weighted) return fail(WEDGE_ERR_NO_WEIGHTS, "graph has no weights");
+            if (which == WEDGE_LAYOUT_XS_SRC) { size = xr * 64 * 4; hsrc = L.xs_src.data(); dsrc = d.xs_src; }
+            if (which == WEDGE_LAYOUT_XS_W) { size = xr * 64 * 4; hsrc = L.xs_w.data(); dsrc = d.xs_w; }
+            if (which == WEDGE_LAYOUT_XS_ROWMASK) { size = xr * 8; hsrc = L.xs_rowmask.data(); dsrc = d.xs_rowmask; }
+            if (which == WEDGE_LAYOUT_XS_ROWSEG) { size = xr * 4; hsrc = L.xs_rowseg.data(); dsrc = d.xs_rowseg; }
+            if (which == WEDGE_LAYOUT_XS_NZDST) { size = xseg * 4; hsrc = L.xs_nzdst.data(); dsrc = d.xs_nzdst; }
+            break;
+        }
         case WEDGE_LAYOUT_PERM:
             size = g->perm_host.empty() ? 0 : (uint64_t)d.n * 4;
             if (!size) return fail(WEDGE_ERR_UNSUPPORTED, "graph keeps the caller's ids (no permutation)");
@@ -1226,8 +1286,12 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
     const bool time_pull = o.flags & WEDGE_RUN_TIME_PULL;
     const int cus = device_cus(g->device);
     std::vector<hipEvent_t> evs;
-    auto cleanup = [&] { for (auto ev : evs) if (ev) (void)hipEventDestroy(ev); };
+    auto cleanup = [&] {
+        SetupLock lock;
+        for (auto ev : evs) if (ev) (void)hipEventDestroy(ev);
+    };
     if (time_pull) {
+        SetupLock lock;
         evs.assign(2 * (size_t)iters, nullptr);
         for (auto& ev : evs) {
             const hipError_t ce = hipEventCreate(&ev);
@@ -1320,6 +1384,7 @@ wedge_status wedge_frontier_translate(wedge_graph_t g, const uint32_t* frontier_
     }
     // compact a copy so the caller keeps the bitmap
     uint64_t* tmp = nullptr;
+    SetupLock scratch_lock;
     HIP_TRY(hipMallocAsync((void**)&tmp, words ? words * 8 : 8, s), "scratch bitmap");
     hipError_t e = hipMemcpyAsync(tmp, wbits_dev, words * 8, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = launch_compact_chunks(tmp, words, chunk_list_dev, w.ctl, nullptr, s);
@@ -1445,13 +1510,23 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
     c16.lc = 4;
     if ((st = clear_bitmaps(g, c16, s)) != WEDGE_OK) return st;
     const uint64_t fwords = ((uint64_t)d.n + 63) / 64;
-    struct Tmp { void* p = nullptr; ~Tmp() { if (p) (void)hipFree(p); } } tval, sv, sp, sf, sc;
+    struct Tmp {
+        void* p = nullptr;
+        ~Tmp() {
+            if (!p) return;
+            SetupLock lock;
+            (void)hipFree(p);
+        }
+    } tval, sv, sp, sf, sc;
     uint32_t* val = d.inv ? w.val : nullptr;
-    if (!val) { HIP_TRY(hipMalloc(&tval.p, (size_t)d.n * 4), "trace values"); val = (uint32_t*)tval.p; }
-    HIP_TRY(hipMalloc(&sv.p, (size_t)d.n * 4), "snapshot");
-    HIP_TRY(hipMalloc(&sp.p, (size_t)d.n * 4), "snapshot");
-    HIP_TRY(hipMalloc(&sf.p, fwords * 8), "snapshot");
-    HIP_TRY(hipMalloc(&sc.p, sum_flags(d.n) * 4), "snapshot");
+    {
+        SetupLock lock;
+        if (!val) { HIP_TRY(hipMalloc(&tval.p, (size_t)d.n * 4), "trace values"); val = (uint32_t*)tval.p; }
+        HIP_TRY(hipMalloc(&sv.p, (size_t)d.n * 4), "snapshot");
+        HIP_TRY(hipMalloc(&sp.p, (size_t)d.n * 4), "snapshot");
+        HIP_TRY(hipMalloc(&sf.p, fwords * 8), "snapshot");
+        HIP_TRY(hipMalloc(&sc.p, sum_flags(d.n) * 4), "snapshot");
+    }
     uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
     const uint32_t isrc = (app != kCc && !g->perm_host.empty()) ? g->perm_host[src] : src;
     HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");

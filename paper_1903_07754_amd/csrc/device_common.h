@@ -443,7 +443,8 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
         if (!valid[i]) continue;
         WEDGE_DCHECK(pc[i] < g.m, kDbgPullPos);
         WEDGE_DCHECK(dst[i] < g.n, kDbgPullDst);
-        if (dst[i] < g.n) WEDGE_DCHECK(g.col_off[dst[i]] <= pc[i] && pc[i] < g.col_off[dst[i] + 1], kDbgPullEdge);
+        if (dst[i] < g.n && g.col_off)
+            WEDGE_DCHECK(g.col_off[dst[i]] <= pc[i] && pc[i] < g.col_off[dst[i] + 1], kDbgPullEdge);
     }
 #endif
 

@@ -182,6 +182,33 @@ __global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_full(Graph
     pull_lanes<APP, R, true, INPLACE>(g, p, valid, iter, val, val_prev, fcur, fbits, fsum);
 }
 
+// Full pull over one slice of the source-sliced copy (CC and SSSP). The pull
+// over every in-edge is run slice after slice, one launch each, over the whole
+// GPU: during a launch every XCD gathers only the values of that slice's
+// sources (an eighth of the value array), so they stay in its L2. Inside a
+// launch a slice is pulled exactly like the canonical array (wave-owned
+// destinations take a plain store, the wave's first and last segments a
+// min-atomic); successive launches lower the same destinations in turn.
+template <int APP, int R, bool INPLACE>
+__global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_slice(
+    GraphArgs g, uint32_t row_begin, uint32_t row_end, uint32_t edge_end, uint32_t iter,
+    uint32_t* __restrict__ val, const uint32_t* __restrict__ val_prev,
+    const uint64_t* __restrict__ fcur, uint64_t* __restrict__ fbits, uint32_t* __restrict__ fsum) {
+    const int lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t r0 = (uint64_t)row_begin + wave * R;
+    if (r0 >= row_end) return;
+    uint32_t p[R];
+    bool valid[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint64_t pp = (r0 + i) * 64 + lane;
+        valid[i] = pp < edge_end;
+        p[i] = (uint32_t)pp;
+    }
+    pull_lanes<APP, R, true, INPLACE>(g, p, valid, iter, val, val_prev, fcur, fbits, fsum);
+}
+
 // Pull over the marked chunks: the chunk list holds K = *marked chunk ids of
 // 2^lc positions each. A 64-lane slot covers 64 >> lc chunks (lc <= 6) or one
 // 64-position part of a chunk (lc > 6). Waves stride over the slots, R slots at
@@ -570,6 +597,26 @@ hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t*
     if (!g.rows) return hipSuccess;
     if (app != kBfs && rows != kPullRows) return hipErrorInvalidValue;
     if (inplace && app == kBfs) return hipErrorInvalidValue;
+    if (app != kBfs && g.xs_rows) {
+        const GraphArgs xa = xs_args_of(g);
+        for (int j = 0; j < kXcdSlices; ++j) {
+            const uint32_t rb = g.xs_row_begin[j], re = g.xs_row_begin[j + 1];
+            if (re == rb) continue;
+            const uint64_t waves = ((uint64_t)(re - rb) + kPullRows - 1) / kPullRows;
+            const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+            const uint32_t ee = g.xs_edge_end[j];
+            if (app == kCc) {
+                if (inplace) k_pull_slice<kCc, kPullRows, true><<<blocks, kBlock, 0, s>>>(xa, rb, re, ee, iter, val, val_prev, fcur, fbits, fsum);
+                else k_pull_slice<kCc, kPullRows, false><<<blocks, kBlock, 0, s>>>(xa, rb, re, ee, iter, val, val_prev, fcur, fbits, fsum);
+            } else {
+                if (inplace) k_pull_slice<kSssp, kPullRows, true><<<blocks, kBlock, 0, s>>>(xa, rb, re, ee, iter, val, val_prev, fcur, fbits, fsum);
+                else k_pull_slice<kSssp, kPullRows, false><<<blocks, kBlock, 0, s>>>(xa, rb, re, ee, iter, val, val_prev, fcur, fbits, fsum);
+            }
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     GraphArgs a = args_of(g);
     if (app == kBfs) {
         switch (rows) {

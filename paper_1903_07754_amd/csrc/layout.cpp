@@ -293,6 +293,100 @@ wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_o
     return WEDGE_OK;
 }
 
+void build_xcd_slices(HostLayout* L) {
+    const uint32_t n = L->n;
+    const bool weighted = !L->in_w.empty();
+    // per thread range of destinations: edge counts per slice
+    const unsigned T = std::max(1u, std::min<unsigned>(host_threads(), 64));
+    const uint64_t step = ((uint64_t)n + T - 1) / T;
+    std::vector<uint64_t> cnt((size_t)T * kXcdSlices, 0);
+    auto for_ranges = [&](auto&& f) {
+        std::vector<std::thread> pool;
+        for (unsigned t = 0; t < T; ++t) {
+            const uint64_t b = t * step, e = std::min<uint64_t>(n, b + step);
+            if (b >= e) break;
+            pool.emplace_back([=, &f] { f(t, b, e); });
+        }
+        for (auto& th : pool) th.join();
+    };
+    for_ranges([&](unsigned t, uint64_t vb, uint64_t ve) {
+        uint64_t* c = &cnt[(size_t)t * kXcdSlices];
+        for (uint64_t p = L->col_off[vb]; p < L->col_off[ve]; ++p) c[xcd_slice_of(L->in_src[p])]++;
+    });
+    // slice starts are row-aligned; inside a slice, thread ranges follow in order
+    std::vector<uint64_t> base((size_t)T * kXcdSlices, 0);
+    uint64_t at = 0;
+    for (int j = 0; j < kXcdSlices; ++j) {
+        at = (at + 63) & ~63ull;
+        L->xs_row_begin[j] = (uint32_t)(at / 64);
+        for (unsigned t = 0; t < T; ++t) {
+            base[(size_t)t * kXcdSlices + j] = at;
+            at += cnt[(size_t)t * kXcdSlices + j];
+        }
+        L->xs_edge_end[j] = (uint32_t)at;
+    }
+    const uint64_t total = (at + 63) & ~63ull;
+    const uint64_t rows = total / 64;
+    L->xs_row_begin[kXcdSlices] = (uint32_t)rows;
+    L->xs_src.assign(total ? total : 1, 0);
+    if (weighted) L->xs_w.assign(total ? total : 1, 0);
+    // destination of every position (padding: none), for the row layout below
+    std::vector<uint32_t> dst(total ? total : 1, 0xFFFFFFFFu);
+    for_ranges([&](unsigned t, uint64_t vb, uint64_t ve) {
+        uint64_t cur[kXcdSlices];
+        for (int j = 0; j < kXcdSlices; ++j) cur[j] = base[(size_t)t * kXcdSlices + j];
+        // destinations ascend, and each destination's sources ascend, so every
+        // slice keeps the canonical (destination, source) order
+        for (uint64_t v = vb; v < ve; ++v)
+            for (uint64_t p = L->col_off[v]; p < L->col_off[v + 1]; ++p) {
+                const uint32_t u = L->in_src[p];
+                const uint64_t q = cur[xcd_slice_of(u)]++;
+                L->xs_src[q] = u;
+                if (weighted) L->xs_w[q] = L->in_w[p];
+                dst[q] = (uint32_t)v;
+            }
+    });
+    // row layout: a segment starts at a slice's first position and wherever the
+    // destination changes; padding positions start nothing
+    L->xs_rowmask.assign(rows ? rows : 1, 0);
+    std::vector<uint32_t> starts(rows ? rows : 1, 0);
+    parallel_ranges(rows, [&](uint64_t rb, uint64_t re) {
+        for (uint64_t r = rb; r < re; ++r) {
+            uint64_t mk = 0;
+            for (int l = 0; l < 64; ++l) {
+                const uint64_t q = r * 64 + l;
+                if (dst[q] == 0xFFFFFFFFu) continue;
+                bool start = q == 0 || dst[q - 1] != dst[q];
+                for (int j = 0; j < kXcdSlices; ++j)
+                    if (q == (uint64_t)L->xs_row_begin[j] * 64) start = true;  // a new slice
+                if (start) mk |= 1ull << l;
+            }
+            L->xs_rowmask[r] = mk;
+            starts[r] = (uint32_t)__builtin_popcountll(mk);
+        }
+    });
+    L->xs_rowseg.assign(rows ? rows : 1, 0);
+    uint64_t segs = 0;
+    for (uint64_t r = 0; r < rows; ++r) {
+        // the segment covering the row's first position: the one starting there,
+        // else the last one started before it
+        L->xs_rowseg[r] = (uint32_t)((L->xs_rowmask[r] & 1ull) ? segs : segs - 1);
+        segs += starts[r];
+    }
+    L->xs_nzdst.resize(segs ? segs : 1);
+    {
+        uint64_t sidx = 0;
+        for (uint64_t r = 0; r < rows; ++r) {
+            uint64_t mk = L->xs_rowmask[r];
+            while (mk) {
+                const int l = __builtin_ctzll(mk);
+                mk &= mk - 1;
+                L->xs_nzdst[sidx++] = dst[r * 64 + l];
+            }
+        }
+    }
+}
+
 wedge_status build_layout_from_csc(uint32_t n, uint64_t m, const uint64_t* col_off,
                                    const uint32_t* src, const uint32_t* w, bool symmetrize,
                                    bool relabel, HostLayout* L, std::string* err) {

@@ -38,6 +38,7 @@ uint64_t splitmix(uint64_t& s) {
 }
 
 void free_device(wedge_model_s* m) {
+    wedge::SetupLock lock;
     if (m->dev_params) (void)hipFree(m->dev_params);
     if (m->dev_lo) (void)hipFree(m->dev_lo);
     if (m->dev_hi) (void)hipFree(m->dev_hi);
@@ -48,7 +49,11 @@ void free_device(wedge_model_s* m) {
 
 struct DevBuf {
     void* p = nullptr;
-    ~DevBuf() { if (p) (void)hipFree(p); }
+    ~DevBuf() {
+        if (!p) return;
+        wedge::SetupLock lock;
+        (void)hipFree(p);
+    }
 };
 
 }  // namespace
@@ -68,6 +73,7 @@ void mlp_features(float* x, double fcount, double active, double n, double m, do
 }
 
 wedge_status model_to_device(wedge_model_s* m) {
+    SetupLock lock;
     int dev = 0;
     HTRY(hipGetDevice(&dev), "hipGetDevice");
     if (m->dev_params && m->device != dev) free_device(m);
@@ -269,6 +275,7 @@ wedge_status wedge_model_predict(wedge_model_t m, const float* x, uint32_t count
     wedge_status st = model_to_device(m);
     if (st != WEDGE_OK) return st;
     DevBuf dx, dy;
+    SetupLock alloc_lock;
     HTRY(hipMalloc(&dx.p, (size_t)count * kMlpIn * 4), "features");
     HTRY(hipMalloc(&dy.p, (size_t)count * kMlpOut * 4), "predictions");
     HTRY(hipMemcpyAsync(dx.p, x, (size_t)count * kMlpIn * 4, hipMemcpyHostToDevice, stream), "features");
@@ -286,6 +293,7 @@ wedge_status wedge_model_grad(wedge_model_t m, const float* x, const float* t, c
     wedge_status st = model_to_device(m);
     if (st != WEDGE_OK) return st;
     DevBuf dx, dt, dm, dg, dl;
+    SetupLock alloc_lock;
     HTRY(hipMalloc(&dx.p, (size_t)count * kMlpIn * 4), "grad buffers");
     HTRY(hipMalloc(&dt.p, (size_t)count * kMlpOut * 4), "grad buffers");
     HTRY(hipMalloc(&dm.p, (size_t)count * kMlpOut * 4), "grad buffers");
@@ -344,6 +352,7 @@ wedge_status wedge_model_train(wedge_model_t m, const wedge_trace_sample* s, uin
     wedge_status st = model_to_device(m);
     if (st != WEDGE_OK) return st;
     DevBuf dx, dt, dm, dg, d1, d2, dl;
+    SetupLock alloc_lock;
     HTRY(hipMalloc(&dx.p, X.size() * 4), "training buffers");
     HTRY(hipMalloc(&dt.p, T.size() * 4), "training buffers");
     HTRY(hipMalloc(&dm.p, M.size() * 4), "training buffers");

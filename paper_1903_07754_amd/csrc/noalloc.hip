@@ -31,6 +31,7 @@ hipError_t noalloc_scratch(int dev, void** ptr) {
     if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lk(g_lookup_mu);
     if (!g_scratch[dev]) {
+        SetupLock setup;  // the lookup may load the module on this device
         int cur = -1;
         hipError_t e = hipGetDevice(&cur);
         if (e != hipSuccess) return e;

@@ -20,6 +20,8 @@ constexpr int kWave = 64;
 constexpr int kPullRows = 8;         // default rows (64 positions each) per wave in the integer pulls
 constexpr uint32_t kPrTileRows = 8;  // PageRank pull tile: 8 rows of 64 in-edge positions
 constexpr uint32_t kPrShortSpan = 8; // spans over at most this many extra tiles are fixed up per lane
+constexpr int kXcdSlices = 8;        // source slices of the sliced full pulls (an eighth of the values each)
+constexpr int kXcdGroupShift = 10;   // source slices deal out groups of 1024 vertices
 
 enum App : int { kBfs = 1, kCc = 2, kSssp = 3 };
 
@@ -42,7 +44,30 @@ struct HostLayout {
     std::vector<uint32_t> inv;       // internal id -> original id
     uint32_t dangling = 0;
     uint32_t max_w = 0;
+    // source-sliced copy of the in-edges for the CC/SSSP full pulls (empty
+    // when not built): slice j holds the in-edges whose source lies in slice
+    // j (xcd_slice_of), grouped by destination like the canonical array, and
+    // starts at row xs_row_begin[j]; positions from xs_edge_end[j] to the
+    // next slice's first row are padding
+    std::vector<uint32_t> xs_src, xs_w, xs_rowseg, xs_nzdst;
+    std::vector<uint64_t> xs_rowmask;
+    uint32_t xs_row_begin[kXcdSlices + 1] = {};
+    uint32_t xs_edge_end[kXcdSlices] = {};
 };
+
+// Source slice of internal vertex u for the sliced full pulls: 1024-vertex
+// groups (4 KB of 32-bit values, whole cache lines) dealt to the 8 slices in
+// a snake order (0..7, 7..0, ...), which balances the out-degree-sorted
+// vertices' edges across slices. The slices are pulled one launch after
+// another, so at any time the L2 of every XCD only needs the values of one
+// slice's sources (an eighth of the array).
+inline uint32_t xcd_slice_of(uint32_t u) {
+    const uint32_t g = u >> kXcdGroupShift;
+    return ((g >> 3) & 1u) ? 7u - (g & 7u) : (g & 7u);
+}
+
+// Builds the source-sliced copy of L's in-edges (L must hold the canonical layout).
+void build_xcd_slices(HostLayout* L);
 
 // Validates and builds the layout from CSR (edges grouped by source) or CSC
 // (grouped by destination). Returns WEDGE_OK or an error with *err set.
@@ -72,6 +97,17 @@ struct DevGraph {
     uint32_t* spans = nullptr;
     uint32_t* perm = nullptr;  // original -> internal (null: identity)
     uint32_t* inv = nullptr;   // internal -> original (null: identity)
+    // source-sliced in-edges for the CC/SSSP full pulls (null: not built)
+    uint32_t* xs_src = nullptr;
+    uint32_t* xs_w = nullptr;
+    uint64_t* xs_rowmask = nullptr;
+    uint32_t* xs_rowseg = nullptr;
+    uint32_t* xs_nzdst = nullptr;
+    uint64_t xs_rows = 0;
+    uint64_t xs_positions = 0;  // padded length
+    uint64_t xs_segments = 0;
+    uint32_t xs_row_begin[kXcdSlices + 1] = {};
+    uint32_t xs_edge_end[kXcdSlices] = {};
     // push engine (built on first use): out-edge destinations and weights in CSR order
     uint32_t* out_dst = nullptr;
     uint32_t* out_w = nullptr;
@@ -105,6 +141,23 @@ inline GraphArgs args_of(const DevGraph& g) {
     a.nzdst = g.nzdst;
 #ifdef WEDGE_DEBUG_CHECKS
     a.col_off = g.col_off;
+#endif
+    return a;
+}
+
+// Kernel view of the source-sliced copy (positions over all slices, padded).
+inline GraphArgs xs_args_of(const DevGraph& g) {
+    GraphArgs a;
+    a.n = g.n;
+    a.m = (uint32_t)g.xs_positions;
+    a.rows = (uint32_t)g.xs_rows;
+    a.in_src = g.xs_src;
+    a.in_w = g.xs_w;
+    a.rowmask = g.xs_rowmask;
+    a.rowseg = g.xs_rowseg;
+    a.nzdst = g.xs_nzdst;
+#ifdef WEDGE_DEBUG_CHECKS
+    a.col_off = nullptr;  // positions are not canonical in-edge positions
 #endif
     return a;
 }
@@ -285,6 +338,17 @@ namespace wedge {
 
 // Records msg as the thread's last error and returns st.
 wedge_status set_error(wedge_status st, const std::string& msg);
+
+// One process-wide lock around the library's calls that are not stream
+// ordered (hipMalloc, hipFree, synchronous memsets, pinned allocations, event
+// creation, module symbol lookup) and around its stream captures: such a call
+// made by one thread while another thread's stream is being captured can
+// invalidate that capture, so the two never overlap. Recursive, because the
+// setup paths nest.
+std::recursive_mutex& setup_mutex();
+struct SetupLock {
+    std::lock_guard<std::recursive_mutex> guard{setup_mutex()};
+};
 // Uploads the model to the current device if needed.
 wedge_status model_to_device(wedge_model_s* m);
 

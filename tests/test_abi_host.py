@@ -200,3 +200,75 @@ def test_batch_union_is_the_concatenation():
     with pytest.raises(W.WedgeError):
         bad = [(parts[0][0], parts[0][1] + 100)]
         W.Graph.from_batch_csr(bad, host_only=True)
+
+
+def _slice_of(u):
+    """Source slice of internal id u: 1024-id groups dealt to 8 slices in snake order."""
+    g = u.astype(np.int64) >> 10
+    return np.where((g >> 3) & 1, 7 - (g & 7), g & 7)
+
+
+@pytest.mark.parametrize("seed,scale,weighted,sym,keep", [
+    (6, 12, True, False, True), (7, 13, False, True, False), (8, 14, True, False, False)])
+def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
+    """The source-sliced in-edge copy holds every in-edge once, in the slice of
+    its source, each slice grouped by destination with sources ascending (the
+    canonical order restricted to the slice), starting on a row boundary; its
+    row layout names every real position's destination."""
+    monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
+    ro, col = gen.rmat(scale, 16, seed=seed)
+    w = gen.edge_weights(ro, col, seed=seed) if weighted else None
+    g = host_graph(ro, col, w, symmetrize=sym, keep_ids=keep)
+    info = g.info
+    assert info["xs_rows"] > 0
+    co = g.layout("col_off").astype(np.int64)
+    src = g.layout("in_src")
+    n, m = len(co) - 1, len(src)
+    dst_c = np.repeat(np.arange(n), np.diff(co))
+    b = g.layout("xs_bounds").astype(np.int64)
+    row_begin, edge_end = b[:9], b[9:]
+    assert row_begin[0] == 0 and np.all(np.diff(row_begin) >= 0)
+    assert row_begin[8] == info["xs_rows"]
+    assert np.all(edge_end <= row_begin[1:] * 64) and np.all(edge_end >= row_begin[:8] * 64)
+    xsrc = g.layout("xs_src")
+    xw = g.layout("xs_w") if weighted else None
+    mask = g.layout("xs_rowmask")
+    seg = g.layout("xs_rowseg").astype(np.int64)
+    nz = g.layout("xs_nzdst").astype(np.int64)
+    sl = _slice_of(src)
+    P = 64 * info["xs_rows"]
+    p = np.arange(P)
+    r, bb = p >> 6, p & 63
+    bits = ((mask[r] >> bb.astype(np.uint64)) & np.uint64(1)).astype(bool)
+    cum = np.cumsum(bits)
+    dst_x = nz[seg[r] + (cum - cum[r * 64])]  # the row-layout destination of every position
+    total = 0
+    for j in range(8):
+        lo, hi = row_begin[j] * 64, edge_end[j]
+        want = np.flatnonzero(sl == j)                      # canonical order, slice j only
+        assert hi - lo == len(want), j
+        np.testing.assert_array_equal(xsrc[lo:hi], src[want])
+        np.testing.assert_array_equal(dst_x[lo:hi], dst_c[want])
+        if weighted:
+            np.testing.assert_array_equal(xw[lo:hi], g.layout("in_w")[want])
+        if hi > lo:
+            assert bits[lo]                                 # a slice starts a segment
+        # segment starts inside the slice are exactly the destination changes
+        d = dst_c[want]
+        starts = np.ones(len(d), bool)
+        starts[1:] = d[1:] != d[:-1]
+        np.testing.assert_array_equal(bits[lo:hi], starts)
+        assert not bits[hi:row_begin[j + 1] * 64].any()     # padding starts nothing
+        total += hi - lo
+    assert total == m
+    assert info["xs_segments"] == int(bits.sum())
+
+
+def test_source_sliced_copy_threshold(monkeypatch):
+    ro, col = gen.rmat(10, 8, seed=3)
+    monkeypatch.delenv("WEDGE_SLICED_PULL", raising=False)
+    assert host_graph(ro, col).info["xs_rows"] == 0        # small graphs: not built
+    monkeypatch.setenv("WEDGE_SLICED_PULL", "0")
+    assert host_graph(ro, col).info["xs_rows"] == 0
+    monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
+    assert host_graph(ro, col).info["xs_rows"] > 0
