@@ -69,15 +69,56 @@ def pr_pull_bytes(info):
             + 4 * (info["n"] - info["dangling"]) + 4 * info["nonempty"])
 
 
-def pr_kernel_name(info):
-    """The PageRank pull the library launches for this graph: the LDS variant
-    once every resident wave (2 blocks of 12 waves per compute unit) has at
-    least four 8-row tiles, and at least 4096 vertices."""
+def slice_launches(g):
+    """Kernel launches per full pull: one per non-empty source slice when the
+    graph has the source-sliced in-edge copy, else one."""
+    import numpy as np
+    if not g.info["xs_rows"]:
+        return 1
+    b = g.layout("xs_bounds")[:9].astype(np.int64)
+    return int(np.count_nonzero(np.diff(b)))
+
+
+def pr_kernel_name(g):
+    """The PageRank pull the library launches for this graph: one launch per
+    source slice over the sliced copy when the graph has one; else the LDS
+    variant once every resident wave (2 blocks of 12 waves per compute unit)
+    has at least four 8-row tiles, and at least 4096 vertices."""
     import torch
+    info = g.info
+    if info["xs_rows"]:
+        return "k_pr_pull_slice"
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     tiles = (info["rows"] + 7) // 8
     hot = info["n"] >= 4096 and tiles >= 4 * cus * 2 * 12
     return "k_pr_pull_hot" if hot else "k_pr_pull"
+
+
+def full_pull_kernel_name(g, app):
+    return f"k_pull_slice<{app}>" if g.info["xs_rows"] else f"k_pull_full<{app}>"
+
+
+def roofline(name, ms, pulls, alg, workload, per_pull=1):
+    """HBM roofline entry of one kernel: `pulls` full pulls took `ms` in all
+    (HIP events around each pull, on the library's stream); a pull is
+    `per_pull` launches of the kernel (the source slices), so one launch
+    moves alg / per_pull algorithmic bytes in ms / (pulls * per_pull)."""
+    launches = pulls * per_pull
+    alg_l = alg / per_pull
+    avg = ms / 1e3 / launches
+    achieved = alg_l / avg / 1e9
+    traffic = measured_traffic(name, workload)
+    r = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+         "avg_launch_us": round(avg * 1e6, 2), "launches": launches, "total_ms": round(ms, 3),
+         "algorithmic_bytes_per_launch": int(alg_l)}
+    if per_pull > 1:
+        r["launches_per_pull"] = per_pull
+    if traffic:
+        # the bytes the memory system actually moved (whole lines for 4-byte gathers)
+        r["traffic_gbs"] = round(traffic / avg / 1e9, 1)
+        r["traffic_frac"] = round(traffic / avg / 1e9 / HBM_PEAK_GBS, 4)
+    return r
 
 
 def minpull_bytes(info, weighted):
@@ -177,19 +218,8 @@ def pagerank_only(args):
         launches += st["pull_launches"]
         log(f"step {i + 1}/{args.steps} done")
     K = args.steps
-    avg_launch_s = pull_ms / 1e3 / launches
-    alg = pr_pull_bytes(g.info)
-    name = pr_kernel_name(g.info)
-    workload = f"rmat{args.scale}"
-    traffic = measured_traffic(name, workload)
-    roof = {"kernel": name, "bound": "hbm", "achieved": round(alg / avg_launch_s / 1e9, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(alg / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": launches,
-            "algorithmic_bytes_per_launch": int(alg)}
-    if traffic:
-        roof["traffic_gbs"] = round(traffic / avg_launch_s / 1e9, 1)
-        roof["traffic_frac"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    roof = roofline(pr_kernel_name(g), pull_ms, launches, pr_pull_bytes(g.info),
+                    f"rmat{args.scale}", slice_launches(g))
     out = {"metric": "PageRank GTEPS (20 iterations, full pull) R-MAT s%d" % args.scale,
            "value": round(20 * m * K / (ms / 1e3) / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
            "steps": K, "warmup": args.warmup, "ms_per_step": round(ms / K, 3),
@@ -411,18 +441,8 @@ def configs_section(m_rmat24, steps=10):
         ms += st["ms"]
         pull_ms += st["pull_ms"]
         launches += st["pull_launches"]
-    info = g.info
-    alg = pr_pull_bytes(info)
-    avg = pull_ms / 1e3 / launches
-    name = pr_kernel_name(info)
-    traffic = measured_traffic(name, "rmat26")
-    roof = {"kernel": name, "bound": "hbm", "achieved": round(alg / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(alg / avg / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "avg_launch_us": round(avg * 1e6, 2), "launches": launches,
-            "algorithmic_bytes_per_launch": int(alg)}
-    if traffic:
-        roof["traffic_gbs"] = round(traffic / avg / 1e9, 1)
-        roof["traffic_frac"] = round(traffic / avg / 1e9 / HBM_PEAK_GBS, 4)
+    roof = roofline(pr_kernel_name(g), pull_ms, launches, pr_pull_bytes(g.info), "rmat26",
+                    slice_launches(g))
     res["config3_pagerank_rmat26"] = {"n": n, "m": m, "ms_per_run": round(ms / 2, 3),
                                       "gteps": round(20 * m * 2 / (ms / 1e3) / 1e9, 3),
                                       "roofline": roof}
@@ -611,27 +631,14 @@ def main():
                   for k, v in app_s.items()}
     workload = f"rmat{args.scale}"
     cands = [
-        (pr_kernel_name(g.info), pull["ms"], pull["launches"], pr_pull_bytes(g.info)),
-        ("k_pull_full<SSSP>", fullpull["sssp"][0], fullpull["sssp"][1], minpull_bytes(g.info, True)),
-        ("k_pull_full<CC>", fullpull["cc"][0], fullpull["cc"][1], minpull_bytes(gs.info, False)),
+        (pr_kernel_name(g), pull["ms"], pull["launches"], pr_pull_bytes(g.info), slice_launches(g)),
+        (full_pull_kernel_name(g, "SSSP"), fullpull["sssp"][0], fullpull["sssp"][1],
+         minpull_bytes(g.info, True), slice_launches(g)),
+        (full_pull_kernel_name(gs, "CC"), fullpull["cc"][0], fullpull["cc"][1],
+         minpull_bytes(gs.info, False), slice_launches(gs)),
     ]
-    roofs = []
-    for name, ms, launches, alg in cands:
-        if not launches:
-            continue
-        avg_launch_s = ms / 1e3 / launches
-        achieved = alg / avg_launch_s / 1e9
-        traffic = measured_traffic(name, workload)
-        r = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
-             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-             "traffic": traffic, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-             "launches": launches, "total_ms": round(ms, 3),
-             "algorithmic_bytes_per_launch": int(alg)}
-        if traffic:
-            # the bytes the memory system actually moved (whole lines for 4-byte gathers)
-            r["traffic_gbs"] = round(traffic / avg_launch_s / 1e9, 1)
-            r["traffic_frac"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
-        roofs.append(r)
+    roofs = [roofline(name, ms, pulls, alg, workload, per)
+             for name, ms, pulls, alg, per in cands if pulls]
     roofs.sort(key=lambda r: -r["total_ms"])  # the dominant kernel first
     roof = roofs[0]
     out = {

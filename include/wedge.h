@@ -153,6 +153,11 @@ typedef struct {
     uint32_t relabeled;    /* 1 when the internal vertex order differs from the caller's */
     uint64_t xs_rows;      /* rows of the source-sliced in-edge copy (0: not built) */
     uint64_t xs_segments;  /* its destination segments */
+    uint64_t xs_pr_spans;  /* destinations with a sliced-copy segment that crosses a
+                              PageRank tile boundary (short ones listed first) */
+    uint64_t xs_pr_short_spans; /* of xs_pr_spans, those whose crossing segments
+                                   cover at most 8 extra tiles in all */
+    uint64_t xs_pr_span_pairs;  /* crossing segments over all of them */
 } wedge_graph_info;
 
 wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info);
@@ -175,8 +180,13 @@ typedef enum {
     WEDGE_LAYOUT_XS_ROWMASK = 12, /* uint64[xs_rows] */
     WEDGE_LAYOUT_XS_ROWSEG = 13,  /* uint32[xs_rows] */
     WEDGE_LAYOUT_XS_NZDST = 14,   /* uint32[xs_segments] */
-    WEDGE_LAYOUT_XS_BOUNDS = 15   /* uint32[17]: first row of slices 0..8, then the end
+    WEDGE_LAYOUT_XS_BOUNDS = 15,  /* uint32[17]: first row of slices 0..8, then the end
                                      position of slices 0..7 */
+    /* PageRank fix-up lists of the sliced copy (empty when xs_pr_spans is 0): */
+    WEDGE_LAYOUT_XS_PR_SPAN_V = 16,     /* uint32[xs_pr_spans] destination */
+    WEDGE_LAYOUT_XS_PR_SPAN_OFF = 17,   /* uint32[xs_pr_spans+1] first pair of each */
+    WEDGE_LAYOUT_XS_PR_SPAN_TILES = 18  /* uint32[2*xs_pr_span_pairs] (first tile, last tile)
+                                           of each crossing segment, in slice order */
 } wedge_layout_array;
 
 /* Layout arrays are indexed and valued by internal vertex ids. */

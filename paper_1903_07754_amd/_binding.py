@@ -30,7 +30,8 @@ RUN_TIME_PULL, RUN_TIME_ITERS, RUN_PERSISTENT, RUN_INPLACE = 0x1, 0x2, 0x4, 0x8
 TUNE = {"single": 0, "multisource": 1, "batch": 2}
 LAYOUT = {"col_off": 0, "in_src": 1, "in_w": 2, "row_off": 3, "pos": 4, "rowmask": 5,
           "rowseg": 6, "nzdst": 7, "pr_spans": 8, "perm": 9, "xs_src": 10, "xs_w": 11,
-          "xs_rowmask": 12, "xs_rowseg": 13, "xs_nzdst": 14, "xs_bounds": 15}
+          "xs_rowmask": 12, "xs_rowseg": 13, "xs_nzdst": 14, "xs_bounds": 15,
+          "xs_pr_span_v": 16, "xs_pr_span_off": 17, "xs_pr_span_tiles": 18}
 
 
 class WedgeError(RuntimeError):
@@ -46,7 +47,9 @@ class GraphInfo(C.Structure):
                 ("dangling", C.c_uint32), ("pr_tile_edges", C.c_uint32),
                 ("pr_spans", C.c_uint64), ("device_bytes", C.c_uint64),
                 ("pr_short_spans", C.c_uint64), ("relabeled", C.c_uint32),
-                ("xs_rows", C.c_uint64), ("xs_segments", C.c_uint64)]
+                ("xs_rows", C.c_uint64), ("xs_segments", C.c_uint64),
+                ("xs_pr_spans", C.c_uint64), ("xs_pr_short_spans", C.c_uint64),
+                ("xs_pr_span_pairs", C.c_uint64)]
 
 
 class IterRecord(C.Structure):
@@ -247,7 +250,10 @@ class Graph:
                  "nzdst": info["nonempty"], "pr_spans": 3 * info["pr_spans"],
                  "perm": self.n, "xs_src": 64 * info["xs_rows"], "xs_w": 64 * info["xs_rows"],
                  "xs_rowmask": info["xs_rows"], "xs_rowseg": info["xs_rows"],
-                 "xs_nzdst": info["xs_segments"], "xs_bounds": 17}
+                 "xs_nzdst": info["xs_segments"], "xs_bounds": 17,
+                 "xs_pr_span_v": info["xs_pr_spans"],
+                 "xs_pr_span_off": info["xs_pr_spans"] + 1 if info["xs_pr_spans"] else 0,
+                 "xs_pr_span_tiles": 2 * info["xs_pr_span_pairs"]}
         out = np.zeros(max(int(sizes[name]), 1), dt)
         nbytes = int(sizes[name]) * out.itemsize
         check(lib().wedge_graph_layout(self._h, LAYOUT[name], out.ctypes.data, nbytes))

@@ -103,7 +103,7 @@ void free_all(wedge_graph_s* g) {
     DevGraph& d = g->dev;
     void* ptrs[] = {d.col_off, d.in_src, d.in_w, d.row_off, d.pos, d.rowmask, d.rowseg, d.nzdst, d.spans,
                     d.perm, d.inv, d.out_dst, d.out_w, d.xs_src, d.xs_w, d.xs_rowmask, d.xs_rowseg,
-                    d.xs_nzdst};
+                    d.xs_nzdst, d.xs_pspan_v, d.xs_pspan_off, d.xs_pspan_tt};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     Workspace& w = g->ws;
@@ -195,6 +195,9 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
         d.xs_segments = L.xs_nzdst.size();
         std::memcpy(d.xs_row_begin, L.xs_row_begin, sizeof d.xs_row_begin);
         std::memcpy(d.xs_edge_end, L.xs_edge_end, sizeof d.xs_edge_end);
+        d.xs_pspans = L.xs_pspan_v.size();
+        d.xs_pspan_short = L.xs_pspan_short;
+        d.xs_pspan_pairs = L.xs_pspan_tt.size() / 2;
     }
     g->perm_host = L.perm;
     if (g->host_only) { *out = g; return WEDGE_OK; }
@@ -220,6 +223,9 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowmask, L.xs_rowmask, stream, "sliced row masks");
     if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowseg, L.xs_rowseg, stream, "sliced row segments");
     if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_nzdst, L.xs_nzdst, stream, "sliced segment destinations");
+    if (st == WEDGE_OK && d.xs_pspans) st = upload(g, &d.xs_pspan_v, L.xs_pspan_v, stream, "sliced PageRank spans");
+    if (st == WEDGE_OK && d.xs_pspans) st = upload(g, &d.xs_pspan_off, L.xs_pspan_off, stream, "sliced PageRank span offsets");
+    if (st == WEDGE_OK && d.xs_pspans) st = upload(g, &d.xs_pspan_tt, L.xs_pspan_tt, stream, "sliced PageRank span tiles");
     if (st == WEDGE_OK) {
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) st = hip_fail(e, "uploading graph");
@@ -1168,6 +1174,9 @@ wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info) {
     info->xs_rows = g->host_only ? (g->host.xs_rowmask.empty() ? 0 : g->host.xs_row_begin[kXcdSlices])
                                  : g->dev.xs_rows;
     info->xs_segments = g->host_only ? g->host.xs_nzdst.size() : g->dev.xs_segments;
+    info->xs_pr_spans = g->dev.xs_pspans;
+    info->xs_pr_short_spans = g->dev.xs_pspan_short;
+    info->xs_pr_span_pairs = g->dev.xs_pspan_pairs;
     return WEDGE_OK;
 }
 
@@ -1196,6 +1205,9 @@ wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void*
         case WEDGE_LAYOUT_XS_ROWMASK:
         case WEDGE_LAYOUT_XS_ROWSEG:
         case WEDGE_LAYOUT_XS_NZDST:
+        case WEDGE_LAYOUT_XS_PR_SPAN_V:
+        case WEDGE_LAYOUT_XS_PR_SPAN_OFF:
+        case WEDGE_LAYOUT_XS_PR_SPAN_TILES:
         case WEDGE_LAYOUT_XS_BOUNDS: {
             const uint64_t xr = g->host_only ? (L.xs_rowmask.empty() ? 0 : L.xs_row_begin[kXcdSlices]) : d.xs_rows;
             const uint64_t xseg = g->host_only ? L.xs_nzdst.size() : d.xs_segments;
@@ -1214,6 +1226,12 @@ wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void*
             if (which == WEDGE_LAYOUT_XS_ROWMASK) { size = xr * 8; hsrc = L.xs_rowmask.data(); dsrc = d.xs_rowmask; }
             if (which == WEDGE_LAYOUT_XS_ROWSEG) { size = xr * 4; hsrc = L.xs_rowseg.data(); dsrc = d.xs_rowseg; }
             if (which == WEDGE_LAYOUT_XS_NZDST) { size = xseg * 4; hsrc = L.xs_nzdst.data(); dsrc = d.xs_nzdst; }
+            if (which == WEDGE_LAYOUT_XS_PR_SPAN_V) { size = d.xs_pspans * 4; hsrc = L.xs_pspan_v.data(); dsrc = d.xs_pspan_v; }
+            if (which == WEDGE_LAYOUT_XS_PR_SPAN_OFF) {
+                size = d.xs_pspans ? (d.xs_pspans + 1) * 4 : 0;
+                hsrc = L.xs_pspan_off.data(); dsrc = d.xs_pspan_off;
+            }
+            if (which == WEDGE_LAYOUT_XS_PR_SPAN_TILES) { size = d.xs_pspan_pairs * 8; hsrc = L.xs_pspan_tt.data(); dsrc = d.xs_pspan_tt; }
             break;
         }
         case WEDGE_LAYOUT_PERM:
@@ -1270,7 +1288,9 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
     Workspace& w = g->ws;
     if ((st = ensure_workspace(g, 6, false, false)) != WEDGE_OK) return st;
     // each buffer is allocated on its own when missing (see ensure_workspace)
-    w.pr_tiles = (d.rows + kPrTileRows - 1) / kPrTileRows;
+    // tiles of the canonical layout, or of the source-sliced copy when the
+    // pull runs over that (its slices start on tile boundaries)
+    w.pr_tiles = std::max<uint64_t>((d.rows + kPrTileRows - 1) / kPrTileRows, d.xs_rows / kPrTileRows);
     w.pr_parts = pr_epilogue_blocks(d.n);
     auto need = [&](void** p, size_t bytes, const char* what) -> wedge_status {
         return *p ? WEDGE_OK : dev_alloc(g, p, bytes, what);

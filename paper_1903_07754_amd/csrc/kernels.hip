@@ -245,7 +245,9 @@ __global__ __launch_bounds__(kBlock) WEDGE_CHUNK_OCCUPANCY void k_pull_chunks(Gr
 // from the tile where it starts in tail[tile] and its partials from later tiles
 // in head[tile]; k_pr_fixup adds them in a fixed order. No float atomics: the
 // result is deterministic.
-template <int R, int B, class Gather>
+// ACCUM: interior destinations are added to sum instead of written (the
+// sliced pull adds each slice's partial sums in turn).
+template <int R, int B, bool ACCUM = false, class Gather>
 __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gather gather,
                                         float* __restrict__ sum, float* __restrict__ head_part,
                                         float* __restrict__ tail_part) {
@@ -317,7 +319,8 @@ __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gathe
                 } else if (seg_before) {
                     head_part[tile] = s;
                 } else {
-                    sum[dst[j]] = s;
+                    if (ACCUM) sum[dst[j]] += s;
+                    else sum[dst[j]] = s;
                 }
             }
             const float last_s = __shfl(s, h_last, 64);
@@ -390,6 +393,123 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_hot(GraphArgs g, const fl
             sum, head_part, tail_part);
 }
 
+// Slice-local index of a source of slice j (its 1024-vertex groups, in
+// order, numbered 0, 1, ...) and back.
+__device__ __forceinline__ uint32_t slice_local(uint32_t u) { return ((u >> 13) << 10) | (u & 1023u); }
+__device__ __forceinline__ uint32_t slice_global(uint32_t i, uint32_t j) {
+    const uint32_t b = i >> 10;
+    const uint32_t gidx = b * 8u + ((b & 1u) ? 7u - j : j);
+    return (gidx << 10) | (i & 1023u);
+}
+
+// PageRank pull over one slice of the source-sliced copy: the slices are
+// pulled one launch after another and each adds its partial sums into S, in
+// slice order (deterministic). Each block first copies the contributions of
+// the slice's first `hot` sources (its highest out-degree ones) into LDS; a
+// launch gathers only this slice's sources, so the rest of its gathers stay in
+// the L2. Segments crossing a tile boundary leave their parts in head/tail;
+// k_pr_fixup_xs adds them afterwards.
+template <int R>
+__global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32_t slice,
+                                                             uint64_t tile_begin, uint64_t tile_end,
+                                                             const float* __restrict__ contrib,
+                                                             float* __restrict__ sum,
+                                                             float* __restrict__ head_part,
+                                                             float* __restrict__ tail_part,
+                                                             uint32_t hot) {
+    extern __shared__ float s_hot[];
+    {
+        constexpr int kPer = (int)((kHotVerts + kHotBlock - 1) / kHotBlock);
+        float t[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
+            const uint32_t gi = slice_global(i < hot ? i : 0u, slice);
+            t[k] = contrib[gi < g.n ? gi : 0u];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
+            if (i < hot) s_hot[i] = slice_global(i, slice) < g.n ? t[k] : 0.0f;
+        }
+    }
+    __syncthreads();
+    const uint64_t wpb = kHotBlock / 64;
+    const uint64_t stride = (uint64_t)gridDim.x * wpb;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint64_t t = tile_begin + blockIdx.x * wpb + wib; t < tile_end; t += stride)
+        pr_tile<R, kHotBatch, true>(
+            g, t,
+            [&](uint32_t u) {
+                const uint32_t l = slice_local(u);
+                const float gv = contrib[l < hot ? 0u : u];
+                const float lv = s_hot[l < hot ? l : 0u];
+                return l < hot ? lv : gv;
+            },
+            sum, head_part, tail_part);
+}
+
+// Crossing segments of the sliced pull: one lane per destination with few
+// crossing tiles, one wave per destination with many; each adds, in slice
+// order and tile order, the tail part of every crossing segment and the head
+// parts of the tiles it runs into, then adds the total to S. The last block
+// of the long launch reduces the previous epilogue's dangling partials.
+__global__ __launch_bounds__(kBlock) void k_pr_fixup_xs_short(const uint32_t* __restrict__ vs,
+                                                              const uint32_t* __restrict__ off,
+                                                              const uint32_t* __restrict__ tt,
+                                                              uint64_t count,
+                                                              const float* __restrict__ head_part,
+                                                              const float* __restrict__ tail_part,
+                                                              float* __restrict__ sum) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    float acc = 0.0f;
+    for (uint32_t q = off[e]; q < off[e + 1]; ++q) {
+        const uint32_t ta = tt[2 * q], tb = tt[2 * q + 1];
+        acc += tail_part[ta];
+        for (uint32_t t = ta + 1; t <= tb; ++t) acc += head_part[t];
+    }
+    sum[vs[e]] += acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pr_fixup_xs_long(const uint32_t* __restrict__ vs,
+                                                             const uint32_t* __restrict__ off,
+                                                             const uint32_t* __restrict__ tt,
+                                                             uint64_t first, uint64_t count,
+                                                             const float* __restrict__ head_part,
+                                                             const float* __restrict__ tail_part,
+                                                             float* __restrict__ sum,
+                                                             const double* __restrict__ partials,
+                                                             uint32_t parts, double* __restrict__ dnext) {
+    const int lane = lane_id();
+    if (blockIdx.x == gridDim.x - 1) {
+        __shared__ double s_part[kWavesPerBlock];
+        if (!dnext) return;
+        double acc = 0.0;
+        for (uint32_t i = threadIdx.x; i < parts; i += blockDim.x) acc += partials[i];
+        acc = wave_sum_tree(acc);
+        if (lane == 0) s_part[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < kWavesPerBlock; ++i) t += s_part[i];
+            *dnext = t;
+        }
+        return;
+    }
+    const uint64_t e = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (e >= count) return;
+    const uint64_t k = first + e;
+    float acc = 0.0f;
+    for (uint32_t q = off[k]; q < off[k + 1]; ++q) {
+        const uint32_t ta = tt[2 * q], tb = tt[2 * q + 1];
+        if (lane == 0) acc += tail_part[ta];
+        for (uint32_t t = ta + 1 + lane; t <= tb; t += 64) acc += head_part[t];
+    }
+    acc = wave_sum_tree(acc);
+    if (lane == 0) sum[vs[k]] += acc;
+}
+
 // S(v) = tail[first tile] + sum of head[t] over the later tiles v covers.
 // Short spans: one lane each, summed in tile order.
 __global__ __launch_bounds__(kBlock) void k_pr_fixup_short(const uint32_t* __restrict__ spans,
@@ -458,10 +578,11 @@ __global__ void k_set_f64(double* p, double v) {
 // r'(v) = (1-d)/n + d (S(v) + D/n); contrib'(v) = r'/outdeg; per-block sum of
 // the new rank mass on out-degree-0 vertices (the next D), in FP64. Each block
 // covers a fixed contiguous vertex range, so the partials (and their order)
-// do not depend on timing.
+// do not depend on timing. S is cleared once read, so that a pull that adds
+// into it (the sliced pull) starts from zero.
 __global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n, uint32_t per_block,
                                                         const uint32_t* __restrict__ row_off,
-                                                        const float* __restrict__ sum, double d,
+                                                        float* __restrict__ sum, double d,
                                                         const double* __restrict__ dcur,
                                                         float* __restrict__ rank,
                                                         float* __restrict__ contrib,
@@ -474,6 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n, uint32_t per
     double acc = 0.0;
     for (uint32_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
         const float r = (float)(base + d * ((double)sum[v] + dn));
+        sum[v] = 0.0f;
         const uint32_t od = row_off[v + 1] - row_off[v];
         rank[v] = r;
         contrib[v] = od ? r / (float)od : 0.0f;
@@ -697,6 +819,44 @@ hipError_t launch_pr_init(uint32_t n, const uint32_t* row_off, float* rank, floa
 hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, float* head,
                           float* tail, int cus, hipStream_t s) {
     if (!g.rows) return hipSuccess;
+    if (g.xs_rows) {
+        // one launch per source slice, each over the whole GPU (resident blocks
+        // at the full LDS size), adding into S; head/tail are indexed by the
+        // sliced copy's tiles (no tile straddles two slices)
+        static const int per_cu = [] {
+            int b = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_pr_pull_slice<kPrTileRows>, kHotBlock,
+                                                             (kHotVerts + 8) * sizeof(float)) != hipSuccess) {
+                (void)hipGetLastError();
+                return 0;
+            }
+            return b;
+        }();
+        if (per_cu <= 0) return hipErrorInvalidConfiguration;
+        for (int j = 0; j < kXcdSlices; ++j) {
+            const uint64_t rb = g.xs_row_begin[j], re = g.xs_row_begin[j + 1];
+            if (re == rb) continue;
+            GraphArgs xa = xs_args_of(g);
+            xa.m = g.xs_edge_end[j];  // positions past the slice's last in-edge are idle
+            xa.rows = (uint32_t)re;
+            // the slice's first kHotVerts slice-local sources that exist
+            uint32_t hot = 0;
+            for (uint32_t i = 0; i < kHotVerts; i += 1024u) {
+                const uint32_t b = i >> 10;
+                const uint64_t gidx = (uint64_t)b * 8 + ((b & 1u) ? 7u - j : (uint32_t)j);
+                if ((gidx << 10) >= g.n) break;
+                hot = i + (uint32_t)std::min<uint64_t>(1024, g.n - (gidx << 10));
+            }
+            const uint64_t tb = rb / kPrTileRows, te = re / kPrTileRows;
+            const uint64_t blocks = std::min<uint64_t>((uint64_t)std::max(cus, 1) * (uint64_t)per_cu,
+                                                       (te - tb + kHotBlock / 64 - 1) / (kHotBlock / 64));
+            k_pr_pull_slice<kPrTileRows><<<(uint32_t)blocks, kHotBlock, (kHotVerts + 8) * sizeof(float), s>>>(
+                xa, (uint32_t)j, tb, te, contrib, sum, head, tail, hot);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     const uint64_t tiles = (g.rows + kPrTileRows - 1) / kPrTileRows;
     const uint32_t hot = std::min<uint32_t>(g.n, kHotVerts);
     if (cus > 0 && hot >= kHotMinVerts) {
@@ -727,6 +887,19 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
 
 hipError_t launch_pr_fixup(const DevGraph& g, const float* head, const float* tail, float* sum,
                            const double* partials, uint32_t parts, double* d_next, hipStream_t s) {
+    if (g.xs_rows) {
+        const uint64_t ns = g.xs_pspan_short, nl = g.xs_pspans - g.xs_pspan_short;
+        if (ns) {
+            k_pr_fixup_xs_short<<<(uint32_t)((ns + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+                g.xs_pspan_v, g.xs_pspan_off, g.xs_pspan_tt, ns, head, tail, sum);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        const uint32_t blocks = (uint32_t)((nl + kWavesPerBlock - 1) / kWavesPerBlock) + 1;
+        k_pr_fixup_xs_long<<<blocks, kBlock, 0, s>>>(g.xs_pspan_v, g.xs_pspan_off, g.xs_pspan_tt, ns, nl,
+                                                     head, tail, sum, partials, parts, d_next);
+        return hipGetLastError();
+    }
     const uint64_t ns = g.short_spans, nl = g.nspans - g.short_spans;
     if (ns) {
         k_pr_fixup_short<<<(uint32_t)((ns + kBlock - 1) / kBlock), kBlock, 0, s>>>(g.spans, ns, head, tail, sum);
@@ -744,7 +917,7 @@ uint32_t pr_epilogue_blocks(uint32_t n) {
     return b ? b : 1;
 }
 
-hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* sum,
+hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, float* sum,
                               double damping, const double* d_cur, float* rank, float* contrib,
                               double* partials, uint32_t parts, hipStream_t s) {
     if (!n) return hipSuccess;

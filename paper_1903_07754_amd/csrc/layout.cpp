@@ -313,11 +313,13 @@ void build_xcd_slices(HostLayout* L) {
         uint64_t* c = &cnt[(size_t)t * kXcdSlices];
         for (uint64_t p = L->col_off[vb]; p < L->col_off[ve]; ++p) c[xcd_slice_of(L->in_src[p])]++;
     });
-    // slice starts are row-aligned; inside a slice, thread ranges follow in order
+    // slice starts are aligned to PageRank tiles (kPrTileRows rows), so no tile
+    // straddles two slices; inside a slice, thread ranges follow in order
+    const uint64_t align = 64ull * kPrTileRows;
     std::vector<uint64_t> base((size_t)T * kXcdSlices, 0);
     uint64_t at = 0;
     for (int j = 0; j < kXcdSlices; ++j) {
-        at = (at + 63) & ~63ull;
+        at = (at + align - 1) & ~(align - 1);
         L->xs_row_begin[j] = (uint32_t)(at / 64);
         for (unsigned t = 0; t < T; ++t) {
             base[(size_t)t * kXcdSlices + j] = at;
@@ -325,7 +327,7 @@ void build_xcd_slices(HostLayout* L) {
         }
         L->xs_edge_end[j] = (uint32_t)at;
     }
-    const uint64_t total = (at + 63) & ~63ull;
+    const uint64_t total = (at + align - 1) & ~(align - 1);
     const uint64_t rows = total / 64;
     L->xs_row_begin[kXcdSlices] = (uint32_t)rows;
     L->xs_src.assign(total ? total : 1, 0);
@@ -374,6 +376,7 @@ void build_xcd_slices(HostLayout* L) {
         segs += starts[r];
     }
     L->xs_nzdst.resize(segs ? segs : 1);
+    std::vector<uint64_t> seg_begin(segs + 1, 0);
     {
         uint64_t sidx = 0;
         for (uint64_t r = 0; r < rows; ++r) {
@@ -381,10 +384,57 @@ void build_xcd_slices(HostLayout* L) {
             while (mk) {
                 const int l = __builtin_ctzll(mk);
                 mk &= mk - 1;
+                seg_begin[sidx] = r * 64 + l;
                 L->xs_nzdst[sidx++] = dst[r * 64 + l];
             }
         }
     }
+    L->xs_nzdst.resize(segs);
+    // PageRank: segments whose positions cross a tile boundary, grouped by
+    // destination (a destination has at most one segment per slice; its
+    // crossing segments are listed in slice order). A segment ends at the next
+    // segment's start or its slice's end.
+    const uint64_t TE = 64ull * kPrTileRows;  // positions per tile
+    struct Span { uint32_t v, a, b; };
+    std::vector<Span> sp;
+    {
+        int j = 0;
+        for (uint64_t t = 0; t < segs; ++t) {
+            const uint64_t a = seg_begin[t];
+            while (j + 1 < kXcdSlices && a >= (uint64_t)L->xs_row_begin[j + 1] * 64) ++j;
+            uint64_t e = t + 1 < segs ? seg_begin[t + 1] : (uint64_t)L->xs_edge_end[j];
+            e = std::min<uint64_t>(e, L->xs_edge_end[j]);
+            const uint64_t b = e - 1;
+            if (a / TE != b / TE) sp.push_back({L->xs_nzdst[t], (uint32_t)(a / TE), (uint32_t)(b / TE)});
+        }
+    }
+    std::stable_sort(sp.begin(), sp.end(), [](const Span& x, const Span& y) { return x.v < y.v; });
+    // per destination: its pairs; short destinations (at most kPrShortSpan
+    // extra tiles over all their spans) first, then the long ones
+    std::vector<uint32_t> sv, sl, lv, ll;  // vertex, first pair index
+    std::vector<uint32_t> pairs_short, pairs_long;
+    for (size_t i = 0; i < sp.size();) {
+        size_t k = i;
+        uint64_t extra = 0;
+        while (k < sp.size() && sp[k].v == sp[i].v) { extra += sp[k].b - sp[k].a; ++k; }
+        const bool is_short = extra <= kPrShortSpan;
+        std::vector<uint32_t>& vv = is_short ? sv : lv;
+        std::vector<uint32_t>& off = is_short ? sl : ll;
+        std::vector<uint32_t>& pr = is_short ? pairs_short : pairs_long;
+        vv.push_back(sp[i].v);
+        off.push_back((uint32_t)(pr.size() / 2));
+        for (size_t q = i; q < k; ++q) { pr.push_back(sp[q].a); pr.push_back(sp[q].b); }
+        i = k;
+    }
+    L->xs_pspan_short = sv.size();
+    L->xs_pspan_v = sv;
+    L->xs_pspan_v.insert(L->xs_pspan_v.end(), lv.begin(), lv.end());
+    const uint32_t npairs_short = (uint32_t)(pairs_short.size() / 2);
+    L->xs_pspan_off = sl;
+    for (uint32_t o : ll) L->xs_pspan_off.push_back(o + npairs_short);
+    L->xs_pspan_off.push_back((uint32_t)((pairs_short.size() + pairs_long.size()) / 2));
+    L->xs_pspan_tt = pairs_short;
+    L->xs_pspan_tt.insert(L->xs_pspan_tt.end(), pairs_long.begin(), pairs_long.end());
 }
 
 wedge_status build_layout_from_csc(uint32_t n, uint64_t m, const uint64_t* col_off,

@@ -51,6 +51,11 @@ struct HostLayout {
     // next slice's first row are padding
     std::vector<uint32_t> xs_src, xs_w, xs_rowseg, xs_nzdst;
     std::vector<uint64_t> xs_rowmask;
+    // PageRank over the sliced copy: destinations with segments crossing a
+    // tile boundary (short ones first), the offsets of their (first tile,
+    // last tile) pairs, and the pairs
+    std::vector<uint32_t> xs_pspan_v, xs_pspan_off, xs_pspan_tt;
+    uint64_t xs_pspan_short = 0;
     uint32_t xs_row_begin[kXcdSlices + 1] = {};
     uint32_t xs_edge_end[kXcdSlices] = {};
 };
@@ -106,6 +111,12 @@ struct DevGraph {
     uint64_t xs_rows = 0;
     uint64_t xs_positions = 0;  // padded length
     uint64_t xs_segments = 0;
+    uint32_t* xs_pspan_v = nullptr;
+    uint32_t* xs_pspan_off = nullptr;
+    uint32_t* xs_pspan_tt = nullptr;
+    uint64_t xs_pspans = 0;       // destinations with crossing segments
+    uint64_t xs_pspan_short = 0;  // of which listed first as short
+    uint64_t xs_pspan_pairs = 0;  // crossing segments over all of them
     uint32_t xs_row_begin[kXcdSlices + 1] = {};
     uint32_t xs_edge_end[kXcdSlices] = {};
     // push engine (built on first use): out-edge destinations and weights in CSR order
@@ -404,7 +415,7 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
 // previous epilogue's dangling partials into *d_next (when d_next is set).
 hipError_t launch_pr_fixup(const DevGraph& g, const float* head, const float* tail, float* sum,
                            const double* partials, uint32_t parts, double* d_next, hipStream_t s);
-hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, const float* sum,
+hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, float* sum,
                               double damping, const double* d_cur, float* rank, float* contrib,
                               double* partials, uint32_t parts, hipStream_t s);
 uint32_t pr_epilogue_blocks(uint32_t n);

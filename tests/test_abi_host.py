@@ -262,6 +262,33 @@ def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
         total += hi - lo
     assert total == m
     assert info["xs_segments"] == int(bits.sum())
+    # PageRank tiles (8 rows) never straddle two slices
+    T = info["pr_tile_edges"]
+    assert np.all(row_begin * 64 % T == 0)
+    # fix-up lists: every slice segment whose positions cross a tile boundary,
+    # grouped by destination in slice order; destinations whose segments cover
+    # at most 8 extra tiles in all come first
+    per_v = {}
+    for j in range(8):
+        lo, hi = int(row_begin[j] * 64), int(edge_end[j])
+        if hi == lo:
+            continue
+        d = dst_x[lo:hi]
+        cut = np.flatnonzero(np.diff(d)) + 1
+        for a, b in zip(np.r_[0, cut] + lo, np.r_[cut, hi - lo] + lo - 1):
+            if a // T != b // T:
+                per_v.setdefault(int(dst_x[a]), []).append((a // T, b // T))
+    order = sorted(per_v)
+    short = [v for v in order if sum(b - a for a, b in per_v[v]) <= 8]
+    long_ = [v for v in order if sum(b - a for a, b in per_v[v]) > 8]
+    assert info["xs_pr_spans"] == len(order)
+    assert info["xs_pr_short_spans"] == len(short)
+    np.testing.assert_array_equal(g.layout("xs_pr_span_v"), np.array(short + long_, np.uint32))
+    off = g.layout("xs_pr_span_off").astype(np.int64)
+    tiles = g.layout("xs_pr_span_tiles").reshape(-1, 2).astype(np.int64)
+    for k, v in enumerate(short + long_):
+        assert [tuple(x) for x in tiles[off[k]:off[k + 1]]] == per_v[v]
+    assert (len(off) == 0 and len(tiles) == 0) or off[-1] == len(tiles)
 
 
 def test_source_sliced_copy_threshold(monkeypatch):

@@ -285,22 +285,56 @@ def test_pagerank_parity(name, keep_ids):
     assert torch.equal(r, r2)
 
 
+@pytest.mark.parametrize("sliced", ["0", "1"])
 @pytest.mark.parametrize("kind", ["rmat", "er"])
-def test_pagerank_large_graph_lds_pull(kind):
-    """Scale 20 is large enough for the pull that keeps the highest-degree
-    vertices' contributions in LDS and strides over the tiles (at least four
-    tiles per resident wave on 256 CUs); its result must still be the oracle's
-    and deterministic."""
+def test_pagerank_large_graph_lds_pull(monkeypatch, kind, sliced):
+    """Scale 20 is large enough for the pulls that keep the highest-degree
+    vertices' contributions in LDS and stride over the tiles (at least four
+    tiles per resident wave on 256 CUs), over the canonical in-edge order and
+    over the source-sliced copy (one launch per slice, adding into S, then the
+    crossing segments' fix-up); results must be the oracle's and
+    deterministic."""
+    monkeypatch.setenv("WEDGE_SLICED_PULL", sliced)
     ro, col = gen.rmat(20, 16, seed=81)
     if kind == "er":
         ro, col = gen.erdos_renyi(1 << 20, len(col), seed=81)
     g = W.Graph.from_csr(ro, col)
     assert (g.info["rows"] + 7) // 8 >= 4 * 2 * 256 * 12
+    assert (g.info["xs_rows"] > 0) == (sliced == "1")
     r, _ = W.pagerank(g, 20, 0.85)
     ref = oracle.pagerank(ro, col, 20, 0.85)
-    assert rel_l1(r.cpu().numpy(), ref) <= 1e-5
+    got = r.cpu().numpy()
+    assert rel_l1(got, ref) <= 1e-5
+    assert np.max(np.abs(got - ref) / ref) <= 1e-4
     r2, _ = W.pagerank(g, 20, 0.85)
     assert torch.equal(r, r2)
+
+
+@pytest.mark.parametrize("name", ["er_ragged", "rmat12", "rmat14", "grid", "hub"])
+def test_pagerank_source_sliced_small(monkeypatch, name):
+    """The sliced PageRank pull forced on small graphs (slices of a few tiles,
+    empty slices, a hub whose in-edges cross many tiles in every slice)."""
+    monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
+    if name == "hub":
+        n = 70000
+        rng = np.random.default_rng(1)
+        src = np.concatenate([np.arange(1, n), rng.integers(0, n, 200000)]).astype(np.uint32)
+        dst = np.concatenate([np.zeros(n - 1), rng.integers(1, n, 200000)]).astype(np.uint32)
+        ro, col = gen.csr_from_edges(n, src, dst)
+    else:
+        ro, col = GRAPHS[name]()
+    g = W.Graph.from_csr(ro, col)
+    assert g.info["xs_rows"] > 0
+    if name == "hub":
+        assert g.info["xs_pr_spans"] > g.info["xs_pr_short_spans"] > 0
+    r, _ = W.pagerank(g, 20, 0.85)
+    ref = oracle.pagerank(ro, col, 20, 0.85)
+    got = r.cpu().numpy()
+    assert rel_l1(got, ref) <= 1e-5
+    assert np.max(np.abs(got - ref) / ref) <= 1e-4
+    r2, _ = W.pagerank(g, 20, 0.85)
+    assert torch.equal(r, r2)
+    g.close()
 
 
 def test_pagerank_closed_forms():
