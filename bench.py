@@ -98,7 +98,7 @@ def full_pull_kernel_name(g, app):
     return f"k_pull_slice<{app}>" if g.info["xs_rows"] else f"k_pull_full<{app}>"
 
 
-def roofline(name, ms, pulls, alg, workload, per_pull=1):
+def roofline(name, ms, pulls, alg, workload, per_pull=1, extra=None):
     """HBM roofline entry of one kernel: `pulls` full pulls took `ms` in all
     (HIP events around each pull, on the library's stream); a pull is
     `per_pull` launches of the kernel (the source slices), so one launch
@@ -114,6 +114,7 @@ def roofline(name, ms, pulls, alg, workload, per_pull=1):
          "algorithmic_bytes_per_launch": int(alg_l)}
     if per_pull > 1:
         r["launches_per_pull"] = per_pull
+    r.update(extra or {})
     if traffic:
         # the bytes the memory system actually moved (whole lines for 4-byte gathers)
         r["traffic_gbs"] = round(traffic / avg / 1e9, 1)
@@ -637,8 +638,19 @@ def main():
         (full_pull_kernel_name(gs, "CC"), fullpull["cc"][0], fullpull["cc"][1],
          minpull_bytes(gs.info, False), slice_launches(gs)),
     ]
-    roofs = [roofline(name, ms, pulls, alg, workload, per)
-             for name, ms, pulls, alg, per in cands if pulls]
+    roofs = []
+    for name, ms, pulls, alg, per in cands:
+        if not pulls:
+            continue
+        extra = None
+        if name.startswith("k_pull_slice<SSSP") and g.info["xs_packed"]:
+            # the packed copy reads one 4-byte word per in-edge where the
+            # algorithmic figure counts a source and a weight (8 bytes)
+            packed = alg - 4 * g.info["m"]
+            extra = {"packed_edge_words": True,
+                     "packed_bytes_per_launch": int(packed / per),
+                     "packed_frac": round(packed / per / (ms / 1e3 / (pulls * per)) / 1e9 / HBM_PEAK_GBS, 4)}
+        roofs.append(roofline(name, ms, pulls, alg, workload, per, extra))
     roofs.sort(key=lambda r: -r["total_ms"])  # the dominant kernel first
     roof = roofs[0]
     out = {

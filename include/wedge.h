@@ -158,6 +158,8 @@ typedef struct {
     uint64_t xs_pr_short_spans; /* of xs_pr_spans, those whose crossing segments
                                    cover at most 8 extra tiles in all */
     uint64_t xs_pr_span_pairs;  /* crossing segments over all of them */
+    uint32_t xs_packed;    /* 1: each sliced-copy word is (slice-local source << 8) | weight
+                              (weighted graphs with weights <= 255 and n <= 2^27) */
 } wedge_graph_info;
 
 wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info);
@@ -175,8 +177,12 @@ typedef enum {
     WEDGE_LAYOUT_PR_SPANS = 8,/* uint32[3*pr_spans] (vertex, first tile, last tile) */
     WEDGE_LAYOUT_PERM = 9,    /* uint32[n] internal id of each caller id (relabelled graphs) */
     /* the source-sliced copy of the in-edges (graphs with xs_rows > 0): */
-    WEDGE_LAYOUT_XS_SRC = 10,     /* uint32[64*xs_rows] sources; padding positions hold 0 */
-    WEDGE_LAYOUT_XS_W = 11,       /* uint32[64*xs_rows] weights (weighted graphs) */
+    WEDGE_LAYOUT_XS_SRC = 10,     /* uint32[64*xs_rows] sources, or packed words when
+                                     xs_packed (the slice-local id i of slice j's source is
+                                     its index among the ids of the slice's 1024-id groups,
+                                     groups dealt to slices in the order 0..7, 7..0, ...);
+                                     padding positions hold 0 */
+    WEDGE_LAYOUT_XS_W = 11,       /* uint32[64*xs_rows] weights (weighted, not packed) */
     WEDGE_LAYOUT_XS_ROWMASK = 12, /* uint64[xs_rows] */
     WEDGE_LAYOUT_XS_ROWSEG = 13,  /* uint32[xs_rows] */
     WEDGE_LAYOUT_XS_NZDST = 14,   /* uint32[xs_segments] */

@@ -49,7 +49,7 @@ class GraphInfo(C.Structure):
                 ("pr_short_spans", C.c_uint64), ("relabeled", C.c_uint32),
                 ("xs_rows", C.c_uint64), ("xs_segments", C.c_uint64),
                 ("xs_pr_spans", C.c_uint64), ("xs_pr_short_spans", C.c_uint64),
-                ("xs_pr_span_pairs", C.c_uint64)]
+                ("xs_pr_span_pairs", C.c_uint64), ("xs_packed", C.c_uint32)]
 
 
 class IterRecord(C.Structure):

@@ -141,6 +141,8 @@ wedge_status copy_input(const T* p, uint64_t count, bool on_device, std::vector<
     return WEDGE_OK;
 }
 
+int device_cus(int dev);
+
 // Whether a graph gets the source-sliced in-edge copy (WEDGE_SLICED_PULL).
 bool sliced_pull_wanted(uint64_t m) {
     const char* e = std::getenv("WEDGE_SLICED_PULL");
@@ -195,6 +197,7 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
         d.xs_segments = L.xs_nzdst.size();
         std::memcpy(d.xs_row_begin, L.xs_row_begin, sizeof d.xs_row_begin);
         std::memcpy(d.xs_edge_end, L.xs_edge_end, sizeof d.xs_edge_end);
+        d.xs_packed = L.xs_packed;
         d.xs_pspans = L.xs_pspan_v.size();
         d.xs_pspan_short = L.xs_pspan_short;
         d.xs_pspan_pairs = L.xs_pspan_tt.size() / 2;
@@ -204,6 +207,7 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     {
         const hipError_t e = hipGetDevice(&g->device);
         if (e != hipSuccess) { delete g; return hip_fail(e, "hipGetDevice"); }
+        d.cus = device_cus(g->device);
     }
     st = WEDGE_OK;
     SetupLock upload_lock;
@@ -1177,6 +1181,7 @@ wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info) {
     info->xs_pr_spans = g->dev.xs_pspans;
     info->xs_pr_short_spans = g->dev.xs_pspan_short;
     info->xs_pr_span_pairs = g->dev.xs_pspan_pairs;
+    info->xs_packed = g->dev.xs_packed ? 1u : 0u;
     return WEDGE_OK;
 }
 
@@ -1221,6 +1226,8 @@ wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void*
                 return WEDGE_OK;
             }
             if (which == WEDGE_LAYOUT_XS_W && !g->weighted) return fail(WEDGE_ERR_NO_WEIGHTS, "graph has no weights");
+            if (which == WEDGE_LAYOUT_XS_W && d.xs_packed)
+                return fail(WEDGE_ERR_UNSUPPORTED, "the sliced copy packs the weights into its source words");
             if (which == WEDGE_LAYOUT_XS_SRC) { size = xr * 64 * 4; hsrc = L.xs_src.data(); dsrc = d.xs_src; }
             if (which == WEDGE_LAYOUT_XS_W) { size = xr * 64 * 4; hsrc = L.xs_w.data(); dsrc = d.xs_w; }
             if (which == WEDGE_LAYOUT_XS_ROWMASK) { size = xr * 8; hsrc = L.xs_rowmask.data(); dsrc = d.xs_rowmask; }

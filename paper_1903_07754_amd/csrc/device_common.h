@@ -413,14 +413,53 @@ __device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint3
 // iteration travels on at once). Every value read is still the length of a
 // real path (or a real label), and values only fall, so the fixed point, and
 // the final result, are those of the synchronous pull.
-template <int APP, int R, bool ROWS = false, bool INPLACE = false>
+//
+// Edges says how a pull reads an in-edge: the canonical arrays (a source id
+// per position, SSSP weights in their own array), or the source-sliced copy,
+// whose words may pack (slice-local source << 8) | weight and whose slice's
+// highest-out-degree sources can have their values staged in LDS.
+struct CanonicalEdges {
+    static constexpr bool kPacked = false;
+    __device__ __forceinline__ uint32_t gather(const uint32_t* __restrict__ src, uint32_t u) const {
+        return src[u];
+    }
+};
+
+template <bool PACKED, bool HOT>
+struct SliceEdges {
+    static constexpr bool kPacked = PACKED;
+    uint32_t slice;
+    uint32_t n;
+    uint32_t hot;                       // values of slice-local ids [0, hot) are in s_hot
+    const uint32_t* __restrict__ s_hot;  // LDS
+    __device__ __forceinline__ uint32_t gather(const uint32_t* __restrict__ src, uint32_t word) const {
+        const uint32_t l = PACKED ? (word >> 8) : xcd_slice_local(word);
+        uint32_t u = word;
+        if (PACKED) {
+            // a lane without an edge holds another slice's word: keep its
+            // (masked) read inside the array
+            u = xcd_slice_global(l, slice);
+            u = u < n ? u : 0u;
+        }
+        if (!HOT) return src[u];
+        // branch-free: the lane's global and LDS reads are both issued
+        const bool h = l < hot;
+        const uint32_t gv = src[h ? 0u : u];
+        const uint32_t lv = s_hot[h ? l : 0u];
+        return h ? lv : gv;
+    }
+};
+
+template <int APP, int R, bool ROWS = false, bool INPLACE = false, class Edges = CanonicalEdges>
 __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&p)[R],
                                            const bool (&valid)[R], uint32_t iter,
                                            uint32_t* __restrict__ val,
                                            const uint32_t* __restrict__ val_prev,
                                            const uint64_t* __restrict__ fcur,
                                            uint64_t* __restrict__ fbits,
-                                           uint32_t* __restrict__ fsum) {
+                                           uint32_t* __restrict__ fsum,
+                                           const Edges edges = Edges{}) {
+    static_assert(ROWS || !Edges::kPacked, "the chunk pulls read the canonical arrays");
     const int lane = lane_id();
     // loads are branch-free: a lane without an edge reads position 0 (its
     // results are masked), so all rows' loads of one step are in flight at once
@@ -432,7 +471,8 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
 #pragma unroll
         for (int i = 0; i < R; ++i) u[i] = ld_stream(g.in_src + pc[i]);
 #pragma unroll
-        for (int i = 0; i < R; ++i) wt[i] = APP == kSssp ? ld_stream(g.in_w + pc[i]) : 0u;
+        for (int i = 0; i < R; ++i)
+            wt[i] = APP == kSssp ? (Edges::kPacked ? (u[i] & 255u) : ld_stream(g.in_w + pc[i])) : 0u;
     }
     dst_of_rows<R>(g, pc, dst);
 #pragma unroll
@@ -515,7 +555,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
             for (int i = 0; i < R; ++i) x[i] = act[i] ? x[i] : kInf;
         } else {
 #pragma unroll
-            for (int i = 0; i < R; ++i) x[i] = (INPLACE ? val : val_prev)[u[i]];
+            for (int i = 0; i < R; ++i) x[i] = edges.gather(INPLACE ? val : val_prev, u[i]);
 #pragma unroll
             for (int i = 0; i < R; ++i) cur[i] = val[valid[i] ? dst[i] : 0u];
 #pragma unroll

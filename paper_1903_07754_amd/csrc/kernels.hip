@@ -185,28 +185,58 @@ __global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_full(Graph
 // Full pull over one slice of the source-sliced copy (CC and SSSP). The pull
 // over every in-edge is run slice after slice, one launch each, over the whole
 // GPU: during a launch every XCD gathers only the values of that slice's
-// sources (an eighth of the value array), so they stay in its L2. Inside a
-// launch a slice is pulled exactly like the canonical array (wave-owned
-// destinations take a plain store, the wave's first and last segments a
-// min-atomic); successive launches lower the same destinations in turn.
-template <int APP, int R, bool INPLACE>
-__global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_slice(
-    GraphArgs g, uint32_t row_begin, uint32_t row_end, uint32_t edge_end, uint32_t iter,
+// sources (an eighth of the value array), so they stay in its L2. In the
+// synchronous pull each block first copies the committed values of the
+// slice's first `hot` sources (slice-local ids, its highest out-degrees) into
+// LDS, where their gathers are served; the in-place pull reads the values as
+// they fall and stages nothing. Waves then stride over R-row tiles, each
+// pulled exactly like the canonical array (wave-owned destinations take a
+// plain store, the tile's first and last segments a min-atomic); successive
+// launches lower the same destinations in turn. PACKED: each position holds
+// (slice-local source << 8) | weight.
+template <int APP, int R, bool INPLACE, bool PACKED>
+__global__ __launch_bounds__(kHotBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_pull_slice(
+    GraphArgs g, uint32_t slice, uint32_t row_begin, uint32_t row_end, uint32_t edge_end, uint32_t iter,
     uint32_t* __restrict__ val, const uint32_t* __restrict__ val_prev,
-    const uint64_t* __restrict__ fcur, uint64_t* __restrict__ fbits, uint32_t* __restrict__ fsum) {
-    const int lane = lane_id();
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t r0 = (uint64_t)row_begin + wave * R;
-    if (r0 >= row_end) return;
-    uint32_t p[R];
-    bool valid[R];
+    const uint64_t* __restrict__ fcur, uint64_t* __restrict__ fbits, uint32_t* __restrict__ fsum,
+    uint32_t hot) {
+    extern __shared__ uint32_t s_val[];
+    if (!INPLACE) {
+        // all of a thread's loads are issued before its first store
+        constexpr int kPer = (int)((kHotVerts + kHotBlock - 1) / kHotBlock);
+        uint32_t t[kPer];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const uint64_t pp = (r0 + i) * 64 + lane;
-        valid[i] = pp < edge_end;
-        p[i] = (uint32_t)pp;
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
+            const uint32_t gi = xcd_slice_global(i < hot ? i : 0u, slice);
+            t[k] = val_prev[gi < g.n ? gi : 0u];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
+            if (i < hot) s_val[i] = t[k];
+        }
+        __syncthreads();
     }
-    pull_lanes<APP, R, true, INPLACE>(g, p, valid, iter, val, val_prev, fcur, fbits, fsum);
+    const SliceEdges<PACKED, !INPLACE> edges{slice, g.n, INPLACE ? 0u : hot, s_val};
+    const int lane = lane_id();
+    const uint64_t wpb = kHotBlock / 64;
+    const uint64_t stride = (uint64_t)gridDim.x * wpb;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint64_t w = blockIdx.x * wpb + wib;; w += stride) {
+        const uint64_t r0 = (uint64_t)row_begin + w * R;
+        if (r0 >= row_end) break;
+        uint32_t p[R];
+        bool valid[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const uint64_t pp = (r0 + i) * 64 + lane;
+            valid[i] = pp < edge_end;
+            p[i] = (uint32_t)pp;
+        }
+        pull_lanes<APP, R, true, INPLACE, SliceEdges<PACKED, !INPLACE>>(g, p, valid, iter, val, val_prev,
+                                                                      fcur, fbits, fsum, edges);
+    }
 }
 
 // Pull over the marked chunks: the chunk list holds K = *marked chunk ids of
@@ -393,14 +423,6 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_hot(GraphArgs g, const fl
             sum, head_part, tail_part);
 }
 
-// Slice-local index of a source of slice j (its 1024-vertex groups, in
-// order, numbered 0, 1, ...) and back.
-__device__ __forceinline__ uint32_t slice_local(uint32_t u) { return ((u >> 13) << 10) | (u & 1023u); }
-__device__ __forceinline__ uint32_t slice_global(uint32_t i, uint32_t j) {
-    const uint32_t b = i >> 10;
-    const uint32_t gidx = b * 8u + ((b & 1u) ? 7u - j : j);
-    return (gidx << 10) | (i & 1023u);
-}
 
 // PageRank pull over one slice of the source-sliced copy: the slices are
 // pulled one launch after another and each adds its partial sums into S, in
@@ -409,7 +431,7 @@ __device__ __forceinline__ uint32_t slice_global(uint32_t i, uint32_t j) {
 // launch gathers only this slice's sources, so the rest of its gathers stay in
 // the L2. Segments crossing a tile boundary leave their parts in head/tail;
 // k_pr_fixup_xs adds them afterwards.
-template <int R>
+template <int R, bool PACKED>
 __global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32_t slice,
                                                              uint64_t tile_begin, uint64_t tile_end,
                                                              const float* __restrict__ contrib,
@@ -424,13 +446,13 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
-            const uint32_t gi = slice_global(i < hot ? i : 0u, slice);
+            const uint32_t gi = xcd_slice_global(i < hot ? i : 0u, slice);
             t[k] = contrib[gi < g.n ? gi : 0u];
         }
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
-            if (i < hot) s_hot[i] = slice_global(i, slice) < g.n ? t[k] : 0.0f;
+            if (i < hot) s_hot[i] = t[k];
         }
     }
     __syncthreads();
@@ -440,11 +462,18 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32
     for (uint64_t t = tile_begin + blockIdx.x * wpb + wib; t < tile_end; t += stride)
         pr_tile<R, kHotBatch, true>(
             g, t,
-            [&](uint32_t u) {
-                const uint32_t l = slice_local(u);
-                const float gv = contrib[l < hot ? 0u : u];
-                const float lv = s_hot[l < hot ? l : 0u];
-                return l < hot ? lv : gv;
+            [&](uint32_t word) {
+                const uint32_t l = PACKED ? (word >> 8) : xcd_slice_local(word);
+                uint32_t u = word;
+                if (PACKED) {
+                    // a lane without an edge may hold another slice's word
+                    u = xcd_slice_global(l, slice);
+                    u = u < g.n ? u : 0u;
+                }
+                const bool h = l < hot;
+                const float gv = contrib[h ? 0u : u];
+                const float lv = s_hot[h ? l : 0u];
+                return h ? lv : gv;
             },
             sum, head_part, tail_part);
 }
@@ -706,6 +735,47 @@ hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
     return hipGetLastError();
 }
 
+// Resident blocks per compute unit of a kernel at a block size and dynamic
+// LDS size (the same on every MI355X); queried once per kernel (a
+// function-local static, initialised safely across threads); 0 if the query
+// fails.
+template <auto KERNEL>
+int resident_blocks(int block, size_t lds) {
+    static const int b = [&] {
+        int x = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&x, KERNEL, block, lds) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        return x;
+    }();
+    return b;
+}
+
+int slice_pull_resident(int app, bool inplace, bool packed, size_t lds) {
+    if (app == kCc)
+        return inplace ? resident_blocks<k_pull_slice<kCc, kPullRows, true, false>>(kHotBlock, lds)
+                       : resident_blocks<k_pull_slice<kCc, kPullRows, false, false>>(kHotBlock, lds);
+    if (packed)
+        return inplace ? resident_blocks<k_pull_slice<kSssp, kPullRows, true, true>>(kHotBlock, lds)
+                       : resident_blocks<k_pull_slice<kSssp, kPullRows, false, true>>(kHotBlock, lds);
+    return inplace ? resident_blocks<k_pull_slice<kSssp, kPullRows, true, false>>(kHotBlock, lds)
+                   : resident_blocks<k_pull_slice<kSssp, kPullRows, false, false>>(kHotBlock, lds);
+}
+
+// How many of slice j's first kHotVerts slice-local ids are vertices (the
+// slice's groups in order; only the graph's last group can be partial).
+uint32_t slice_hot_count(uint32_t n, uint32_t j) {
+    constexpr uint32_t kGroup = 1u << kXcdGroupShift;
+    uint32_t hot = 0;
+    for (uint32_t i = 0; i < kHotVerts; i += kGroup) {
+        const uint64_t first = xcd_slice_global(i, j);
+        if (first >= n) break;
+        hot = i + (uint32_t)std::min<uint64_t>(kGroup, n - first);
+    }
+    return std::min(hot, kHotVerts);
+}
+
 // BFS pulls come in three shapes (rows per wave step); CC and SSSP in one.
 template <int R>
 uint32_t full_blocks(const DevGraph& g) {
@@ -721,19 +791,31 @@ hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t*
     if (inplace && app == kBfs) return hipErrorInvalidValue;
     if (app != kBfs && g.xs_rows) {
         const GraphArgs xa = xs_args_of(g);
+        const size_t lds = inplace ? 0 : (size_t)kHotVerts * sizeof(uint32_t);
+        const int per_cu = slice_pull_resident(app, inplace, g.xs_packed, lds);
+        if (per_cu <= 0) return hipErrorInvalidConfiguration;
         for (int j = 0; j < kXcdSlices; ++j) {
             const uint32_t rb = g.xs_row_begin[j], re = g.xs_row_begin[j + 1];
             if (re == rb) continue;
             const uint64_t waves = ((uint64_t)(re - rb) + kPullRows - 1) / kPullRows;
-            const uint32_t blocks = (uint32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+            const uint32_t blocks = (uint32_t)std::min<uint64_t>(
+                (uint64_t)std::max(g.cus, 1) * (uint64_t)per_cu, (waves + kHotBlock / 64 - 1) / (kHotBlock / 64));
             const uint32_t ee = g.xs_edge_end[j];
+            const uint32_t hot = inplace ? 0u : slice_hot_count(g.n, (uint32_t)j);
+#define WEDGE_SLICE_LAUNCH(A, IP, PK)                                                              \
+    k_pull_slice<A, kPullRows, IP, PK><<<blocks, kHotBlock, lds, s>>>(xa, (uint32_t)j, rb, re, ee, iter, \
+                                                                      val, val_prev, fcur, fbits, fsum, hot)
             if (app == kCc) {
-                if (inplace) k_pull_slice<kCc, kPullRows, true><<<blocks, kBlock, 0, s>>>(xa, rb, re, ee, iter, val, val_prev, fcur, fbits, fsum);
-                else k_pull_slice<kCc, kPullRows, false><<<blocks, kBlock, 0, s>>>(xa, rb, re, ee, iter, val, val_prev, fcur, fbits, fsum);
+                if (inplace) WEDGE_SLICE_LAUNCH(kCc, true, false);
+                else WEDGE_SLICE_LAUNCH(kCc, false, false);
+            } else if (g.xs_packed) {
+                if (inplace) WEDGE_SLICE_LAUNCH(kSssp, true, true);
+                else WEDGE_SLICE_LAUNCH(kSssp, false, true);
             } else {
-                if (inplace) k_pull_slice<kSssp, kPullRows, true><<<blocks, kBlock, 0, s>>>(xa, rb, re, ee, iter, val, val_prev, fcur, fbits, fsum);
-                else k_pull_slice<kSssp, kPullRows, false><<<blocks, kBlock, 0, s>>>(xa, rb, re, ee, iter, val, val_prev, fcur, fbits, fsum);
+                if (inplace) WEDGE_SLICE_LAUNCH(kSssp, true, false);
+                else WEDGE_SLICE_LAUNCH(kSssp, false, false);
             }
+#undef WEDGE_SLICE_LAUNCH
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -823,15 +905,9 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
         // one launch per source slice, each over the whole GPU (resident blocks
         // at the full LDS size), adding into S; head/tail are indexed by the
         // sliced copy's tiles (no tile straddles two slices)
-        static const int per_cu = [] {
-            int b = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_pr_pull_slice<kPrTileRows>, kHotBlock,
-                                                             (kHotVerts + 8) * sizeof(float)) != hipSuccess) {
-                (void)hipGetLastError();
-                return 0;
-            }
-            return b;
-        }();
+        constexpr size_t lds = (kHotVerts + 8) * sizeof(float);
+        const int per_cu = g.xs_packed ? resident_blocks<k_pr_pull_slice<kPrTileRows, true>>(kHotBlock, lds)
+                                       : resident_blocks<k_pr_pull_slice<kPrTileRows, false>>(kHotBlock, lds);
         if (per_cu <= 0) return hipErrorInvalidConfiguration;
         for (int j = 0; j < kXcdSlices; ++j) {
             const uint64_t rb = g.xs_row_begin[j], re = g.xs_row_begin[j + 1];
@@ -839,19 +915,16 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
             GraphArgs xa = xs_args_of(g);
             xa.m = g.xs_edge_end[j];  // positions past the slice's last in-edge are idle
             xa.rows = (uint32_t)re;
-            // the slice's first kHotVerts slice-local sources that exist
-            uint32_t hot = 0;
-            for (uint32_t i = 0; i < kHotVerts; i += 1024u) {
-                const uint32_t b = i >> 10;
-                const uint64_t gidx = (uint64_t)b * 8 + ((b & 1u) ? 7u - j : (uint32_t)j);
-                if ((gidx << 10) >= g.n) break;
-                hot = i + (uint32_t)std::min<uint64_t>(1024, g.n - (gidx << 10));
-            }
+            const uint32_t hot = slice_hot_count(g.n, (uint32_t)j);
             const uint64_t tb = rb / kPrTileRows, te = re / kPrTileRows;
             const uint64_t blocks = std::min<uint64_t>((uint64_t)std::max(cus, 1) * (uint64_t)per_cu,
                                                        (te - tb + kHotBlock / 64 - 1) / (kHotBlock / 64));
-            k_pr_pull_slice<kPrTileRows><<<(uint32_t)blocks, kHotBlock, (kHotVerts + 8) * sizeof(float), s>>>(
-                xa, (uint32_t)j, tb, te, contrib, sum, head, tail, hot);
+            if (g.xs_packed)
+                k_pr_pull_slice<kPrTileRows, true><<<(uint32_t)blocks, kHotBlock, lds, s>>>(
+                    xa, (uint32_t)j, tb, te, contrib, sum, head, tail, hot);
+            else
+                k_pr_pull_slice<kPrTileRows, false><<<(uint32_t)blocks, kHotBlock, lds, s>>>(
+                    xa, (uint32_t)j, tb, te, contrib, sum, head, tail, hot);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

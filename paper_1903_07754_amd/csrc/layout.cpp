@@ -296,6 +296,10 @@ wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_o
 void build_xcd_slices(HostLayout* L) {
     const uint32_t n = L->n;
     const bool weighted = !L->in_w.empty();
+    // weighted graphs whose weights fit 8 bits and slice-local ids 24 bits
+    // store one word per in-edge instead of two
+    const bool packed = weighted && L->max_w <= kXsPackMaxW && (uint64_t)n <= kXsPackMaxN;
+    L->xs_packed = packed;
     // per thread range of destinations: edge counts per slice
     const unsigned T = std::max(1u, std::min<unsigned>(host_threads(), 64));
     const uint64_t step = ((uint64_t)n + T - 1) / T;
@@ -331,7 +335,7 @@ void build_xcd_slices(HostLayout* L) {
     const uint64_t rows = total / 64;
     L->xs_row_begin[kXcdSlices] = (uint32_t)rows;
     L->xs_src.assign(total ? total : 1, 0);
-    if (weighted) L->xs_w.assign(total ? total : 1, 0);
+    if (weighted && !packed) L->xs_w.assign(total ? total : 1, 0);
     // destination of every position (padding: none), for the row layout below
     std::vector<uint32_t> dst(total ? total : 1, 0xFFFFFFFFu);
     for_ranges([&](unsigned t, uint64_t vb, uint64_t ve) {
@@ -343,8 +347,12 @@ void build_xcd_slices(HostLayout* L) {
             for (uint64_t p = L->col_off[v]; p < L->col_off[v + 1]; ++p) {
                 const uint32_t u = L->in_src[p];
                 const uint64_t q = cur[xcd_slice_of(u)]++;
-                L->xs_src[q] = u;
-                if (weighted) L->xs_w[q] = L->in_w[p];
+                if (packed) {
+                    L->xs_src[q] = (xcd_slice_local(u) << 8) | L->in_w[p];
+                } else {
+                    L->xs_src[q] = u;
+                    if (weighted) L->xs_w[q] = L->in_w[p];
+                }
                 dst[q] = (uint32_t)v;
             }
     });

@@ -51,6 +51,9 @@ struct HostLayout {
     // next slice's first row are padding
     std::vector<uint32_t> xs_src, xs_w, xs_rowseg, xs_nzdst;
     std::vector<uint64_t> xs_rowmask;
+    // packed form (weighted graphs with weights <= 255 and n <= 2^27): xs_src
+    // holds (slice-local source << 8) | weight and xs_w is empty
+    bool xs_packed = false;
     // PageRank over the sliced copy: destinations with segments crossing a
     // tile boundary (short ones first), the offsets of their (first tile,
     // last tile) pairs, and the pairs
@@ -70,6 +73,20 @@ inline uint32_t xcd_slice_of(uint32_t u) {
     const uint32_t g = u >> kXcdGroupShift;
     return ((g >> 3) & 1u) ? 7u - (g & 7u) : (g & 7u);
 }
+// Index of u among its slice's vertices (the slice's groups in order), and
+// back: the slice-local ids of a slice's highest-out-degree sources are the
+// lowest.
+__host__ __device__ inline uint32_t xcd_slice_local(uint32_t u) {
+    return ((u >> (kXcdGroupShift + 3)) << kXcdGroupShift) | (u & ((1u << kXcdGroupShift) - 1u));
+}
+__host__ __device__ inline uint32_t xcd_slice_global(uint32_t i, uint32_t j) {
+    const uint32_t b = i >> kXcdGroupShift;
+    const uint32_t gidx = b * 8u + ((b & 1u) ? 7u - j : j);
+    return (gidx << kXcdGroupShift) | (i & ((1u << kXcdGroupShift) - 1u));
+}
+// The packed sliced copy: (slice-local source << 8) | weight in one word.
+constexpr uint32_t kXsPackMaxW = 255;
+constexpr uint64_t kXsPackMaxN = 1ull << 27;  // slice-local ids below 2^24
 
 // Builds the source-sliced copy of L's in-edges (L must hold the canonical layout).
 void build_xcd_slices(HostLayout* L);
@@ -109,6 +126,8 @@ struct DevGraph {
     uint32_t* xs_rowseg = nullptr;
     uint32_t* xs_nzdst = nullptr;
     uint64_t xs_rows = 0;
+    bool xs_packed = false;     // xs_src holds (slice-local source << 8) | weight
+    int cus = 0;                // compute units of the graph's device
     uint64_t xs_positions = 0;  // padded length
     uint64_t xs_segments = 0;
     uint32_t* xs_pspan_v = nullptr;

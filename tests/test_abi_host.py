@@ -209,7 +209,8 @@ def _slice_of(u):
 
 
 @pytest.mark.parametrize("seed,scale,weighted,sym,keep", [
-    (6, 12, True, False, True), (7, 13, False, True, False), (8, 14, True, False, False)])
+    (6, 12, True, False, True), (7, 13, False, True, False), (8, 14, True, False, False),
+    (9, 12, "heavy", False, False)])
 def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
     """The source-sliced in-edge copy holds every in-edge once, in the slice of
     its source, each slice grouped by destination with sources ascending (the
@@ -217,10 +218,14 @@ def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
     row layout names every real position's destination."""
     monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
     ro, col = gen.rmat(scale, 16, seed=seed)
-    w = gen.edge_weights(ro, col, seed=seed) if weighted else None
+    w = None
+    if weighted:
+        # weights up to 255 are packed with the slice-local source; heavier not
+        w = gen.edge_weights(ro, col, seed=seed, hi=100_000 if weighted == "heavy" else 255)
     g = host_graph(ro, col, w, symmetrize=sym, keep_ids=keep)
     info = g.info
     assert info["xs_rows"] > 0
+    assert info["xs_packed"] == (weighted is True)
     co = g.layout("col_off").astype(np.int64)
     src = g.layout("in_src")
     n, m = len(co) - 1, len(src)
@@ -231,7 +236,24 @@ def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
     assert row_begin[8] == info["xs_rows"]
     assert np.all(edge_end <= row_begin[1:] * 64) and np.all(edge_end >= row_begin[:8] * 64)
     xsrc = g.layout("xs_src")
-    xw = g.layout("xs_w") if weighted else None
+    xw = None
+    if weighted and info["xs_packed"]:
+        # one word per position: (slice-local source << 8) | weight
+        xw = xsrc & np.uint32(255)
+        loc = (xsrc >> np.uint32(8)).astype(np.int64)
+        b_ = loc >> 10
+        xsrc = np.zeros(len(loc), np.uint32)
+        for j in range(8):
+            lo, hi = row_begin[j] * 64, row_begin[j + 1] * 64
+            gidx = b_[lo:hi] * 8 + np.where(b_[lo:hi] & 1, 7 - j, j)
+            xsrc[lo:hi] = ((gidx << 10) | (loc[lo:hi] & 1023)).astype(np.uint32)
+        with pytest.raises(W.WedgeError):
+            g.layout("xs_w")
+    elif weighted:
+        assert not info["xs_packed"]
+        xw = g.layout("xs_w")
+    else:
+        assert not info["xs_packed"]
     mask = g.layout("xs_rowmask")
     seg = g.layout("xs_rowseg").astype(np.int64)
     nz = g.layout("xs_nzdst").astype(np.int64)

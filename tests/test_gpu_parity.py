@@ -125,21 +125,25 @@ def test_mode_and_granularity_invariance(app, chunk, gate):
     parity(app, ro, col, w, s, gate=gate, chunk=chunk)
 
 
-@pytest.mark.parametrize("name", ["er_ragged", "rmat14", "grid"])
+@pytest.mark.parametrize("name", ["er_ragged", "rmat14", "grid", "rmat14_heavy"])
 @pytest.mark.parametrize("gate", ["threshold", "full"])
 @pytest.mark.parametrize("app", ["cc", "sssp"])
 def test_parity_source_sliced_full_pull(monkeypatch, app, gate, name):
     """CC and SSSP with the full pulls over the source-sliced copy (forced on
     small graphs): values and every per-iteration record equal the oracle, as
-    with the canonical pull, in the synchronous and the in-place forms."""
+    with the canonical pull, in the synchronous and the in-place forms. SSSP
+    weights up to 255 run on the packed copy (one word per in-edge), heavier
+    ones on separate source and weight arrays."""
     monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
-    ro, col = GRAPHS[name]()
-    w = gen.edge_weights(ro, col, seed=4) if app == "sssp" else None
+    heavy = name.endswith("_heavy")
+    ro, col = GRAPHS[name.replace("_heavy", "")]()
+    w = gen.edge_weights(ro, col, seed=4, hi=100_000 if heavy else 255) if app == "sssp" else None
     src = int(gen.pick_sources(ro, 1, seed=6)[0]) if app != "cc" else 0
     tr = parity(app, ro, col, w, src, gate=gate)
     assert tr is not None
     g = (W.Graph.from_csr(ro, col, symmetrize=True) if app == "cc" else W.Graph.from_csr(ro, col, w))
     assert g.info["xs_rows"] > 0
+    assert g.info["xs_packed"] == (app == "sssp" and not heavy)
     want = oracle.cc(ro, col) if app == "cc" else oracle.sssp(ro, col, w, src)
     out, _, _ = run_app(app, g, src, gate=gate, inplace=True)
     np.testing.assert_array_equal(out, want)
@@ -310,10 +314,13 @@ def test_pagerank_large_graph_lds_pull(monkeypatch, kind, sliced):
     assert torch.equal(r, r2)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
 @pytest.mark.parametrize("name", ["er_ragged", "rmat12", "rmat14", "grid", "hub"])
-def test_pagerank_source_sliced_small(monkeypatch, name):
+def test_pagerank_source_sliced_small(monkeypatch, name, weighted):
     """The sliced PageRank pull forced on small graphs (slices of a few tiles,
-    empty slices, a hub whose in-edges cross many tiles in every slice)."""
+    empty slices, a hub whose in-edges cross many tiles in every slice), over
+    the plain copy and over the packed copy of a weighted graph (PageRank
+    ignores the weights)."""
     monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
     if name == "hub":
         n = 70000
@@ -323,8 +330,9 @@ def test_pagerank_source_sliced_small(monkeypatch, name):
         ro, col = gen.csr_from_edges(n, src, dst)
     else:
         ro, col = GRAPHS[name]()
-    g = W.Graph.from_csr(ro, col)
+    g = W.Graph.from_csr(ro, col, gen.edge_weights(ro, col, seed=5) if weighted else None)
     assert g.info["xs_rows"] > 0
+    assert g.info["xs_packed"] == weighted
     if name == "hub":
         assert g.info["xs_pr_spans"] > g.info["xs_pr_short_spans"] > 0
     r, _ = W.pagerank(g, 20, 0.85)
