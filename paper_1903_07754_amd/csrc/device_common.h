@@ -423,6 +423,23 @@ struct CanonicalEdges {
     __device__ __forceinline__ uint32_t gather(const uint32_t* __restrict__ src, uint32_t u) const {
         return src[u];
     }
+    // 32-bit word wq of the current frontier bitmap (BFS)
+    __device__ __forceinline__ uint32_t fword(const uint32_t* __restrict__ f, uint32_t wq) const {
+        return f[wq];
+    }
+};
+
+// BFS full pull with the frontier bitmap's first `words` 32-bit words (the
+// bits of the lowest, highest-out-degree ids) copied into LDS.
+struct HotFrontierEdges : CanonicalEdges {
+    uint32_t words;
+    const uint32_t* __restrict__ s_bits;  // LDS
+    __device__ __forceinline__ uint32_t fword(const uint32_t* __restrict__ f, uint32_t wq) const {
+        const bool h = wq < words;
+        const uint32_t gv = f[h ? 0u : wq];
+        const uint32_t lv = s_bits[h ? wq : 0u];
+        return h ? lv : gv;
+    }
 };
 
 template <bool PACKED, bool HOT>
@@ -447,6 +464,9 @@ struct SliceEdges {
         const uint32_t gv = src[h ? 0u : u];
         const uint32_t lv = s_hot[h ? l : 0u];
         return h ? lv : gv;
+    }
+    __device__ __forceinline__ uint32_t fword(const uint32_t* __restrict__ f, uint32_t wq) const {
+        return f[wq];  // BFS does not pull over the sliced copy
     }
 };
 
@@ -503,7 +523,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const uint32_t q = need[i] ? u[i] : 0u;
-            fw[i] = reinterpret_cast<const uint32_t*>(fcur)[q >> 5] >> (q & 31);
+            fw[i] = edges.fword(reinterpret_cast<const uint32_t*>(fcur), q >> 5) >> (q & 31);
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) need[i] = need[i] & ((fw[i] & 1u) != 0u);

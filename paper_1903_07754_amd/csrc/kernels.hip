@@ -182,6 +182,57 @@ __global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_full(Graph
     pull_lanes<APP, R, true, INPLACE>(g, p, valid, iter, val, val_prev, fcur, fbits, fsum);
 }
 
+// BFS full pull: each block first copies the first `words` 32-bit words of
+// the current frontier bitmap into LDS (with out-degree-sorted ids, the bits
+// of the sources of most in-edges: on R-MAT scale 24 the first 2^19 ids
+// source about two thirds of them); the frontier tests of those sources are
+// served by LDS. Waves then stride over R-row tiles.
+template <int R>
+__global__ __launch_bounds__(kHotBlock) void k_pull_full_bfs(GraphArgs g, uint32_t iter,
+                                                             uint32_t* __restrict__ val,
+                                                             const uint64_t* __restrict__ fcur,
+                                                             uint64_t* __restrict__ fbits,
+                                                             uint32_t* __restrict__ fsum, uint32_t words) {
+    extern __shared__ uint32_t s_bits[];
+    {
+        const uint32_t* f32 = reinterpret_cast<const uint32_t*>(fcur);
+        constexpr int kPer = (int)((kHotVerts + kHotBlock - 1) / kHotBlock);
+        uint32_t t[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
+            t[k] = f32[i < words ? i : 0u];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
+            if (i < words) s_bits[i] = t[k];
+        }
+    }
+    __syncthreads();
+    HotFrontierEdges edges;
+    edges.words = words;
+    edges.s_bits = s_bits;
+    const int lane = lane_id();
+    const uint64_t wpb = kHotBlock / 64;
+    const uint64_t stride = (uint64_t)gridDim.x * wpb;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint64_t w = blockIdx.x * wpb + wib;; w += stride) {
+        const uint64_t r0 = w * R;
+        if (r0 >= g.rows) break;
+        uint32_t p[R];
+        bool valid[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const uint64_t pp = (r0 + i) * 64 + lane;
+            valid[i] = pp < g.m;
+            p[i] = (uint32_t)pp;
+        }
+        pull_lanes<kBfs, R, true, false, HotFrontierEdges>(g, p, valid, iter, val, nullptr, fcur, fbits,
+                                                           fsum, edges);
+    }
+}
+
 // Full pull over one slice of the source-sliced copy (CC and SSSP). The pull
 // over every in-edge is run slice after slice, one launch each, over the whole
 // GPU: during a launch every XCD gathers only the values of that slice's
@@ -823,11 +874,27 @@ hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t*
     }
     GraphArgs a = args_of(g);
     if (app == kBfs) {
+        // resident blocks at the full LDS size, striding over the tiles
+        const uint32_t words = (uint32_t)std::min<uint64_t>(kHotVerts, ((uint64_t)g.n + 31) / 32);
+        const size_t lds = (size_t)kHotVerts * sizeof(uint32_t);
+        int per_cu = 0;
+        uint64_t tiles = 0;
         switch (rows) {
-            case 4: k_pull_full<kBfs, 4><<<full_blocks<4>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum); break;
-            case 16: k_pull_full<kBfs, 16><<<full_blocks<16>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum); break;
-            case kPullRows: k_pull_full<kBfs, kPullRows><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum); break;
+            case 4: per_cu = resident_blocks<k_pull_full_bfs<4>>(kHotBlock, lds); tiles = (g.rows + 3) / 4; break;
+            case 16: per_cu = resident_blocks<k_pull_full_bfs<16>>(kHotBlock, lds); tiles = (g.rows + 15) / 16; break;
+            case kPullRows:
+                per_cu = resident_blocks<k_pull_full_bfs<kPullRows>>(kHotBlock, lds);
+                tiles = (g.rows + kPullRows - 1) / kPullRows;
+                break;
             default: return hipErrorInvalidValue;
+        }
+        if (per_cu <= 0) return hipErrorInvalidConfiguration;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((uint64_t)std::max(g.cus, 1) * (uint64_t)per_cu,
+                                                             (tiles + kHotBlock / 64 - 1) / (kHotBlock / 64));
+        switch (rows) {
+            case 4: k_pull_full_bfs<4><<<blocks, kHotBlock, lds, s>>>(a, iter, val, fcur, fbits, fsum, words); break;
+            case 16: k_pull_full_bfs<16><<<blocks, kHotBlock, lds, s>>>(a, iter, val, fcur, fbits, fsum, words); break;
+            default: k_pull_full_bfs<kPullRows><<<blocks, kHotBlock, lds, s>>>(a, iter, val, fcur, fbits, fsum, words); break;
         }
     } else if (app == kCc) {
         if (inplace) k_pull_full<kCc, kPullRows, true><<<full_blocks<kPullRows>(g), kBlock, 0, s>>>(a, iter, val, val_prev, fcur, fbits, fsum);
