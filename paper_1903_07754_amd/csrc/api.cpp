@@ -263,7 +263,23 @@ wedge_status ensure_workspace(wedge_graph_s* g, int log_chunk, bool need_frontie
         return dev_alloc(g, p, bytes, what);
     };
     if ((st = need((void**)&w.ctl, sizeof(Ctl), "counters")) != WEDGE_OK) return st;
-    if (!w.ctl_host) HIP_TRY(hipHostMalloc((void**)&w.ctl_host, sizeof(Ctl), hipHostMallocDefault), "pinned counters");
+    if (!w.ctl_host) {
+        // coherent: the device writes the counters straight into it
+        // the counter block, then the publishing sequence number
+        HIP_TRY(hipHostMalloc((void**)&w.ctl_host, 2 * sizeof(Ctl), hipHostMallocCoherent), "pinned counters");
+        void* dp = nullptr;
+        const hipError_t e = hipHostGetDevicePointer(&dp, w.ctl_host, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(w.ctl_host);
+            w.ctl_host = nullptr;
+            return hip_fail(e, "mapping pinned counters");
+        }
+        w.ctl_host_dev = static_cast<Ctl*>(dp);
+        w.seq_host = reinterpret_cast<volatile uint64_t*>(w.ctl_host + 1);
+        w.seq_dev = reinterpret_cast<uint64_t*>(w.ctl_host_dev + 1);
+        *w.seq_host = 0;
+        w.seq = 0;
+    }
     for (auto& e : w.ev)
         if (!e) HIP_TRY(hipEventCreate(&e), "event");
     if (need_frontier) {
@@ -413,6 +429,43 @@ struct LoopCfg {
     uint64_t chunks_of(int l) const { return (m + (1ull << l) - 1) >> l; }
 };
 
+// Enqueue the copy of the counter block to the host (complete once the stream
+// is synchronised) and, when `clear`, the zeroing of its accumulated counters.
+// Workspaces without device-writable host memory (the allocation-free entry
+// point) copy with the runtime instead.
+hipError_t read_counters(Workspace& w, bool clear, hipStream_t s) {
+    if (w.ctl_host_dev) return launch_publish_ctl(w.ctl, w.ctl_host_dev, clear, w.seq_dev, ++w.seq, s);
+    hipError_t e = hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && clear) e = launch_publish_ctl(w.ctl, nullptr, true, nullptr, 0, s);
+    return e;
+}
+
+// Wait until the counters enqueued by read_counters are in host memory. With
+// the publishing kernel the host polls the sequence number it stores last (a
+// stream synchronisation wakes the host some tens of microseconds later);
+// every few thousand polls the stream is queried, so a failed launch ends the
+// wait with its error. Without it, the stream is synchronised.
+hipError_t wait_counters(Workspace& w, hipStream_t s) {
+    if (!w.seq_host) return hipStreamSynchronize(s);
+    for (uint64_t polls = 1;; ++polls) {
+        if (*w.seq_host == w.seq) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return hipSuccess;
+        }
+        if ((polls & 4095u) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return e;
+            // the stream has drained: the sequence number must be there now
+            if (*w.seq_host == w.seq) {
+                std::atomic_thread_fence(std::memory_order_acquire);
+                return hipSuccess;
+            }
+            return hipErrorUnknown;
+        }
+    }
+}
+
 template <class Pull, class Fin>
 wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const LoopCfg& c,
                      hipStream_t s, wedge_stats& local, double t0, wedge_stats* stats, Pull pull,
@@ -421,8 +474,11 @@ wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const L
     if (c.learned)
         HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, c.margin, w.ctl, (double)d.n, (double)d.m, c.thr, (uint32_t)c.lc,
                                  c.ticks_per_us, c.app, s), "gate inference");
-    HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
-    HIP_TRY(hipStreamSynchronize(s), "initialising run");
+    // the counters come back through host memory the device writes; the
+    // publishing kernel also clears them for the next iteration (the learned
+    // gate's stamp kernel clears them instead)
+    HIP_TRY(read_counters(w, !c.learned, s), "reading counters");
+    HIP_TRY(wait_counters(w, s), "initialising run");
     uint64_t fcount = w.ctl_host->ftotal;               // |F_k|
     uint64_t flisted = w.ctl_host->fnext >> kDegBits;   // of which have out-edges
     uint64_t active = w.ctl_host->fnext & kDegMask;     // A_k
@@ -453,7 +509,6 @@ wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const L
         Range iter_range(mode == kModeWedge ? "wedge iteration"
                          : mode == kModePush ? "push iteration" : "full-pull iteration");
         if (c.learned) HIP_TRY(launch_gate_stamp(w.ctl, s), "clearing counters");
-        else HIP_TRY(hipMemsetAsync(w.ctl, 0, 24, s), "clearing counters");
         if (c.time_iter) HIP_TRY(hipEventRecord(w.ev[2], s), "event");
         uint64_t maxk = 0;
         if (wedge_mode) {
@@ -475,9 +530,13 @@ wedge_status iterate(wedge_graph_t g, Workspace& w, const wedge_opts& o, const L
         if (c.learned)
             HIP_TRY(launch_mlp_infer(c.P, c.members, c.lo, c.hi, c.margin, w.ctl, (double)d.n, (double)d.m, c.thr,
                                      (uint32_t)c.lc, c.ticks_per_us, c.app, s), "gate inference");
-        HIP_TRY(hipMemcpyAsync(w.ctl_host, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "reading counters");
-        HIP_TRY(hipStreamSynchronize(s), "iteration");
+        HIP_TRY(read_counters(w, !c.learned, s), "reading counters");
+        HIP_TRY(wait_counters(w, s), "iteration");
         float pms = 0.f, ims = 0.f;
+        // the events precede the publishing kernel: done on the device, and
+        // waited for here so that the runtime has taken their completion
+        if (c.time_pull) HIP_TRY(hipEventSynchronize(w.ev[1]), "event");
+        if (c.time_iter) HIP_TRY(hipEventSynchronize(w.ev[3]), "event");
         if (c.time_pull) HIP_TRY(hipEventElapsedTime(&pms, w.ev[0], w.ev[1]), "event time");
         if (c.time_iter) HIP_TRY(hipEventElapsedTime(&ims, w.ev[2], w.ev[3]), "event time");
         local.pull_ms += pms;
@@ -566,19 +625,23 @@ wedge_status prepare_gate(wedge_graph_t g, const wedge_opts& o, LoopCfg* c) {
     return WEDGE_OK;
 }
 
-// Clears both frontier bitmaps (and the Wedge bitmap when it may be used).
+// Clears both frontier bitmaps (and the Wedge bitmap when it may be used)
+// and the counter block, in one launch.
 wedge_status clear_bitmaps(wedge_graph_t g, const LoopCfg& c, hipStream_t s) {
     const Workspace& w = g->ws;
     const uint64_t fwords = ((uint64_t)g->dev.n + 63) / 64;
-    HIP_TRY(hipMemsetAsync(w.fbits, 0, fwords * 8, s), "clearing frontier bitmap");
-    HIP_TRY(hipMemsetAsync(w.fcur, 0, fwords * 8, s), "clearing frontier bitmap");
-    HIP_TRY(hipMemsetAsync(w.fsum, 0, sum_flags(g->dev.n) * 4, s), "clearing frontier summary");
-    HIP_TRY(hipMemsetAsync(w.csum, 0, sum_flags(g->dev.n) * 4, s), "clearing frontier summary");
+    ClearList l;
+    l.add(w.fbits, fwords * 8);
+    l.add(w.fcur, fwords * 8);
+    l.add(w.fsum, sum_flags(g->dev.n) * 4);
+    l.add(w.csum, sum_flags(g->dev.n) * 4);
+    l.add(w.ctl, sizeof(Ctl));
     if (wedge_gate_used(c.gate)) {
         const uint64_t words = (c.chunks_of(c.min_lc()) + 63) / 64;
-        HIP_TRY(hipMemsetAsync(w.wbits, 0, words * 8, s), "clearing Wedge bitmap");
-        HIP_TRY(hipMemsetAsync(w.wsum, 0, sum_flags(words * 64) * 4, s), "clearing Wedge summary");
+        l.add(w.wbits, words * 8);
+        l.add(w.wsum, sum_flags(words * 64) * 4);
     }
+    HIP_TRY(launch_clear(l, s), "clearing bitmaps and counters");
     return WEDGE_OK;
 }
 
@@ -624,7 +687,6 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     uint32_t* vprev = app == kBfs ? nullptr : w.val_prev;
     c.val = val;
     c.val_prev = vprev;
-    HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
     if (app == kCc) {
         HIP_TRY(launch_seed_all(d.n, d.m, d.row_off, d.inv, val, w.val_prev, w.flist[0], w.degpre[0],
                                 w.fcur, w.csum, w.ctl, s), "seeding CC");
@@ -1021,7 +1083,6 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
         if ((st = clear_bitmaps(g, c, s)) != WEDGE_OK) return st;
         uint32_t* val = d.inv ? w.val : out;
         c.val = val;
-        HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
         HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
         HIP_TRY(launch_roots_seed(w.roots, count, val, w.fbits, w.fsum, s), "seeding roots");
         HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr,
@@ -1081,10 +1142,11 @@ wedge_status run_multisource(wedge_graph_t g, const uint32_t* srcs, uint32_t cou
         st = run_persistent(g, true, count, out, o, c, s, local);
     } else {
         if ((st = clear_bitmaps(g, c, s)) != WEDGE_OK) return st;
-        HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), s), "clearing counters");
-        HIP_TRY(hipMemsetAsync(w.visited, 0, (size_t)d.n * 8, s), "clearing masks");
-        HIP_TRY(hipMemsetAsync(w.masks[0], 0, (size_t)d.n * 8, s), "clearing masks");
-        HIP_TRY(hipMemsetAsync(w.masks[1], 0, (size_t)d.n * 8, s), "clearing masks");
+        ClearList ml;
+        ml.add(w.visited, (size_t)d.n * 8);
+        ml.add(w.masks[0], (size_t)d.n * 8);
+        ml.add(w.masks[1], (size_t)d.n * 8);
+        HIP_TRY(launch_clear(ml, s), "clearing masks");
         HIP_TRY(launch_fill_u32_kernel(w.lev, (uint64_t)d.n * count, kInf, s), "initialising levels");
         HIP_TRY(launch_ms_seed(w.roots, count, w.masks[0], w.fbits, w.fsum, s), "seeding sources");
         HIP_TRY(launch_ms_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, w.fcur,

@@ -27,6 +27,40 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t count, uint32_t va
         p[i] = value;
 }
 
+__global__ void k_clear(ClearList l) {
+    const int r = blockIdx.y;
+    uint32_t* p = l.p[r];
+    const uint64_t n = l.words[r];
+    const uint64_t n4 = n / 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint4* p4 = reinterpret_cast<uint4*>(p);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        p4[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+// One wave: lanes 0..15 copy the 64-byte counter block to host memory, then
+// (clear) lanes 0..5 zero fnext, marked and ftotal. The system-scope fence
+// waits until the wave's stores are visible to the host; only then does lane
+// 0 store the sequence number the host polls for.
+__global__ void k_publish_ctl(Ctl* __restrict__ ctl, Ctl* __restrict__ host, int clear,
+                              uint64_t* __restrict__ seq_host, uint64_t seq) {
+    static_assert(sizeof(Ctl) == 64, "64-byte counter block");
+    const uint32_t lane = threadIdx.x;
+    uint32_t* c = reinterpret_cast<uint32_t*>(ctl);
+    uint32_t* h = reinterpret_cast<uint32_t*>(host);
+    if (lane < 16) {
+        const uint32_t v = c[lane];
+        if (h) h[lane] = v;
+        if (clear && lane < 6) c[lane] = 0u;
+    }
+    __threadfence_system();
+    if (seq_host && lane == 0) {
+        *reinterpret_cast<volatile uint64_t*>(seq_host) = seq;
+        __threadfence_system();
+    }
+}
+
 __global__ void k_iota_u32(uint32_t* __restrict__ p, uint32_t count) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
         p[i] = i;
@@ -700,6 +734,25 @@ uint32_t grid_for(uint64_t threads, uint32_t cap = 1u << 20) {
 }  // namespace
 
 // ------------------------------------------------------------- launchers
+
+hipError_t launch_clear(const ClearList& l, hipStream_t s) {
+    if (!l.count) return hipSuccess;
+    uint64_t most = 0;
+    for (int i = 0; i < l.count; ++i) {
+        if (reinterpret_cast<uintptr_t>(l.p[i]) & 15u) return hipErrorInvalidValue;
+        most = std::max(most, l.words[i]);
+    }
+    const uint64_t blocks = std::min<uint64_t>(2048, std::max<uint64_t>(1, (most / 4 + kBlock - 1) / kBlock));
+    k_clear<<<dim3((uint32_t)blocks, (uint32_t)l.count), kBlock, 0, s>>>(l);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish_ctl(Ctl* ctl, Ctl* host_dev, bool clear, uint64_t* seq_dev, uint64_t seq,
+                              hipStream_t s) {
+    if (!ctl) return hipErrorInvalidValue;
+    k_publish_ctl<<<1, 64, 0, s>>>(ctl, host_dev, clear ? 1 : 0, seq_dev, seq);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s) {
     if (!count) return hipSuccess;

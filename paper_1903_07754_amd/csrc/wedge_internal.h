@@ -300,7 +300,14 @@ struct Workspace {
     uint32_t* chunks = nullptr;    // chunk list
     uint64_t chunks_cap = 0;
     Ctl* ctl = nullptr;            // device counters
-    Ctl* ctl_host = nullptr;       // pinned mirror
+    Ctl* ctl_host = nullptr;       // pinned mirror (host address)
+    Ctl* ctl_host_dev = nullptr;   // its device address (written by launch_publish_ctl)
+    // sequence number the publishing kernel writes after the counters (host
+    // memory, in the same allocation): the host waits for it instead of the
+    // stream
+    volatile uint64_t* seq_host = nullptr;
+    uint64_t* seq_dev = nullptr;
+    uint64_t seq = 0;
     // PageRank
     float* pr_sum = nullptr;       // n
     float* pr_contrib = nullptr;   // n
@@ -385,6 +392,25 @@ wedge_status model_to_device(wedge_model_s* m);
 // ------------------------------------------------------ kernel launchers
 // (kernels.hip). Every launcher enqueues on `s` and returns the launch status.
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
+// Zero up to kClearMax device regions (16-byte aligned starts, sizes in
+// 4-byte words) in one launch: one kernel instead of a runtime fill per
+// buffer.
+constexpr int kClearMax = 8;
+struct ClearList {
+    uint32_t* p[kClearMax] = {};
+    uint64_t words[kClearMax] = {};
+    int count = 0;
+    void add(void* ptr, uint64_t bytes) {
+        if (ptr && bytes) { p[count] = static_cast<uint32_t*>(ptr); words[count] = bytes / 4; ++count; }
+    }
+};
+hipError_t launch_clear(const ClearList& l, hipStream_t s);
+// Copy the counter block into host memory the device can write (host_dev:
+// its device address; null: no copy), when `clear` zero the three
+// accumulated counters for the next iteration, then (seq_dev non-null) store
+// `seq` into host memory once the copy is visible to the host.
+hipError_t launch_publish_ctl(Ctl* ctl, Ctl* host_dev, bool clear, uint64_t* seq_dev, uint64_t seq,
+                              hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, uint32_t count, hipStream_t s);
 // Summaries (fsum of the next-frontier bitmap, csum of the current one, wsum of
 // the Wedge bitmap): one 32-bit flag per 4096 bits, set by every writer of a
