@@ -150,6 +150,53 @@ def test_parity_source_sliced_full_pull(monkeypatch, app, gate, name):
     g.close()
 
 
+@pytest.mark.parametrize("gate", ["threshold", "wedge", "full"])
+@pytest.mark.parametrize("app", ["bfs", "sssp", "cc"])
+def test_per_iteration_frontier_sets(app, gate):
+    """The frontier of every iteration as a set, not only its size: a run cut
+    off after k iterations (max_iters = k) leaves the values of iteration k in
+    the caller's buffer, and the vertices whose value changed in iteration k-1
+    must be exactly the oracle's frontier F_k (Background, Push vs. Pull: a
+    vertex is active when its value was updated)."""
+    ro, col = gen.rmat(12, 16, seed=13)
+    n = len(ro) - 1
+    w = gen.edge_weights(ro, col, seed=6) if app == "sssp" else None
+    src = int(gen.pick_sources(ro, 1, seed=7)[0])
+    if app == "cc":
+        gro, gcol = oracle.symmetrize(ro, col)
+        g = W.Graph.from_csr(ro, col, symmetrize=True, keep_ids=True)
+        ref = oracle.pull_engine("cc", gro, gcol, keep_frontiers=True)
+        prev = np.arange(n, dtype=np.uint32)
+    else:
+        g = W.Graph.from_csr(ro, col, w, keep_ids=True)
+        ref = oracle.pull_engine(app, ro, col, w, src, keep_frontiers=True)
+        prev = np.full(n, 0xFFFFFFFF, np.uint32)
+        prev[src] = 0
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    run = {"bfs": lambda k: W.bfs(g, src, out=out, gate=gate, max_iters=k),
+           "sssp": lambda k: W.sssp(g, src, out=out, gate=gate, max_iters=k),
+           "cc": lambda k: W.cc(g, out=out, gate=gate, max_iters=k)}[app]
+    print(f"  [{app} gate={gate} iterations={ref.iters}]", flush=True)
+    for k in range(1, ref.iters + 1):
+        try:
+            run(k)
+            converged = True
+        except W.WedgeError as e:
+            assert e.name == "WEDGE_ERR_NOT_CONVERGED"
+            converged = False
+        torch.cuda.synchronize()
+        cur = W.u32(out).copy()
+        changed = cur != prev
+        if k < ref.iters:
+            assert not converged, k
+            np.testing.assert_array_equal(changed, ref.frontiers[k].astype(bool), err_msg=f"F_{k}")
+        else:
+            assert converged and not changed.any()
+            np.testing.assert_array_equal(cur, ref.values)
+        prev = cur
+    g.close()
+
+
 def test_theta_extremes():
     ro, col = gen.rmat(12, 8, seed=31)
     w = gen.edge_weights(ro, col, seed=8)
