@@ -75,7 +75,7 @@ def slice_launches(g):
     import numpy as np
     if not g.info["xs_rows"]:
         return 1
-    b = g.layout("xs_bounds")[:9].astype(np.int64)
+    b = g.layout("xs_bounds")[:g.info["xs_slices"] + 1].astype(np.int64)
     return int(np.count_nonzero(np.diff(b)))
 
 

@@ -160,6 +160,7 @@ typedef struct {
     uint64_t xs_pr_span_pairs;  /* crossing segments over all of them */
     uint32_t xs_packed;    /* 1: each sliced-copy word is (slice-local source << 8) | weight
                               (weighted graphs with weights <= 255 and n <= 2^27) */
+    uint32_t xs_slices;    /* source slices S of the sliced copy (a power of two, 8..64; 0: none) */
 } wedge_graph_info;
 
 wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info);
@@ -180,14 +181,14 @@ typedef enum {
     WEDGE_LAYOUT_XS_SRC = 10,     /* uint32[64*xs_rows] sources, or packed words when
                                      xs_packed (the slice-local id i of slice j's source is
                                      its index among the ids of the slice's 1024-id groups,
-                                     groups dealt to slices in the order 0..7, 7..0, ...);
+                                     groups dealt to the S slices in the order 0..S-1, S-1..0, ...);
                                      padding positions hold 0 */
     WEDGE_LAYOUT_XS_W = 11,       /* uint32[64*xs_rows] weights (weighted, not packed) */
     WEDGE_LAYOUT_XS_ROWMASK = 12, /* uint64[xs_rows] */
     WEDGE_LAYOUT_XS_ROWSEG = 13,  /* uint32[xs_rows] */
     WEDGE_LAYOUT_XS_NZDST = 14,   /* uint32[xs_segments] */
-    WEDGE_LAYOUT_XS_BOUNDS = 15,  /* uint32[17]: first row of slices 0..8, then the end
-                                     position of slices 0..7 */
+    WEDGE_LAYOUT_XS_BOUNDS = 15,  /* uint32[2*S+1]: first row of slices 0..S, then the end
+                                     position of slices 0..S-1 (S = xs_slices) */
     /* PageRank fix-up lists of the sliced copy (empty when xs_pr_spans is 0): */
     WEDGE_LAYOUT_XS_PR_SPAN_V = 16,     /* uint32[xs_pr_spans] destination */
     WEDGE_LAYOUT_XS_PR_SPAN_OFF = 17,   /* uint32[xs_pr_spans+1] first pair of each */

@@ -49,7 +49,8 @@ class GraphInfo(C.Structure):
                 ("pr_short_spans", C.c_uint64), ("relabeled", C.c_uint32),
                 ("xs_rows", C.c_uint64), ("xs_segments", C.c_uint64),
                 ("xs_pr_spans", C.c_uint64), ("xs_pr_short_spans", C.c_uint64),
-                ("xs_pr_span_pairs", C.c_uint64), ("xs_packed", C.c_uint32)]
+                ("xs_pr_span_pairs", C.c_uint64), ("xs_packed", C.c_uint32),
+                ("xs_slices", C.c_uint32)]
 
 
 class IterRecord(C.Structure):
@@ -250,7 +251,7 @@ class Graph:
                  "nzdst": info["nonempty"], "pr_spans": 3 * info["pr_spans"],
                  "perm": self.n, "xs_src": 64 * info["xs_rows"], "xs_w": 64 * info["xs_rows"],
                  "xs_rowmask": info["xs_rows"], "xs_rowseg": info["xs_rows"],
-                 "xs_nzdst": info["xs_segments"], "xs_bounds": 17,
+                 "xs_nzdst": info["xs_segments"], "xs_bounds": 2 * info["xs_slices"] + 1,
                  "xs_pr_span_v": info["xs_pr_spans"],
                  "xs_pr_span_off": info["xs_pr_spans"] + 1 if info["xs_pr_spans"] else 0,
                  "xs_pr_span_tiles": 2 * info["xs_pr_span_pairs"]}

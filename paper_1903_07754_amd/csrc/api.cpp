@@ -191,8 +191,9 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     d.nonempty = (uint32_t)L.nzdst.size();
     d.nspans = L.spans.size() / 3;
     d.short_spans = L.short_spans;
-    if (!L.xs_rowmask.empty() && L.xs_row_begin[kXcdSlices]) {
-        d.xs_rows = L.xs_row_begin[kXcdSlices];
+    if (!L.xs_rowmask.empty() && L.xs_row_begin[1u << L.xs_lg]) {
+        d.xs_lg = L.xs_lg;
+        d.xs_rows = L.xs_row_begin[1u << L.xs_lg];
         d.xs_positions = d.xs_rows * 64;
         d.xs_segments = L.xs_nzdst.size();
         std::memcpy(d.xs_row_begin, L.xs_row_begin, sizeof d.xs_row_begin);
@@ -1237,8 +1238,8 @@ wedge_status wedge_graph_get_info(wedge_graph_t g, wedge_graph_info* info) {
     info->device_bytes = g->device_bytes;
     info->pr_short_spans = g->dev.short_spans;
     info->relabeled = g->perm_host.empty() ? 0u : 1u;
-    info->xs_rows = g->host_only ? (g->host.xs_rowmask.empty() ? 0 : g->host.xs_row_begin[kXcdSlices])
-                                 : g->dev.xs_rows;
+    info->xs_rows = g->dev.xs_rows;
+    info->xs_slices = g->dev.xs_rows ? (1u << g->dev.xs_lg) : 0u;
     info->xs_segments = g->host_only ? g->host.xs_nzdst.size() : g->dev.xs_segments;
     info->xs_pr_spans = g->dev.xs_pspans;
     info->xs_pr_short_spans = g->dev.xs_pspan_short;
@@ -1276,15 +1277,17 @@ wedge_status wedge_graph_layout(wedge_graph_t g, wedge_layout_array which, void*
         case WEDGE_LAYOUT_XS_PR_SPAN_OFF:
         case WEDGE_LAYOUT_XS_PR_SPAN_TILES:
         case WEDGE_LAYOUT_XS_BOUNDS: {
-            const uint64_t xr = g->host_only ? (L.xs_rowmask.empty() ? 0 : L.xs_row_begin[kXcdSlices]) : d.xs_rows;
+            const uint64_t xr = d.xs_rows;
             const uint64_t xseg = g->host_only ? L.xs_nzdst.size() : d.xs_segments;
             if (!xr) return fail(WEDGE_ERR_UNSUPPORTED, "graph has no source-sliced in-edge copy");
             if (which == WEDGE_LAYOUT_XS_BOUNDS) {
-                uint32_t b[2 * kXcdSlices + 1];
-                for (int j = 0; j <= kXcdSlices; ++j) b[j] = g->host_only ? L.xs_row_begin[j] : d.xs_row_begin[j];
-                for (int j = 0; j < kXcdSlices; ++j) b[kXcdSlices + 1 + j] = g->host_only ? L.xs_edge_end[j] : d.xs_edge_end[j];
-                if (bytes != sizeof b) return fail(WEDGE_ERR_INVALID_ARG, "bytes does not match the array size");
-                std::memcpy(dst, b, sizeof b);
+                const int S = 1 << d.xs_lg;
+                uint32_t b[2 * kMaxSlices + 1];
+                for (int j = 0; j <= S; ++j) b[j] = d.xs_row_begin[j];
+                for (int j = 0; j < S; ++j) b[S + 1 + j] = d.xs_edge_end[j];
+                const uint64_t size = (uint64_t)(2 * S + 1) * 4;
+                if (bytes != size) return fail(WEDGE_ERR_INVALID_ARG, "bytes does not match the array size");
+                std::memcpy(dst, b, size);
                 return WEDGE_OK;
             }
             if (which == WEDGE_LAYOUT_XS_W && !g->weighted) return fail(WEDGE_ERR_NO_WEIGHTS, "graph has no weights");

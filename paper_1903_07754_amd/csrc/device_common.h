@@ -446,16 +446,17 @@ template <bool PACKED, bool HOT>
 struct SliceEdges {
     static constexpr bool kPacked = PACKED;
     uint32_t slice;
+    uint32_t lg;                        // log2 of the number of slices
     uint32_t n;
     uint32_t hot;                       // values of slice-local ids [0, hot) are in s_hot
     const uint32_t* __restrict__ s_hot;  // LDS
     __device__ __forceinline__ uint32_t gather(const uint32_t* __restrict__ src, uint32_t word) const {
-        const uint32_t l = PACKED ? (word >> 8) : xcd_slice_local(word);
+        const uint32_t l = PACKED ? (word >> 8) : xcd_slice_local(word, lg);
         uint32_t u = word;
         if (PACKED) {
             // a lane without an edge holds another slice's word: keep its
             // (masked) read inside the array
-            u = xcd_slice_global(l, slice);
+            u = xcd_slice_global(l, slice, lg);
             u = u < n ? u : 0u;
         }
         if (!HOT) return src[u];

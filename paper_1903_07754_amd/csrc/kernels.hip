@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kHotBlock) void k_pull_full_bfs(GraphArgs g, uint32
 // (slice-local source << 8) | weight.
 template <int APP, int R, bool INPLACE, bool PACKED>
 __global__ __launch_bounds__(kHotBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_pull_slice(
-    GraphArgs g, uint32_t slice, uint32_t row_begin, uint32_t row_end, uint32_t edge_end, uint32_t iter,
+    GraphArgs g, uint32_t slice, uint32_t lg, uint32_t row_begin, uint32_t row_end, uint32_t edge_end, uint32_t iter,
     uint32_t* __restrict__ val, const uint32_t* __restrict__ val_prev,
     const uint64_t* __restrict__ fcur, uint64_t* __restrict__ fbits, uint32_t* __restrict__ fsum,
     uint32_t hot) {
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kHotBlock) __attribute__((amdgpu_waves_per_eu(6))) 
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
-            const uint32_t gi = xcd_slice_global(i < hot ? i : 0u, slice);
+            const uint32_t gi = xcd_slice_global(i < hot ? i : 0u, slice, lg);
             t[k] = val_prev[gi < g.n ? gi : 0u];
         }
 #pragma unroll
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kHotBlock) __attribute__((amdgpu_waves_per_eu(6))) 
         }
         __syncthreads();
     }
-    const SliceEdges<PACKED, !INPLACE> edges{slice, g.n, INPLACE ? 0u : hot, s_val};
+    const SliceEdges<PACKED, !INPLACE> edges{slice, lg, g.n, INPLACE ? 0u : hot, s_val};
     const int lane = lane_id();
     const uint64_t wpb = kHotBlock / 64;
     const uint64_t stride = (uint64_t)gridDim.x * wpb;
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_hot(GraphArgs g, const fl
 // the L2. Segments crossing a tile boundary leave their parts in head/tail;
 // k_pr_fixup_xs adds them afterwards.
 template <int R, bool PACKED>
-__global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32_t slice,
+__global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32_t slice, uint32_t lg,
                                                              uint64_t tile_begin, uint64_t tile_end,
                                                              const float* __restrict__ contrib,
                                                              float* __restrict__ sum,
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
-            const uint32_t gi = xcd_slice_global(i < hot ? i : 0u, slice);
+            const uint32_t gi = xcd_slice_global(i < hot ? i : 0u, slice, lg);
             t[k] = contrib[gi < g.n ? gi : 0u];
         }
 #pragma unroll
@@ -548,11 +548,11 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32
         pr_tile<R, kHotBatch, true>(
             g, t,
             [&](uint32_t word) {
-                const uint32_t l = PACKED ? (word >> 8) : xcd_slice_local(word);
+                const uint32_t l = PACKED ? (word >> 8) : xcd_slice_local(word, lg);
                 uint32_t u = word;
                 if (PACKED) {
                     // a lane without an edge may hold another slice's word
-                    u = xcd_slice_global(l, slice);
+                    u = xcd_slice_global(l, slice, lg);
                     u = u < g.n ? u : 0u;
                 }
                 const bool h = l < hot;
@@ -869,11 +869,11 @@ int slice_pull_resident(int app, bool inplace, bool packed, size_t lds) {
 
 // How many of slice j's first kHotVerts slice-local ids are vertices (the
 // slice's groups in order; only the graph's last group can be partial).
-uint32_t slice_hot_count(uint32_t n, uint32_t j) {
+uint32_t slice_hot_count(uint32_t n, uint32_t j, uint32_t lg) {
     constexpr uint32_t kGroup = 1u << kXcdGroupShift;
     uint32_t hot = 0;
     for (uint32_t i = 0; i < kHotVerts; i += kGroup) {
-        const uint64_t first = xcd_slice_global(i, j);
+        const uint64_t first = xcd_slice_global(i, j, lg);
         if (first >= n) break;
         hot = i + (uint32_t)std::min<uint64_t>(kGroup, n - first);
     }
@@ -898,16 +898,16 @@ hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t*
         const size_t lds = inplace ? 0 : (size_t)kHotVerts * sizeof(uint32_t);
         const int per_cu = slice_pull_resident(app, inplace, g.xs_packed, lds);
         if (per_cu <= 0) return hipErrorInvalidConfiguration;
-        for (int j = 0; j < kXcdSlices; ++j) {
+        for (int j = 0; j < (1 << g.xs_lg); ++j) {
             const uint32_t rb = g.xs_row_begin[j], re = g.xs_row_begin[j + 1];
             if (re == rb) continue;
             const uint64_t waves = ((uint64_t)(re - rb) + kPullRows - 1) / kPullRows;
             const uint32_t blocks = (uint32_t)std::min<uint64_t>(
                 (uint64_t)std::max(g.cus, 1) * (uint64_t)per_cu, (waves + kHotBlock / 64 - 1) / (kHotBlock / 64));
             const uint32_t ee = g.xs_edge_end[j];
-            const uint32_t hot = inplace ? 0u : slice_hot_count(g.n, (uint32_t)j);
+            const uint32_t hot = inplace ? 0u : slice_hot_count(g.n, (uint32_t)j, g.xs_lg);
 #define WEDGE_SLICE_LAUNCH(A, IP, PK)                                                              \
-    k_pull_slice<A, kPullRows, IP, PK><<<blocks, kHotBlock, lds, s>>>(xa, (uint32_t)j, rb, re, ee, iter, \
+    k_pull_slice<A, kPullRows, IP, PK><<<blocks, kHotBlock, lds, s>>>(xa, (uint32_t)j, g.xs_lg, rb, re, ee, iter, \
                                                                       val, val_prev, fcur, fbits, fsum, hot)
             if (app == kCc) {
                 if (inplace) WEDGE_SLICE_LAUNCH(kCc, true, false);
@@ -1029,22 +1029,22 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
         const int per_cu = g.xs_packed ? resident_blocks<k_pr_pull_slice<kPrTileRows, true>>(kHotBlock, lds)
                                        : resident_blocks<k_pr_pull_slice<kPrTileRows, false>>(kHotBlock, lds);
         if (per_cu <= 0) return hipErrorInvalidConfiguration;
-        for (int j = 0; j < kXcdSlices; ++j) {
+        for (int j = 0; j < (1 << g.xs_lg); ++j) {
             const uint64_t rb = g.xs_row_begin[j], re = g.xs_row_begin[j + 1];
             if (re == rb) continue;
             GraphArgs xa = xs_args_of(g);
             xa.m = g.xs_edge_end[j];  // positions past the slice's last in-edge are idle
             xa.rows = (uint32_t)re;
-            const uint32_t hot = slice_hot_count(g.n, (uint32_t)j);
+            const uint32_t hot = slice_hot_count(g.n, (uint32_t)j, g.xs_lg);
             const uint64_t tb = rb / kPrTileRows, te = re / kPrTileRows;
             const uint64_t blocks = std::min<uint64_t>((uint64_t)std::max(cus, 1) * (uint64_t)per_cu,
                                                        (te - tb + kHotBlock / 64 - 1) / (kHotBlock / 64));
             if (g.xs_packed)
                 k_pr_pull_slice<kPrTileRows, true><<<(uint32_t)blocks, kHotBlock, lds, s>>>(
-                    xa, (uint32_t)j, tb, te, contrib, sum, head, tail, hot);
+                    xa, (uint32_t)j, g.xs_lg, tb, te, contrib, sum, head, tail, hot);
             else
                 k_pr_pull_slice<kPrTileRows, false><<<(uint32_t)blocks, kHotBlock, lds, s>>>(
-                    xa, (uint32_t)j, tb, te, contrib, sum, head, tail, hot);
+                    xa, (uint32_t)j, g.xs_lg, tb, te, contrib, sum, head, tail, hot);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

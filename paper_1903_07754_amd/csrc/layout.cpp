@@ -293,6 +293,18 @@ wedge_status build_layout_from_csr(uint32_t n, uint64_t m, const uint64_t* row_o
     return WEDGE_OK;
 }
 
+uint32_t xs_slices_lg(uint64_t sources) {
+    const char* e = std::getenv("WEDGE_XS_SLICES");
+    if (e && *e) {
+        const long v = std::strtol(e, nullptr, 10);
+        for (uint32_t lg = 3; (1 << lg) <= kMaxSlices; ++lg)
+            if (v == (1 << lg)) return lg;
+    }
+    uint32_t lg = 3;
+    while ((1 << lg) < kMaxSlices && sources * 4 > (kSliceValueBytes << lg)) ++lg;
+    return lg;
+}
+
 void build_xcd_slices(HostLayout* L) {
     const uint32_t n = L->n;
     const bool weighted = !L->in_w.empty();
@@ -300,10 +312,15 @@ void build_xcd_slices(HostLayout* L) {
     // store one word per in-edge instead of two
     const bool packed = weighted && L->max_w <= kXsPackMaxW && (uint64_t)n <= kXsPackMaxN;
     L->xs_packed = packed;
+    uint64_t sources = 0;
+    for (uint32_t v = 0; v < n; ++v) sources += L->row_off[v + 1] > L->row_off[v];
+    const uint32_t lg = xs_slices_lg(sources);
+    const int S = 1 << lg;
+    L->xs_lg = lg;
     // per thread range of destinations: edge counts per slice
     const unsigned T = std::max(1u, std::min<unsigned>(host_threads(), 64));
     const uint64_t step = ((uint64_t)n + T - 1) / T;
-    std::vector<uint64_t> cnt((size_t)T * kXcdSlices, 0);
+    std::vector<uint64_t> cnt((size_t)T * S, 0);
     auto for_ranges = [&](auto&& f) {
         std::vector<std::thread> pool;
         for (unsigned t = 0; t < T; ++t) {
@@ -314,41 +331,41 @@ void build_xcd_slices(HostLayout* L) {
         for (auto& th : pool) th.join();
     };
     for_ranges([&](unsigned t, uint64_t vb, uint64_t ve) {
-        uint64_t* c = &cnt[(size_t)t * kXcdSlices];
-        for (uint64_t p = L->col_off[vb]; p < L->col_off[ve]; ++p) c[xcd_slice_of(L->in_src[p])]++;
+        uint64_t* c = &cnt[(size_t)t * S];
+        for (uint64_t p = L->col_off[vb]; p < L->col_off[ve]; ++p) c[xcd_slice_of(L->in_src[p], lg)]++;
     });
     // slice starts are aligned to PageRank tiles (kPrTileRows rows), so no tile
     // straddles two slices; inside a slice, thread ranges follow in order
     const uint64_t align = 64ull * kPrTileRows;
-    std::vector<uint64_t> base((size_t)T * kXcdSlices, 0);
+    std::vector<uint64_t> base((size_t)T * S, 0);
     uint64_t at = 0;
-    for (int j = 0; j < kXcdSlices; ++j) {
+    for (int j = 0; j < S; ++j) {
         at = (at + align - 1) & ~(align - 1);
         L->xs_row_begin[j] = (uint32_t)(at / 64);
         for (unsigned t = 0; t < T; ++t) {
-            base[(size_t)t * kXcdSlices + j] = at;
-            at += cnt[(size_t)t * kXcdSlices + j];
+            base[(size_t)t * S + j] = at;
+            at += cnt[(size_t)t * S + j];
         }
         L->xs_edge_end[j] = (uint32_t)at;
     }
     const uint64_t total = (at + align - 1) & ~(align - 1);
     const uint64_t rows = total / 64;
-    L->xs_row_begin[kXcdSlices] = (uint32_t)rows;
+    L->xs_row_begin[S] = (uint32_t)rows;
     L->xs_src.assign(total ? total : 1, 0);
     if (weighted && !packed) L->xs_w.assign(total ? total : 1, 0);
     // destination of every position (padding: none), for the row layout below
     std::vector<uint32_t> dst(total ? total : 1, 0xFFFFFFFFu);
     for_ranges([&](unsigned t, uint64_t vb, uint64_t ve) {
-        uint64_t cur[kXcdSlices];
-        for (int j = 0; j < kXcdSlices; ++j) cur[j] = base[(size_t)t * kXcdSlices + j];
+        uint64_t cur[kMaxSlices];
+        for (int j = 0; j < S; ++j) cur[j] = base[(size_t)t * S + j];
         // destinations ascend, and each destination's sources ascend, so every
         // slice keeps the canonical (destination, source) order
         for (uint64_t v = vb; v < ve; ++v)
             for (uint64_t p = L->col_off[v]; p < L->col_off[v + 1]; ++p) {
                 const uint32_t u = L->in_src[p];
-                const uint64_t q = cur[xcd_slice_of(u)]++;
+                const uint64_t q = cur[xcd_slice_of(u, lg)]++;
                 if (packed) {
-                    L->xs_src[q] = (xcd_slice_local(u) << 8) | L->in_w[p];
+                    L->xs_src[q] = (xcd_slice_local(u, lg) << 8) | L->in_w[p];
                 } else {
                     L->xs_src[q] = u;
                     if (weighted) L->xs_w[q] = L->in_w[p];
@@ -360,6 +377,9 @@ void build_xcd_slices(HostLayout* L) {
     // destination changes; padding positions start nothing
     L->xs_rowmask.assign(rows ? rows : 1, 0);
     std::vector<uint32_t> starts(rows ? rows : 1, 0);
+    std::vector<uint8_t> slice_row(rows ? rows : 1, 0);  // rows where a slice starts
+    for (int j = 0; j < S; ++j)
+        if (L->xs_row_begin[j] < rows) slice_row[L->xs_row_begin[j]] = 1;
     parallel_ranges(rows, [&](uint64_t rb, uint64_t re) {
         for (uint64_t r = rb; r < re; ++r) {
             uint64_t mk = 0;
@@ -367,8 +387,7 @@ void build_xcd_slices(HostLayout* L) {
                 const uint64_t q = r * 64 + l;
                 if (dst[q] == 0xFFFFFFFFu) continue;
                 bool start = q == 0 || dst[q - 1] != dst[q];
-                for (int j = 0; j < kXcdSlices; ++j)
-                    if (q == (uint64_t)L->xs_row_begin[j] * 64) start = true;  // a new slice
+                if (l == 0 && slice_row[r]) start = true;  // a new slice
                 if (start) mk |= 1ull << l;
             }
             L->xs_rowmask[r] = mk;
@@ -409,7 +428,7 @@ void build_xcd_slices(HostLayout* L) {
         int j = 0;
         for (uint64_t t = 0; t < segs; ++t) {
             const uint64_t a = seg_begin[t];
-            while (j + 1 < kXcdSlices && a >= (uint64_t)L->xs_row_begin[j + 1] * 64) ++j;
+            while (j + 1 < S && a >= (uint64_t)L->xs_row_begin[j + 1] * 64) ++j;
             uint64_t e = t + 1 < segs ? seg_begin[t + 1] : (uint64_t)L->xs_edge_end[j];
             e = std::min<uint64_t>(e, L->xs_edge_end[j]);
             const uint64_t b = e - 1;

@@ -20,7 +20,7 @@ constexpr int kWave = 64;
 constexpr int kPullRows = 8;         // default rows (64 positions each) per wave in the integer pulls
 constexpr uint32_t kPrTileRows = 8;  // PageRank pull tile: 8 rows of 64 in-edge positions
 constexpr uint32_t kPrShortSpan = 8; // spans over at most this many extra tiles are fixed up per lane
-constexpr int kXcdSlices = 8;        // source slices of the sliced full pulls (an eighth of the values each)
+constexpr int kMaxSlices = 64;       // most source slices of the sliced full pulls
 constexpr int kXcdGroupShift = 10;   // source slices deal out groups of 1024 vertices
 
 enum App : int { kBfs = 1, kCc = 2, kSssp = 3 };
@@ -59,34 +59,45 @@ struct HostLayout {
     // last tile) pairs, and the pairs
     std::vector<uint32_t> xs_pspan_v, xs_pspan_off, xs_pspan_tt;
     uint64_t xs_pspan_short = 0;
-    uint32_t xs_row_begin[kXcdSlices + 1] = {};
-    uint32_t xs_edge_end[kXcdSlices] = {};
+    uint32_t xs_lg = 0;  // log2 of the number of slices
+    uint32_t xs_row_begin[kMaxSlices + 1] = {};
+    uint32_t xs_edge_end[kMaxSlices] = {};
 };
 
-// Source slice of internal vertex u for the sliced full pulls: 1024-vertex
-// groups (4 KB of 32-bit values, whole cache lines) dealt to the 8 slices in
-// a snake order (0..7, 7..0, ...), which balances the out-degree-sorted
-// vertices' edges across slices. The slices are pulled one launch after
-// another, so at any time the L2 of every XCD only needs the values of one
-// slice's sources (an eighth of the array).
-inline uint32_t xcd_slice_of(uint32_t u) {
+// Source slice of internal vertex u for the sliced full pulls, with 2^lg
+// slices: 1024-vertex groups (4 KB of 32-bit values, whole cache lines) dealt
+// to the slices in a snake order (0..S-1, S-1..0, ...), which balances the
+// out-degree-sorted vertices' edges across slices. The slices are pulled one
+// launch after another, so at any time the L2 of every XCD only needs the
+// values of one slice's sources (1/S of the array).
+__host__ __device__ inline uint32_t xcd_slice_of(uint32_t u, uint32_t lg) {
     const uint32_t g = u >> kXcdGroupShift;
-    return ((g >> 3) & 1u) ? 7u - (g & 7u) : (g & 7u);
+    const uint32_t r = g & ((1u << lg) - 1u);
+    return ((g >> lg) & 1u) ? (1u << lg) - 1u - r : r;
 }
 // Index of u among its slice's vertices (the slice's groups in order), and
 // back: the slice-local ids of a slice's highest-out-degree sources are the
 // lowest.
-__host__ __device__ inline uint32_t xcd_slice_local(uint32_t u) {
-    return ((u >> (kXcdGroupShift + 3)) << kXcdGroupShift) | (u & ((1u << kXcdGroupShift) - 1u));
+__host__ __device__ inline uint32_t xcd_slice_local(uint32_t u, uint32_t lg) {
+    return ((u >> (kXcdGroupShift + lg)) << kXcdGroupShift) | (u & ((1u << kXcdGroupShift) - 1u));
 }
-__host__ __device__ inline uint32_t xcd_slice_global(uint32_t i, uint32_t j) {
+__host__ __device__ inline uint32_t xcd_slice_global(uint32_t i, uint32_t j, uint32_t lg) {
     const uint32_t b = i >> kXcdGroupShift;
-    const uint32_t gidx = b * 8u + ((b & 1u) ? 7u - j : j);
+    const uint32_t gidx = (b << lg) + ((b & 1u) ? (1u << lg) - 1u - j : j);
     return (gidx << kXcdGroupShift) | (i & ((1u << kXcdGroupShift) - 1u));
 }
+// The number of slices for a graph with `sources` vertices that have
+// out-edges (the values a full pull gathers): the smallest power of two from
+// 8 to kMaxSlices whose slices hold at most kSliceValueBytes of their 32-bit
+// values, twice an XCD's L2 (WEDGE_XS_SLICES overrides it). Measured at
+// scale 24 and 26: 8 slices for R-MAT s24 (7.4M sources), 16 for ER s24
+// (16.8M) and for R-MAT s26 (27.1M); more slices cost more than they save
+// (each destination's value is read once per slice it has in-edges in).
+constexpr uint64_t kSliceValueBytes = 8ull << 20;
+uint32_t xs_slices_lg(uint64_t sources);
 // The packed sliced copy: (slice-local source << 8) | weight in one word.
 constexpr uint32_t kXsPackMaxW = 255;
-constexpr uint64_t kXsPackMaxN = 1ull << 27;  // slice-local ids below 2^24
+constexpr uint64_t kXsPackMaxN = 1ull << 27;  // slice-local ids below 2^24 (at least 8 slices)
 
 // Builds the source-sliced copy of L's in-edges (L must hold the canonical layout).
 void build_xcd_slices(HostLayout* L);
@@ -136,8 +147,9 @@ struct DevGraph {
     uint64_t xs_pspans = 0;       // destinations with crossing segments
     uint64_t xs_pspan_short = 0;  // of which listed first as short
     uint64_t xs_pspan_pairs = 0;  // crossing segments over all of them
-    uint32_t xs_row_begin[kXcdSlices + 1] = {};
-    uint32_t xs_edge_end[kXcdSlices] = {};
+    uint32_t xs_lg = 0;         // log2 of the number of slices
+    uint32_t xs_row_begin[kMaxSlices + 1] = {};
+    uint32_t xs_edge_end[kMaxSlices] = {};
     // push engine (built on first use): out-edge destinations and weights in CSR order
     uint32_t* out_dst = nullptr;
     uint32_t* out_w = nullptr;

@@ -202,21 +202,23 @@ def test_batch_union_is_the_concatenation():
         W.Graph.from_batch_csr(bad, host_only=True)
 
 
-def _slice_of(u):
-    """Source slice of internal id u: 1024-id groups dealt to 8 slices in snake order."""
+def _slice_of(u, S):
+    """Source slice of internal id u: 1024-id groups dealt to S slices in snake order."""
     g = u.astype(np.int64) >> 10
-    return np.where((g >> 3) & 1, 7 - (g & 7), g & 7)
+    return np.where((g // S) & 1, S - 1 - (g % S), g % S)
 
 
-@pytest.mark.parametrize("seed,scale,weighted,sym,keep", [
-    (6, 12, True, False, True), (7, 13, False, True, False), (8, 14, True, False, False),
-    (9, 12, "heavy", False, False)])
-def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
+@pytest.mark.parametrize("seed,scale,weighted,sym,keep,slices", [
+    (6, 12, True, False, True, 8), (7, 13, False, True, False, 8), (8, 14, True, False, False, 8),
+    (9, 12, "heavy", False, False, 8), (10, 13, True, False, False, 16), (11, 14, False, True, False, 32),
+    (12, 13, "heavy", False, True, 64)])
+def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep, slices):
     """The source-sliced in-edge copy holds every in-edge once, in the slice of
     its source, each slice grouped by destination with sources ascending (the
     canonical order restricted to the slice), starting on a row boundary; its
     row layout names every real position's destination."""
     monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
+    monkeypatch.setenv("WEDGE_XS_SLICES", str(slices))
     ro, col = gen.rmat(scale, 16, seed=seed)
     w = None
     if weighted:
@@ -226,15 +228,18 @@ def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
     info = g.info
     assert info["xs_rows"] > 0
     assert info["xs_packed"] == (weighted is True)
+    S = slices
+    assert info["xs_slices"] == S
     co = g.layout("col_off").astype(np.int64)
     src = g.layout("in_src")
     n, m = len(co) - 1, len(src)
     dst_c = np.repeat(np.arange(n), np.diff(co))
     b = g.layout("xs_bounds").astype(np.int64)
-    row_begin, edge_end = b[:9], b[9:]
+    assert len(b) == 2 * S + 1
+    row_begin, edge_end = b[:S + 1], b[S + 1:]
     assert row_begin[0] == 0 and np.all(np.diff(row_begin) >= 0)
-    assert row_begin[8] == info["xs_rows"]
-    assert np.all(edge_end <= row_begin[1:] * 64) and np.all(edge_end >= row_begin[:8] * 64)
+    assert row_begin[S] == info["xs_rows"]
+    assert np.all(edge_end <= row_begin[1:] * 64) and np.all(edge_end >= row_begin[:S] * 64)
     xsrc = g.layout("xs_src")
     xw = None
     if weighted and info["xs_packed"]:
@@ -243,9 +248,9 @@ def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
         loc = (xsrc >> np.uint32(8)).astype(np.int64)
         b_ = loc >> 10
         xsrc = np.zeros(len(loc), np.uint32)
-        for j in range(8):
+        for j in range(S):
             lo, hi = row_begin[j] * 64, row_begin[j + 1] * 64
-            gidx = b_[lo:hi] * 8 + np.where(b_[lo:hi] & 1, 7 - j, j)
+            gidx = b_[lo:hi] * S + np.where(b_[lo:hi] & 1, S - 1 - j, j)
             xsrc[lo:hi] = ((gidx << 10) | (loc[lo:hi] & 1023)).astype(np.uint32)
         with pytest.raises(W.WedgeError):
             g.layout("xs_w")
@@ -257,7 +262,7 @@ def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
     mask = g.layout("xs_rowmask")
     seg = g.layout("xs_rowseg").astype(np.int64)
     nz = g.layout("xs_nzdst").astype(np.int64)
-    sl = _slice_of(src)
+    sl = _slice_of(src, S)
     P = 64 * info["xs_rows"]
     p = np.arange(P)
     r, bb = p >> 6, p & 63
@@ -265,7 +270,7 @@ def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
     cum = np.cumsum(bits)
     dst_x = nz[seg[r] + (cum - cum[r * 64])]  # the row-layout destination of every position
     total = 0
-    for j in range(8):
+    for j in range(S):
         lo, hi = row_begin[j] * 64, edge_end[j]
         want = np.flatnonzero(sl == j)                      # canonical order, slice j only
         assert hi - lo == len(want), j
@@ -291,7 +296,7 @@ def test_source_sliced_copy(monkeypatch, seed, scale, weighted, sym, keep):
     # grouped by destination in slice order; destinations whose segments cover
     # at most 8 extra tiles in all come first
     per_v = {}
-    for j in range(8):
+    for j in range(S):
         lo, hi = int(row_begin[j] * 64), int(edge_end[j])
         if hi == lo:
             continue
@@ -321,3 +326,9 @@ def test_source_sliced_copy_threshold(monkeypatch):
     assert host_graph(ro, col).info["xs_rows"] == 0
     monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
     assert host_graph(ro, col).info["xs_rows"] > 0
+    # few sources: the fewest slices (the count grows with the sources' values)
+    assert host_graph(ro, col).info["xs_slices"] == 8
+    monkeypatch.setenv("WEDGE_XS_SLICES", "32")
+    assert host_graph(ro, col).info["xs_slices"] == 32
+    monkeypatch.setenv("WEDGE_XS_SLICES", "12")  # not a power of two: the default
+    assert host_graph(ro, col).info["xs_slices"] == 8

@@ -125,16 +125,18 @@ def test_mode_and_granularity_invariance(app, chunk, gate):
     parity(app, ro, col, w, s, gate=gate, chunk=chunk)
 
 
+@pytest.mark.parametrize("slices", ["8", "64"])
 @pytest.mark.parametrize("name", ["er_ragged", "rmat14", "grid", "rmat14_heavy"])
 @pytest.mark.parametrize("gate", ["threshold", "full"])
 @pytest.mark.parametrize("app", ["cc", "sssp"])
-def test_parity_source_sliced_full_pull(monkeypatch, app, gate, name):
+def test_parity_source_sliced_full_pull(monkeypatch, app, gate, name, slices):
     """CC and SSSP with the full pulls over the source-sliced copy (forced on
     small graphs): values and every per-iteration record equal the oracle, as
     with the canonical pull, in the synchronous and the in-place forms. SSSP
     weights up to 255 run on the packed copy (one word per in-edge), heavier
     ones on separate source and weight arrays."""
     monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
+    monkeypatch.setenv("WEDGE_XS_SLICES", slices)  # 64: most slices of these graphs are empty
     heavy = name.endswith("_heavy")
     ro, col = GRAPHS[name.replace("_heavy", "")]()
     w = gen.edge_weights(ro, col, seed=4, hi=100_000 if heavy else 255) if app == "sssp" else None
@@ -144,6 +146,7 @@ def test_parity_source_sliced_full_pull(monkeypatch, app, gate, name):
     g = (W.Graph.from_csr(ro, col, symmetrize=True) if app == "cc" else W.Graph.from_csr(ro, col, w))
     assert g.info["xs_rows"] > 0
     assert g.info["xs_packed"] == (app == "sssp" and not heavy)
+    assert g.info["xs_slices"] == int(slices)
     want = oracle.cc(ro, col) if app == "cc" else oracle.sssp(ro, col, w, src)
     out, _, _ = run_app(app, g, src, gate=gate, inplace=True)
     np.testing.assert_array_equal(out, want)
@@ -361,14 +364,16 @@ def test_pagerank_large_graph_lds_pull(monkeypatch, kind, sliced):
     assert torch.equal(r, r2)
 
 
+@pytest.mark.parametrize("slices", ["8", "32"])
 @pytest.mark.parametrize("weighted", [False, True])
 @pytest.mark.parametrize("name", ["er_ragged", "rmat12", "rmat14", "grid", "hub"])
-def test_pagerank_source_sliced_small(monkeypatch, name, weighted):
+def test_pagerank_source_sliced_small(monkeypatch, name, weighted, slices):
     """The sliced PageRank pull forced on small graphs (slices of a few tiles,
     empty slices, a hub whose in-edges cross many tiles in every slice), over
     the plain copy and over the packed copy of a weighted graph (PageRank
     ignores the weights)."""
     monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
+    monkeypatch.setenv("WEDGE_XS_SLICES", slices)
     if name == "hub":
         n = 70000
         rng = np.random.default_rng(1)
