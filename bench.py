@@ -5,7 +5,7 @@ One step = one pass of the whole path over the R-MAT scale-24 workload
 (2^24 vertices, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05), seeded vertex
 relabelling, self-loops and duplicates removed; uint32 weights in [1, 255]):
   BFS from 4 seeded sources, SSSP from the same 4 sources (threshold gate,
-  theta 1% / 20%, 32 / 16 edges per Wedge bit), CC on the undirected view,
+  theta BFS 1%, SSSP 5%, CC 20%; 32 / 16 / 16 edges per Wedge bit), CC on the undirected view,
   and PageRank (20 iterations, d = 0.85, full pull).
 Inputs are resident in HBM before the timed region. The value is whole-step
 GTEPS: (4M + 4M + M + 20M) / step time, M = stored directed edges.
@@ -661,7 +661,7 @@ def main():
         "config": {"workload": f"R-MAT s{args.scale} ef16 (a,b,c,d)=(.57,.19,.19,.05): "
                                f"BFS x{len(srcs)} + SSSP x{len(srcs)} + CC + PageRank x20",
                    "n": n, "m": m, "m_undirected": gs.m, "gate": "threshold",
-                   "theta_ppm": {"bfs": 10000, "cc": 200000, "sssp": 200000},
+                   "theta_ppm": {"bfs": 10000, "cc": 200000, "sssp": 50000},
                    "chunk_edges": {"bfs": 32, "cc": 16, "sssp": 16}, "device": dev_name},
         "per_app_gteps": per_app, "per_app_ms": per_app_ms,
         "roofline": roof,

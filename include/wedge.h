@@ -254,8 +254,8 @@ typedef struct {
 typedef struct {
     uint32_t gate;           /* wedge_gate */
     uint32_t threshold_ppm;  /* theta in parts per million of the traversed edge count; 0 = the
-                                application default (BFS 10000 = 1%, CC/SSSP 200000 = 20%;
-                                the hybrid gate: 50000 = 5%) */
+                                application default (BFS 10000 = 1%, CC 200000 = 20%,
+                                SSSP 50000 = 5%; the hybrid gate: 50000 = 5%) */
     uint32_t chunk_edges;    /* edges per Wedge Frontier bit: a power of two in [1, 4096];
                                 0 = application default (BFS 32, CC/SSSP 16) */
     uint32_t max_iters;      /* 0 = unlimited (n + 1 bounds every application) */

@@ -404,6 +404,14 @@ constexpr int kModeFull = 0, kModeWedge = 1, kModePush = 2;
 // Default threshold of the hybrid baseline: 5% of the edges.
 constexpr uint32_t kHybridThetaPpm = 50000;
 
+// Default fullness threshold per application (Evaluation, Frontier Fullness
+// Threshold: theta is tuned per machine by timing iterations with and without
+// the Wedge Frontier). BFS 1% and CC 20% are the paper's values, which a
+// sweep on this GPU confirms; for SSSP the same sweep gives 5% (faster than
+// 20% on every graph swept: the sliced full pull beats marked-chunk pulls
+// that cover most of the edges).
+uint32_t default_theta_ppm(int app) { return app == kBfs ? 10000u : app == kCc ? 200000u : 50000u; }
+
 struct LoopCfg {
     int lc = 5;
     uint64_t thr = 0;
@@ -674,7 +682,7 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
     wedge_stats local{};
     const double t0 = now_ms();
     if (d.n == 0) { if (stats) *stats = local; return WEDGE_OK; }
-    LoopCfg c = loop_cfg(o, d, (App)app, app == kBfs ? 10000u : 200000u, app == kBfs ? 32u : 16u);
+    LoopCfg c = loop_cfg(o, d, (App)app, default_theta_ppm(app), app == kBfs ? 32u : 16u);
     if ((st = prepare_gate(g, o, &c)) != WEDGE_OK) return st;
     if ((st = ensure_workspace(g, c.min_lc(), true, wedge_gate_used(c.gate))) != WEDGE_OK) return st;
     if (push_gate(c.gate) && (st = ensure_push(g, s)) != WEDGE_OK) return st;
@@ -1594,7 +1602,7 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
     if (!guard.ok) return fail(WEDGE_ERR_BUSY, "graph is in use by another run");
     if (d.n == 0) return WEDGE_OK;
     const uint32_t def_chunk = app == kBfs ? 32u : 16u;
-    const LoopCfg c = loop_cfg(o, d, (App)app, app == kBfs ? 10000u : 200000u, def_chunk);
+    const LoopCfg c = loop_cfg(o, d, (App)app, default_theta_ppm(app), def_chunk);
     wedge_status st;
     if ((st = ensure_workspace(g, 4, true, true)) != WEDGE_OK) return st;
     Workspace& w = g->ws;

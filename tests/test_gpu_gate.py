@@ -103,7 +103,7 @@ def test_counterfactual_trace_matches_oracle_iterations(app):
         ref = oracle.pull_engine("cc", sro, scol, theta_ppm=200_000, chunk=0)
     else:
         g = W.Graph.from_csr(ro, col, w)
-        theta = 10_000 if app == "bfs" else 200_000
+        theta = 10_000 if app == "bfs" else 50_000  # the library's SSSP default
         ref = oracle.pull_engine(app, ro, col, w, s, theta_ppm=theta, chunk=0)
     tr = W.trace_counterfactual(g, app, s)
     assert len(tr) == ref.iters
