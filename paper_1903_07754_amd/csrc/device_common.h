@@ -18,7 +18,7 @@ constexpr int kWavesPerBlock = kBlock / 64;
 #define WEDGE_HOT_VERTS 16384
 #endif
 #ifndef WEDGE_HOT_BATCH
-#define WEDGE_HOT_BATCH 4
+#define WEDGE_HOT_BATCH 8
 #endif
 constexpr int kHotBlock = WEDGE_HOT_BLOCK;          // threads per block
 constexpr uint32_t kHotVerts = WEDGE_HOT_VERTS;     // values held in LDS (4 B each)
