@@ -80,6 +80,10 @@ template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
 
 // Lanes from `l` up to (excluding) the next segment head.
+// Integer minimum of 64-bit values (min<uint64_t> resolves to a double
+// overload in device code, which costs a dozen FP64 instructions).
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
 __device__ __forceinline__ int seg_span(uint64_t heads, int l) {
     uint64_t rest = l == 63 ? 0ull : (heads >> (l + 1));
     return rest ? (int)__builtin_ctzll(rest) + 1 : 64 - l;
@@ -176,7 +180,7 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
     const int lane = lane_id();
     const uint64_t base = wave * 64ull * EPT;
     if (base >= active) return;
-    const uint64_t end = min<uint64_t>(base + 64ull * EPT, active);
+    const uint64_t end = umin64(base + 64ull * EPT, active);
     uint32_t j0 = wave_last_le(degpre, 0, fcount - 1, base, lane);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {

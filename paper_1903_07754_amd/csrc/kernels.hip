@@ -410,7 +410,7 @@ __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gathe
             const int i = i0 + j;
             const uint64_t r = r0 + i;
             if (r >= g.rows) break;
-            const uint64_t row_end = min<uint64_t>(r * 64 + 64, g.m);
+            const uint64_t row_end = umin64(r * 64 + 64, g.m);
             const bool cont_in = !(mk[j] & 1ull);
             const bool cont_out = row_end < g.m && !(mk[j + 1] & 1ull);
             const bool last_row = (i == R - 1) || (r + 1 >= g.rows);

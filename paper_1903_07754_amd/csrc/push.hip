@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ fl
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t base = wave * 64ull * EPT;
     if (base >= active) return;
-    const uint64_t end = min<uint64_t>(base + 64ull * EPT, active);
+    const uint64_t end = umin64(base + 64ull * EPT, active);
     uint32_t j0 = wave_last_le(degpre, 0, fcount - 1, base, lane);
     uint32_t q[EPT], x[EPT];
     bool valid[EPT];
