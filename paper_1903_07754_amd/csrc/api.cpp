@@ -1376,7 +1376,10 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
         return *p ? WEDGE_OK : dev_alloc(g, p, bytes, what);
     };
     if ((st = need((void**)&w.pr_sum, (size_t)d.n * 4, "PageRank sums")) != WEDGE_OK) return st;
-    if ((st = need((void**)&w.pr_contrib, (size_t)d.n * 4, "PageRank contributions")) != WEDGE_OK) return st;
+    // slice-major contributions span whole groups of every slice (xs_contrib_cap)
+    const uint64_t cap = xs_contrib_cap(d);
+    const uint64_t contrib_len = std::max<uint64_t>(d.n, cap << d.xs_lg);
+    if ((st = need((void**)&w.pr_contrib, (size_t)contrib_len * 4, "PageRank contributions")) != WEDGE_OK) return st;
     if ((st = need((void**)&w.pr_head, w.pr_tiles * 4, "PageRank tile heads")) != WEDGE_OK) return st;
     if ((st = need((void**)&w.pr_tail, w.pr_tiles * 4, "PageRank tile tails")) != WEDGE_OK) return st;
     if ((st = need((void**)&w.pr_part, (size_t)w.pr_parts * 8, "PageRank partials")) != WEDGE_OK) return st;
@@ -1400,7 +1403,7 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
     }
     // D_0 comes from the host; D_k (k >= 1) is reduced from the previous
     // epilogue's partials by the fix-up launch of iteration k
-    hipError_t e = launch_pr_init(d.n, d.row_off, rank, w.pr_contrib, w.pr_sum, s);
+    hipError_t e = launch_pr_init(d.n, d.row_off, rank, w.pr_contrib, w.pr_sum, s, d.xs_lg, cap);
     if (e == hipSuccess) e = launch_set_f64(w.pr_d, (double)g->dangling / (double)d.n, s);
     for (uint32_t k = 0; k < iters && e == hipSuccess; ++k) {
         double* dk = w.pr_d + (k & 1);
@@ -1412,7 +1415,7 @@ wedge_status wedge_pagerank(wedge_graph_t g, uint32_t iters, float damping, floa
                                 k ? dk : nullptr, s);
         if (e == hipSuccess)
             e = launch_pr_epilogue(d.n, d.row_off, w.pr_sum, (double)damping, dk, rank,
-                                   w.pr_contrib, w.pr_part, w.pr_parts, s);
+                                   w.pr_contrib, w.pr_part, w.pr_parts, s, d.xs_lg, cap);
     }
     if (e == hipSuccess && d.inv) e = launch_unpermute_f32(d.n, d.perm, rank, rank_dev, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

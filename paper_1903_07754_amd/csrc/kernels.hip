@@ -517,13 +517,15 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_hot(GraphArgs g, const fl
 // the L2. Segments crossing a tile boundary leave their parts in head/tail;
 // k_pr_fixup_xs adds them afterwards.
 template <int R, bool PACKED>
-__global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32_t slice, uint32_t lg,
+__global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32_t lg,
                                                              uint64_t tile_begin, uint64_t tile_end,
-                                                             const float* __restrict__ contrib,
+                                                             const float* __restrict__ cs,
                                                              float* __restrict__ sum,
                                                              float* __restrict__ head_part,
                                                              float* __restrict__ tail_part,
                                                              uint32_t hot) {
+    // cs: this slice's contributions, indexed by slice-local id (every id an
+    // in-edge word can hold is below the capacity cs spans)
     extern __shared__ float s_hot[];
     {
         constexpr int kPer = (int)((kHotVerts + kHotBlock - 1) / kHotBlock);
@@ -531,8 +533,7 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint32_t i = threadIdx.x + (uint32_t)k * kHotBlock;
-            const uint32_t gi = xcd_slice_global(i < hot ? i : 0u, slice, lg);
-            t[k] = contrib[gi < g.n ? gi : 0u];
+            t[k] = cs[i < hot ? i : 0u];
         }
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
@@ -549,14 +550,8 @@ __global__ __launch_bounds__(kHotBlock) void k_pr_pull_slice(GraphArgs g, uint32
             g, t,
             [&](uint32_t word) {
                 const uint32_t l = PACKED ? (word >> 8) : xcd_slice_local(word, lg);
-                uint32_t u = word;
-                if (PACKED) {
-                    // a lane without an edge may hold another slice's word
-                    u = xcd_slice_global(l, slice, lg);
-                    u = u < g.n ? u : 0u;
-                }
                 const bool h = l < hot;
-                const float gv = contrib[h ? 0u : u];
+                const float gv = cs[h ? 0u : l];
                 const float lv = s_hot[h ? l : 0u];
                 return h ? lv : gv;
             },
@@ -674,13 +669,19 @@ __global__ __launch_bounds__(kBlock) void k_pr_fixup_long(const uint32_t* __rest
     if (lane == 0) sum[v] = tail_part[ta] + acc;
 }
 
+// Position of vertex v's contribution: vertex order (cap = 0) or slice-major
+// (see xs_contrib_cap).
+__device__ __forceinline__ uint64_t contrib_pos(uint32_t v, uint32_t lg, uint64_t cap) {
+    return cap ? (uint64_t)xcd_slice_of(v, lg) * cap + xcd_slice_local(v, lg) : (uint64_t)v;
+}
+
 __global__ void k_pr_init(uint32_t n, const uint32_t* __restrict__ row_off, float* __restrict__ rank,
-                          float* __restrict__ contrib, float* __restrict__ sum) {
+                          float* __restrict__ contrib, float* __restrict__ sum, uint32_t lg, uint64_t cap) {
     const float r0 = 1.0f / (float)n;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const uint32_t od = row_off[v + 1] - row_off[v];
         rank[v] = r0;
-        contrib[v] = od ? r0 / (float)od : 0.0f;
+        contrib[contrib_pos(v, lg, cap)] = od ? r0 / (float)od : 0.0f;
         sum[v] = 0.0f;
     }
 }
@@ -700,7 +701,8 @@ __global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n, uint32_t per
                                                         const double* __restrict__ dcur,
                                                         float* __restrict__ rank,
                                                         float* __restrict__ contrib,
-                                                        double* __restrict__ partials) {
+                                                        double* __restrict__ partials, uint32_t lg,
+                                                        uint64_t cap) {
     __shared__ double s_part[kWavesPerBlock];
     const double dn = *dcur / (double)n;
     const double base = (1.0 - d) / (double)n;
@@ -712,7 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_epilogue(uint32_t n, uint32_t per
         sum[v] = 0.0f;
         const uint32_t od = row_off[v + 1] - row_off[v];
         rank[v] = r;
-        contrib[v] = od ? r / (float)od : 0.0f;
+        contrib[contrib_pos(v, lg, cap)] = od ? r / (float)od : 0.0f;
         if (!od) acc += (double)r;
     }
     acc = wave_sum_tree(acc);
@@ -1012,9 +1014,9 @@ hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log
 }
 
 hipError_t launch_pr_init(uint32_t n, const uint32_t* row_off, float* rank, float* contrib,
-                          float* sum, hipStream_t s) {
+                          float* sum, hipStream_t s, uint32_t lg, uint64_t cap) {
     if (!n) return hipSuccess;
-    k_pr_init<<<grid_for(n, 8192), kBlock, 0, s>>>(n, row_off, rank, contrib, sum);
+    k_pr_init<<<grid_for(n, 8192), kBlock, 0, s>>>(n, row_off, rank, contrib, sum, lg, cap);
     return hipGetLastError();
 }
 
@@ -1039,12 +1041,14 @@ hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, f
             const uint64_t tb = rb / kPrTileRows, te = re / kPrTileRows;
             const uint64_t blocks = std::min<uint64_t>((uint64_t)std::max(cus, 1) * (uint64_t)per_cu,
                                                        (te - tb + kHotBlock / 64 - 1) / (kHotBlock / 64));
+            // contributions are slice-major (see xs_contrib_cap)
+            const float* cs = contrib + (uint64_t)j * xs_contrib_cap(g);
             if (g.xs_packed)
                 k_pr_pull_slice<kPrTileRows, true><<<(uint32_t)blocks, kHotBlock, lds, s>>>(
-                    xa, (uint32_t)j, g.xs_lg, tb, te, contrib, sum, head, tail, hot);
+                    xa, g.xs_lg, tb, te, cs, sum, head, tail, hot);
             else
                 k_pr_pull_slice<kPrTileRows, false><<<(uint32_t)blocks, kHotBlock, lds, s>>>(
-                    xa, (uint32_t)j, g.xs_lg, tb, te, contrib, sum, head, tail, hot);
+                    xa, g.xs_lg, tb, te, cs, sum, head, tail, hot);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -1112,10 +1116,11 @@ uint32_t pr_epilogue_blocks(uint32_t n) {
 
 hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, float* sum,
                               double damping, const double* d_cur, float* rank, float* contrib,
-                              double* partials, uint32_t parts, hipStream_t s) {
+                              double* partials, uint32_t parts, hipStream_t s, uint32_t lg,
+                              uint64_t cap) {
     if (!n) return hipSuccess;
     k_pr_epilogue<<<parts, kBlock, 0, s>>>(n, kPrEpilogueVerts, row_off, sum, damping, d_cur, rank,
-                                           contrib, partials);
+                                           contrib, partials, lg, cap);
     return hipGetLastError();
 }
 

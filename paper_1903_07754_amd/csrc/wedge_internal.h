@@ -464,8 +464,19 @@ hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
                            uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
                            uint64_t* fcur, uint32_t* fsum, uint32_t* csum, hipStream_t s);
 // PageRank
+// PageRank contributions of a graph with the sliced copy are kept in
+// slice-major order: vertex v at slice_of(v) * cap + slice_local(v), cap the
+// slice-local id capacity (whole 1024-vertex groups), so that the sliced pull
+// indexes them by the slice-local id its in-edge word holds. cap = 0: vertex
+// order.
+inline uint64_t xs_contrib_cap(const DevGraph& g) {
+    if (!g.xs_rows) return 0;
+    const uint64_t groups = ((uint64_t)g.n + (1u << kXcdGroupShift) - 1) >> kXcdGroupShift;
+    const uint64_t per = (groups + (1u << g.xs_lg) - 1) >> g.xs_lg;
+    return per << kXcdGroupShift;
+}
 hipError_t launch_pr_init(uint32_t n, const uint32_t* row_off, float* rank, float* contrib,
-                          float* sum, hipStream_t s);
+                          float* sum, hipStream_t s, uint32_t lg = 0, uint64_t cap = 0);
 hipError_t launch_pr_pull(const DevGraph& g, const float* contrib, float* sum, float* head,
                           float* tail, int cus, hipStream_t s);
 // Completes S for destinations crossing tile boundaries, and reduces the
@@ -474,7 +485,8 @@ hipError_t launch_pr_fixup(const DevGraph& g, const float* head, const float* ta
                            const double* partials, uint32_t parts, double* d_next, hipStream_t s);
 hipError_t launch_pr_epilogue(uint32_t n, const uint32_t* row_off, float* sum,
                               double damping, const double* d_cur, float* rank, float* contrib,
-                              double* partials, uint32_t parts, hipStream_t s);
+                              double* partials, uint32_t parts, hipStream_t s, uint32_t lg = 0,
+                              uint64_t cap = 0);
 uint32_t pr_epilogue_blocks(uint32_t n);
 // Batched BFS (batch.hip)
 hipError_t launch_ms_pull_full(const DevGraph& g, uint64_t all, const uint64_t* visited,
