@@ -57,7 +57,7 @@ __device__ __forceinline__ void ms_pull_lanes(const GraphArgs& g, const uint32_t
     for (int i = 0; i < R; ++i) x[i] = need[i] ? x[i] : 0ull;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const uint32_t prev = __shfl_up(dst[i], 1, 64);
+        const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
         const bool head = lane == 0 || prev != dst[i];
         const uint64_t heads = __ballot(head);
         const uint64_t orv = seg_reduce(x[i], seg_span(heads, lane),

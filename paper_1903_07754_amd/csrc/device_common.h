@@ -80,6 +80,36 @@ template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
 
 // Lanes from `l` up to (excluding) the next segment head.
+// Lane l's value in every lane, for a wave-uniform l (one v_readlane, where
+// __shfl would compute addresses and go through the LDS crossbar).
+__device__ __forceinline__ uint32_t lane_bcast(uint32_t x, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, l & 63);
+}
+__device__ __forceinline__ float lane_bcast(float x, int l) {
+    return __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l & 63));
+}
+
+// Lane l-1's value in lane l (lane 0 keeps its own), and lane l+1's in lane l
+// (lane 63 keeps its own): DPP whole-wave shifts by one lane, one VALU
+// instruction each.
+__device__ __forceinline__ uint32_t lane_prev(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t lane_next(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x130, 0xf, 0xf, false);
+}
+template <typename T>
+__device__ __forceinline__ T lane_next_t(T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, lane_next(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint64_t lo = lane_next((uint32_t)b), hi = lane_next((uint32_t)(b >> 32));
+        return __builtin_bit_cast(T, lo | (hi << 32));
+    }
+}
+
 // Integer minimum of 64-bit values (min<uint64_t> resolves to a double
 // overload in device code, which costs a dozen FP64 instructions).
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
@@ -96,7 +126,8 @@ template <typename T, typename Op>
 __device__ __forceinline__ T seg_reduce(T v, int span, Op op) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        T w = __shfl_down(v, o, 64);
+        // step 1 by a DPP shift (lane 63, whose span is 1, takes nothing)
+        T w = o == 1 ? lane_next_t(v) : __shfl_down(v, o, 64);
         if (o < span) v = op(v, w);
     }
     return v;
@@ -218,9 +249,9 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
         // holding edge row + 63, or the next one when that begins exactly there
         // (every listed vertex has at least one edge, so a window of 64 vertices
         // from there covers the whole next row)
-        j0 += (uint32_t)__shfl(t, 63, 64);
+        j0 += lane_bcast((uint32_t)t, 63);
         if (j0 + 1 < fcount && degpre[j0 + 1] <= row + 64) ++j0;
-        const uint32_t prev = __shfl_up(key, 1, 64);
+        const uint32_t prev = lane_prev(key);  // lane 0 is a head whatever it reads
         const bool head = lane == 0 || prev != key;
         const uint64_t heads = __ballot(head);
         bit = seg_reduce(bit, seg_span(heads, lane), [](uint32_t x, uint32_t y) { return x | y; });
@@ -350,7 +381,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
         if (DEG) {
             uint32_t inc = wave_incl_scan(deg[g], lane);
             dex = inc - deg[g];
-            dtot = __shfl(inc, 63, 64);
+            dtot = lane_bcast(inc, 63);
         }
         if (act && v < limit) {
             list[cb + rank] = v;
@@ -396,7 +427,7 @@ __device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint3
     const bool c = __shfl((int)commit, hl, 64) != 0;
     const uint32_t key = c ? (dst >> 5) : kInf;
     const uint32_t bit = (c && lane == hl) ? (1u << (dst & 31)) : 0u;
-    const uint32_t prev = __shfl_up(key, 1, 64);
+    const uint32_t prev = lane_prev(key);  // lane 0 is a head whatever it reads
     const bool head = lane == 0 || prev != key;
     const uint64_t wheads = __ballot(head);
     const uint32_t orv = seg_reduce(bit, seg_span(wheads, lane), [](uint32_t a, uint32_t b) { return a | b; });
@@ -535,7 +566,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const bool found = need[i];
-            const uint32_t prev = __shfl_up(dst[i], 1, 64);
+            const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
             const bool head = lane == 0 || prev != dst[i];
             const uint64_t heads = __ballot(head);
             const uint64_t fm = __ballot(found);
@@ -597,7 +628,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const uint32_t cand = (APP == kCc || x[i] == kInf) ? x[i] : x[i] + wt[i];
-            const uint32_t prev = __shfl_up(dst[i], 1, 64);
+            const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
             const bool head = lane == 0 || prev != dst[i];
             const uint64_t heads = __ballot(head);
             const uint64_t hv = heads & __ballot(valid[i]);
@@ -608,9 +639,9 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
             int defer = -1;
             const int h_last = hv ? 63 - __clzll(hv) : -1;
             if (hv && i + 1 < R) {
-                if (__shfl(dst[i + 1], 0, 64) == __shfl(dst[i], h_last, 64)) {
+                if (lane_bcast(dst[i + 1], 0) == lane_bcast(dst[i], h_last)) {
                     defer = h_last;
-                    carry = __shfl(best, h_last, 64);
+                    carry = lane_bcast(best, h_last);
                 }
             }
             const bool commit = head && valid[i] && lane != defer && best < cur[i];

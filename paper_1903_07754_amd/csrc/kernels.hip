@@ -438,7 +438,7 @@ __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gathe
                     else sum[dst[j]] = s;
                 }
             }
-            const float last_s = __shfl(s, h_last, 64);
+            const float last_s = lane_bcast(s, h_last);
             const bool nfb = h_last == 0 && cont_in && from_before;
             if (cont_out && !last_row) {
                 carry = last_s;

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ fl
         q[i] = valid[i] ? rt + (uint32_t)(a - dt) : 0u;
         // every listed vertex has an out-edge, so the window of 64 entries
         // from the owner of edge row + 63 (or the next one) covers the next row
-        j0 += (uint32_t)__shfl(t, 63, 64);
+        j0 += lane_bcast((uint32_t)t, 63);
         if (j0 + 1 < fcount && degpre[j0 + 1] <= row + 64) ++j0;
     }
     // every row's edge loads, then every row's destination value, then the updates
