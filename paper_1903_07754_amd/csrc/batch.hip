@@ -60,7 +60,7 @@ __device__ __forceinline__ void ms_pull_lanes(const GraphArgs& g, const uint32_t
         const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
         const bool head = lane == 0 || prev != dst[i];
         const uint64_t heads = __ballot(head);
-        const uint64_t orv = seg_reduce(x[i], seg_span(heads, lane),
+        const uint64_t orv = seg_reduce(x[i], heads,
                                         [](uint64_t a, uint64_t b) { return a | b; });
         if (head && dst[i] != kInf) {
             const uint64_t nb = orv & ~vis[i] & all;

@@ -119,16 +119,27 @@ __device__ __forceinline__ int seg_span(uint64_t heads, int l) {
     return rest ? (int)__builtin_ctzll(rest) + 1 : 64 - l;
 }
 
-// Suffix-doubling reduction restricted to the lane's segment: on return the
-// head lane of each segment holds the reduction of its whole segment, combined
-// in a fixed tree order.
+// Lane l's bit of a wave-uniform mask as a per-lane condition (the mask is
+// used as the lane mask of one v_cndmask; no per-lane shift).
+__device__ __forceinline__ bool lane_bit(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
+
+// Suffix-doubling reduction restricted to the lane's segment (segments start
+// at the lanes set in `heads`, a wave-uniform mask with bit 0 set): on return
+// the head lane of each segment holds the reduction of its whole segment,
+// combined in a fixed tree order. At step o lane l takes lane l + o's partial
+// exactly when l + o <= 63 and no segment starts in (l, l + o]; those lanes
+// form the mask z, which the scalar unit doubles from step to step
+// (z_2o = z_o & (z_o >> o)).
 template <typename T, typename Op>
-__device__ __forceinline__ T seg_reduce(T v, int span, Op op) {
+__device__ __forceinline__ T seg_reduce(T v, uint64_t heads, Op op) {
+    uint64_t z = ~(heads >> 1) & (~0ull >> 1);
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        // step 1 by a DPP shift (lane 63, whose span is 1, takes nothing)
-        T w = o == 1 ? lane_next_t(v) : __shfl_down(v, o, 64);
-        if (o < span) v = op(v, w);
+        // step 1 by a DPP shift (lane 63 takes nothing)
+        const T w = o == 1 ? lane_next_t(v) : __shfl_down(v, o, 64);
+        const T t = op(v, w);
+        v = lane_bit(z) ? t : v;
+        z &= z >> o;
     }
     return v;
 }
@@ -254,7 +265,7 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
         const uint32_t prev = lane_prev(key);  // lane 0 is a head whatever it reads
         const bool head = lane == 0 || prev != key;
         const uint64_t heads = __ballot(head);
-        bit = seg_reduce(bit, seg_span(heads, lane), [](uint32_t x, uint32_t y) { return x | y; });
+        bit = seg_reduce(bit, heads, [](uint32_t x, uint32_t y) { return x | y; });
         if (head && valid) {
             atomicOr(wbits32 + key, bit);
             if (wsum) wsum[key >> (kSumShift - 5)] = 1u;
@@ -319,7 +330,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const uint32_t v = (uint32_t)((w0 + g) * 64 + lane);
-        const bool set = ((mk[g] >> lane) & 1ull) && v < limit;
+        const bool set = lane_bit(mk[g]) && v < limit;
         const uint32_t vs = set ? v : 0u;
         if (DEG) {
             r0[g] = row_off[vs];
@@ -342,7 +353,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
         if (mk[g]) {
             all += __popcll(mk[g]);
             if (DEG) {
-                if ((mk[g] >> lane) & 1ull) deg[g] = r1[g] - r0[g];
+                if (lane_bit(mk[g])) deg[g] = r1[g] - r0[g];
                 // vertices without out-edges are counted but not listed
                 lm[g] = __ballot(deg[g] != 0);
                 dsum += wave_sum_tree(deg[g]);
@@ -368,14 +379,14 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
         const uint64_t wi = w0 + g;
         const uint32_t v = (uint32_t)(wi * 64 + lane);
         if (COPY && wi < words) {
-            if (((old[g] >> lane) & 1ull) && v < limit) on_old(v);
+            if (lane_bit(old[g]) && v < limit) on_old(v);
             if (lane == 0) copy_to[wi] = mk[g];
         }
         if (!mk[g]) continue;
-        if (((mk[g] >> lane) & 1ull) && v < limit) on_set(v, pre[g]);
+        if (lane_bit(mk[g]) && v < limit) on_set(v, pre[g]);
         if (lane == 0) bits[wi] = 0ull;
         if (!lm[g]) continue;
-        const bool act = (lm[g] >> lane) & 1ull;
+        const bool act = lane_bit(lm[g]);
         const uint32_t rank = (uint32_t)__popcll(lm[g] & mask_lt(lane));
         uint32_t dex = 0, dtot = 0;
         if (DEG) {
@@ -430,7 +441,7 @@ __device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint3
     const uint32_t prev = lane_prev(key);  // lane 0 is a head whatever it reads
     const bool head = lane == 0 || prev != key;
     const uint64_t wheads = __ballot(head);
-    const uint32_t orv = seg_reduce(bit, seg_span(wheads, lane), [](uint32_t a, uint32_t b) { return a | b; });
+    const uint32_t orv = seg_reduce(bit, wheads, [](uint32_t a, uint32_t b) { return a | b; });
     if (head && key != kInf) {
         atomicOr(reinterpret_cast<uint32_t*>(fbits) + key, orv);
         if (fsum) fsum[key >> (kSumShift - 5)] = 1u;
@@ -632,7 +643,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
             const bool head = lane == 0 || prev != dst[i];
             const uint64_t heads = __ballot(head);
             const uint64_t hv = heads & __ballot(valid[i]);
-            uint32_t best = seg_reduce(cand, seg_span(heads, lane),
+            uint32_t best = seg_reduce(cand, heads,
                                        [](uint32_t a, uint32_t b) { return a < b ? a : b; });
             if (lane == 0 && carry < best) best = carry;
             carry = kInf;

@@ -415,10 +415,10 @@ __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gathe
             const bool cont_out = row_end < g.m && !(mk[j + 1] & 1ull);
             const bool last_row = (i == R - 1) || (r + 1 >= g.rows);
             const uint64_t pp = r * 64 + lane;
-            const bool head = lane == 0 || ((mk[j] >> lane) & 1ull) || pp == g.m;
+            const bool head = lane == 0 || lane_bit(mk[j]) || pp == g.m;
             const uint64_t heads = __ballot(head);
             const uint64_t vmask = __ballot(valid[j]);
-            float s = seg_reduce(valid[j] ? x[j] : 0.0f, seg_span(heads, lane),
+            float s = seg_reduce(valid[j] ? x[j] : 0.0f, heads,
                                  [](float a, float b) { return a + b; });
             if (i == 0) from_before = cont_in;
             if (lane == 0 && cont_in) s = carry + s;
