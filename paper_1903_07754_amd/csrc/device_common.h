@@ -427,6 +427,25 @@ __device__ __forceinline__ void dst_of_rows(const GraphArgs& g, const uint32_t (
         dst[i] = g.nzdst[sg[i] + (uint32_t)__popcll(mk[i] & ~1ull & mask_le((int)(pc[i] & 63)))];
 }
 
+// The same for R whole rows (the full pulls): lane l of row i holds position
+// row_i * 64 + l, row_i = p[i] >> 6 for every lane, so the row's mask and
+// segment index are wave-uniform (scalar loads), and a lane's segment is
+// counted with mbcnt. Rows past the layout read its last row (their lanes are
+// masked by the caller).
+template <int R>
+__device__ __forceinline__ void dst_of_whole_rows(const GraphArgs& g, const uint32_t (&p)[R],
+                                                  uint32_t (&dst)[R]) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)(p[i] >> 6));
+        const uint32_t rc = r < g.rows ? r : g.rows - 1;
+        const uint64_t m1 = g.rowmask[rc] & ~1ull;
+        const uint32_t sg = g.rowseg[rc];
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
+        dst[i] = g.nzdst[sg + below + (lane_bit(m1) ? 1u : 0u)];
+    }
+}
+
 // Next-frontier bits of one row: every destination segment whose head lane
 // has `commit` set gets its bit, with one atomicOr per distinct bitmap word
 // (consecutive destinations share words, so a row of 64 positions needs one
@@ -541,7 +560,8 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
         for (int i = 0; i < R; ++i)
             wt[i] = APP == kSssp ? (Edges::kPacked ? (u[i] & 255u) : ld_stream(g.in_w + pc[i])) : 0u;
     }
-    dst_of_rows<R>(g, pc, dst);
+    if (ROWS) dst_of_whole_rows<R>(g, p, dst);
+    else dst_of_rows<R>(g, pc, dst);
 #pragma unroll
     for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst[i] : kInf;
 #ifdef WEDGE_DEBUG_CHECKS

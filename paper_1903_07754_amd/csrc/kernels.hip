@@ -397,7 +397,17 @@ __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gathe
             const uint64_t w = g.rowmask[r < g.rows ? r : g.rows - 1];
             mk[j] = r < g.rows ? w : 1ull;  // past the last row: a segment start
         }
-        dst_of_rows<B>(g, pc, dst);
+        // the rows are wave-uniform: their segment indices are scalar loads
+        // and a lane's segment is counted with mbcnt
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const uint64_t r = r0 + i0 + j;
+            const uint32_t sg = g.rowseg[r < g.rows ? r : g.rows - 1];
+            const uint64_t m1 = mk[j] & ~1ull;
+            const uint32_t below =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
+            dst[j] = g.nzdst[sg + below + (lane_bit(m1) ? 1u : 0u)];
+        }
         // dst is only used by the head lanes' stores; pinning it here keeps
         // the compiler from sinking its loads into those branches, which
         // would serialise them row by row
