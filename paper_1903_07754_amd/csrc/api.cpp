@@ -705,17 +705,24 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur,
                                    w.csum, w.ctl, s), "seeding source");
     }
+    // a synchronous CC/SSSP full pull sets no bits: its finalisation takes the
+    // next frontier from val < val_prev (set by the pull, read by the
+    // finalisation of the same iteration)
+    bool bits_from_values = false;
     st = iterate(
         g, w, o, c, s, local, t0, stats,
         [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
+            bits_from_values = app != kBfs && !inplace && !wedge_mode;
             return wedge_mode ? launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev,
                                                    w.fcur, w.fbits, w.fsum, s, c.rows, inplace)
                               : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, w.fsum, s, c.rows, inplace);
         },
         [&](uint32_t, int cur) {
+            const bool fv = bits_from_values;
+            bits_from_values = false;  // a push iteration runs no pull
             // the in-place pull reads no committed copy, so nothing is committed
             return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                   inplace ? nullptr : vprev, val, w.fcur, w.fsum, w.csum, s);
+                                   inplace ? nullptr : vprev, val, w.fcur, w.fsum, w.csum, s, fv);
         });
     if (st != WEDGE_OK) return st;
     if (d.inv) {
@@ -1679,7 +1686,8 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
                                            vprev, w.fcur, w.fbits, w.fsum, s), "chunk pull");
             }
             HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                    vprev, val, w.fcur, w.fsum, w.csum, s), "frontier finalisation");
+                                    vprev, val, w.fcur, w.fsum, w.csum, s, mi == 0 && app != kBfs),
+                    "frontier finalisation");
             HIP_TRY(hipEventRecord(w.ev[1], s), "event");
             HIP_TRY(hipEventSynchronize(w.ev[1]), "trace iteration");
             HIP_TRY(hipEventElapsedTime(&t[mi], w.ev[0], w.ev[1]), "event time");

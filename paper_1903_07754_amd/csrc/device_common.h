@@ -285,13 +285,19 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
 // summary flag's range) are the summaries of bits and copy_to: a block whose
 // flags are both clear returns at once (nothing set, nothing to clear); a
 // processed block clears its bits flag and hands it to copy_to's.
-template <int WAVES, bool DEG, bool COPY, int G, class LoadSet, class OnSet, class OnOld>
+//
+// FROMVAL: the set bits are not read from `bits` (which stays all-zero) but
+// are the vertices v < limit with cmp_new[v] < cmp_old[v], the vertices a
+// synchronous pull lowered; load_set(v) is then cmp_new[v], read with them.
+// Every block is processed, and copy_to's flag says whether any bit was set.
+template <int WAVES, bool DEG, bool COPY, int G, bool FROMVAL = false, class LoadSet, class OnSet, class OnOld>
 __device__ __forceinline__ void bitmap_compact_block_ex(
     uint64_t vblock, uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits,
-    uint32_t* __restrict__ sum_copy, LoadSet load_set, OnSet on_set, OnOld on_old) {
+    uint32_t* __restrict__ sum_copy, LoadSet load_set, OnSet on_set, OnOld on_old,
+    const uint32_t* __restrict__ cmp_new = nullptr, const uint32_t* __restrict__ cmp_old = nullptr) {
     __shared__ unsigned long long s_wave[WAVES];
     __shared__ unsigned long long s_all[WAVES];
     __shared__ unsigned long long s_base;
@@ -300,7 +306,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
     __syncthreads();
     constexpr bool kSummed = WAVES * G * 64 == (1 << kSumShift);
     uint32_t fb = 1u;
-    if (kSummed && sum_bits) {
+    if (kSummed && sum_bits && !FROMVAL) {
         // block-uniform: every thread reads the same flags and leaves together
         fb = sum_bits[vblock];
         const uint32_t fc = (COPY && sum_copy) ? sum_copy[vblock] : 0u;
@@ -312,18 +318,40 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
     uint64_t mk[G], lm[G], old[G], pre[G];
     uint32_t deg[G], r0[G], r1[G];
     uint64_t cnt = 0, all = 0, dsum = 0;
+    uint32_t xn[G];
+    if (FROMVAL) {
+        uint32_t xo[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const uint64_t wi = w0 + g;
-        const uint64_t wc = wi < words ? wi : words - 1;
-        mk[g] = bits[wc];
-        old[g] = COPY ? copy_to[wc] : 0ull;
-    }
+        for (int g = 0; g < G; ++g) {
+            const uint64_t wc = w0 + g < words ? w0 + g : words - 1;
+            const uint32_t v = (uint32_t)(wc * 64 + lane);
+            const uint32_t vc = v < limit ? v : 0u;
+            xn[g] = cmp_new[vc];
+            xo[g] = cmp_old[vc];
+            old[g] = COPY ? copy_to[wc] : 0ull;
+        }
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        __asm__ volatile("" : "+v"(mk[g]));
-        if (COPY) __asm__ volatile("" : "+v"(old[g]));
-        mk[g] = w0 + g < words ? mk[g] : 0ull;
+        for (int g = 0; g < G; ++g) {
+            __asm__ volatile("" : "+v"(xn[g]));
+            __asm__ volatile("" : "+v"(xo[g]));
+            if (COPY) __asm__ volatile("" : "+v"(old[g]));
+            const uint32_t v = (uint32_t)((w0 + g) * 64 + lane);
+            mk[g] = __ballot(w0 + g < words && v < limit && xn[g] < xo[g]);
+        }
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint64_t wi = w0 + g;
+            const uint64_t wc = wi < words ? wi : words - 1;
+            mk[g] = bits[wc];
+            old[g] = COPY ? copy_to[wc] : 0ull;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            __asm__ volatile("" : "+v"(mk[g]));
+            if (COPY) __asm__ volatile("" : "+v"(old[g]));
+            mk[g] = w0 + g < words ? mk[g] : 0ull;
+        }
     }
     // per set bit: out-degree bounds and the caller's value (a lane whose bit
     // is clear reads vertex 0's, which is then ignored)
@@ -336,7 +364,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
             r0[g] = row_off[vs];
             r1[g] = row_off[vs + 1];
         }
-        pre[g] = load_set(vs);
+        pre[g] = FROMVAL ? xn[g] : load_set(vs);
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -344,7 +372,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
             __asm__ volatile("" : "+v"(r0[g]));
             __asm__ volatile("" : "+v"(r1[g]));
         }
-        __asm__ volatile("" : "+v"(pre[g]));
+        if (!FROMVAL) __asm__ volatile("" : "+v"(pre[g]));
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -363,8 +391,9 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
     }
     if (lane == 0) { s_wave[wid] = (cnt << kDegBits) | dsum; s_all[wid] = all; }
     __syncthreads();
+    unsigned long long a = 0;  // set bits of the block (thread 0)
     if (threadIdx.x == 0) {
-        unsigned long long t = 0, a = 0;
+        unsigned long long t = 0;
         for (int i = 0; i < WAVES; ++i) { t += s_wave[i]; a += s_all[i]; }
         s_base = t ? atomicAdd(counter, t) : 0ull;
         if (total && a) atomicAdd(total, a);
@@ -384,7 +413,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
         }
         if (!mk[g]) continue;
         if (lane_bit(mk[g]) && v < limit) on_set(v, pre[g]);
-        if (lane == 0) bits[wi] = 0ull;
+        if (!FROMVAL && lane == 0) bits[wi] = 0ull;
         if (!lm[g]) continue;
         const bool act = lane_bit(lm[g]);
         const uint32_t rank = (uint32_t)__popcll(lm[g] & mask_lt(lane));
@@ -403,7 +432,8 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
     }
     if (kSummed && threadIdx.x == 0) {
         if (sum_bits) sum_bits[vblock] = 0u;
-        if (COPY && sum_copy) sum_copy[vblock] = fb;  // copy_to now holds what bits held
+        // copy_to now holds what bits held
+        if (COPY && sum_copy) sum_copy[vblock] = FROMVAL ? (a != 0ull ? 1u : 0u) : fb;
     }
 }
 
@@ -483,6 +513,12 @@ __device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint3
 // per position, SSSP weights in their own array), or the source-sliced copy,
 // whose words may pack (slice-local source << 8) | weight and whose slice's
 // highest-out-degree sources can have their values staged in LDS.
+//
+// BITS = false (CC and SSSP full pulls that read val_prev): no next-frontier
+// bits are set. At the start of such an iteration val equals val_prev, so
+// the vertices this pull lowers are exactly those with val < val_prev
+// afterwards, and the finalisation derives the bitmap from the two arrays
+// (one streaming pass) instead of every row building its bitmap words.
 struct CanonicalEdges {
     static constexpr bool kPacked = false;
     __device__ __forceinline__ uint32_t gather(const uint32_t* __restrict__ src, uint32_t u) const {
@@ -536,7 +572,8 @@ struct SliceEdges {
     }
 };
 
-template <int APP, int R, bool ROWS = false, bool INPLACE = false, class Edges = CanonicalEdges>
+template <int APP, int R, bool ROWS = false, bool INPLACE = false, class Edges = CanonicalEdges,
+          bool BITS = true>
 __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&p)[R],
                                            const bool (&valid)[R], uint32_t iter,
                                            uint32_t* __restrict__ val,
@@ -546,6 +583,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                                            uint32_t* __restrict__ fsum,
                                            const Edges edges = Edges{}) {
     static_assert(ROWS || !Edges::kPacked, "the chunk pulls read the canonical arrays");
+    static_assert(BITS || (APP != kBfs && !INPLACE), "bits come from values only against val_prev");
     const int lane = lane_id();
     // loads are branch-free: a lane without an edge reads position 0 (its
     // results are masked), so all rows' loads of one step are in flight at once
@@ -682,13 +720,14 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                 if (shared) atomicMin(val + dst[i], best);
                 else val[dst[i]] = best;
             }
-            set_bits_row(fbits, fsum, dst[i], commit, heads, lane);
+            if (BITS) set_bits_row(fbits, fsum, dst[i], commit, heads, lane);
             lane0_first = lane0_first && defer == 0;
         }
     }
 }
 
-template <bool DEG, bool COMMIT, bool COPY, int G, int WAVES = kWavesPerBlock>
+// FROMVAL (with COMMIT): the set bits are the vertices with val < val_prev.
+template <bool DEG, bool COMMIT, bool COPY, int G, int WAVES = kWavesPerBlock, bool FROMVAL = false>
 __device__ __forceinline__ void bitmap_compact_block(
     uint64_t vblock, uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
@@ -696,10 +735,12 @@ __device__ __forceinline__ void bitmap_compact_block(
     uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
     uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits = nullptr,
     uint32_t* __restrict__ sum_copy = nullptr) {
-    bitmap_compact_block_ex<WAVES, DEG, COPY, G>(
+    static_assert(!FROMVAL || COMMIT, "bits from values compare against the committed copy");
+    bitmap_compact_block_ex<WAVES, DEG, COPY, G, FROMVAL>(
         vblock, bits, words, limit, row_off, list, degpre, counter, total, copy_to, sum_bits, sum_copy,
         [&](uint32_t v) -> uint64_t { return COMMIT ? val[v] : 0u; },
-        [&](uint32_t v, uint64_t x) { if (COMMIT) val_prev[v] = (uint32_t)x; }, [](uint32_t) {});
+        [&](uint32_t v, uint64_t x) { if (COMMIT) val_prev[v] = (uint32_t)x; }, [](uint32_t) {},
+        FROMVAL ? val : nullptr, FROMVAL ? val_prev : nullptr);
 }
 
 // Positions covered by lane `lane` of the chunk-list slots s0 .. s0+R-1: a

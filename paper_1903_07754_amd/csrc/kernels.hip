@@ -168,6 +168,22 @@ __global__ __launch_bounds__(kCompactWaves * 64) void k_bitmap_compact(
                                                               val, copy_to, sum_bits, sum_copy);
 }
 
+// The finalisation after a synchronous CC/SSSP full pull, which sets no
+// bits: the next frontier is every vertex with val < val_prev (the vertices
+// the pull lowered), listed and committed as k_bitmap_compact<true, true,
+// true> does for the bits a pull sets.
+template <int G>
+__global__ __launch_bounds__(kCompactWaves * 64) void k_finalize_from_values(
+    uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
+    const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
+    uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
+    uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
+    uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits, uint32_t* __restrict__ sum_copy) {
+    bitmap_compact_block<true, true, true, G, kCompactWaves, true>(blockIdx.x, bits, words, limit, row_off,
+                                                                  list, degpre, counter, total, val_prev,
+                                                                  val, copy_to, sum_bits, sum_copy);
+}
+
 // ------------------------------------------------------------- the pulls
 //
 // One lane per in-edge position. A lane reads its destination from the row
@@ -213,7 +229,8 @@ __global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_full(Graph
         valid[i] = pp < g.m;
         p[i] = (uint32_t)pp;
     }
-    pull_lanes<APP, R, true, INPLACE>(g, p, valid, iter, val, val_prev, fcur, fbits, fsum);
+    pull_lanes<APP, R, true, INPLACE, CanonicalEdges, APP == kBfs || INPLACE>(g, p, valid, iter, val, val_prev,
+                                                                          fcur, fbits, fsum);
 }
 
 // BFS full pull: each block first copies the first `words` 32-bit words of
@@ -319,8 +336,8 @@ __global__ __launch_bounds__(kHotBlock) __attribute__((amdgpu_waves_per_eu(6))) 
             valid[i] = pp < edge_end;
             p[i] = (uint32_t)pp;
         }
-        pull_lanes<APP, R, true, INPLACE, SliceEdges<PACKED, !INPLACE>>(g, p, valid, iter, val, val_prev,
-                                                                      fcur, fbits, fsum, edges);
+        pull_lanes<APP, R, true, INPLACE, SliceEdges<PACKED, !INPLACE>, INPLACE>(g, p, valid, iter, val, val_prev,
+                                                                               fcur, fbits, fsum, edges);
     }
 }
 
@@ -832,14 +849,19 @@ hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list
 
 hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
                            uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
-                           uint64_t* fcur, uint32_t* fsum, uint32_t* csum, hipStream_t s) {
+                           uint64_t* fcur, uint32_t* fsum, uint32_t* csum, hipStream_t s,
+                           bool from_values) {
     const uint64_t words = ((uint64_t)n + 63) / 64;
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
     const uint32_t blocks = (uint32_t)((waves + kCompactWaves - 1) / kCompactWaves);
     unsigned long long* c = &ctl->fnext;
     unsigned long long* t = &ctl->ftotal;
-    if (val_prev && fcur)
+    if (from_values) {
+        if (!val_prev || !val || !fcur) return hipErrorInvalidValue;
+        k_finalize_from_values<kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
+            fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur, fsum, csum);
+    } else if (val_prev && fcur)
         k_bitmap_compact<true, true, true, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
             fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur, fsum, csum);
     else if (fcur)
