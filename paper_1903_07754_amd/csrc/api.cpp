@@ -217,16 +217,33 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     if (st == WEDGE_OK && g->weighted) st = upload(g, &d.in_w, L.in_w, stream, "in_w");
     if (st == WEDGE_OK) st = upload(g, &d.row_off, L.row_off, stream, "row_off");
     if (st == WEDGE_OK) st = upload(g, &d.pos, L.pos, stream, "pos");
-    if (st == WEDGE_OK) st = upload(g, &d.rowmask, L.rowmask, stream, "rowmask");
-    if (st == WEDGE_OK) st = upload(g, &d.rowseg, L.rowseg, stream, "rowseg");
+    // the row layouts go up with kRowPad rows of padding: the full pulls read
+    // a few rows past the end instead of clamping (a mask of 1 and the last
+    // segment index, which keep those rows' destination reads in bounds)
+    // (the padded copies live until the stream is synchronised below)
+    auto pad_masks = [](std::vector<uint64_t> mk) {
+        mk.insert(mk.end(), kRowPad, 1ull);
+        return mk;
+    };
+    auto pad_segs = [](std::vector<uint32_t> sg, size_t nz) {
+        sg.insert(sg.end(), kRowPad, nz ? (uint32_t)(nz - 1) : 0u);
+        return sg;
+    };
+    const std::vector<uint64_t> rowmask_p = pad_masks(L.rowmask);
+    const std::vector<uint32_t> rowseg_p = pad_segs(L.rowseg, L.nzdst.size());
+    const std::vector<uint64_t> xs_rowmask_p = d.xs_rows ? pad_masks(L.xs_rowmask) : std::vector<uint64_t>();
+    const std::vector<uint32_t> xs_rowseg_p =
+        d.xs_rows ? pad_segs(L.xs_rowseg, L.xs_nzdst.size()) : std::vector<uint32_t>();
+    if (st == WEDGE_OK) st = upload(g, &d.rowmask, rowmask_p, stream, "rowmask");
+    if (st == WEDGE_OK) st = upload(g, &d.rowseg, rowseg_p, stream, "rowseg");
     if (st == WEDGE_OK) st = upload(g, &d.nzdst, L.nzdst, stream, "nzdst");
     if (st == WEDGE_OK) st = upload(g, &d.spans, L.spans, stream, "spans");
     if (st == WEDGE_OK && !L.perm.empty()) st = upload(g, &d.perm, L.perm, stream, "perm");
     if (st == WEDGE_OK && !L.inv.empty()) st = upload(g, &d.inv, L.inv, stream, "inv");
     if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_src, L.xs_src, stream, "sliced in-edges");
     if (st == WEDGE_OK && d.xs_rows && !L.xs_w.empty()) st = upload(g, &d.xs_w, L.xs_w, stream, "sliced weights");
-    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowmask, L.xs_rowmask, stream, "sliced row masks");
-    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowseg, L.xs_rowseg, stream, "sliced row segments");
+    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowmask, xs_rowmask_p, stream, "sliced row masks");
+    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowseg, xs_rowseg_p, stream, "sliced row segments");
     if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_nzdst, L.xs_nzdst, stream, "sliced segment destinations");
     if (st == WEDGE_OK && d.xs_pspans) st = upload(g, &d.xs_pspan_v, L.xs_pspan_v, stream, "sliced PageRank spans");
     if (st == WEDGE_OK && d.xs_pspans) st = upload(g, &d.xs_pspan_off, L.xs_pspan_off, stream, "sliced PageRank span offsets");

@@ -457,23 +457,40 @@ __device__ __forceinline__ void dst_of_rows(const GraphArgs& g, const uint32_t (
         dst[i] = g.nzdst[sg[i] + (uint32_t)__popcll(mk[i] & ~1ull & mask_le((int)(pc[i] & 63)))];
 }
 
-// The same for R whole rows (the full pulls): lane l of row i holds position
-// row_i * 64 + l, row_i = p[i] >> 6 for every lane, so the row's mask and
-// segment index are wave-uniform (scalar loads), and a lane's segment is
-// counted with mbcnt. Rows past the layout read its last row (their lanes are
-// masked by the caller).
-template <int R>
-__device__ __forceinline__ void dst_of_whole_rows(const GraphArgs& g, const uint32_t (&p)[R],
-                                                  uint32_t (&dst)[R]) {
+// Wave-uniform read of a table no kernel writes, through the constant address
+// space: the compiler may then use a scalar load, and merges the reads of
+// consecutive entries into a few wide ones waited for once. (A vector load of
+// a uniform address is waited for before its value can move to a scalar
+// register, one entry at a time.)
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T* p, uint64_t i) {
+    typedef const __attribute__((address_space(4))) T ConstT;
+    return ((ConstT*)p)[i];
+}
+
+// Row layout of the N rows r0 .. r0 + N - 1 (r0 wave-uniform, below the
+// layout's row count): their masks and segment indices, and the mask of the
+// row after them. The device arrays carry kRowPad rows of padding (mask 1,
+// the last segment index), so rows past the layout need no clamp.
+template <int N>
+__device__ __forceinline__ void row_layout(const GraphArgs& g, uint64_t r0, uint64_t (&mk)[N + 1],
+                                           uint32_t (&sg)[N]) {
+    static_assert(N + 1 <= (int)kRowPad, "rows read past the layout stay in its padding");
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)(p[i] >> 6));
-        const uint32_t rc = r < g.rows ? r : g.rows - 1;
-        const uint64_t m1 = g.rowmask[rc] & ~1ull;
-        const uint32_t sg = g.rowseg[rc];
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
-        dst[i] = g.nzdst[sg + below + (lane_bit(m1) ? 1u : 0u)];
-    }
+    for (int i = 0; i <= N; ++i) mk[i] = ld_uniform(g.rowmask, r0 + (uint64_t)i);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sg[i] = ld_uniform(g.rowseg, r0 + (uint64_t)i);
+}
+
+// Destination of this lane's position in a whole row with mask mk and segment
+// index sg (the full pulls: lane l of the row holds position row * 64 + l):
+// the lane's segment is counted with mbcnt over the wave-uniform mask. A row
+// of the padding gives the last segment's destination (its lanes are masked
+// by the caller).
+__device__ __forceinline__ uint32_t dst_of_whole_row(const GraphArgs& g, uint64_t mk, uint32_t sg) {
+    const uint64_t m1 = mk & ~1ull;
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
+    return g.nzdst[sg + below + (lane_bit(m1) ? 1u : 0u)];
 }
 
 // Next-frontier bits of one row: every destination segment whose head lane
@@ -598,8 +615,17 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
         for (int i = 0; i < R; ++i)
             wt[i] = APP == kSssp ? (Edges::kPacked ? (u[i] & 255u) : ld_stream(g.in_w + pc[i])) : 0u;
     }
-    if (ROWS) dst_of_whole_rows<R>(g, p, dst);
-    else dst_of_rows<R>(g, pc, dst);
+    // ROWS: the wave's rows are r0 .. r0 + R - 1, their layout read once
+    uint64_t rmk[R + 1];
+    uint32_t rsg[R];
+    if constexpr (ROWS) {
+        const uint64_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p[0]) >> 6;
+        row_layout<R>(g, r0, rmk, rsg);
+#pragma unroll
+        for (int i = 0; i < R; ++i) dst[i] = dst_of_whole_row(g, rmk[i], rsg[i]);
+    } else {
+        dst_of_rows<R>(g, pc, dst);
+    }
 #pragma unroll
     for (int i = 0; i < R; ++i) dst[i] = valid[i] ? dst[i] : kInf;
 #ifdef WEDGE_DEBUG_CHECKS
@@ -635,9 +661,19 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const bool found = need[i];
-            const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
-            const bool head = lane == 0 || prev != dst[i];
-            const uint64_t heads = __ballot(head);
+            uint64_t heads;
+            bool head;
+            if constexpr (ROWS) {
+                // segment starts are the row's mask bits (consecutive segments
+                // have distinct destinations); every lane without an edge
+                // forms a segment of its own
+                heads = rmk[i] | 1ull | ~__ballot(valid[i]);
+                head = lane_bit(heads);
+            } else {
+                const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
+                head = lane == 0 || prev != dst[i];
+                heads = __ballot(head);
+            }
             const uint64_t fm = __ballot(found);
             bool commit = false;
             if (head && dst[i] != kInf) {
@@ -688,18 +724,25 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
         }
         uint32_t carry = kInf;
         bool first_shared = true, last_shared = true, lane0_first = true;
-        if (ROWS) {
-            const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane(pc[0]) >> 6;
-            first_shared = !(g.rowmask[r0] & 1ull);
-            const uint64_t rn = (uint64_t)r0 + R;
-            last_shared = rn < g.rows && !(g.rowmask[rn < g.rows ? rn : r0] & 1ull);
+        if constexpr (ROWS) {
+            // the row after the wave's rows is in the layout's padding (mask 1)
+            // when the wave holds the last rows
+            first_shared = !(rmk[0] & 1ull);
+            last_shared = !(rmk[R] & 1ull);
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const uint32_t cand = (APP == kCc || x[i] == kInf) ? x[i] : x[i] + wt[i];
-            const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
-            const bool head = lane == 0 || prev != dst[i];
-            const uint64_t heads = __ballot(head);
+            uint64_t heads;
+            bool head;
+            if constexpr (ROWS) {
+                heads = rmk[i] | 1ull | ~__ballot(valid[i]);  // as in the BFS branch
+                head = lane_bit(heads);
+            } else {
+                const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
+                head = lane == 0 || prev != dst[i];
+                heads = __ballot(head);
+            }
             const uint64_t hv = heads & __ballot(valid[i]);
             uint32_t best = seg_reduce(cand, heads,
                                        [](uint32_t a, uint32_t b) { return a < b ? a : b; });

@@ -391,40 +391,26 @@ __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gathe
     bool from_before = false;
     // Rows are loaded B at a time and reduced in order; the carry links
     // segments across rows and batches. Loads are branch-free (a lane past
-    // the last edge reads position 0 and is masked) so that the batch's
-    // memory round trips overlap.
+    // the last edge reads the last position and is masked) so that the
+    // batch's memory round trips overlap. Which lanes hold an edge, and where
+    // segments start, are wave-uniform masks built by the scalar unit from
+    // the row's mask and the edge count.
 #pragma unroll
     for (int i0 = 0; i0 < R; i0 += B) {
         if (r0 + i0 >= g.rows) break;
-        uint32_t pc[B], u[B], dst[B];
+        uint32_t pc[B], u[B], dst[B], sg[B];
         uint64_t mk[B + 1];
-        bool valid[B];
         float x[B];
+        // the rows' layout: scalar loads (rows past the end read the layout's
+        // padding, whose mask 1 marks a segment start)
+        row_layout<B>(g, r0 + i0, mk, sg);
 #pragma unroll
-        for (int j = 0; j < B; ++j) {
-            const uint64_t pp = (r0 + i0 + j) * 64 + lane;
-            valid[j] = (r0 + i0 + j) < g.rows && pp < g.m;
-            pc[j] = valid[j] ? (uint32_t)pp : 0u;
-        }
+        for (int j = 0; j < B; ++j) pc[j] = (uint32_t)umin64((r0 + i0 + j) * 64 + lane, g.m - 1);
 #pragma unroll
         for (int j = 0; j < B; ++j) u[j] = ld_stream(g.in_src + pc[j]);
+        // a lane's segment is counted with mbcnt over the row's mask
 #pragma unroll
-        for (int j = 0; j <= B; ++j) {
-            const uint64_t r = r0 + i0 + j;
-            const uint64_t w = g.rowmask[r < g.rows ? r : g.rows - 1];
-            mk[j] = r < g.rows ? w : 1ull;  // past the last row: a segment start
-        }
-        // the rows are wave-uniform: their segment indices are scalar loads
-        // and a lane's segment is counted with mbcnt
-#pragma unroll
-        for (int j = 0; j < B; ++j) {
-            const uint64_t r = r0 + i0 + j;
-            const uint32_t sg = g.rowseg[r < g.rows ? r : g.rows - 1];
-            const uint64_t m1 = mk[j] & ~1ull;
-            const uint32_t below =
-                __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
-            dst[j] = g.nzdst[sg + below + (lane_bit(m1) ? 1u : 0u)];
-        }
+        for (int j = 0; j < B; ++j) dst[j] = dst_of_whole_row(g, mk[j], sg[j]);
         // dst is only used by the head lanes' stores; pinning it here keeps
         // the compiler from sinking its loads into those branches, which
         // would serialise them row by row
@@ -437,21 +423,22 @@ __device__ __forceinline__ void pr_tile(const GraphArgs& g, uint64_t tile, Gathe
             const int i = i0 + j;
             const uint64_t r = r0 + i;
             if (r >= g.rows) break;
-            const uint64_t row_end = umin64(r * 64 + 64, g.m);
+            // edges from this row's first position on (none in the rows that
+            // pad a slice up to its aligned end); lanes past the last edge hold
+            // none, and the first of them starts a segment of its own
+            const uint64_t left = g.m > r * 64 ? g.m - r * 64 : 0ull;
+            const uint64_t vmask = left >= 64 ? ~0ull : ((1ull << left) - 1ull);
+            const uint64_t heads = mk[j] | 1ull | (left >= 64 ? 0ull : (1ull << left));
             const bool cont_in = !(mk[j] & 1ull);
-            const bool cont_out = row_end < g.m && !(mk[j + 1] & 1ull);
+            const bool cont_out = left > 64 && !(mk[j + 1] & 1ull);
             const bool last_row = (i == R - 1) || (r + 1 >= g.rows);
-            const uint64_t pp = r * 64 + lane;
-            const bool head = lane == 0 || lane_bit(mk[j]) || pp == g.m;
-            const uint64_t heads = __ballot(head);
-            const uint64_t vmask = __ballot(valid[j]);
-            float s = seg_reduce(valid[j] ? x[j] : 0.0f, heads,
+            float s = seg_reduce(lane_bit(vmask) ? x[j] : 0.0f, heads,
                                  [](float a, float b) { return a + b; });
             if (i == 0) from_before = cont_in;
             if (lane == 0 && cont_in) s = carry + s;
             const uint64_t hv = heads & vmask;
             const int h_last = 63 - __clzll(hv);
-            if (head && valid[j]) {
+            if (lane_bit(hv)) {
                 const bool seg_before = lane == 0 && cont_in && from_before;
                 if (lane == h_last && cont_out) {
                     if (last_row) {

@@ -97,6 +97,10 @@ constexpr uint64_t kSliceValueBytes = 8ull << 20;
 uint32_t xs_slices_lg(uint64_t sources);
 // The packed sliced copy: (slice-local source << 8) | weight in one word.
 constexpr uint32_t kXsPackMaxW = 255;
+// Rows of padding after the row layout's masks and segment indices on the
+// device (mask 1, the last segment index): the full pulls read the entries of
+// a wave's rows and the row after them without clamping to the layout.
+constexpr uint32_t kRowPad = 32;
 constexpr uint64_t kXsPackMaxN = 1ull << 27;  // slice-local ids below 2^24 (at least 8 slices)
 
 // Builds the source-sliced copy of L's in-edges (L must hold the canonical layout).
