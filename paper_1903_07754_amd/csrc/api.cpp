@@ -722,24 +722,25 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur,
                                    w.csum, w.ctl, s), "seeding source");
     }
-    // a synchronous CC/SSSP full pull sets no bits: its finalisation takes the
-    // next frontier from val < val_prev (set by the pull, read by the
-    // finalisation of the same iteration)
+    // a full pull (BFS, or synchronous CC/SSSP) sets no bits: its
+    // finalisation takes the next frontier from the values (val < val_prev,
+    // or val == k + 1 for BFS; set by the pull, read by the finalisation of
+    // the same iteration)
     bool bits_from_values = false;
     st = iterate(
         g, w, o, c, s, local, t0, stats,
         [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
-            bits_from_values = app != kBfs && !inplace && !wedge_mode;
+            bits_from_values = !inplace && !wedge_mode;
             return wedge_mode ? launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev,
                                                    w.fcur, w.fbits, w.fsum, s, c.rows, inplace)
                               : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, w.fsum, s, c.rows, inplace);
         },
-        [&](uint32_t, int cur) {
+        [&](uint32_t k, int cur) {
             const bool fv = bits_from_values;
             bits_from_values = false;  // a push iteration runs no pull
             // the in-place pull reads no committed copy, so nothing is committed
             return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                   inplace ? nullptr : vprev, val, w.fcur, w.fsum, w.csum, s, fv);
+                                   inplace ? nullptr : vprev, val, w.fcur, w.fsum, w.csum, s, fv, k + 1);
         });
     if (st != WEDGE_OK) return st;
     if (d.inv) {
@@ -856,16 +857,20 @@ wedge_status run_bfs_noalloc(wedge_graph_t g, uint32_t src, uint32_t* out, const
     HIP_TRY(launch_fill_u32(val, d.n, kInf, s), "initialising values");
     HIP_TRY(launch_seed_source(isrc, d.row_off, val, nullptr, w.flist[0], w.degpre[0], w.fcur, w.csum, w.ctl, s),
             "seeding source");
+    bool bits_from_values = false;  // a full pull sets no bits (see run_frontier_app)
     st = iterate(
         g, w, o, c, s, local, t0, stats,
         [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
+            bits_from_values = !wedge_mode;
             return wedge_mode ? launch_pull_chunks(kBfs, d, k, lc, w.chunks, w.ctl, maxk, val, nullptr,
                                                    w.fcur, w.fbits, w.fsum, s, c.rows)
                               : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, w.fsum, s, c.rows);
         },
-        [&](uint32_t, int cur) {
+        [&](uint32_t k, int cur) {
+            const bool fv = bits_from_values;
+            bits_from_values = false;
             return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                   nullptr, val, w.fcur, w.fsum, w.csum, s);
+                                   nullptr, val, w.fcur, w.fsum, w.csum, s, fv, k + 1);
         });
     if (st != WEDGE_OK) {
         (void)hipStreamSynchronize(s);  // the next user of the scratch must not meet this run's kernels
@@ -1120,16 +1125,20 @@ wedge_status run_bfs_roots(wedge_graph_t g, const uint32_t* roots, uint32_t coun
         HIP_TRY(launch_roots_seed(w.roots, count, val, w.fbits, w.fsum, s), "seeding roots");
         HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[0], w.degpre[0], w.ctl, nullptr, nullptr,
                                 w.fcur, w.fsum, w.csum, s), "listing roots");
+        bool bits_from_values = false;  // a full pull sets no bits (see run_frontier_app)
         st = iterate(
             g, w, o, c, s, local, t0, stats,
             [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
+                bits_from_values = !wedge_mode;
                 return wedge_mode ? launch_pull_chunks(kBfs, d, k, lc, w.chunks, w.ctl, maxk, val,
                                                        nullptr, w.fcur, w.fbits, w.fsum, s, c.rows)
                                   : launch_pull_full(kBfs, d, k, val, nullptr, w.fcur, w.fbits, w.fsum, s, c.rows);
             },
-            [&](uint32_t, int cur) {
+            [&](uint32_t k, int cur) {
+                const bool fv = bits_from_values;
+                bits_from_values = false;
                 return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1],
-                                       w.ctl, nullptr, val, w.fcur, w.fsum, w.csum, s);
+                                       w.ctl, nullptr, val, w.fcur, w.fsum, w.csum, s, fv, k + 1);
             });
         if (st == WEDGE_OK && d.inv) {
             HIP_TRY(launch_unpermute_u32(d.n, d.perm, val, out, s), "writing results");
@@ -1703,7 +1712,7 @@ wedge_status wedge_trace_counterfactual(wedge_graph_t g, uint32_t app, uint32_t 
                                            vprev, w.fcur, w.fbits, w.fsum, s), "chunk pull");
             }
             HIP_TRY(launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                    vprev, val, w.fcur, w.fsum, w.csum, s, mi == 0 && app != kBfs),
+                                    vprev, val, w.fcur, w.fsum, w.csum, s, mi == 0, k + 1),
                     "frontier finalisation");
             HIP_TRY(hipEventRecord(w.ev[1], s), "event");
             HIP_TRY(hipEventSynchronize(w.ev[1]), "trace iteration");

@@ -287,9 +287,11 @@ __device__ __forceinline__ void translate_wave(uint64_t wave, const uint32_t* __
 // processed block clears its bits flag and hands it to copy_to's.
 //
 // FROMVAL: the set bits are not read from `bits` (which stays all-zero) but
-// are the vertices v < limit with cmp_new[v] < cmp_old[v], the vertices a
-// synchronous pull lowered; load_set(v) is then cmp_new[v], read with them.
-// Every block is processed, and copy_to's flag says whether any bit was set.
+// are the vertices v < limit with cmp_new[v] < cmp_old[v] (the vertices a
+// synchronous CC/SSSP pull lowered) or, without cmp_old, with cmp_new[v] ==
+// level (the vertices a BFS pull reached); load_set(v) is then cmp_new[v],
+// read with them. Every block is processed, and copy_to's flag says whether
+// any bit was set.
 template <int WAVES, bool DEG, bool COPY, int G, bool FROMVAL = false, class LoadSet, class OnSet, class OnOld>
 __device__ __forceinline__ void bitmap_compact_block_ex(
     uint64_t vblock, uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
@@ -297,7 +299,8 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits,
     uint32_t* __restrict__ sum_copy, LoadSet load_set, OnSet on_set, OnOld on_old,
-    const uint32_t* __restrict__ cmp_new = nullptr, const uint32_t* __restrict__ cmp_old = nullptr) {
+    const uint32_t* __restrict__ cmp_new = nullptr, const uint32_t* __restrict__ cmp_old = nullptr,
+    uint32_t level = 0) {
     __shared__ unsigned long long s_wave[WAVES];
     __shared__ unsigned long long s_all[WAVES];
     __shared__ unsigned long long s_base;
@@ -327,7 +330,7 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
             const uint32_t v = (uint32_t)(wc * 64 + lane);
             const uint32_t vc = v < limit ? v : 0u;
             xn[g] = cmp_new[vc];
-            xo[g] = cmp_old[vc];
+            xo[g] = cmp_old ? cmp_old[vc] : 0u;
             old[g] = COPY ? copy_to[wc] : 0ull;
         }
 #pragma unroll
@@ -336,7 +339,8 @@ __device__ __forceinline__ void bitmap_compact_block_ex(
             __asm__ volatile("" : "+v"(xo[g]));
             if (COPY) __asm__ volatile("" : "+v"(old[g]));
             const uint32_t v = (uint32_t)((w0 + g) * 64 + lane);
-            mk[g] = __ballot(w0 + g < words && v < limit && xn[g] < xo[g]);
+            const bool changed = cmp_old ? xn[g] < xo[g] : xn[g] == level;
+            mk[g] = __ballot(w0 + g < words && v < limit && changed);
         }
     } else {
 #pragma unroll
@@ -531,11 +535,13 @@ __device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint3
 // whose words may pack (slice-local source << 8) | weight and whose slice's
 // highest-out-degree sources can have their values staged in LDS.
 //
-// BITS = false (CC and SSSP full pulls that read val_prev): no next-frontier
-// bits are set. At the start of such an iteration val equals val_prev, so
-// the vertices this pull lowers are exactly those with val < val_prev
-// afterwards, and the finalisation derives the bitmap from the two arrays
-// (one streaming pass) instead of every row building its bitmap words.
+// BITS = false (full pulls): no next-frontier bits are set. CC and SSSP
+// reading val_prev: at the start of such an iteration val equals val_prev,
+// so the vertices this pull lowers are exactly those with val < val_prev
+// afterwards. BFS: the vertices this pull reaches are exactly those with
+// val == iter + 1 afterwards (no earlier iteration wrote that level). The
+// finalisation derives the bitmap from the values (one streaming pass)
+// instead of every row building its bitmap words.
 struct CanonicalEdges {
     static constexpr bool kPacked = false;
     __device__ __forceinline__ uint32_t gather(const uint32_t* __restrict__ src, uint32_t u) const {
@@ -600,7 +606,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                                            uint32_t* __restrict__ fsum,
                                            const Edges edges = Edges{}) {
     static_assert(ROWS || !Edges::kPacked, "the chunk pulls read the canonical arrays");
-    static_assert(BITS || (APP != kBfs && !INPLACE), "bits come from values only against val_prev");
+    static_assert(BITS || !INPLACE, "an in-place pull keeps no committed copy to compare with");
     const int lane = lane_id();
     // loads are branch-free: a lane without an edge reads position 0 (its
     // results are masked), so all rows' loads of one step are in flight at once
@@ -682,7 +688,7 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                 commit = ((fm >> lane) & seg) != 0;
                 if (commit) val[dst[i]] = iter + 1;
             }
-            set_bits_row(fbits, fsum, dst[i], commit, heads, lane);
+            if (BITS) set_bits_row(fbits, fsum, dst[i], commit, heads, lane);
         }
     } else {
         // All loads of the R rows are issued before any result is used, and
@@ -769,7 +775,8 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
     }
 }
 
-// FROMVAL (with COMMIT): the set bits are the vertices with val < val_prev.
+// FROMVAL: the set bits are the vertices with val < val_prev (COMMIT) or
+// with val == level (BFS, without COMMIT).
 template <bool DEG, bool COMMIT, bool COPY, int G, int WAVES = kWavesPerBlock, bool FROMVAL = false>
 __device__ __forceinline__ void bitmap_compact_block(
     uint64_t vblock, uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
@@ -777,13 +784,12 @@ __device__ __forceinline__ void bitmap_compact_block(
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
     uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits = nullptr,
-    uint32_t* __restrict__ sum_copy = nullptr) {
-    static_assert(!FROMVAL || COMMIT, "bits from values compare against the committed copy");
+    uint32_t* __restrict__ sum_copy = nullptr, uint32_t level = 0) {
     bitmap_compact_block_ex<WAVES, DEG, COPY, G, FROMVAL>(
         vblock, bits, words, limit, row_off, list, degpre, counter, total, copy_to, sum_bits, sum_copy,
         [&](uint32_t v) -> uint64_t { return COMMIT ? val[v] : 0u; },
         [&](uint32_t v, uint64_t x) { if (COMMIT) val_prev[v] = (uint32_t)x; }, [](uint32_t) {},
-        FROMVAL ? val : nullptr, FROMVAL ? val_prev : nullptr);
+        FROMVAL ? val : nullptr, (FROMVAL && COMMIT) ? val_prev : nullptr, level);
 }
 
 // Positions covered by lane `lane` of the chunk-list slots s0 .. s0+R-1: a

@@ -168,20 +168,21 @@ __global__ __launch_bounds__(kCompactWaves * 64) void k_bitmap_compact(
                                                               val, copy_to, sum_bits, sum_copy);
 }
 
-// The finalisation after a synchronous CC/SSSP full pull, which sets no
-// bits: the next frontier is every vertex with val < val_prev (the vertices
-// the pull lowered), listed and committed as k_bitmap_compact<true, true,
-// true> does for the bits a pull sets.
-template <int G>
+// The finalisation after a full pull, which sets no bits: the next frontier
+// is every vertex with val < val_prev (COMMIT: CC and SSSP, the vertices the
+// pull lowered) or with val == level (BFS, the vertices the pull reached),
+// listed (and committed) as k_bitmap_compact does for the bits a pull sets.
+template <bool COMMIT, int G>
 __global__ __launch_bounds__(kCompactWaves * 64) void k_finalize_from_values(
     uint64_t* __restrict__ bits, uint64_t words, uint32_t limit,
     const uint32_t* __restrict__ row_off, uint32_t* __restrict__ list,
     uint32_t* __restrict__ degpre, unsigned long long* counter, unsigned long long* total,
     uint32_t* __restrict__ val_prev, const uint32_t* __restrict__ val,
-    uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits, uint32_t* __restrict__ sum_copy) {
-    bitmap_compact_block<true, true, true, G, kCompactWaves, true>(blockIdx.x, bits, words, limit, row_off,
-                                                                  list, degpre, counter, total, val_prev,
-                                                                  val, copy_to, sum_bits, sum_copy);
+    uint64_t* __restrict__ copy_to, uint32_t* __restrict__ sum_bits, uint32_t* __restrict__ sum_copy,
+    uint32_t level) {
+    bitmap_compact_block<true, COMMIT, true, G, kCompactWaves, true>(blockIdx.x, bits, words, limit, row_off,
+                                                                    list, degpre, counter, total, val_prev,
+                                                                    val, copy_to, sum_bits, sum_copy, level);
 }
 
 // ------------------------------------------------------------- the pulls
@@ -279,8 +280,8 @@ __global__ __launch_bounds__(kHotBlock) void k_pull_full_bfs(GraphArgs g, uint32
             valid[i] = pp < g.m;
             p[i] = (uint32_t)pp;
         }
-        pull_lanes<kBfs, R, true, false, HotFrontierEdges>(g, p, valid, iter, val, nullptr, fcur, fbits,
-                                                           fsum, edges);
+        pull_lanes<kBfs, R, true, false, HotFrontierEdges, false>(g, p, valid, iter, val, nullptr, fcur,
+                                                                  fbits, fsum, edges);
     }
 }
 
@@ -837,7 +838,7 @@ hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list
 hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
                            uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
                            uint64_t* fcur, uint32_t* fsum, uint32_t* csum, hipStream_t s,
-                           bool from_values) {
+                           bool from_values, uint32_t level) {
     const uint64_t words = ((uint64_t)n + 63) / 64;
     if (!words) return hipSuccess;
     const uint64_t waves = (words + kCompactWords - 1) / kCompactWords;
@@ -845,9 +846,13 @@ hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off,
     unsigned long long* c = &ctl->fnext;
     unsigned long long* t = &ctl->ftotal;
     if (from_values) {
-        if (!val_prev || !val || !fcur) return hipErrorInvalidValue;
-        k_finalize_from_values<kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
-            fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur, fsum, csum);
+        if (!val || !fcur) return hipErrorInvalidValue;
+        if (val_prev)
+            k_finalize_from_values<true, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
+                fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur, fsum, csum, 0u);
+        else
+            k_finalize_from_values<false, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
+                fbits, words, n, row_off, flist, degpre, c, t, nullptr, val, fcur, fsum, csum, level);
     } else if (val_prev && fcur)
         k_bitmap_compact<true, true, true, kCompactWords><<<blocks, kCompactWaves * 64, 0, s>>>(
             fbits, words, n, row_off, flist, degpre, c, t, val_prev, val, fcur, fsum, csum);

@@ -453,8 +453,8 @@ hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list
 // rows: 64-edge rows per wave step, 4, 8 or 16 for BFS, 8 for CC and SSSP
 // (anything else returns hipErrorInvalidValue before any launch).
 // inplace (CC and SSSP): gather sources' values from val instead of val_prev.
-// CC and SSSP without inplace set no next-frontier bits: finalise such an
-// iteration with launch_finalize(..., from_values = true).
+// BFS, and CC and SSSP without inplace, set no next-frontier bits: finalise
+// such an iteration with launch_finalize(..., from_values = true, iter + 1).
 hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
                             const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
                             uint32_t* fsum, hipStream_t s, int rows = kPullRows, bool inplace = false);
@@ -465,13 +465,13 @@ hipError_t launch_pull_chunks(int app, const DevGraph& g, uint32_t iter, int log
                               bool inplace = false);
 // Lists the next-frontier bitmap (with out-degree prefix), commits val to
 // val_prev for listed vertices (when val_prev is set), moves the bitmap into
-// fcur (when set) and clears it. from_values (after a synchronous CC/SSSP
-// full pull, which sets no bits; needs val_prev, val and fcur): the next
-// frontier is every vertex with val < val_prev instead.
+// fcur (when set) and clears it. from_values (after a full pull, which sets
+// no bits; needs val and fcur): the next frontier is every vertex with val <
+// val_prev (CC, SSSP) or, without val_prev, with val == level (BFS) instead.
 hipError_t launch_finalize(uint64_t* fbits, uint32_t n, const uint32_t* row_off, uint32_t* flist,
                            uint32_t* degpre, Ctl* ctl, uint32_t* val_prev, const uint32_t* val,
                            uint64_t* fcur, uint32_t* fsum, uint32_t* csum, hipStream_t s,
-                           bool from_values = false);
+                           bool from_values = false, uint32_t level = 0);
 // PageRank
 // PageRank contributions of a graph with the sliced copy are kept in
 // slice-major order: vertex v at slice_of(v) * cap + slice_local(v), cap the
