@@ -213,8 +213,17 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     st = WEDGE_OK;
     SetupLock upload_lock;
     if (st == WEDGE_OK) st = upload(g, &d.col_off, L.col_off, stream, "col_off");
-    if (st == WEDGE_OK) st = upload(g, &d.in_src, L.in_src, stream, "in_src");
-    if (st == WEDGE_OK && g->weighted) st = upload(g, &d.in_w, L.in_w, stream, "in_w");
+    // the in-edge arrays go up extended to whole rows plus kRowPad rows (zeros:
+    // vertex 0, weight 0), so the full pulls read every lane of a wave's rows
+    // without clamping
+    auto to_whole_rows = [](std::vector<uint32_t> a) {
+        a.resize(((a.size() + 63) / 64 + kRowPad) * 64, 0u);
+        return a;
+    };
+    const std::vector<uint32_t> in_src_p = to_whole_rows(L.in_src);
+    const std::vector<uint32_t> in_w_p = g->weighted ? to_whole_rows(L.in_w) : std::vector<uint32_t>();
+    if (st == WEDGE_OK) st = upload(g, &d.in_src, in_src_p, stream, "in_src");
+    if (st == WEDGE_OK && g->weighted) st = upload(g, &d.in_w, in_w_p, stream, "in_w");
     if (st == WEDGE_OK) st = upload(g, &d.row_off, L.row_off, stream, "row_off");
     if (st == WEDGE_OK) st = upload(g, &d.pos, L.pos, stream, "pos");
     // the row layouts go up with kRowPad rows of padding: the full pulls read
@@ -240,8 +249,10 @@ wedge_status create(bool from_csr, uint32_t n, uint64_t m, const uint64_t* off, 
     if (st == WEDGE_OK) st = upload(g, &d.spans, L.spans, stream, "spans");
     if (st == WEDGE_OK && !L.perm.empty()) st = upload(g, &d.perm, L.perm, stream, "perm");
     if (st == WEDGE_OK && !L.inv.empty()) st = upload(g, &d.inv, L.inv, stream, "inv");
-    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_src, L.xs_src, stream, "sliced in-edges");
-    if (st == WEDGE_OK && d.xs_rows && !L.xs_w.empty()) st = upload(g, &d.xs_w, L.xs_w, stream, "sliced weights");
+    const std::vector<uint32_t> xs_src_p = d.xs_rows ? to_whole_rows(L.xs_src) : std::vector<uint32_t>();
+    const std::vector<uint32_t> xs_w_p = d.xs_rows && !L.xs_w.empty() ? to_whole_rows(L.xs_w) : std::vector<uint32_t>();
+    if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_src, xs_src_p, stream, "sliced in-edges");
+    if (st == WEDGE_OK && d.xs_rows && !L.xs_w.empty()) st = upload(g, &d.xs_w, xs_w_p, stream, "sliced weights");
     if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowmask, xs_rowmask_p, stream, "sliced row masks");
     if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_rowseg, xs_rowseg_p, stream, "sliced row segments");
     if (st == WEDGE_OK && d.xs_rows) st = upload(g, &d.xs_nzdst, L.xs_nzdst, stream, "sliced segment destinations");

@@ -613,19 +613,26 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
     uint32_t pc[R], dst[R], u[R], wt[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) pc[i] = valid[i] ? p[i] : 0u;
+    // ROWS: the wave's rows are r0 .. r0 + R - 1. Their edge streams are read
+    // at a wave-uniform row address plus the lane (the in-edge arrays extend
+    // to whole rows: padded on the device, and the sliced copy by its layout)
+    const uint64_t r0 = ROWS ? (uint32_t)__builtin_amdgcn_readfirstlane((int)p[0]) >> 6 : 0u;
     if (APP != kBfs) {
         // the edge streams do not depend on the destinations: issue them first
 #pragma unroll
-        for (int i = 0; i < R; ++i) u[i] = ld_stream(g.in_src + pc[i]);
+        for (int i = 0; i < R; ++i)
+            u[i] = ld_stream(ROWS ? g.in_src + ((r0 + i) << 6) + lane : g.in_src + pc[i]);
 #pragma unroll
         for (int i = 0; i < R; ++i)
-            wt[i] = APP == kSssp ? (Edges::kPacked ? (u[i] & 255u) : ld_stream(g.in_w + pc[i])) : 0u;
+            wt[i] = APP == kSssp ? (Edges::kPacked ? (u[i] & 255u)
+                                                   : ld_stream(ROWS ? g.in_w + ((r0 + i) << 6) + lane
+                                                                    : g.in_w + pc[i]))
+                                 : 0u;
     }
-    // ROWS: the wave's rows are r0 .. r0 + R - 1, their layout read once
+    // ROWS: the rows' layout is read once
     uint64_t rmk[R + 1];
     uint32_t rsg[R];
     if constexpr (ROWS) {
-        const uint64_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p[0]) >> 6;
         row_layout<R>(g, r0, rmk, rsg);
 #pragma unroll
         for (int i = 0; i < R; ++i) dst[i] = dst_of_whole_row(g, rmk[i], rsg[i]);
@@ -738,7 +745,9 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const uint32_t cand = (APP == kCc || x[i] == kInf) ? x[i] : x[i] + wt[i];
+            // an unreached source (kInf) stays kInf; a reached one's sum does not
+            // overflow ((n - 1) * max weight < kInf)
+            const uint32_t cand = APP == kCc ? x[i] : __builtin_elementwise_add_sat(x[i], wt[i]);
             uint64_t heads;
             bool head;
             if constexpr (ROWS) {
@@ -756,18 +765,34 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
             carry = kInf;
             int defer = -1;
             const int h_last = hv ? 63 - __clzll(hv) : -1;
-            if (hv && i + 1 < R) {
-                if (lane_bcast(dst[i + 1], 0) == lane_bcast(dst[i], h_last)) {
+            bool commit;
+            if constexpr (ROWS) {
+                // the last segment runs on into the next row when that row's
+                // lane 0 holds an edge and starts no segment (then every lane
+                // of this row holds one, so the segment is h_last's); which
+                // lanes commit, and which of those share their destination
+                // with a neighbouring wave, are wave-uniform masks
+                if (hv && i + 1 < R && !(rmk[i + 1] & 1ull) && (__ballot(valid[i + 1]) & 1ull)) {
                     defer = h_last;
                     carry = lane_bcast(best, h_last);
                 }
-            }
-            const bool commit = head && valid[i] && lane != defer && best < cur[i];
-            if (commit) {
-                const bool shared = !ROWS || (lane == 0 && lane0_first && first_shared) ||
-                                    (i == R - 1 && lane == h_last && last_shared);
-                if (shared) atomicMin(val + dst[i], best);
-                else val[dst[i]] = best;
+                const uint64_t cm = defer >= 0 ? hv & ~(1ull << defer) : hv;
+                const uint64_t sm = ((lane0_first && first_shared) ? 1ull : 0ull) |
+                                    ((i == R - 1 && last_shared && h_last >= 0) ? (1ull << h_last) : 0ull);
+                commit = lane_bit(cm) && best < cur[i];
+                if (commit) {
+                    if (lane_bit(sm)) atomicMin(val + dst[i], best);
+                    else val[dst[i]] = best;
+                }
+            } else {
+                if (hv && i + 1 < R) {
+                    if (lane_bcast(dst[i + 1], 0) == lane_bcast(dst[i], h_last)) {
+                        defer = h_last;
+                        carry = lane_bcast(best, h_last);
+                    }
+                }
+                commit = head && valid[i] && lane != defer && best < cur[i];
+                if (commit) atomicMin(val + dst[i], best);
             }
             if (BITS) set_bits_row(fbits, fsum, dst[i], commit, heads, lane);
             lane0_first = lane0_first && defer == 0;
