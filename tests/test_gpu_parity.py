@@ -160,7 +160,23 @@ def test_per_iteration_frontier_sets(app, gate):
     off after k iterations (max_iters = k) leaves the values of iteration k in
     the caller's buffer, and the vertices whose value changed in iteration k-1
     must be exactly the oracle's frontier F_k (Background, Push vs. Pull: a
-    vertex is active when its value was updated)."""
+    vertex is active when its value was updated). After a full pull the next
+    frontier is taken from the values, after a chunk pull from the bits the
+    pull set: both must give F_k."""
+    check_frontier_sets(app, gate)
+
+
+@pytest.mark.parametrize("gate", ["threshold", "full"])
+@pytest.mark.parametrize("app", ["sssp", "cc"])
+def test_per_iteration_frontier_sets_sliced(monkeypatch, app, gate):
+    """The same with the CC/SSSP full pulls over the source-sliced copy
+    (forced on this small graph), one launch per slice before the frontier is
+    taken from the values."""
+    monkeypatch.setenv("WEDGE_SLICED_PULL", "1")
+    check_frontier_sets(app, gate, sliced=True)
+
+
+def check_frontier_sets(app, gate, sliced=False):
     ro, col = gen.rmat(12, 16, seed=13)
     n = len(ro) - 1
     w = gen.edge_weights(ro, col, seed=6) if app == "sssp" else None
@@ -175,6 +191,7 @@ def test_per_iteration_frontier_sets(app, gate):
         ref = oracle.pull_engine(app, ro, col, w, src, keep_frontiers=True)
         prev = np.full(n, 0xFFFFFFFF, np.uint32)
         prev[src] = 0
+    assert (g.info["xs_rows"] > 0) == sliced
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     run = {"bfs": lambda k: W.bfs(g, src, out=out, gate=gate, max_iters=k),
            "sssp": lambda k: W.sssp(g, src, out=out, gate=gate, max_iters=k),
