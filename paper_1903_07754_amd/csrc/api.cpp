@@ -733,15 +733,14 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         HIP_TRY(launch_seed_source(isrc, d.row_off, val, vprev, w.flist[0], w.degpre[0], w.fcur,
                                    w.csum, w.ctl, s), "seeding source");
     }
-    // a full pull (BFS, or synchronous CC/SSSP) sets no bits: its
-    // finalisation takes the next frontier from the values (val < val_prev,
-    // or val == k + 1 for BFS; set by the pull, read by the finalisation of
-    // the same iteration)
+    // a full pull sets no bits: its finalisation takes the next frontier from
+    // the values (val < val_prev, or val == k + 1 for BFS; set by the pull,
+    // read by the finalisation of the same iteration)
     bool bits_from_values = false;
     st = iterate(
         g, w, o, c, s, local, t0, stats,
         [&](uint32_t k, bool wedge_mode, uint64_t maxk, int, int lc) {
-            bits_from_values = !inplace && !wedge_mode;
+            bits_from_values = !wedge_mode;
             return wedge_mode ? launch_pull_chunks(app, d, k, lc, w.chunks, w.ctl, maxk, val, vprev,
                                                    w.fcur, w.fbits, w.fsum, s, c.rows, inplace)
                               : launch_pull_full(app, d, k, val, vprev, w.fcur, w.fbits, w.fsum, s, c.rows, inplace);
@@ -749,9 +748,10 @@ wedge_status run_frontier_app(int app, wedge_graph_t g, uint32_t src, uint32_t* 
         [&](uint32_t k, int cur) {
             const bool fv = bits_from_values;
             bits_from_values = false;  // a push iteration runs no pull
-            // the in-place pull reads no committed copy, so nothing is committed
+            // the in-place pull gathers no committed values, but the committed
+            // copy is kept: a full pull's next frontier is compared against it
             return launch_finalize(w.fbits, d.n, d.row_off, w.flist[cur ^ 1], w.degpre[cur ^ 1], w.ctl,
-                                   inplace ? nullptr : vprev, val, w.fcur, w.fsum, w.csum, s, fv, k + 1);
+                                   vprev, val, w.fcur, w.fsum, w.csum, s, fv, k + 1);
         });
     if (st != WEDGE_OK) return st;
     if (d.inv) {

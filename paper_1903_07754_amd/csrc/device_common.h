@@ -535,12 +535,13 @@ __device__ __forceinline__ void set_bits_row(uint64_t* __restrict__ fbits, uint3
 // whose words may pack (slice-local source << 8) | weight and whose slice's
 // highest-out-degree sources can have their values staged in LDS.
 //
-// BITS = false (full pulls): no next-frontier bits are set. CC and SSSP
-// reading val_prev: at the start of such an iteration val equals val_prev,
-// so the vertices this pull lowers are exactly those with val < val_prev
-// afterwards. BFS: the vertices this pull reaches are exactly those with
-// val == iter + 1 afterwards (no earlier iteration wrote that level). The
-// finalisation derives the bitmap from the values (one streaming pass)
+// BITS = false (full pulls): no next-frontier bits are set. CC and SSSP: at
+// the start of an iteration val equals val_prev, the committed copy (the
+// in-place pull keeps it too, only to compare against), and values only
+// fall, so the vertices this pull lowers are exactly those with val <
+// val_prev afterwards. BFS: the vertices this pull reaches are exactly those
+// with val == iter + 1 afterwards (no earlier iteration wrote that level).
+// The finalisation derives the bitmap from the values (one streaming pass)
 // instead of every row building its bitmap words.
 struct CanonicalEdges {
     static constexpr bool kPacked = false;
@@ -606,7 +607,6 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
                                            uint32_t* __restrict__ fsum,
                                            const Edges edges = Edges{}) {
     static_assert(ROWS || !Edges::kPacked, "the chunk pulls read the canonical arrays");
-    static_assert(BITS || !INPLACE, "an in-place pull keeps no committed copy to compare with");
     const int lane = lane_id();
     // loads are branch-free: a lane without an edge reads position 0 (its
     // results are masked), so all rows' loads of one step are in flight at once

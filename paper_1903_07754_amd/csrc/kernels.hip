@@ -230,8 +230,8 @@ __global__ __launch_bounds__(kBlock) WEDGE_PULL_OCCUPANCY void k_pull_full(Graph
         valid[i] = pp < g.m;
         p[i] = (uint32_t)pp;
     }
-    pull_lanes<APP, R, true, INPLACE, CanonicalEdges, APP == kBfs || INPLACE>(g, p, valid, iter, val, val_prev,
-                                                                          fcur, fbits, fsum);
+    static_assert(APP != kBfs, "the BFS full pull is k_pull_full_bfs");
+    pull_lanes<APP, R, true, INPLACE, CanonicalEdges, false>(g, p, valid, iter, val, val_prev, fcur, fbits, fsum);
 }
 
 // BFS full pull: each block first copies the first `words` 32-bit words of
@@ -337,8 +337,8 @@ __global__ __launch_bounds__(kHotBlock) __attribute__((amdgpu_waves_per_eu(6))) 
             valid[i] = pp < edge_end;
             p[i] = (uint32_t)pp;
         }
-        pull_lanes<APP, R, true, INPLACE, SliceEdges<PACKED, !INPLACE>, INPLACE>(g, p, valid, iter, val, val_prev,
-                                                                               fcur, fbits, fsum, edges);
+        pull_lanes<APP, R, true, INPLACE, SliceEdges<PACKED, !INPLACE>, false>(g, p, valid, iter, val, val_prev,
+                                                                             fcur, fbits, fsum, edges);
     }
 }
 

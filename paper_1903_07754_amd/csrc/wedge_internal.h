@@ -453,8 +453,9 @@ hipError_t launch_compact_chunks(uint64_t* wbits, uint64_t words, uint32_t* list
 // rows: 64-edge rows per wave step, 4, 8 or 16 for BFS, 8 for CC and SSSP
 // (anything else returns hipErrorInvalidValue before any launch).
 // inplace (CC and SSSP): gather sources' values from val instead of val_prev.
-// BFS, and CC and SSSP without inplace, set no next-frontier bits: finalise
-// such an iteration with launch_finalize(..., from_values = true, iter + 1).
+// Full pulls set no next-frontier bits: finalise such an iteration with
+// launch_finalize(..., from_values = true, iter + 1) (CC and SSSP, also in
+// place, with val_prev holding the values the iteration started from).
 hipError_t launch_pull_full(int app, const DevGraph& g, uint32_t iter, uint32_t* val,
                             const uint32_t* val_prev, const uint64_t* fcur, uint64_t* fbits,
                             uint32_t* fsum, hipStream_t s, int rows = kPullRows, bool inplace = false);
