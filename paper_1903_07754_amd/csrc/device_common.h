@@ -743,24 +743,40 @@ __device__ __forceinline__ void pull_lanes(const GraphArgs& g, const uint32_t (&
             first_shared = !(rmk[0] & 1ull);
             last_shared = !(rmk[R] & 1ull);
         }
+        // ROWS: the segment starts of a row are its mask bits (consecutive
+        // segments have distinct destinations), and every lane without an
+        // edge forms a segment of its own. The rows' reductions are
+        // independent of each other and of the commits: they run first, in
+        // one branch-free block, so that their dependent cross-lane steps
+        // overlap instead of waiting for each row's commit branches.
+        uint32_t red[R];
+        if constexpr (ROWS) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                // an unreached source (kInf) stays kInf; a reached one's sum
+                // does not overflow ((n - 1) * max weight < kInf)
+                const uint32_t cand = APP == kCc ? x[i] : __builtin_elementwise_add_sat(x[i], wt[i]);
+                red[i] = seg_reduce(cand, rmk[i] | 1ull | ~__ballot(valid[i]),
+                                    [](uint32_t a, uint32_t b) { return a < b ? a : b; });
+            }
+        }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            // an unreached source (kInf) stays kInf; a reached one's sum does not
-            // overflow ((n - 1) * max weight < kInf)
-            const uint32_t cand = APP == kCc ? x[i] : __builtin_elementwise_add_sat(x[i], wt[i]);
             uint64_t heads;
             bool head;
+            uint32_t best;
             if constexpr (ROWS) {
                 heads = rmk[i] | 1ull | ~__ballot(valid[i]);  // as in the BFS branch
                 head = lane_bit(heads);
+                best = red[i];
             } else {
+                const uint32_t cand = APP == kCc ? x[i] : __builtin_elementwise_add_sat(x[i], wt[i]);
                 const uint32_t prev = lane_prev(dst[i]);  // lane 0 is a head whatever it reads
                 head = lane == 0 || prev != dst[i];
                 heads = __ballot(head);
+                best = seg_reduce(cand, heads, [](uint32_t a, uint32_t b) { return a < b ? a : b; });
             }
             const uint64_t hv = heads & __ballot(valid[i]);
-            uint32_t best = seg_reduce(cand, heads,
-                                       [](uint32_t a, uint32_t b) { return a < b ? a : b; });
             if (lane == 0 && carry < best) best = carry;
             carry = kInf;
             int defer = -1;
